@@ -1,0 +1,93 @@
+"""Planted mistakes in the oracle (on the CPU) must each fail at least one pin.
+
+Each test swaps one oracle function for a plausibly wrong version and checks that a
+pin from tests/pins.py raises.  This shows the pins constrain every step: the bearing
+(sign and handedness), the exponent sign, the bin rule, the normaliser, the
+contraction's operand order and the pivot weight.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import ref
+from tests import pins
+
+
+def _mirror_basis(orig):
+    def f(piv):
+        e_n, e_e = orig(piv)
+        return e_n, -e_e
+    return f
+
+
+def test_mirrored_bearing_fails_three_point(monkeypatch):
+    monkeypatch.setattr(ref, "bearing_basis", _mirror_basis(ref.bearing_basis))
+    with pytest.raises(AssertionError):
+        pins.check_three_point()
+
+
+def test_swapped_north_east_fails_three_point(monkeypatch):
+    orig = ref.bearing_basis
+    monkeypatch.setattr(ref, "bearing_basis", lambda piv: orig(piv)[::-1])
+    with pytest.raises(AssertionError):
+        pins.check_three_point()
+
+
+def test_positive_exponent_fails_three_point(monkeypatch):
+    orig = ref.multipoles
+
+    def plus(*a, **k):
+        am, W, N = orig(*a, **k)
+        return np.conj(am), W, N
+    monkeypatch.setattr(ref, "multipoles", plus)
+    with pytest.raises(AssertionError):
+        pins.check_three_point()
+
+
+def test_transposed_contraction_fails_three_point(monkeypatch):
+    orig = ref.contract
+    monkeypatch.setattr(ref, "contract", lambda X, vp: np.swapaxes(orig(X, vp), 1, 2))
+    with pytest.raises(AssertionError):
+        pins.check_three_point()
+
+
+def test_dropped_normaliser_fails_weight_invariance(monkeypatch):
+    monkeypatch.setattr(ref, "normalise", lambda a, W: a)
+    with pytest.raises(AssertionError):
+        pins.check_weight_invariance()
+
+
+def test_total_weight_normaliser_fails_m0_means(monkeypatch):
+    # per-pivot total weight instead of the per-bin weight
+    monkeypatch.setattr(ref, "normalise", lambda a, W: a / np.maximum(W.sum(1), 1e-300)[:, None, None])
+    with pytest.raises(AssertionError):
+        pins.check_m0_annulus_means()
+
+
+def test_closed_bins_fail_brute(monkeypatch):
+    def closed(d2, edges):
+        nb = len(edges) - 1
+        b = np.searchsorted(edges, d2, side="left") - 1
+        b[(b < 0) | (b >= nb)] = -1
+        return b
+    monkeypatch.setattr(ref, "bin_index", closed)
+    xyz, w, x = pins.random_cap(40, 2.0, 21)
+    d = xyz[:, 1] - xyz[:, 0]
+    d2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]
+    E = np.array([d2 / 3, d2, 3 * d2])
+    _, _, N = ref.multipoles(xyz[:, :1], xyz[:, :2], w[:2], x[:2], E, 0)
+    assert N[0].tolist() != [0, 1]
+
+
+def test_doubled_phase_fails_brute(monkeypatch):
+    orig = ref.bearing
+    monkeypatch.setattr(ref, "bearing", lambda d, n, e: 2.0 * orig(d, n, e))
+    with pytest.raises(AssertionError):
+        pins.check_brute(n=120, seed=3, m_max=3)
+
+
+def test_unweighted_pivots_fail_brute(monkeypatch):
+    orig = ref.contract
+    monkeypatch.setattr(ref, "contract", lambda X, vp: orig(X, np.sign(vp)))
+    with pytest.raises(AssertionError):
+        pins.check_brute(n=120, seed=4, m_max=3)
