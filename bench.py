@@ -1,0 +1,226 @@
+"""Benchmark of the harmonic-basis 3PCF hot path on one MI355X.
+
+One step = the whole hot path on one synthetic map already resident in HBM:
+build the sky-cell index -> fused multipoles + MFMA contraction over all pivots ->
+normalise by the pivots' total weight -> zeta_m copied to the host.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config nside2048]
+Prints one JSON line (progress goes to stderr).
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "pair-multipole updates/s; ζ_m wall time Nside=2048, mixed vs FP64 at 1e-6"
+PEAK_VALU_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz (non-packed FP32 or FP64 FMA)
+FLOPS_PER_UPDATE = 12.5  # algorithmic flops per (pair, m) at m_max = 10: 10 per m + ~35 per pair / 11
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_model():
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def err_m(test, ref):
+    out = []
+    for m in range(ref.shape[0]):
+        r = np.concatenate([ref[m].real.ravel(), ref[m].imag.ravel()])
+        t = np.concatenate([test[m].real.ravel(), test[m].imag.ravel()])
+        den = np.abs(r).max()
+        out.append(float(np.abs(t - r).max() / (den if den > 0 else 1.0)))
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="nside2048")
+    ap.add_argument("--prec", default="both", choices=["both", "fp64", "mixed"])
+    ap.add_argument("--cpu-sample", type=int, default=-1, help="oracle pivots (-1: automatic, 0: skip)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of known size (for HBM counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the estimator's pivot sum would shard over GPUs with one "
+              "final all-reduce of zeta, which this build does not run; use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2408_16847_amd as z3
+    from synth import CONFIGS, make_positions, make_values
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+
+    if args.copy_calibration:
+        n = 1 << 28  # 2 GiB of FP64
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8}))
+        return
+
+    cfg = CONFIGS[args.config]
+    t0 = time.time()
+    xyz = make_positions(cfg, device="cuda")
+    x = make_values(cfg, xyz, seed=0)
+    torch.cuda.synchronize()
+    log(f"[bench] inputs {cfg.name}: n={xyz.shape[1]} generated in {time.time() - t0:.1f}s; "
+        f"delta min {float(x.min()):.3g} max {float(x.max()):.3g}")
+    E = cfg.edges_chord2()
+    M = cfg.m_max
+    n = xyz.shape[1]
+
+    def step(prec):
+        idx = z3.Index(xyz, E)
+        idx.set_values(x)
+        zeta = torch.zeros((M + 1, cfg.nbins, cfg.nbins, 2), dtype=torch.float64, device="cuda")
+        pairs = torch.zeros(1, dtype=torch.int64, device="cuda")
+        sw = torch.zeros(1, dtype=torch.float64, device="cuda")
+        z3.estimate_raw(idx, M, prec=prec, zeta=zeta, pair_total=pairs, sum_w=sw)
+        z3.zeta3._lib.call("z3_finalize", 1, M, cfg.nbins, z3.zeta3._ptr(zeta), z3.zeta3._ptr(sw),
+                           z3.zeta3._stream())
+        zh = zeta.cpu().numpy()
+        npairs = int(pairs.item())
+        idx.free()
+        return zh[..., 0] + 1j * zh[..., 1], npairs
+
+    precs = ["fp64", "mixed"] if args.prec == "both" else [args.prec]
+    res = {}
+    for prec in precs:
+        for w in range(args.warmup):
+            step(prec)
+            log(f"[bench] {prec} warmup {w + 1}/{args.warmup} done")
+        z3.profile_read(reset=True)
+        z3.profile_enable(True)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for s in range(args.steps):
+            zeta, npairs = step(prec)
+            log(f"[bench] {prec} step {s + 1}/{args.steps} done")
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / args.steps
+        z3.profile_enable(False)
+        launches, kms = z3.profile_read(reset=True)
+        res[prec] = {"zeta": zeta, "pairs": npairs, "s_per_step": dt, "kernel_ms_total": kms,
+                     "kernel_launches": launches}
+        log(f"[bench] {prec}: {dt * 1e3:.1f} ms/step, pairs {npairs}, "
+            f"k_multipoles {kms / max(launches, 1):.2f} ms x {launches / args.steps:.0f} per step")
+
+    main_prec = "mixed" if "mixed" in res else "fp64"
+    r = res[main_prec]
+    updates = r["pairs"] * (M + 1)
+    value = updates / r["s_per_step"]
+    launches_per_step = r["kernel_launches"] / args.steps
+    kern_s_per_step = r["kernel_ms_total"] / args.steps / 1e3
+    achieved = FLOPS_PER_UPDATE * updates / kern_s_per_step / 1e12
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "pair-multipole updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["s_per_step"] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if main_prec == "fp64" else "f64 geometry + f32 multipoles/MFMA",
+        "data": "synthetic",
+        "config": {"workload": cfg.name, "npoints": n, "nbins": cfg.nbins, "m_max": M,
+                   "theta_arcmin": [cfg.theta_min * 10800 / np.pi, cfg.theta_max * 10800 / np.pi],
+                   "log_bins": cfg.log_bins, "precision": main_prec, "pairs": r["pairs"]},
+        "roofline": {"bound": "alu", "kernel": "k_multipoles", "achieved": achieved,
+                     "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_VALU_TFLOPS,
+                     "traffic": None, "avg_launch_ms": r["kernel_ms_total"] / max(r["kernel_launches"], 1),
+                     "launches_per_step": launches_per_step, "flops_per_update": FLOPS_PER_UPDATE},
+    }
+    for prec in res:
+        out[f"zeta_wall_ms_{prec}"] = res[prec]["s_per_step"] * 1e3
+        out[f"updates_per_s_{prec}"] = res[prec]["pairs"] * (M + 1) / res[prec]["s_per_step"]
+    if "fp64" in res and "mixed" in res:
+        e = err_m(res["mixed"]["zeta"], res["fp64"]["zeta"])
+        out["mixed_vs_fp64_err_m"] = e
+        out["mixed_vs_fp64_err_max"] = max(e)
+        out["speedup_mixed_vs_fp64"] = res["fp64"]["s_per_step"] / res["mixed"]["s_per_step"]
+        out["pairs_equal"] = res["fp64"]["pairs"] == res["mixed"]["pairs"]
+
+    if args.cpu_sample != 0:
+        out["cpu_baseline"] = cpu_baseline(cfg, xyz, x, E, M, main_prec, args.cpu_sample, z3, torch)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(cfg, xyz, x, E, M, prec, nsample, z3, torch):
+    """Time the FP64 C oracle on a contiguous index-order range of pivots against the full
+    neighbour catalogue, and check the GPU path on the same pivots."""
+    from oracle import cpu
+    n = xyz.shape[1]
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    idx = z3.Index(xyz, E)
+    idx.set_values(x)
+    perm = idx.perm().cpu().numpy()
+    # size the sample to ~15 s of oracle work: one call with a single pivot measures the
+    # oracle's fixed cost (its own O(N) grid build), one with 320 pivots its pair rate
+    xyz_h = xyz.cpu().numpy()
+    x_h = x.cpu().numpy()
+    w_h = np.ones(n)
+    p0 = n // 3
+    if nsample < 0:
+        t = time.perf_counter()
+        sel = perm[p0:p0 + 1]
+        cpu.estimate(xyz_h[:, sel], xyz_h, w_h, x_h, E, M, w_h[sel], x_h[sel], nthreads=threads)
+        t_fixed = time.perf_counter() - t
+        t = time.perf_counter()
+        sel = perm[p0:p0 + 320]
+        _, p320 = cpu.estimate(xyz_h[:, sel], xyz_h, w_h, x_h, E, M, w_h[sel], x_h[sel], nthreads=threads)
+        rate = p320 / max(time.perf_counter() - t - t_fixed, 1e-3)
+        nsample = int(min(n - p0, max(320, 15.0 * rate / max(p320 / 320.0, 1.0))))
+        log(f"[bench] cpu_baseline calibration: fixed {t_fixed:.2f}s, {rate:.3g} pairs/s")
+    sel = perm[p0:p0 + nsample]
+    log(f"[bench] cpu_baseline: oracle on {nsample} pivots x {threads} threads")
+    t = time.perf_counter()
+    zo, po = cpu.estimate(xyz_h[:, sel], xyz_h, w_h, x_h, E, M, w_h[sel], x_h[sel], nthreads=threads)
+    dt = time.perf_counter() - t
+    zeta = torch.zeros((M + 1, cfg.nbins, cfg.nbins, 2), dtype=torch.float64, device="cuda")
+    pairs = torch.zeros(1, dtype=torch.int64, device="cuda")
+    sw = torch.zeros(1, dtype=torch.float64, device="cuda")
+    z3.estimate_raw(idx, M, prec=prec, p0=p0, p1=p0 + nsample, zeta=zeta, pair_total=pairs, sum_w=sw)
+    zg = (zeta / sw).cpu().numpy()
+    zg = zg[..., 0] + 1j * zg[..., 1]
+    idx.free()
+    e = err_m(zg, zo)
+    log(f"[bench] cpu_baseline: {dt:.1f}s, pairs oracle {po} gpu {int(pairs.item())}, err_m max {max(e):.2e}")
+    return {"value": po * (M + 1) / dt, "unit": "pair-multipole updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{nsample} contiguous index-order pivots from position {p0} of the {cfg.name} map "
+                      f"against all {n} neighbours (includes the oracle's O(N) grid build)",
+            "seconds": dt, "cpu_model": cpu_model(),
+            "gpu_parity_on_sample": {"pairs_equal": po == int(pairs.item()), "err_m_max": max(e),
+                                     "precision": prec}}
+
+
+if __name__ == "__main__":
+    main()

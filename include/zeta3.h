@@ -1,0 +1,175 @@
+/*
+ * zeta3.h -- C ABI of libzeta3, the MI355X (gfx950) harmonic-basis 3PCF estimator.
+ *
+ * The library computes the binned multipole estimator of the three-point correlation
+ * function of a spin-0 field on the sphere (arXiv 2408.16847, section "3PCF binned
+ * estimator", eqs. Xm.binned, Ym/Zm.binned, zetamEst, zetamEst2; resummation eq.
+ * eq_zeta_harmonic):
+ *
+ *   a_{m,b}(p)    = sum_{j in bin b of p} w_j x_j exp(-i m phi_pj)       (multipoles)
+ *   W_{p,b}       = sum_{j in bin b of p} w_j
+ *   X_m(b; p)     = a_{m,b}(p) / W_{p,b}     (0 when W_{p,b} = 0)          (normalise)
+ *   zeta_m(b1,b2) = (1 / sum_p w_p) sum_p w_p x_p X_m(b1; p) conj(X_m(b2; p))  (contract)
+ *   zeta(b1,b2,phi) = sum_{|m|<=M} zeta_m exp(i m phi),  zeta_{-m} = conj(zeta_m)
+ *
+ * phi_pj is the position angle of neighbour j seen from pivot p, measured from local
+ * north through east.  A neighbour j is in bin b of pivot p iff
+ * E_b <= d2 < E_{b+1} where d2 = (dx*dx + dy*dy) + dz*dz is the squared chord
+ * computed in FP64 with each operation rounded separately, dx = x_j - x_p, and
+ * E_0 < ... < E_nbins is the caller's chord-squared edge table (E = (2 sin(theta/2))^2).
+ * A pivot is never its own neighbour because E_0 > 0 is required.
+ *
+ * Conventions common to every entry point
+ * ---------------------------------------
+ *  - Array arguments are DEVICE pointers owned by the caller unless marked [host].
+ *  - "stream" is a hipStream_t passed as void* (NULL = the legacy default stream).
+ *    Every call only enqueues work on that stream and returns; the exceptions are
+ *    z3_build_index (synchronises once on the stream to size its tables) and z3_sync.
+ *  - Every function returns a z3_status and never throws.  On Z3_ERR_INVALID_ARG no
+ *    output has been written.  The text of the last error of the calling thread is
+ *    returned by z3_last_error().  Asynchronous device faults surface as Z3_ERR_HIP
+ *    from the next call or from z3_sync.
+ *  - zeta arrays are FP64 [m_max+1][nbins][nbins][2] (re, im), full Hermitian matrices,
+ *    and are ACCUMULATED (+=), so pivot ranges can be processed in pieces and summed.
+ *  - Pivots are the catalogue's own points, addressed by their position in the index
+ *    order (see z3_index_perm), so that pivot ranges [p0, p1) can be streamed.
+ */
+#ifndef ZETA3_H
+#define ZETA3_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct z3_index_s *z3_index;
+
+typedef enum {
+    Z3_OK = 0,
+    Z3_ERR_INVALID_ARG = 1,   /* bad sizes, NULL pointers, unsorted edges, ...         */
+    Z3_ERR_OUT_OF_MEMORY = 2, /* device allocation failed                               */
+    Z3_ERR_HIP = 3,           /* a HIP runtime call or a kernel failed                  */
+    Z3_ERR_UNSUPPORTED = 4,   /* valid request outside what this build implements       */
+    Z3_ERR_OVERFLOW = 5       /* catalogue or pair count beyond the supported range     */
+} z3_status;
+
+enum {
+    Z3_PREC_FP64 = 0,  /* all arithmetic in FP64                                         */
+    Z3_PREC_MIXED = 1  /* FP64 separations and bin decisions, FP32 bearing/recurrence
+                          with FP64 per-bin sums, FP32 MFMA contraction with FP64 sums */
+};
+
+enum {
+    Z3_NORM_BIN = 0,  /* X = a / W_{p,b} (the per-bin average of the estimator)          */
+    Z3_NORM_NONE = 1  /* raw sums a_{m,b}; callers can apply any other normaliser       */
+};
+
+/* Largest supported multipole and bin count. */
+#define Z3_MAX_MMAX 16
+#define Z3_MAX_NBINS 64
+
+/*
+ * Build the sky-cell index of a catalogue of n points (the neighbour search of the
+ * binned estimator; it replaces the paper's tree search with a latitude-band x
+ * longitude-cell grid, points sorted by cell).
+ *   n              number of points, 0 <= n < 2^31
+ *   xyz            [3][n] FP64 unit vectors (x row, y row, z row)
+ *   w              [n] FP64 weights w_i (eq. of the discrete field), or NULL for all 1
+ *   nbins          1 .. Z3_MAX_NBINS
+ *   edges_chord2   [host] nbins+1 strictly increasing chord-squared edges, 0 < E_0,
+ *                  E_nbins <= 4
+ *   cell_size      band height in radians; <= 0 selects 0.35 * sqrt(A / n) where A is
+ *                  the area of the catalogue's colatitude range
+ *   out            receives the index; free it with z3_index_free
+ * Synchronises once on `stream`.  The input arrays may be freed after it returns.
+ */
+z3_status z3_build_index(int64_t n, const double *xyz, const double *w, int nbins,
+                         const double *edges_chord2, double cell_size, void *stream,
+                         z3_index *out);
+
+/*
+ * Attach field values: nmaps maps of n values each, x [nmaps][n] FP64 in the
+ * catalogue's original order.  The index stores w_i x_i in index order (FP64, and an
+ * FP32 copy for the mixed path).  Replaces values attached before.
+ */
+z3_status z3_index_set_values(z3_index idx, int nmaps, const double *x, void *stream);
+
+/* Sizes of an index ([host] outputs, any may be NULL). */
+z3_status z3_index_info(z3_index idx, int64_t *n, int *nbins, int *nmaps, int *nbands,
+                        int64_t *ncells);
+
+/* perm [n] int64: original catalogue index of the point at index position i. */
+z3_status z3_index_perm(z3_index idx, int64_t *perm, void *stream);
+
+/* Release an index and its device memory (NULL is ignored).  Waits for its work. */
+void z3_index_free(z3_index idx);
+
+/*
+ * Per-pivot multipoles (eqs. Xm.binned, Ym/Zm.binned) for pivots [p0, p1) in index
+ * order, map `map` of the attached values.  P = p1 - p0.
+ *   A       [m_max+1][2][nbins][P]: re and im of X_m(b; p) (or raw a with Z3_NORM_NONE);
+ *           FP64 for Z3_PREC_FP64, FP32 for Z3_PREC_MIXED.  May be NULL.
+ *   W       [nbins][P] FP64 W_{p,b}, or NULL
+ *   counts  [nbins][P] int64 N_{p,b}, or NULL
+ *   idhash  [nbins][P] uint64: sum over the bin's neighbours j of SplitMix64(j), j the
+ *           original catalogue index (an order-independent fingerprint of the
+ *           neighbour list), or NULL
+ *   pair_total [1] uint64, += the number of pairs found, or NULL
+ */
+z3_status z3_accumulate_multipoles(z3_index idx, int map, int m_max, int prec, int norm,
+                                   int64_t p0, int64_t p1, void *A, double *W,
+                                   int64_t *counts, uint64_t *idhash, uint64_t *pair_total,
+                                   void *stream);
+
+/*
+ * Contraction (eq. zetamEst / zetamEst2) of materialised multipoles:
+ *   zeta[m][b1][b2] += sum_p v_p X_m(b1; p) conj(X_m(b2; p))
+ * A has the layout written by z3_accumulate_multipoles (FP64 or FP32 per prec);
+ * piv_v [npiv] FP64 pivot products w_p x_p.  Not divided by sum_p w_p (z3_finalize).
+ */
+z3_status z3_contract(int64_t npiv, int m_max, int nbins, int prec, const void *A,
+                      const double *piv_v, double *zeta, void *stream);
+
+/*
+ * Fused estimator for pivots [p0, p1) of map `map`: multipoles per pivot chunk into a
+ * library-owned workspace, then the contraction, zeta += (unnormalised), and
+ * pair_total += pairs (may be NULL).  Equivalent to accumulate + contract.
+ */
+z3_status z3_estimate(z3_index idx, int map, int m_max, int prec, int64_t p0, int64_t p1,
+                      double *zeta, uint64_t *pair_total, void *stream);
+
+/* sum_p w_p over pivots [p0, p1), FP64, out[0] += . */
+z3_status z3_pivot_weight_sum(z3_index idx, int64_t p0, int64_t p1, double *out, void *stream);
+
+/* zeta /= sum_w[0] for nmaps consecutive zeta arrays (the 1/sum_i w_i of eq. zetamEst). */
+z3_status z3_finalize(int nmaps, int m_max, int nbins, double *zeta, const double *sum_w,
+                      void *stream);
+
+/*
+ * Resummation (eq. eq_zeta_harmonic truncated at |m| <= m_max):
+ *   out[b1][b2][k] = Re zeta_0 + 2 sum_{m=1}^{m_max} (Re zeta_m cos(m phi_k) - Im zeta_m sin(m phi_k))
+ * phi [nphi] FP64 radians; out [nbins][nbins][nphi] FP64.
+ */
+z3_status z3_resum(int m_max, int nbins, const double *zeta, int nphi, const double *phi,
+                   double *out, void *stream);
+
+/* Wait for the stream and report any asynchronous error. */
+z3_status z3_sync(void *stream);
+
+const char *z3_status_string(z3_status s);
+const char *z3_last_error(void);
+
+/*
+ * Kernel timing for measurement: when enabled, the library brackets every launch of
+ * its multipole kernel with HIP events on the launch stream.  z3_profile_read waits
+ * for those events and returns the number of launches and their summed duration.
+ */
+z3_status z3_profile_enable(int on);
+z3_status z3_profile_read(int64_t *launches, double *total_ms, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ZETA3_H */

@@ -1,0 +1,335 @@
+// libzeta3 entry points: argument validation, error reporting, orchestration.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <mutex>
+#include <vector>
+
+#include "z3_internal.h"
+
+namespace z3 {
+
+static thread_local char g_err[1024] = "";
+
+z3_status fail(z3_status s, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+z3_status check_hip(hipError_t e, const char *what)
+{
+    if (e == hipSuccess) return Z3_OK;
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
+        (void)hipGetLastError();
+        return fail(Z3_ERR_OUT_OF_MEMORY, "%s: %s", what, hipGetErrorString(e));
+    }
+    return fail(Z3_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+z3_status check_launch(const char *what) { return check_hip(hipGetLastError(), what); }
+
+z3_status ensure_workspace(Workspace &w, size_t bytes)
+{
+    if (w.bytes >= bytes && w.ptr) return Z3_OK;
+    if (w.ptr) {
+        hipError_t e = hipFree(w.ptr);  // waits for outstanding work on the buffer
+        w.ptr = nullptr;
+        w.bytes = 0;
+        if (e != hipSuccess) return check_hip(e, "hipFree(workspace)");
+    }
+    z3_status st = check_hip(hipMalloc(&w.ptr, bytes), "hipMalloc(workspace)");
+    if (st != Z3_OK) {
+        w.ptr = nullptr;
+        return st;
+    }
+    w.bytes = bytes;
+    return Z3_OK;
+}
+
+// ---- kernel timing -------------------------------------------------------------------
+static std::mutex g_prof_mu;
+static bool g_prof_on = false;
+static std::vector<std::pair<hipEvent_t, hipEvent_t>> g_prof_events;
+static int64_t g_prof_launches = 0;
+static double g_prof_ms = 0.0;
+
+bool profiling() { return g_prof_on; }
+
+void profile_begin(hipStream_t s, hipEvent_t *ev0)
+{
+    *ev0 = nullptr;
+    if (!g_prof_on) return;
+    if (hipEventCreate(ev0) != hipSuccess) { *ev0 = nullptr; return; }
+    (void)hipEventRecord(*ev0, s);
+}
+
+void profile_end(hipStream_t s, hipEvent_t ev0)
+{
+    if (!ev0) return;
+    hipEvent_t ev1;
+    if (hipEventCreate(&ev1) != hipSuccess) { (void)hipEventDestroy(ev0); return; }
+    (void)hipEventRecord(ev1, s);
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_events.emplace_back(ev0, ev1);
+}
+
+}  // namespace z3
+
+using namespace z3;
+
+static hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+Z3_API const char *z3_last_error(void) { return g_err; }
+
+Z3_API const char *z3_status_string(z3_status s)
+{
+    switch (s) {
+    case Z3_OK: return "ok";
+    case Z3_ERR_INVALID_ARG: return "invalid argument";
+    case Z3_ERR_OUT_OF_MEMORY: return "out of device memory";
+    case Z3_ERR_HIP: return "HIP error";
+    case Z3_ERR_UNSUPPORTED: return "unsupported";
+    case Z3_ERR_OVERFLOW: return "overflow";
+    }
+    return "unknown status";
+}
+
+Z3_API z3_status z3_build_index(int64_t n, const double *xyz, const double *w, int nbins,
+                                const double *edges_chord2, double cell_size, void *stream,
+                                z3_index *out)
+{
+    if (!out) return fail(Z3_ERR_INVALID_ARG, "z3_build_index: out is NULL");
+    *out = nullptr;
+    if (n < 0) return fail(Z3_ERR_INVALID_ARG, "z3_build_index: n < 0");
+    if (n >= (int64_t)0x7fffffff) return fail(Z3_ERR_OVERFLOW, "z3_build_index: n >= 2^31 - 1");
+    if (n > 0 && !xyz) return fail(Z3_ERR_INVALID_ARG, "z3_build_index: xyz is NULL");
+    if (nbins < 1 || nbins > Z3_MAX_NBINS)
+        return fail(Z3_ERR_INVALID_ARG, "z3_build_index: nbins=%d outside 1..%d", nbins, Z3_MAX_NBINS);
+    if (!edges_chord2) return fail(Z3_ERR_INVALID_ARG, "z3_build_index: edges_chord2 is NULL");
+    for (int b = 0; b <= nbins; ++b)
+        if (!std::isfinite(edges_chord2[b]))
+            return fail(Z3_ERR_INVALID_ARG, "z3_build_index: edge %d is not finite", b);
+    if (!(edges_chord2[0] > 0.0))
+        return fail(Z3_ERR_INVALID_ARG, "z3_build_index: E_0 must be > 0 (excludes self-pairs)");
+    for (int b = 0; b < nbins; ++b)
+        if (!(edges_chord2[b + 1] > edges_chord2[b]))
+            return fail(Z3_ERR_INVALID_ARG, "z3_build_index: edges not strictly increasing at %d", b);
+    if (edges_chord2[nbins] > 4.0)
+        return fail(Z3_ERR_INVALID_ARG, "z3_build_index: E_nbins > 4 (chord of antipodal points)");
+    if (!std::isfinite(cell_size))
+        return fail(Z3_ERR_INVALID_ARG, "z3_build_index: cell_size is not finite");
+    return build_index_impl(n, xyz, w, nbins, edges_chord2, cell_size, as_stream(stream), out);
+}
+
+Z3_API z3_status z3_index_set_values(z3_index idx, int nmaps, const double *x, void *stream)
+{
+    if (!idx) return fail(Z3_ERR_INVALID_ARG, "z3_index_set_values: idx is NULL");
+    if (nmaps < 1) return fail(Z3_ERR_INVALID_ARG, "z3_index_set_values: nmaps < 1");
+    if (idx->n > 0 && !x) return fail(Z3_ERR_INVALID_ARG, "z3_index_set_values: x is NULL");
+    if ((double)nmaps * (double)idx->n >= 9.0e18 / 8.0)
+        return fail(Z3_ERR_OVERFLOW, "z3_index_set_values: nmaps * n too large");
+    return set_values_impl(idx, nmaps, x, as_stream(stream));
+}
+
+Z3_API z3_status z3_index_info(z3_index idx, int64_t *n, int *nbins, int *nmaps, int *nbands,
+                               int64_t *ncells)
+{
+    if (!idx) return fail(Z3_ERR_INVALID_ARG, "z3_index_info: idx is NULL");
+    if (n) *n = idx->n;
+    if (nbins) *nbins = idx->nbins;
+    if (nmaps) *nmaps = idx->nmaps;
+    if (nbands) *nbands = idx->nbands;
+    if (ncells) *ncells = idx->ncells;
+    return Z3_OK;
+}
+
+__global__ void k_perm_to_i64(const int *perm, int64_t n, int64_t *out)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = perm[i];
+}
+
+Z3_API z3_status z3_index_perm(z3_index idx, int64_t *perm, void *stream)
+{
+    if (!idx) return fail(Z3_ERR_INVALID_ARG, "z3_index_perm: idx is NULL");
+    if (idx->n == 0) return Z3_OK;
+    if (!perm) return fail(Z3_ERR_INVALID_ARG, "z3_index_perm: perm is NULL");
+    int64_t nb = (idx->n + 255) / 256;
+    hipLaunchKernelGGL(k_perm_to_i64, dim3((unsigned)nb), dim3(256), 0, as_stream(stream),
+                       idx->d_perm, idx->n, perm);
+    return check_launch("k_perm_to_i64");
+}
+
+Z3_API void z3_index_free(z3_index idx)
+{
+    if (idx) free_index(idx);
+}
+
+static z3_status check_common(const char *fn, const z3_index_s *idx, int map, int m_max, int prec,
+                              int64_t p0, int64_t p1)
+{
+    if (!idx) return fail(Z3_ERR_INVALID_ARG, "%s: idx is NULL", fn);
+    if (m_max < 0 || m_max > Z3_MAX_MMAX)
+        return fail(Z3_ERR_INVALID_ARG, "%s: m_max=%d outside 0..%d", fn, m_max, Z3_MAX_MMAX);
+    if (prec != Z3_PREC_FP64 && prec != Z3_PREC_MIXED)
+        return fail(Z3_ERR_INVALID_ARG, "%s: unknown precision %d", fn, prec);
+    if (p0 < 0 || p1 < p0 || p1 > idx->n)
+        return fail(Z3_ERR_INVALID_ARG, "%s: pivot range [%lld, %lld) outside [0, %lld]", fn,
+                    (long long)p0, (long long)p1, (long long)idx->n);
+    if (idx->n > 0 && (idx->nmaps < 1 || !idx->d_v))
+        return fail(Z3_ERR_INVALID_ARG, "%s: no values attached (z3_index_set_values)", fn);
+    if (idx->n > 0 && (map < 0 || map >= idx->nmaps))
+        return fail(Z3_ERR_INVALID_ARG, "%s: map %d outside 0..%d", fn, map, idx->nmaps - 1);
+    return Z3_OK;
+}
+
+Z3_API z3_status z3_accumulate_multipoles(z3_index idx, int map, int m_max, int prec, int norm,
+                                          int64_t p0, int64_t p1, void *A, double *W,
+                                          int64_t *counts, uint64_t *idhash, uint64_t *pair_total,
+                                          void *stream)
+{
+    z3_status st = check_common("z3_accumulate_multipoles", idx, map, m_max, prec, p0, p1);
+    if (st != Z3_OK) return st;
+    if (norm != Z3_NORM_BIN && norm != Z3_NORM_NONE)
+        return fail(Z3_ERR_INVALID_ARG, "z3_accumulate_multipoles: unknown norm %d", norm);
+    if (p1 == p0) return Z3_OK;
+    return launch_multipoles(idx, map, m_max, prec, norm, p0, p1, A, p1 - p0, W, counts, idhash,
+                             pair_total, as_stream(stream));
+}
+
+Z3_API z3_status z3_contract(int64_t npiv, int m_max, int nbins, int prec, const void *A,
+                             const double *piv_v, double *zeta, void *stream)
+{
+    if (npiv < 0) return fail(Z3_ERR_INVALID_ARG, "z3_contract: npiv < 0");
+    if (m_max < 0 || m_max > Z3_MAX_MMAX) return fail(Z3_ERR_INVALID_ARG, "z3_contract: bad m_max");
+    if (nbins < 1 || nbins > Z3_MAX_NBINS) return fail(Z3_ERR_INVALID_ARG, "z3_contract: bad nbins");
+    if (prec != Z3_PREC_FP64 && prec != Z3_PREC_MIXED)
+        return fail(Z3_ERR_INVALID_ARG, "z3_contract: unknown precision %d", prec);
+    if (!zeta) return fail(Z3_ERR_INVALID_ARG, "z3_contract: zeta is NULL");
+    if (npiv == 0) return Z3_OK;
+    if (!A || !piv_v) return fail(Z3_ERR_INVALID_ARG, "z3_contract: A or piv_v is NULL");
+    size_t pb = contract_partial_bytes(npiv, m_max, nbins);
+    void *part = nullptr;
+    z3_status st = check_hip(hipMallocAsync(&part, pb, as_stream(stream)), "hipMallocAsync(partials)");
+    if (st != Z3_OK) return st;
+    st = launch_contract(npiv, m_max, nbins, prec, A, npiv, piv_v, zeta, part, pb, as_stream(stream));
+    z3_status st2 = check_hip(hipFreeAsync(part, as_stream(stream)), "hipFreeAsync(partials)");
+    return st != Z3_OK ? st : st2;
+}
+
+static int64_t chunk_pivots(const z3_index_s *idx, int m_max, int prec)
+{
+    size_t elem = prec == Z3_PREC_FP64 ? 8 : 4;
+    size_t per_piv = (size_t)(m_max + 1) * 2 * idx->nbins * elem;
+    size_t budget = (size_t)4 << 30;
+    if (const char *e = getenv("Z3_WORKSPACE_MB")) {
+        long long mb = atoll(e);
+        if (mb > 0) budget = (size_t)mb << 20;
+    }
+    int64_t c = (int64_t)(budget / per_piv);
+    c = (c / kBlock) * kBlock;
+    if (c < 16 * kBlock) c = 16 * kBlock;
+    return c;
+}
+
+Z3_API z3_status z3_estimate(z3_index idx, int map, int m_max, int prec, int64_t p0, int64_t p1,
+                             double *zeta, uint64_t *pair_total, void *stream)
+{
+    z3_status st = check_common("z3_estimate", idx, map, m_max, prec, p0, p1);
+    if (st != Z3_OK) return st;
+    if (!zeta) return fail(Z3_ERR_INVALID_ARG, "z3_estimate: zeta is NULL");
+    if (p1 == p0) return Z3_OK;
+    hipStream_t s = as_stream(stream);
+    int64_t chunk = chunk_pivots(idx, m_max, prec);
+    if (chunk > p1 - p0) chunk = ((p1 - p0 + kBlock - 1) / kBlock) * kBlock;
+    size_t elem = prec == Z3_PREC_FP64 ? 8 : 4;
+    size_t abytes = (size_t)chunk * (size_t)(m_max + 1) * 2 * idx->nbins * elem;
+    size_t pbytes = contract_partial_bytes(chunk, m_max, idx->nbins);
+    if ((st = ensure_workspace(idx->ws_a, abytes)) != Z3_OK) return st;
+    if ((st = ensure_workspace(idx->ws_part, pbytes)) != Z3_OK) return st;
+    const double *v = idx->d_v + (size_t)map * idx->n;
+    for (int64_t c0 = p0; c0 < p1; c0 += chunk) {
+        int64_t c1 = c0 + chunk < p1 ? c0 + chunk : p1;
+        st = launch_multipoles(idx, map, m_max, prec, Z3_NORM_BIN, c0, c1, idx->ws_a.ptr, c1 - c0,
+                               nullptr, nullptr, nullptr, pair_total, s);
+        if (st != Z3_OK) return st;
+        st = launch_contract(c1 - c0, m_max, idx->nbins, prec, idx->ws_a.ptr, c1 - c0, v + c0, zeta,
+                             idx->ws_part.ptr, idx->ws_part.bytes, s);
+        if (st != Z3_OK) return st;
+    }
+    return Z3_OK;
+}
+
+Z3_API z3_status z3_pivot_weight_sum(z3_index idx, int64_t p0, int64_t p1, double *out, void *stream)
+{
+    if (!idx) return fail(Z3_ERR_INVALID_ARG, "z3_pivot_weight_sum: idx is NULL");
+    if (p0 < 0 || p1 < p0 || p1 > idx->n) return fail(Z3_ERR_INVALID_ARG, "z3_pivot_weight_sum: bad range");
+    if (!out) return fail(Z3_ERR_INVALID_ARG, "z3_pivot_weight_sum: out is NULL");
+    if (p1 == p0) return Z3_OK;
+    return launch_weight_sum(idx->d_w + p0, p1 - p0, out, as_stream(stream));
+}
+
+Z3_API z3_status z3_finalize(int nmaps, int m_max, int nbins, double *zeta, const double *sum_w,
+                             void *stream)
+{
+    if (nmaps < 1 || m_max < 0 || m_max > Z3_MAX_MMAX || nbins < 1 || nbins > Z3_MAX_NBINS)
+        return fail(Z3_ERR_INVALID_ARG, "z3_finalize: bad sizes");
+    if (!zeta || !sum_w) return fail(Z3_ERR_INVALID_ARG, "z3_finalize: NULL pointer");
+    return launch_finalize(nmaps, m_max, nbins, zeta, sum_w, as_stream(stream));
+}
+
+Z3_API z3_status z3_resum(int m_max, int nbins, const double *zeta, int nphi, const double *phi,
+                          double *out, void *stream)
+{
+    if (m_max < 0 || m_max > Z3_MAX_MMAX || nbins < 1 || nbins > Z3_MAX_NBINS || nphi < 0)
+        return fail(Z3_ERR_INVALID_ARG, "z3_resum: bad sizes");
+    if (nphi == 0) return Z3_OK;
+    if (!zeta || !phi || !out) return fail(Z3_ERR_INVALID_ARG, "z3_resum: NULL pointer");
+    return launch_resum(m_max, nbins, zeta, nphi, phi, out, as_stream(stream));
+}
+
+Z3_API z3_status z3_sync(void *stream)
+{
+    z3_status st = check_hip(hipStreamSynchronize(as_stream(stream)), "hipStreamSynchronize");
+    if (st != Z3_OK) return st;
+    return check_hip(hipGetLastError(), "asynchronous error");
+}
+
+Z3_API z3_status z3_profile_enable(int on)
+{
+    g_prof_on = on != 0;
+    return Z3_OK;
+}
+
+Z3_API z3_status z3_profile_read(int64_t *launches, double *total_ms, int reset)
+{
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> evs;
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        evs.swap(g_prof_events);
+    }
+    z3_status st = Z3_OK;
+    for (auto &e : evs) {
+        if (st == Z3_OK) st = check_hip(hipEventSynchronize(e.second), "hipEventSynchronize");
+        float ms = 0.0f;
+        if (st == Z3_OK) st = check_hip(hipEventElapsedTime(&ms, e.first, e.second), "hipEventElapsedTime");
+        if (st == Z3_OK) {
+            g_prof_ms += ms;
+            g_prof_launches += 1;
+        }
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+    }
+    if (launches) *launches = g_prof_launches;
+    if (total_ms) *total_ms = g_prof_ms;
+    if (reset) {
+        g_prof_launches = 0;
+        g_prof_ms = 0.0;
+    }
+    return st;
+}

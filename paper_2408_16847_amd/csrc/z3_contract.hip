@@ -1,0 +1,247 @@
+// Contraction of the per-pivot multipoles (eqs. zetamEst, zetamEst2) on MFMA.
+//
+// For every m, with U_p = [Re X_m(0..nb-1; p), Im X_m(0..nb-1; p)] (length 2 nb):
+//     G = sum_p v_p U_p U_p^T                       (2nb x 2nb real Gram matrix)
+//     Re zeta_m(b1, b2) = G(r1, r2) + G(i1, i2),   Im zeta_m(b1, b2) = G(i1, r2) - G(r1, i2)
+// (r = b, i = nb + b), which is sum_p v_p X(b1) conj(X(b2)) written in real arithmetic.
+// The Gram matrix is a dense contraction over pivots: one wave64 computes one 16x16 tile
+// of G over a segment of pivots with v_mfma_f64_16x16x4f64 (FP64 path) or
+// v_mfma_f32_16x16x4f32 (mixed path: FP32 multipoles U; the scaled operand v_p U_i is
+// formed in FP64 and split into FP32 hi + lo parts, two MFMAs per step; FP32 sums over
+// 16 pivots are added into FP64 segment sums).
+// Only tiles on or above the diagonal are formed; entries below are read from their
+// mirror, so zeta(b2, b1) is exactly conj(zeta(b1, b2)) and Im zeta(b, b) is exactly 0.
+// Segment partials are summed in FP64 in segment order (deterministic).
+#include <algorithm>
+
+#include "z3_internal.h"
+
+namespace z3 {
+
+constexpr int kSeg = 4096;  // pivots per contraction wave
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+static inline int tiles_for(int nbins) { return (2 * nbins + 15) / 16; }
+
+size_t contract_partial_bytes(int64_t npiv, int m_max, int nbins)
+{
+    const int T = tiles_for(nbins);
+    const int64_t nseg = (npiv + kSeg - 1) / kSeg;
+    return (size_t)(nseg > 0 ? nseg : 1) * (size_t)(m_max + 1) * (size_t)(T * (T + 1) / 2) * 256 * sizeof(double);
+}
+
+struct ContractArgs {
+    const void *A;
+    int64_t ldA;
+    int64_t npiv;
+    const double *v;
+    int nb, T, ntp;
+    double *part;
+};
+
+template <bool F32>
+__global__ __launch_bounds__(64) void k_gram_tiles(ContractArgs c)
+{
+    const int tp = blockIdx.x, seg = blockIdx.y, m = blockIdx.z;
+    int I = 0, r = tp;
+    while (r >= c.T - I) { r -= c.T - I; ++I; }
+    const int J = I + r;
+    const int lane = threadIdx.x;
+    const int row = lane & 15, kq = lane >> 4;
+    const int ui = I * 16 + row, uj = J * 16 + row;
+    const int two_nb = 2 * c.nb;
+    const bool vi = ui < two_nb, vj = uj < two_nb;
+    // U index u = comp * nb + b lives at A[(2m + comp) * nb + b][p] = A[2 m nb + u][p]
+    const size_t oi = vi ? ((size_t)2 * m * c.nb + ui) * (size_t)c.ldA : 0;
+    const size_t oj = vj ? ((size_t)2 * m * c.nb + uj) * (size_t)c.ldA : 0;
+    const int64_t pbeg = (int64_t)seg * kSeg;
+    const int64_t pend = min(c.npiv, pbeg + kSeg);
+
+    if constexpr (!F32) {
+        const double *A = static_cast<const double *>(c.A);
+        v4d acc = {0.0, 0.0, 0.0, 0.0};
+        for (int64_t s = pbeg; s < pend; s += 16) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t p = s + 4 * kq + q;
+                const bool in = p < pend;
+                const double vp = in ? c.v[p] : 0.0;
+                const double ai = (vi && in) ? A[oi + p] : 0.0;
+                const double bj = (vj && in) ? A[oj + p] : 0.0;
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ai * vp, bj, acc, 0, 0, 0);
+            }
+        }
+        // v_mfma_f64_16x16x4f64 result layout: register k of lane l holds D[4k + l/16][l % 16]
+        double *out = c.part + ((size_t)(seg * gridDim.z + m) * c.ntp + tp) * 256;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) out[(4 * k + kq) * 16 + row] = acc[k];
+    } else {
+        const float *A = static_cast<const float *>(c.A);
+        v4d acc = {0.0, 0.0, 0.0, 0.0};
+        for (int64_t s = pbeg; s < pend; s += 16) {
+            // FP32 products and sums over 16 pivots, then into the FP64 segment sum
+            v4f part = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t p = s + 4 * kq + q;
+                const bool in = p < pend;
+                const double vp = in ? c.v[p] : 0.0;
+                const float ui = (vi && in) ? A[oi + p] : 0.0f;
+                const float bj = (vj && in) ? A[oj + p] : 0.0f;
+                // split-precision operand: v_p U_i formed in FP64, carried as hi + lo
+                const double a = (double)ui * vp;
+                const float ahi = (float)a;
+                const float alo = (float)(a - (double)ahi);
+                part = __builtin_amdgcn_mfma_f32_16x16x4f32(ahi, bj, part, 0, 0, 0);
+                part = __builtin_amdgcn_mfma_f32_16x16x4f32(alo, bj, part, 0, 0, 0);
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) acc[k] += (double)part[k];
+        }
+        // v_mfma_f32_16x16x4f32 result layout: register k of lane l holds D[4 (l/16) + k][l % 16]
+        double *out = c.part + ((size_t)(seg * gridDim.z + m) * c.ntp + tp) * 256;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) out[(4 * kq + k) * 16 + row] = (double)acc[k];
+    }
+}
+
+// G(u, v) of one segment, read from the tile holding min/max of (u, v).
+__device__ __forceinline__ double gram_at(const double *seg_m, int T, int u, int v)
+{
+    if (u > v) { int t = u; u = v; v = t; }
+    const int I = u >> 4, J = v >> 4;
+    const int tp = I * T - I * (I - 1) / 2 + (J - I);
+    return seg_m[(size_t)tp * 256 + (u & 15) * 16 + (v & 15)];
+}
+
+__global__ void k_gram_reduce(const double *part, int64_t nseg, int M1, int nb, int T, int ntp, double *zeta)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int total = M1 * nb * nb;
+    if (t >= total) return;
+    const int m = t / (nb * nb), rem = t % (nb * nb), b1 = rem / nb, b2 = rem % nb;
+    const int r1 = b1, r2 = b2, i1 = nb + b1, i2 = nb + b2;
+    double rr = 0.0, ii = 0.0, ir = 0.0, ri = 0.0;
+    for (int64_t s = 0; s < nseg; ++s) {
+        const double *g = part + (size_t)(s * M1 + m) * ntp * 256;
+        rr += gram_at(g, T, r1, r2);
+        ii += gram_at(g, T, i1, i2);
+        ir += gram_at(g, T, i1, r2);
+        ri += gram_at(g, T, r1, i2);
+    }
+    double *z = zeta + ((size_t)(m * nb + b1) * nb + b2) * 2;
+    z[0] += rr + ii;
+    z[1] += ir - ri;
+}
+
+z3_status launch_contract(int64_t npiv, int m_max, int nbins, int prec, const void *A, int64_t ldA,
+                          const double *piv_v, double *zeta, void *partials, size_t partial_bytes,
+                          hipStream_t s)
+{
+    if (npiv <= 0) return Z3_OK;
+    const int T = tiles_for(nbins), ntp = T * (T + 1) / 2;
+    const int64_t nseg = (npiv + kSeg - 1) / kSeg;
+    if (contract_partial_bytes(npiv, m_max, nbins) > partial_bytes)
+        return fail(Z3_ERR_INVALID_ARG, "contraction workspace too small");
+    if (nseg > 65535) return fail(Z3_ERR_OVERFLOW, "too many pivots for one contraction (%lld)", (long long)npiv);
+    ContractArgs c;
+    c.A = A; c.ldA = ldA; c.npiv = npiv; c.v = piv_v; c.nb = nbins; c.T = T; c.ntp = ntp;
+    c.part = static_cast<double *>(partials);
+    dim3 grid(ntp, (unsigned)nseg, m_max + 1);
+    if (prec == Z3_PREC_MIXED) hipLaunchKernelGGL(k_gram_tiles<true>, grid, dim3(64), 0, s, c);
+    else hipLaunchKernelGGL(k_gram_tiles<false>, grid, dim3(64), 0, s, c);
+    z3_status st = check_launch("k_gram_tiles");
+    if (st != Z3_OK) return st;
+    const int total = (m_max + 1) * nbins * nbins;
+    hipLaunchKernelGGL(k_gram_reduce, dim3((total + 127) / 128), dim3(128), 0, s,
+                       static_cast<const double *>(partials), nseg, m_max + 1, nbins, T, ntp, zeta);
+    return check_launch("k_gram_reduce");
+}
+
+// ---- sum of pivot weights (fixed order) ------------------------------------------------
+
+__global__ void k_sum_partials(const double *w, int64_t n, int64_t per_block, double *partial)
+{
+    __shared__ double sh[256];
+    const int64_t beg = (int64_t)blockIdx.x * per_block;
+    const int64_t end = min(n, beg + per_block);
+    double acc = 0.0;
+    for (int64_t i = beg + threadIdx.x; i < end; i += 256) acc += w[i];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+
+__global__ void k_sum_final(const double *partial, int nblk, double *out)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double acc = 0.0;
+        for (int b = 0; b < nblk; ++b) acc += partial[b];
+        out[0] += acc;
+    }
+}
+
+z3_status launch_weight_sum(const double *w, int64_t n, double *out, hipStream_t s)
+{
+    int64_t want = (n + 4095) / 4096;
+    int nblk = (int)(want < 1024 ? want : 1024);
+    if (nblk < 1) nblk = 1;
+    const int64_t per = (n + nblk - 1) / nblk;
+    double *partial = nullptr;
+    z3_status st = check_hip(hipMallocAsync((void **)&partial, nblk * sizeof(double), s), "hipMallocAsync");
+    if (st != Z3_OK) return st;
+    hipLaunchKernelGGL(k_sum_partials, dim3(nblk), dim3(256), 0, s, w, n, per, partial);
+    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(64), 0, s, partial, nblk, out);
+    st = check_launch("k_sum");
+    (void)hipFreeAsync(partial, s);
+    return st;
+}
+
+__global__ void k_finalize(double *zeta, int64_t count, const double *sum_w)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // an empty pivot set (sum of weights 0) leaves the (zero) sums unchanged
+    if (i < count && sum_w[0] != 0.0) zeta[i] /= sum_w[0];
+}
+
+z3_status launch_finalize(int nmaps, int m_max, int nbins, double *zeta, const double *sum_w, hipStream_t s)
+{
+    const int64_t count = (int64_t)nmaps * (m_max + 1) * nbins * nbins * 2;
+    hipLaunchKernelGGL(k_finalize, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, zeta, count, sum_w);
+    return check_launch("k_finalize");
+}
+
+// zeta(b1, b2, phi) = Re zeta_0 + 2 sum_{m>=1} (Re zeta_m cos(m phi) - Im zeta_m sin(m phi))
+__global__ void k_resum(int M, int nb, const double *zeta, int nphi, const double *phi, double *out)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)nb * nb * nphi) return;
+    const int k = (int)(t % nphi);
+    const int64_t bb = t / nphi;
+    const double ph = phi[k];
+    double acc = zeta[bb * 2];
+    for (int m = 1; m <= M; ++m) {
+        const double *z = zeta + ((size_t)m * nb * nb + bb) * 2;
+        double sm, cm;
+        sincos(m * ph, &sm, &cm);
+        acc += 2.0 * (z[0] * cm - z[1] * sm);
+    }
+    out[t] = acc;
+}
+
+z3_status launch_resum(int m_max, int nbins, const double *zeta, int nphi, const double *phi, double *out,
+                       hipStream_t s)
+{
+    const int64_t total = (int64_t)nbins * nbins * nphi;
+    hipLaunchKernelGGL(k_resum, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, m_max, nbins, zeta, nphi,
+                       phi, out);
+    return check_launch("k_resum");
+}
+
+}  // namespace z3

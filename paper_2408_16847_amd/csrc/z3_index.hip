@@ -1,0 +1,427 @@
+// Sky-cell index: latitude bands x longitude cells, points sorted by cell.
+//
+// The paper finds the neighbours of each pivot with an octree (cBalls, "log N steps"
+// per pivot).  On the GPU the catalogue is instead bucketed once into a regular grid:
+// band k holds colatitudes [k H, (k+1) H), and inside band k the points are split into
+// ncell_k equal longitude cells (one cell per point of the band on average).  Points are
+// stored in cell order, so any longitude window of a band is a contiguous index range
+// (two ranges when it wraps through phi = 0), which the multipole kernel streams with
+// coalesced loads.  The order inside a cell is the original catalogue order, which makes
+// the index and every later sum deterministic.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "z3_internal.h"
+
+namespace z3 {
+
+// ---- small device helpers ------------------------------------------------------------
+
+__device__ __forceinline__ void atomic_min_pos_double(double *addr, double v)
+{
+    // non-negative doubles order like their bit patterns
+    atomicMin(reinterpret_cast<unsigned long long *>(addr), (unsigned long long)__double_as_longlong(v));
+}
+
+__device__ __forceinline__ void atomic_max_pos_double(double *addr, double v)
+{
+    atomicMax(reinterpret_cast<unsigned long long *>(addr), (unsigned long long)__double_as_longlong(v));
+}
+
+__device__ __forceinline__ double colatitude(double x, double y, double z)
+{
+    return atan2(sqrt(x * x + y * y), z);
+}
+
+__device__ __forceinline__ double longitude(double x, double y)
+{
+    double phi = atan2(y, x);
+    if (phi < 0.0) phi += kTwoPi;
+    return phi;
+}
+
+// ---- kernels ---------------------------------------------------------------------------
+
+__global__ void k_theta_range(const double *xyz, int64_t n, double *range /* [2]: min, max */)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double th = colatitude(xyz[i], xyz[n + i], xyz[2 * n + i]);
+    atomic_min_pos_double(&range[0], th);
+    atomic_max_pos_double(&range[1], th);
+}
+
+__global__ void k_band_of_point(const double *xyz, int64_t n, double inv_h, int nbands, int *band,
+                                double *phi_out, int *band_count, double *band_th /* [nbands][2] */)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double x = xyz[i], y = xyz[n + i], z = xyz[2 * n + i];
+    double th = colatitude(x, y, z);
+    int k = (int)(th * inv_h);
+    k = k < 0 ? 0 : (k >= nbands ? nbands - 1 : k);
+    band[i] = k;
+    phi_out[i] = longitude(x, y);
+    atomicAdd(&band_count[k], 1);
+    atomic_min_pos_double(&band_th[2 * k], th);
+    atomic_max_pos_double(&band_th[2 * k + 1], th);
+}
+
+__global__ void k_cell_of_point(int64_t n, const int *band, const double *phi, const Band *bands,
+                                int *cell, int *cell_count)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const Band &bd = bands[band[i]];
+    int c = (int)floor(phi[i] * ((double)bd.ncell / kTwoPi));
+    c = c < 0 ? 0 : (c >= bd.ncell ? bd.ncell - 1 : c);
+    int g = bd.cell_off + c;
+    cell[i] = g;
+    atomicAdd(&cell_count[g], 1);
+}
+
+__global__ void k_scatter(int64_t n, const int *cell, const int *cell_start, int *cell_fill, int *order)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int c = cell[i];
+    int pos = cell_start[c] + atomicAdd(&cell_fill[c], 1);
+    order[pos] = (int)i;
+}
+
+// Put the points of every cell in increasing original index (cells hold ~1 point).
+__global__ void k_sort_cells(int64_t ncells, const int *cell_start, int *order)
+{
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncells) return;
+    int s = cell_start[c], e = cell_start[c + 1];
+    for (int i = s + 1; i < e; ++i) {
+        int v = order[i];
+        int j = i - 1;
+        while (j >= s && order[j] > v) {
+            order[j + 1] = order[j];
+            --j;
+        }
+        order[j + 1] = v;
+    }
+}
+
+__global__ void k_gather_points(int64_t n, const int *perm, const double *xyz, const double *w,
+                                double *x, double *y, double *z, double *ws)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int64_t j = perm[i];
+    x[i] = xyz[j];
+    y[i] = xyz[n + j];
+    z[i] = xyz[2 * n + j];
+    ws[i] = w ? w[j] : 1.0;
+}
+
+__global__ void k_gather_values(int64_t n, int nmaps, const int *perm, const double *wsorted,
+                                const double *xv, double *v, float *vf)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int64_t j = perm[i];
+    double w = wsorted[i];
+    for (int m = 0; m < nmaps; ++m) {
+        double val = w * xv[(size_t)m * n + j];
+        v[(size_t)m * n + i] = val;
+        vf[(size_t)m * n + i] = (float)val;
+    }
+}
+
+__global__ void k_fill_double(double *p, int64_t n, double v)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_fill_int(int *p, int64_t n, int v)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// ---- exclusive scan of int counts (n < 2^31 total) -----------------------------------
+
+constexpr int kScanThreads = 256;
+constexpr int kScanPer = 8;
+constexpr int kScanTile = kScanThreads * kScanPer;
+
+__global__ void k_scan_tiles(const int *in, int64_t n, int *out, int *tile_sums)
+{
+    __shared__ int sh[kScanThreads];
+    int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
+    int v[kScanPer];
+    int sum = 0;
+    for (int k = 0; k < kScanPer; ++k) {
+        int64_t i = base + k;
+        v[k] = i < n ? in[i] : 0;
+        sum += v[k];
+    }
+    sh[threadIdx.x] = sum;
+    __syncthreads();
+    for (int off = 1; off < kScanThreads; off <<= 1) {
+        int t = threadIdx.x >= (unsigned)off ? sh[threadIdx.x - off] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += t;
+        __syncthreads();
+    }
+    int run = sh[threadIdx.x] - sum;  // exclusive prefix of this thread
+    for (int k = 0; k < kScanPer; ++k) {
+        int64_t i = base + k;
+        if (i < n) out[i] = run;
+        run += v[k];
+    }
+    if (threadIdx.x == kScanThreads - 1) tile_sums[blockIdx.x] = sh[threadIdx.x];
+}
+
+__global__ void k_scan_add(int *out, int64_t n, const int *tile_offsets)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] += tile_offsets[i / kScanTile];
+}
+
+// out[i] = sum_{k<i} in[k] for i in [0, n) (the caller stores the total in out[n]).
+static z3_status exclusive_scan(const int *in, int64_t n, int *out, hipStream_t s)
+{
+    int64_t tiles = (n + kScanTile - 1) / kScanTile;
+    if (tiles < 1) tiles = 1;
+    int *sums = nullptr;
+    z3_status st = check_hip(hipMallocAsync((void **)&sums, (size_t)(tiles + 1) * sizeof(int), s), "scan alloc");
+    if (st != Z3_OK) return st;
+    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)tiles), dim3(kScanThreads), 0, s, in, n, out, sums);
+    if ((st = check_launch("k_scan_tiles")) != Z3_OK) return st;
+    if (tiles > 1) {
+        int *offs = nullptr;
+        st = check_hip(hipMallocAsync((void **)&offs, (size_t)(tiles + 1) * sizeof(int), s), "scan alloc");
+        if (st != Z3_OK) return st;
+        if ((st = exclusive_scan(sums, tiles, offs, s)) != Z3_OK) return st;
+        hipLaunchKernelGGL(k_scan_add, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, out, n, offs);
+        if ((st = check_launch("k_scan_add")) != Z3_OK) return st;
+        (void)hipFreeAsync(offs, s);
+    }
+    (void)hipFreeAsync(sums, s);
+    return Z3_OK;
+}
+
+static void free_ptrs(z3_index idx)
+{
+    void *ps[] = {idx->d_edges, idx->d_bands, idx->d_cell_start, idx->d_x, idx->d_y, idx->d_z,
+                  idx->d_w, idx->d_perm, idx->d_v, idx->d_vf, idx->ws_a.ptr, idx->ws_part.ptr};
+    for (void *p : ps)
+        if (p) (void)hipFree(p);
+}
+
+void free_index(z3_index idx)
+{
+    (void)hipSetDevice(idx->device);
+    (void)hipDeviceSynchronize();
+    free_ptrs(idx);
+    delete idx;
+}
+
+template <class T>
+static z3_status dalloc(T **p, size_t count, const char *what)
+{
+    *p = nullptr;
+    return check_hip(hipMalloc((void **)p, (count ? count : 1) * sizeof(T)), what);
+}
+
+static inline unsigned grid_for(int64_t n) { return (unsigned)((n + 255) / 256 > 0 ? (n + 255) / 256 : 1); }
+
+z3_status build_index_impl(int64_t n, const double *xyz, const double *w, int nbins,
+                           const double *edges, double cell_size, hipStream_t s, z3_index *out)
+{
+    z3_index idx = new (std::nothrow) z3_index_s();
+    if (!idx) return fail(Z3_ERR_OUT_OF_MEMORY, "z3_build_index: host allocation failed");
+    (void)hipGetDevice(&idx->device);
+    idx->n = n;
+    idx->nbins = nbins;
+    for (int b = 0; b <= nbins; ++b) {
+        double e = edges[b];
+        idx->edges.e[b] = e;
+        // Rounding guards for the window search only (membership is decided by the exact
+        // d2 test): the FP64 squared chord of two FP64 unit vectors differs from the
+        // exact chord by far less than 1e-9 relative at the separations supported here.
+        idx->edges.hav_out[b] = 0.25 * e * (1.0 + 1e-9) + 1e-16;
+        idx->edges.hav_in[b] = 0.25 * e * (1.0 - 1e-9) - 1e-16;
+        double r = 2.0 * asin(std::min(1.0, sqrt(e) / 2.0));
+        idx->edges.rad_out[b] = r * (1.0 + 1e-9) + 1e-12;
+    }
+    z3_status st = Z3_OK;
+    auto bail = [&](z3_status code) {
+        (void)hipStreamSynchronize(s);
+        free_ptrs(idx);
+        delete idx;
+        return code;
+    };
+    if ((st = dalloc(&idx->d_edges, 1, "alloc edges")) != Z3_OK) return bail(st);
+    if ((st = check_hip(hipMemcpyAsync(idx->d_edges, &idx->edges, sizeof(EdgeTab), hipMemcpyHostToDevice, s),
+                        "copy edges")) != Z3_OK)
+        return bail(st);
+
+    // ---- band height -------------------------------------------------------------------
+    double h = cell_size;
+    double *d_range = nullptr;
+    if ((st = dalloc(&d_range, 2, "alloc range")) != Z3_OK) return bail(st);
+    if (h <= 0.0) {
+        double init[2] = {kPi, 0.0};
+        st = check_hip(hipMemcpyAsync(d_range, init, sizeof(init), hipMemcpyHostToDevice, s), "copy range");
+        if (st == Z3_OK && n > 0) {
+            hipLaunchKernelGGL(k_theta_range, dim3(grid_for(n)), dim3(256), 0, s, xyz, n, d_range);
+            st = check_launch("k_theta_range");
+        }
+        double rg[2] = {0.0, kPi};
+        if (st == Z3_OK) st = check_hip(hipMemcpyAsync(rg, d_range, sizeof(rg), hipMemcpyDeviceToHost, s), "copy range");
+        if (st == Z3_OK) st = check_hip(hipStreamSynchronize(s), "sync");
+        if (st != Z3_OK) { (void)hipFree(d_range); return bail(st); }
+        double area = 2.0 * kPi * (cos(std::min(rg[0], rg[1])) - cos(std::max(rg[0], rg[1])));
+        if (!(area > 0.0)) area = 1e-12;
+        h = 0.35 * sqrt(area / (double)std::max<int64_t>(n, 1));
+    }
+    (void)hipFree(d_range);
+    h = std::min(h, kPi);
+    int nbands = (int)std::ceil(kPi / h);
+    if (nbands < 1) nbands = 1;
+    if (nbands > (1 << 26)) return bail(fail(Z3_ERR_INVALID_ARG, "z3_build_index: cell_size too small"));
+    idx->band_h = h;
+    idx->nbands = nbands;
+
+    // ---- bands -------------------------------------------------------------------------
+    int *d_band = nullptr, *d_band_count = nullptr, *d_cell = nullptr, *d_cell_count = nullptr;
+    double *d_phi = nullptr, *d_band_th = nullptr;
+    auto cleanup_tmp = [&]() {
+        void *ps[] = {d_band, d_band_count, d_cell, d_cell_count, d_phi, d_band_th};
+        for (void *p : ps)
+            if (p) (void)hipFree(p);
+    };
+    auto bail2 = [&](z3_status code) {
+        (void)hipStreamSynchronize(s);
+        cleanup_tmp();
+        return bail(code);
+    };
+    if ((st = dalloc(&d_band, n, "alloc band")) != Z3_OK) return bail2(st);
+    if ((st = dalloc(&d_phi, n, "alloc phi")) != Z3_OK) return bail2(st);
+    if ((st = dalloc(&d_band_count, nbands, "alloc band count")) != Z3_OK) return bail2(st);
+    if ((st = dalloc(&d_band_th, 2 * (size_t)nbands, "alloc band theta")) != Z3_OK) return bail2(st);
+    hipLaunchKernelGGL(k_fill_int, dim3(grid_for(nbands)), dim3(256), 0, s, d_band_count, (int64_t)nbands, 0);
+    {
+        // th_lo starts at +big, th_hi at 0
+        std::vector<double> init(2 * (size_t)nbands);
+        for (int k = 0; k < nbands; ++k) { init[2 * k] = 4.0; init[2 * k + 1] = 0.0; }
+        st = check_hip(hipMemcpyAsync(d_band_th, init.data(), init.size() * sizeof(double), hipMemcpyHostToDevice, s),
+                       "copy band init");
+        if (st == Z3_OK) st = check_hip(hipStreamSynchronize(s), "sync");
+        if (st != Z3_OK) return bail2(st);
+    }
+    if (n > 0) {
+        hipLaunchKernelGGL(k_band_of_point, dim3(grid_for(n)), dim3(256), 0, s, xyz, n, 1.0 / h, nbands, d_band,
+                           d_phi, d_band_count, d_band_th);
+        if ((st = check_launch("k_band_of_point")) != Z3_OK) return bail2(st);
+    }
+    std::vector<int> bcount(nbands);
+    std::vector<double> bth(2 * (size_t)nbands);
+    st = check_hip(hipMemcpyAsync(bcount.data(), d_band_count, nbands * sizeof(int), hipMemcpyDeviceToHost, s), "copy");
+    if (st == Z3_OK)
+        st = check_hip(hipMemcpyAsync(bth.data(), d_band_th, bth.size() * sizeof(double), hipMemcpyDeviceToHost, s), "copy");
+    if (st == Z3_OK) st = check_hip(hipStreamSynchronize(s), "sync");
+    if (st != Z3_OK) return bail2(st);
+
+    std::vector<Band> bands(nbands);
+    int64_t pt = 0, cells = 0;
+    for (int k = 0; k < nbands; ++k) {
+        Band &b = bands[k];
+        std::memset(&b, 0, sizeof(Band));
+        b.npts = bcount[k];
+        b.pt_start = (int)pt;
+        b.ncell = std::max(1, b.npts);
+        b.cell_off = (int)cells;
+        b.cells_per_rad = (float)((double)b.ncell / kTwoPi);
+        double lo = b.npts ? bth[2 * k] : k * h, hi = b.npts ? bth[2 * k + 1] : k * h;
+        b.th_lo = lo;
+        b.th_hi = hi;
+        b.sh_lo = sin(0.5 * lo); b.ch_lo = cos(0.5 * lo);
+        b.sh_hi = sin(0.5 * hi); b.ch_hi = cos(0.5 * hi);
+        double slo = sin(lo), shi = sin(hi);
+        double smin = std::min(slo, shi);
+        double smax = (lo <= 0.5 * kPi && hi >= 0.5 * kPi) ? 1.0 : std::max(slo, shi);
+        b.inv_smin = smin > 0.0 ? (float)(1.0 / smin) : INFINITY;
+        b.inv_smax = smax > 0.0 ? (float)(1.0 / smax) : INFINITY;
+        pt += b.npts;
+        cells += b.ncell;
+    }
+    if (cells >= (int64_t)0x7fffffff) return bail2(fail(Z3_ERR_OVERFLOW, "z3_build_index: too many cells"));
+    idx->ncells = cells;
+    if ((st = dalloc(&idx->d_bands, nbands, "alloc bands")) != Z3_OK) return bail2(st);
+    st = check_hip(hipMemcpyAsync(idx->d_bands, bands.data(), nbands * sizeof(Band), hipMemcpyHostToDevice, s),
+                   "copy bands");
+    if (st != Z3_OK) return bail2(st);
+
+    // ---- cells, sort -----------------------------------------------------------------------
+    if ((st = dalloc(&d_cell, n, "alloc cell")) != Z3_OK) return bail2(st);
+    if ((st = dalloc(&d_cell_count, cells + 1, "alloc cell count")) != Z3_OK) return bail2(st);
+    if ((st = dalloc(&idx->d_cell_start, cells + 1, "alloc cell start")) != Z3_OK) return bail2(st);
+    hipLaunchKernelGGL(k_fill_int, dim3(grid_for(cells + 1)), dim3(256), 0, s, d_cell_count, cells + 1, 0);
+    if (n > 0) {
+        hipLaunchKernelGGL(k_cell_of_point, dim3(grid_for(n)), dim3(256), 0, s, n, d_band, d_phi, idx->d_bands,
+                           d_cell, d_cell_count);
+        if ((st = check_launch("k_cell_of_point")) != Z3_OK) return bail2(st);
+    }
+    if ((st = exclusive_scan(d_cell_count, cells, idx->d_cell_start, s)) != Z3_OK) return bail2(st);
+    // cell_start[cells] = n (bands are contiguous and cover all points)
+    {
+        int nn = (int)n;
+        st = check_hip(hipMemcpyAsync(idx->d_cell_start + cells, &nn, sizeof(int), hipMemcpyHostToDevice, s),
+                       "copy total");
+        if (st == Z3_OK) st = check_hip(hipStreamSynchronize(s), "sync");
+        if (st != Z3_OK) return bail2(st);
+    }
+    if ((st = dalloc(&idx->d_perm, n, "alloc perm")) != Z3_OK) return bail2(st);
+    hipLaunchKernelGGL(k_fill_int, dim3(grid_for(cells + 1)), dim3(256), 0, s, d_cell_count, cells + 1, 0);
+    if (n > 0) {
+        hipLaunchKernelGGL(k_scatter, dim3(grid_for(n)), dim3(256), 0, s, n, d_cell, idx->d_cell_start,
+                           d_cell_count, idx->d_perm);
+        hipLaunchKernelGGL(k_sort_cells, dim3(grid_for(cells)), dim3(256), 0, s, cells, idx->d_cell_start,
+                           idx->d_perm);
+        if ((st = check_launch("k_scatter/k_sort_cells")) != Z3_OK) return bail2(st);
+    }
+    if ((st = dalloc(&idx->d_x, n, "alloc x")) != Z3_OK) return bail2(st);
+    if ((st = dalloc(&idx->d_y, n, "alloc y")) != Z3_OK) return bail2(st);
+    if ((st = dalloc(&idx->d_z, n, "alloc z")) != Z3_OK) return bail2(st);
+    if ((st = dalloc(&idx->d_w, n, "alloc w")) != Z3_OK) return bail2(st);
+    if (n > 0) {
+        hipLaunchKernelGGL(k_gather_points, dim3(grid_for(n)), dim3(256), 0, s, n, idx->d_perm, xyz, w, idx->d_x,
+                           idx->d_y, idx->d_z, idx->d_w);
+        if ((st = check_launch("k_gather_points")) != Z3_OK) return bail2(st);
+    }
+    st = check_hip(hipStreamSynchronize(s), "sync");
+    cleanup_tmp();
+    if (st != Z3_OK) return bail(st);
+    *out = idx;
+    return Z3_OK;
+}
+
+z3_status set_values_impl(z3_index idx, int nmaps, const double *x, hipStream_t s)
+{
+    z3_status st;
+    if (idx->d_v) { (void)hipFree(idx->d_v); idx->d_v = nullptr; }
+    if (idx->d_vf) { (void)hipFree(idx->d_vf); idx->d_vf = nullptr; }
+    idx->nmaps = 0;
+    size_t cnt = (size_t)nmaps * (size_t)idx->n;
+    if ((st = dalloc(&idx->d_v, cnt, "alloc values")) != Z3_OK) return st;
+    if ((st = dalloc(&idx->d_vf, cnt, "alloc values32")) != Z3_OK) return st;
+    if (idx->n > 0) {
+        hipLaunchKernelGGL(k_gather_values, dim3(grid_for(idx->n)), dim3(256), 0, s, idx->n, nmaps, idx->d_perm,
+                           idx->d_w, x, idx->d_v, idx->d_vf);
+        if ((st = check_launch("k_gather_values")) != Z3_OK) return st;
+    }
+    idx->nmaps = nmaps;
+    return Z3_OK;
+}
+
+}  // namespace z3

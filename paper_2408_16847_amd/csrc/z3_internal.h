@@ -1,0 +1,105 @@
+// Internal declarations of libzeta3 (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "zeta3.h"
+
+#define Z3_API extern "C" __attribute__((visibility("default")))
+
+namespace z3 {
+
+constexpr int kBlock = 256;      // threads per block of the multipole kernel (4 wave64s)
+constexpr int kWave = 64;
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kTwoPi = 6.28318530717958647692;
+
+// One latitude band of the sky-cell grid.  A band holds the points whose colatitude
+// lies in [k H, (k+1) H); inside the band the points are bucketed into `ncell` equal
+// longitude cells and sorted by cell.  th_lo/th_hi are the smallest and largest
+// colatitude actually present, and the window computation uses their half-angle
+// sines and cosines.
+struct Band {
+    double sh_lo, ch_lo, sh_hi, ch_hi;  // sin, cos of th_lo/2 and th_hi/2
+    double th_lo, th_hi;                // colatitude range of the band's points
+    float inv_smin, inv_smax;           // 1 / min and 1 / max of sin(theta) over [th_lo, th_hi]
+    float cells_per_rad;                // ncell / (2 pi)
+    int pt_start, npts;                 // first index-order point and count
+    int cell_off, ncell;                // first global cell id and count
+    int pad_;
+};
+
+// Edge tables derived from the caller's chord-squared edges.  hav = E/4 = sin^2(theta/2).
+struct EdgeTab {
+    double e[Z3_MAX_NBINS + 1];        // chord-squared edges (exact copy)
+    double hav_out[Z3_MAX_NBINS + 1];  // E/4 enlarged by a rounding guard (outer windows)
+    double hav_in[Z3_MAX_NBINS + 1];   // E/4 reduced by a rounding guard (inner exclusion)
+    double rad_out[Z3_MAX_NBINS + 1];  // angular radius 2 asin(sqrt(E)/2), enlarged
+};
+
+struct Workspace {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace z3
+
+struct z3_index_s {
+    int device = 0;
+    int64_t n = 0;
+    int nbins = 0;
+    double band_h = 0.0;
+    int nbands = 0;
+    int64_t ncells = 0;
+    z3::EdgeTab edges{};
+    z3::EdgeTab *d_edges = nullptr;   // device copy
+    z3::Band *d_bands = nullptr;      // [nbands]
+    int *d_cell_start = nullptr;      // [ncells + 1], index-order point positions
+    double *d_x = nullptr, *d_y = nullptr, *d_z = nullptr, *d_w = nullptr;  // [n], index order
+    int *d_perm = nullptr;            // [n] original catalogue index
+    int nmaps = 0;
+    double *d_v = nullptr;            // [nmaps][n] w * x in index order
+    float *d_vf = nullptr;            // [nmaps][n] FP32 copy
+    z3::Workspace ws_a, ws_part;      // fused-estimator workspaces
+};
+
+namespace z3 {
+
+// error reporting (z3_api.hip)
+z3_status fail(z3_status s, const char *fmt, ...);
+z3_status check_hip(hipError_t e, const char *what);
+z3_status check_launch(const char *what);
+
+// index kernels (z3_index.hip)
+z3_status build_index_impl(int64_t n, const double *xyz, const double *w, int nbins,
+                           const double *edges, double cell_size, hipStream_t s, z3_index *out);
+z3_status set_values_impl(z3_index idx, int nmaps, const double *x, hipStream_t s);
+void free_index(z3_index idx);
+
+// multipole kernels (z3_multipoles.hip)
+z3_status launch_multipoles(const z3_index_s *idx, int map, int m_max, int prec, int norm,
+                            int64_t p0, int64_t p1, void *A, int64_t ldA, double *W,
+                            int64_t *counts, uint64_t *idhash, uint64_t *pair_total,
+                            hipStream_t s);
+
+// contraction and small kernels (z3_contract.hip)
+z3_status launch_contract(int64_t npiv, int m_max, int nbins, int prec, const void *A,
+                          int64_t ldA, const double *piv_v, double *zeta, void *partials,
+                          size_t partial_bytes, hipStream_t s);
+size_t contract_partial_bytes(int64_t npiv, int m_max, int nbins);
+z3_status launch_weight_sum(const double *w, int64_t n, double *out, hipStream_t s);
+z3_status launch_finalize(int nmaps, int m_max, int nbins, double *zeta, const double *sum_w,
+                          hipStream_t s);
+z3_status launch_resum(int m_max, int nbins, const double *zeta, int nphi, const double *phi,
+                       double *out, hipStream_t s);
+
+// kernel timing (z3_api.hip)
+bool profiling();
+void profile_begin(hipStream_t s, hipEvent_t *ev0);
+void profile_end(hipStream_t s, hipEvent_t ev0);
+
+z3_status ensure_workspace(Workspace &w, size_t bytes);
+
+}  // namespace z3

@@ -1,0 +1,422 @@
+// Ball search + binning + multipole accumulation (eqs. Xm.binned and Ym/Zm.binned).
+//
+// Work decomposition: one lane per pivot, 64 consecutive index-order pivots per wave
+// (neighbouring points of one latitude band, so their neighbour windows overlap and the
+// lanes' loads of neighbour points fall on the same cache lines).  Each lane walks the
+// radial bins in order; for bin b it visits, band by band, only the longitude window
+// that can hold neighbours at chord-squared distance in [E_b, E_{b+1}), and keeps the
+// bin's sums in registers:
+//
+//   Y_m = sum w_j x_j cos(m phi),  Z_m = sum w_j x_j sin(m phi),  W = sum w_j,  N = #pairs
+//
+// so a_{m,b} = Y_m - i Z_m.  There are no atomics and no cross-lane reductions, and the
+// summation order of every (pivot, bin) is fixed, so results are bit-reproducible.
+//
+// Exactness of the pair decision: d2 = (dx*dx + dy*dy) + dz*dz in FP64 with every
+// operation rounded separately (this file is compiled with -ffp-contract=off), compared
+// with the caller's FP64 edges.  The longitude windows are conservative (rounding
+// guards), so they never drop a pair that the d2 test accepts.
+//
+// Harmonics: cos(m phi) and sin(m phi) follow from cos(phi) by the Chebyshev three-term
+// recurrences T_m = 2 c T_{m-1} - T_{m-2} (first kind, for cos) and the same recurrence
+// for sin(m phi) = U_{m-1}(c) sin(phi) (second kind); the paper's code uses the same two
+// polynomial families so that no trigonometric function is evaluated per pair.  Scaling
+// both recurrences by w_j x_j folds the field value in: two FMAs and two adds per m.
+#include "z3_internal.h"
+
+namespace z3 {
+
+struct MultArgs {
+    const double *x, *y, *z, *w;  // index-order neighbour catalogue
+    const double *v;              // w * x of the map, index order
+    const float *vf;              // FP32 copy of v
+    const int *cell_start;
+    const Band *bands;
+    int nbands;
+    double inv_h;
+    const EdgeTab *edges;
+    int nb;
+    const int *perm;              // original catalogue index (neighbour fingerprints)
+    int64_t p0, p1;
+    int norm;
+    void *A;
+    int64_t ldA;
+    double *W;
+    int64_t *counts;
+    uint64_t *idhash;
+    uint64_t *pair_total;
+    int nblocks;
+};
+
+__device__ __forceinline__ int wave_min(int v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ int wave_max(int v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v)
+{
+    unsigned lo = (unsigned)v, hi = (unsigned)(v >> 32);
+    // two 32-bit halves, carried through a 64-bit sum at every step
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        unsigned olo = __shfl_xor(lo, o, 64), ohi = __shfl_xor(hi, o, 64);
+        uint64_t s = ((uint64_t)hi << 32 | lo) + ((uint64_t)ohi << 32 | olo);
+        lo = (unsigned)s;
+        hi = (unsigned)(s >> 32);
+    }
+    return (uint64_t)hi << 32 | lo;
+}
+
+__device__ __forceinline__ uint64_t mix64(uint64_t v)
+{  // SplitMix64 finaliser (Steele, Lea & Flood 2014)
+    v += 0x9E3779B97F4A7C15ull;
+    v = (v ^ (v >> 30)) * 0xBF58476D1CE4E5B9ull;
+    v = (v ^ (v >> 27)) * 0x94D049BB133111EBull;
+    return v ^ (v >> 31);
+}
+
+__device__ __forceinline__ int floor_div(int a, int c) { return a >= 0 ? a / c : -((-a + c - 1) / c); }
+
+// Logical cell range [ca, cb] of a band (indices may run one band-length below 0 or
+// above ncell to express wrap-around) -> start (in [0, npts)) and length in points.
+__device__ __forceinline__ void cells_to_points(const Band &bd, const int *cell_start, int ca, int cb,
+                                                int &s, int &len)
+{
+    if (cb < ca) {
+        s = 0;
+        len = 0;
+        return;
+    }
+    const int C = bd.ncell, np = bd.npts;
+    // windows span at most one band length around [0, C); the clamps only matter for
+    // non-finite inputs and keep every index inside the band regardless
+    ca = max(ca, -C);
+    cb = min(cb, 2 * C - 1);
+    const int q0 = floor_div(ca, C), r0 = ca - q0 * C;
+    const int q1 = floor_div(cb + 1, C), r1 = cb + 1 - q1 * C;
+    const int st = cell_start[bd.cell_off + r0] - bd.pt_start + q0 * np;
+    const int en = cell_start[bd.cell_off + r1] - bd.pt_start + q1 * np;
+    len = min(max(en - st, 0), np);
+    s = st < 0 ? st + np : (st >= np ? st - np : st);
+    s = min(max(s, 0), np - 1);
+}
+
+// Longitude window(s) of band `bd` that can hold points at angular distance in
+// [R_in, R_out) of the pivot, with hav(R) = E/4 (hav_in, hav_out already carry their
+// rounding guards).  Spherical law of haversines, for a point at colatitude t in the
+// band and longitude offset dphi:
+//     hav(d) = hav(t - th_p) + sin(th_p) sin(t) hav(dphi)
+// so d < R_out needs hav(dphi) < (hav_out - min hav(t - th_p)) / (sin th_p * min sin t),
+// and d >= R_in needs hav(dphi) >= (hav_in - max hav(t - th_p)) / (sin th_p * max sin t).
+__device__ __forceinline__ void band_window(const Band &bd, const int *cell_start, double th, double sh,
+                                            double ch, float inv_sp, float phf, double hav_out,
+                                            double hav_in, int &s0, int &l0, int &s1, int &l1)
+{
+    s0 = l0 = s1 = l1 = 0;
+    const double dlo = bd.sh_lo * ch - bd.ch_lo * sh;  // sin((th_lo - th_p) / 2)
+    const double dhi = bd.sh_hi * ch - bd.ch_hi * sh;  // sin((th_hi - th_p) / 2)
+    const double hlo = dlo * dlo, hhi = dhi * dhi;
+    const double hmin = th < bd.th_lo ? hlo : (th > bd.th_hi ? hhi : 0.0);
+    const double hmax = fmax(hlo, hhi);
+    const double num_out = hav_out - hmin;
+    if (!(num_out > 0.0)) return;  // the band lies entirely beyond R_out
+    const double num_in = hav_in - hmax;
+    const int C = bd.ncell;
+    const float cpr = bd.cells_per_rad;
+
+    const float q_out = (float)num_out * inv_sp * bd.inv_smin * (1.0f + 1e-5f);
+    bool full = !(q_out < 1.0f);
+    float dout = 0.0f;
+    if (!full) {
+        dout = 2.0f * asinf(sqrtf(q_out)) * (1.0f + 4e-6f) + 4e-6f;
+        full = dout >= 3.14159265f;
+    }
+    bool excl = false;
+    float din = 0.0f;
+    if (num_in > 0.0) {
+        const float q_in = (float)num_in * inv_sp * bd.inv_smax * (1.0f - 1e-5f);
+        if (!(q_in < 1.0f)) return;  // the whole band lies inside R_in
+        din = 2.0f * asinf(sqrtf(q_in)) * (1.0f - 4e-6f) - 4e-6f;
+        excl = din > 0.0f;
+    }
+    // cells entirely inside the excluded arc (phf - din, phf + din)
+    int es = 0, ee = -1;
+    const float lim = 2.0f * (float)C;  // window bounds stay within +-2 band lengths
+    if (excl) {
+        es = (int)fminf(fmaxf(ceilf((phf - din) * cpr), -lim), lim);
+        ee = (int)fminf(fmaxf(floorf((phf + din) * cpr), -lim), lim) - 1;
+    }
+    int ca0 = 0, cb0 = -1, ca1 = 0, cb1 = -1;
+    if (!full) {
+        const int clo = (int)fminf(fmaxf(floorf((phf - dout) * cpr), -lim), lim);
+        const int chi = (int)fminf(fmaxf(floorf((phf + dout) * cpr), -lim), lim);
+        if (chi - clo + 1 >= C) {
+            full = true;
+        } else {
+            if (excl) {
+                es = max(es, clo);
+                ee = min(ee, chi);
+            }
+            if (excl && es <= ee) {
+                ca0 = clo; cb0 = es - 1;
+                ca1 = ee + 1; cb1 = chi;
+            } else {
+                ca0 = clo; cb0 = chi;
+            }
+        }
+    }
+    if (full) {
+        if (excl && es <= ee) {
+            if (ee - es + 1 >= C) return;
+            ca0 = ee + 1; cb0 = es - 1 + C;
+        } else {
+            ca0 = 0; cb0 = C - 1;
+        }
+        ca1 = 0; cb1 = -1;
+    }
+    cells_to_points(bd, cell_start, ca0, cb0, s0, l0);
+    cells_to_points(bd, cell_start, ca1, cb1, s1, l1);
+}
+
+template <int M, bool MIXED, bool IDS>
+__global__ __launch_bounds__(kBlock) void k_multipoles(MultArgs a)
+{
+    // XCD-aware order: hardware hands consecutive block ids to the 8 XCDs in turn;
+    // give each XCD a contiguous run of pivot tiles so neighbour data stays in its L2.
+    const int nblk = a.nblocks;
+    const int bid = blockIdx.x;
+    const int per = nblk / 8, rem = nblk % 8;
+    const int xcd = bid % 8, k8 = bid / 8;
+    const int lb = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + k8;
+    const int64_t wave0 = a.p0 + (int64_t)lb * kBlock + (threadIdx.x & ~(kWave - 1));
+    if (wave0 >= a.p1) return;  // whole wave past the end
+    const int64_t p = a.p0 + (int64_t)lb * kBlock + threadIdx.x;
+    const bool valid = p < a.p1;
+    const int64_t pp = valid ? p : a.p1 - 1;  // idle lanes shadow the last pivot
+
+    const double xp = a.x[pp], yp = a.y[pp], zp = a.z[pp];
+    const double sinth = sqrt(xp * xp + yp * yp);
+    const double th = atan2(sinth, zp);
+    double ph = atan2(yp, xp);
+    if (ph < 0.0) ph += kTwoPi;
+    double sh, ch;
+    sincos(0.5 * th, &sh, &ch);
+    const float inv_sp = sinth > 0.0 ? (float)(1.0 / sinth) : INFINITY;
+    const float phf = (float)ph;
+    // local north and east
+    double nx = -zp * xp, ny = -zp * yp, nz = 1.0 - zp * zp;
+    double nn = sqrt(nx * nx + ny * ny + nz * nz);
+    if (nn < 1e-12) {
+        nx = 1.0 - xp * xp; ny = -xp * yp; nz = -xp * zp;
+        nn = sqrt(nx * nx + ny * ny + nz * nz);
+    }
+    nx /= nn; ny /= nn; nz /= nn;
+    const double ex = ny * zp - nz * yp, ey = nz * xp - nx * zp, ez = nx * yp - ny * xp;
+    const float nxf = (float)nx, nyf = (float)ny, nzf = (float)nz;
+    const float exf = (float)ex, eyf = (float)ey, ezf = (float)ez;
+
+    const int64_t col = p - a.p0;
+    const int nb = a.nb;
+    uint64_t my_pairs = 0;
+
+    for (int bin = 0; bin < nb; ++bin) {
+        const double elo = a.edges->e[bin], ehi = a.edges->e[bin + 1];
+        const double hav_out = a.edges->hav_out[bin + 1], hav_in = a.edges->hav_in[bin];
+        const double rad = a.edges->rad_out[bin + 1];
+        int klo = (int)floor((th - rad) * a.inv_h);
+        int khi = (int)floor((th + rad) * a.inv_h);
+        klo = max(klo, 0);
+        khi = min(khi, a.nbands - 1);
+        klo = __builtin_amdgcn_readfirstlane(wave_min(klo));
+        khi = __builtin_amdgcn_readfirstlane(wave_max(khi));
+
+        double Y[M + 1], Z[M + 1];
+#pragma unroll
+        for (int m = 0; m <= M; ++m) { Y[m] = 0.0; Z[m] = 0.0; }
+        double Wb = 0.0;
+        int cnt = 0;
+        uint64_t hsum = 0;
+
+        for (int k = klo; k <= khi; ++k) {
+            const Band bd = a.bands[k];
+            if (bd.npts == 0) continue;
+            int s0, l0, s1, l1;
+            band_window(bd, a.cell_start, th, sh, ch, inv_sp, phf, hav_out, hav_in, s0, l0, s1, l1);
+            const int L = l0 + l1;
+            float Yf[M + 1], Zf[M + 1];
+            if constexpr (MIXED) {
+#pragma unroll
+                for (int m = 0; m <= M; ++m) { Yf[m] = 0.0f; Zf[m] = 0.0f; }
+            }
+            for (int t = 0; t < L; ++t) {
+                int idx = t < l0 ? s0 + t : s1 + (t - l0);
+                if (idx >= bd.npts) idx -= bd.npts;
+                const int j = bd.pt_start + idx;
+                const double dx = a.x[j] - xp, dy = a.y[j] - yp, dz = a.z[j] - zp;
+                const double d2 = (dx * dx + dy * dy) + dz * dz;
+                if (d2 >= elo && d2 < ehi) {
+                    Wb += a.w[j];
+                    cnt += 1;
+                    if constexpr (IDS) hsum += mix64((uint64_t)a.perm[j]);
+                    if constexpr (!MIXED) {
+                        const double v = a.v[j];
+                        const double u1 = fma(dx, nx, fma(dy, ny, dz * nz));
+                        const double u2 = fma(dx, ex, fma(dy, ey, dz * ez));
+                        const double q = fma(u1, u1, u2 * u2);
+                        double c = 1.0, s = 0.0;
+                        if (q > 0.0) {
+                            const double r = rsqrt(q);
+                            c = u1 * r;
+                            s = u2 * r;
+                        }
+                        Y[0] += v;
+                        if constexpr (M >= 1) {
+                            const double tc = c + c;
+                            double t2 = v, t1 = v * c, s2 = 0.0, s1 = v * s;
+                            Y[1] += t1;
+                            Z[1] += s1;
+#pragma unroll
+                            for (int m = 2; m <= M; ++m) {
+                                const double tm = fma(tc, t1, -t2);
+                                const double sm = fma(tc, s1, -s2);
+                                Y[m] += tm;
+                                Z[m] += sm;
+                                t2 = t1; t1 = tm;
+                                s2 = s1; s1 = sm;
+                            }
+                        }
+                    } else {
+                        const float v = a.vf[j];
+                        const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
+                        const float u1 = fmaf(fx, nxf, fmaf(fy, nyf, fz * nzf));
+                        const float u2 = fmaf(fx, exf, fmaf(fy, eyf, fz * ezf));
+                        const float q = fmaf(u1, u1, u2 * u2);
+                        float c = 1.0f, s = 0.0f;
+                        if (q > 0.0f) {
+                            const float r = rsqrtf(q);
+                            c = u1 * r;
+                            s = u2 * r;
+                        }
+                        Yf[0] += v;
+                        if constexpr (M >= 1) {
+                            const float tc = c + c;
+                            float t2 = v, t1 = v * c, s2 = 0.0f, s1 = v * s;
+                            Yf[1] += t1;
+                            Zf[1] += s1;
+#pragma unroll
+                            for (int m = 2; m <= M; ++m) {
+                                const float tm = fmaf(tc, t1, -t2);
+                                const float sm = fmaf(tc, s1, -s2);
+                                Yf[m] += tm;
+                                Zf[m] += sm;
+                                t2 = t1; t1 = tm;
+                                s2 = s1; s1 = sm;
+                            }
+                        }
+                    }
+                }
+            }
+            if constexpr (MIXED) {
+                // per-window FP32 partial sums go into the bin's FP64 sums
+#pragma unroll
+                for (int m = 0; m <= M; ++m) {
+                    Y[m] += (double)Yf[m];
+                    Z[m] += (double)Zf[m];
+                }
+            }
+        }
+
+        if (valid) {
+            my_pairs += (uint64_t)cnt;
+            double inv = 1.0;
+            if (a.norm == Z3_NORM_BIN) inv = Wb > 0.0 ? 1.0 / Wb : 0.0;
+            if (a.A) {
+#pragma unroll
+                for (int m = 0; m <= M; ++m) {
+                    const double re = Y[m] * inv;
+                    const double im = m == 0 ? 0.0 : -Z[m] * inv;
+                    const size_t ore = ((size_t)(2 * m) * nb + bin) * (size_t)a.ldA + col;
+                    const size_t oim = ((size_t)(2 * m + 1) * nb + bin) * (size_t)a.ldA + col;
+                    if constexpr (MIXED) {
+                        static_cast<float *>(a.A)[ore] = (float)re;
+                        static_cast<float *>(a.A)[oim] = (float)im;
+                    } else {
+                        static_cast<double *>(a.A)[ore] = re;
+                        static_cast<double *>(a.A)[oim] = im;
+                    }
+                }
+            }
+            const size_t ob = (size_t)bin * (size_t)a.ldA + col;
+            if (a.W) a.W[ob] = Wb;
+            if (a.counts) a.counts[ob] = cnt;
+            if constexpr (IDS) a.idhash[ob] = hsum;
+        }
+    }
+
+    if (a.pair_total) {
+        const uint64_t tot = wave_sum_u64(valid ? my_pairs : 0);
+        if ((threadIdx.x & (kWave - 1)) == 0 && tot) atomicAdd((unsigned long long *)a.pair_total, (unsigned long long)tot);
+    }
+}
+
+template <int M>
+static void launch_m(bool mixed, bool ids, const MultArgs &a, hipStream_t s)
+{
+    dim3 grid(a.nblocks), block(kBlock);
+    if (mixed) {
+        if (ids) hipLaunchKernelGGL((k_multipoles<M, true, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_multipoles<M, true, false>), grid, block, 0, s, a);
+    } else {
+        if (ids) hipLaunchKernelGGL((k_multipoles<M, false, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_multipoles<M, false, false>), grid, block, 0, s, a);
+    }
+}
+
+z3_status launch_multipoles(const z3_index_s *idx, int map, int m_max, int prec, int norm,
+                            int64_t p0, int64_t p1, void *A, int64_t ldA, double *W,
+                            int64_t *counts, uint64_t *idhash, uint64_t *pair_total, hipStream_t s)
+{
+    int64_t nblk = (p1 - p0 + kBlock - 1) / kBlock;
+    if (nblk > 0x7fffffff) return fail(Z3_ERR_OVERFLOW, "too many pivot blocks");
+    MultArgs a;
+    a.x = idx->d_x; a.y = idx->d_y; a.z = idx->d_z; a.w = idx->d_w;
+    a.v = idx->d_v + (size_t)map * idx->n;
+    a.vf = idx->d_vf + (size_t)map * idx->n;
+    a.cell_start = idx->d_cell_start;
+    a.bands = idx->d_bands;
+    a.nbands = idx->nbands;
+    a.inv_h = 1.0 / idx->band_h;
+    a.edges = idx->d_edges;
+    a.nb = idx->nbins;
+    a.perm = idx->d_perm;
+    a.p0 = p0; a.p1 = p1;
+    a.norm = norm;
+    a.A = A; a.ldA = ldA;
+    a.W = W; a.counts = counts; a.idhash = idhash; a.pair_total = pair_total;
+    a.nblocks = (int)nblk;
+    const bool mixed = prec == Z3_PREC_MIXED, ids = idhash != nullptr;
+    hipEvent_t ev0;
+    profile_begin(s, &ev0);
+    switch (m_max) {
+#define Z3_CASE(MM) case MM: launch_m<MM>(mixed, ids, a, s); break;
+        Z3_CASE(0) Z3_CASE(1) Z3_CASE(2) Z3_CASE(3) Z3_CASE(4) Z3_CASE(5) Z3_CASE(6) Z3_CASE(7)
+        Z3_CASE(8) Z3_CASE(9) Z3_CASE(10) Z3_CASE(11) Z3_CASE(12) Z3_CASE(13) Z3_CASE(14)
+        Z3_CASE(15) Z3_CASE(16)
+#undef Z3_CASE
+    default: return fail(Z3_ERR_UNSUPPORTED, "m_max=%d not compiled", m_max);
+    }
+    z3_status st = check_launch("k_multipoles");
+    profile_end(s, ev0);
+    return st;
+}
+
+}  // namespace z3

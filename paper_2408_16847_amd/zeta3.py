@@ -1,0 +1,179 @@
+"""Python binding of libzeta3: argument marshalling only; every step runs in HIP kernels.
+
+Typical use (auto-correlation of one catalogue):
+
+    idx = Index(xyz, edges_chord2, weights=None)   # xyz: [3, n] float64 CUDA tensor
+    idx.set_values(x)                               # x: [n] or [nmaps, n] float64 CUDA tensor
+    zeta, pairs = estimate(idx, m_max=10, prec="fp64")   # complex128 [m_max+1, nb, nb] (host)
+"""
+
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+
+PREC = {"fp64": 0, "mixed": 1}
+NORM = {"bin": 0, "none": 1}
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t, dtype=torch.float64):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a CUDA (HIP) tensor")
+    return t.to(dtype).contiguous()
+
+
+class Index:
+    """Sky-cell index of a catalogue (z3_build_index)."""
+
+    def __init__(self, xyz, edges_chord2, weights=None, cell_size: float = 0.0):
+        xyz = _dev(xyz)
+        if xyz.dim() != 2 or xyz.shape[0] != 3:
+            raise ValueError("xyz must be [3, n]")
+        self.n = int(xyz.shape[1])
+        self.edges = np.ascontiguousarray(edges_chord2, dtype=np.float64)
+        self.nbins = len(self.edges) - 1
+        self._w = None if weights is None else _dev(weights)
+        h = ctypes.c_void_p()
+        _lib.call("z3_build_index", self.n, _ptr(xyz), _ptr(self._w), self.nbins,
+                  self.edges.ctypes.data_as(ctypes.c_void_p), float(cell_size), _stream(), ctypes.byref(h))
+        self._h = h
+        self.nmaps = 0
+        self._values = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_values(self, x):
+        x = _dev(x)
+        if x.dim() == 1:
+            x = x.unsqueeze(0)
+        if x.shape[1] != self.n:
+            raise ValueError("values must be [nmaps, n]")
+        _lib.call("z3_index_set_values", self._h, int(x.shape[0]), _ptr(x), _stream())
+        self.nmaps = int(x.shape[0])
+        self._values = x  # keep alive until the gather has run
+        return self
+
+    def info(self):
+        n = ctypes.c_int64()
+        nb = ctypes.c_int()
+        nm = ctypes.c_int()
+        nbands = ctypes.c_int()
+        nc = ctypes.c_int64()
+        _lib.call("z3_index_info", self._h, ctypes.byref(n), ctypes.byref(nb), ctypes.byref(nm),
+                  ctypes.byref(nbands), ctypes.byref(nc))
+        return {"n": n.value, "nbins": nb.value, "nmaps": nm.value, "nbands": nbands.value, "ncells": nc.value}
+
+    def perm(self):
+        out = torch.empty(self.n, dtype=torch.int64, device="cuda")
+        _lib.call("z3_index_perm", self._h, _ptr(out), _stream())
+        return out
+
+    def free(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            torch.cuda.current_stream().synchronize()
+            _lib.load().z3_index_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def accumulate(idx: Index, m_max: int, p0: int = 0, p1: int | None = None, prec="fp64", norm="bin",
+               map_index: int = 0, want_a=True, want_w=False, want_counts=False, want_idhash=False,
+               pair_total=None):
+    """Per-pivot multipoles for pivots [p0, p1) (index order). Returns a dict of CUDA tensors:
+    A [m_max+1, 2, nb, P] (float64 or float32), W [nb, P], counts [nb, P], idhash [nb, P]."""
+    p1 = idx.n if p1 is None else p1
+    P = p1 - p0
+    dev = "cuda"
+    out = {}
+    adt = torch.float64 if prec == "fp64" else torch.float32
+    A = torch.empty((m_max + 1, 2, idx.nbins, P), dtype=adt, device=dev) if want_a else None
+    W = torch.empty((idx.nbins, P), dtype=torch.float64, device=dev) if want_w else None
+    C = torch.empty((idx.nbins, P), dtype=torch.int64, device=dev) if want_counts else None
+    H = torch.empty((idx.nbins, P), dtype=torch.int64, device=dev) if want_idhash else None
+    _lib.call("z3_accumulate_multipoles", idx.handle, map_index, m_max, PREC[prec], NORM[norm], p0, p1,
+              _ptr(A), _ptr(W), _ptr(C), _ptr(H), _ptr(pair_total), _stream())
+    out["A"], out["W"], out["counts"], out["idhash"] = A, W, C, H
+    return out
+
+
+def contract(A, piv_v, m_max: int, nbins: int, prec="fp64", zeta=None):
+    """zeta += sum_p v_p X X* over materialised multipoles A [m_max+1, 2, nb, P]."""
+    P = int(A.shape[-1])
+    if zeta is None:
+        zeta = torch.zeros((m_max + 1, nbins, nbins, 2), dtype=torch.float64, device="cuda")
+    _lib.call("z3_contract", P, m_max, nbins, PREC[prec], _ptr(A.contiguous()), _ptr(_dev(piv_v)), _ptr(zeta),
+              _stream())
+    return zeta
+
+
+def estimate_raw(idx: Index, m_max: int, prec="fp64", p0: int = 0, p1: int | None = None, map_index: int = 0,
+                 zeta=None, pair_total=None, sum_w=None):
+    """Enqueue the fused estimator for pivots [p0, p1): zeta += (unnormalised),
+    pair_total += pairs, sum_w += sum of pivot weights. All CUDA tensors; no sync."""
+    p1 = idx.n if p1 is None else p1
+    if zeta is None:
+        zeta = torch.zeros((m_max + 1, idx.nbins, idx.nbins, 2), dtype=torch.float64, device="cuda")
+    _lib.call("z3_estimate", idx.handle, map_index, m_max, PREC[prec], p0, p1, _ptr(zeta), _ptr(pair_total),
+              _stream())
+    if sum_w is not None:
+        _lib.call("z3_pivot_weight_sum", idx.handle, p0, p1, _ptr(sum_w), _stream())
+    return zeta
+
+
+def estimate(idx: Index, m_max: int, prec="fp64", p0: int = 0, p1: int | None = None, map_index: int = 0):
+    """zeta_m(b1, b2) normalised by the pivots' total weight, as complex128 numpy [m+1, nb, nb],
+    and the number of pairs."""
+    zeta = torch.zeros((m_max + 1, idx.nbins, idx.nbins, 2), dtype=torch.float64, device="cuda")
+    pairs = torch.zeros(1, dtype=torch.int64, device="cuda")
+    sw = torch.zeros(1, dtype=torch.float64, device="cuda")
+    estimate_raw(idx, m_max, prec, p0, p1, map_index, zeta, pairs, sw)
+    _lib.call("z3_finalize", 1, m_max, idx.nbins, _ptr(zeta), _ptr(sw), _stream())
+    z = zeta.cpu().numpy()
+    return z[..., 0] + 1j * z[..., 1], int(pairs.item())
+
+
+def resum(zeta, phi):
+    """zeta(b1, b2, phi) from zeta_m (complex [m+1, nb, nb] or a [m+1, nb, nb, 2] tensor)."""
+    if not isinstance(zeta, torch.Tensor):
+        z = np.asarray(zeta)
+        zeta = torch.from_numpy(np.stack([z.real, z.imag], -1).astype(np.float64)).cuda()
+    zeta = zeta.contiguous()
+    m_max, nb = zeta.shape[0] - 1, zeta.shape[1]
+    phi = torch.as_tensor(phi, dtype=torch.float64).cuda().contiguous()
+    out = torch.empty((nb, nb, phi.numel()), dtype=torch.float64, device="cuda")
+    _lib.call("z3_resum", m_max, nb, _ptr(zeta), int(phi.numel()), _ptr(phi), _ptr(out), _stream())
+    return out
+
+
+def profile_enable(on=True):
+    _lib.call("z3_profile_enable", int(bool(on)))
+
+
+def profile_read(reset=True):
+    n = ctypes.c_int64()
+    ms = ctypes.c_double()
+    _lib.call("z3_profile_read", ctypes.byref(n), ctypes.byref(ms), int(bool(reset)))
+    return n.value, ms.value
+
+
+def sync():
+    _lib.call("z3_sync", _stream())

@@ -1,0 +1,207 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 CPU oracle.
+
+Bars: pair counts, per-bin weights of unit weights and neighbour-list fingerprints are
+bit-exact; zeta_m within 1e-10 (FP64 path) and 1e-6 (mixed path) per-m max-normalised
+relative error; multipoles within 1e-11 (FP64) relative to each bin's scale.
+"""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2408_16847_amd as z3
+from oracle import cpu
+from synth import CONFIGS, make_positions, make_values, ring_centres
+from synth.bins import arcmin, chord2_edges, theta_edges
+from tests import gpu_helpers as G
+from tests import pins
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cap():
+    cfg = CONFIGS["cap20k"]
+    xyz_t = make_positions(cfg)
+    x = make_values(cfg, xyz_t).numpy()
+    return cfg, xyz_t.numpy(), x
+
+
+def test_three_point_closed_form_on_gpu():
+    G.say("case: three-point closed form")
+    xyz, E, x = pins.three_point_case()
+    idx = G.build(xyz, x, E)
+    z, pairs = z3.estimate(idx, 4)
+    exp = pins.three_point_expected(x, 4)
+    assert pairs == 4
+    assert np.abs(z - exp).max() < 1e-14
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("mixed", 1e-6)])
+def test_cap20k_full_zeta(cap, prec, tol):
+    cfg, xyz, x = cap
+    G.say("case: cap20k full", prec)
+    E = cfg.edges_chord2()
+    w = np.ones(xyz.shape[1])
+    idx = G.build(xyz, x, E)
+    z, pairs = z3.estimate(idx, cfg.m_max, prec=prec)
+    zo, po = cpu.estimate(xyz, xyz, w, x, E, cfg.m_max, w, x)
+    assert pairs == po
+    e = G.err_m(z, zo)
+    G.say("err_m", prec, e)
+    assert e.max() <= tol, e
+    assert np.array_equal(z, np.conj(np.swapaxes(z, 1, 2)))
+    assert np.all(np.diagonal(z, axis1=1, axis2=2).imag == 0)
+
+
+def test_cap20k_per_pivot_multipoles_bitexact_pairs(cap):
+    cfg, xyz, x = cap
+    G.say("case: cap20k per-pivot multipoles")
+    E = cfg.edges_chord2()
+    w = np.ones(xyz.shape[1])
+    idx = G.build(xyz, x, E)
+    pm = G.perm(idx)
+    # ragged ranges: first tile, a middle range that is not tile aligned, the tail
+    for p0, p1 in ((0, 300), (7777, 8001), (19_900, 20_000)):
+        a, W, N, H = G.gpu_multipoles(idx, cfg.m_max, p0, p1, norm="none")
+        ao, Wo, No, _, Ho = G.oracle_multipoles(xyz, x, w, E, cfg.m_max, pm[p0:p1])
+        assert np.array_equal(N, No)
+        assert np.array_equal(W, Wo)
+        assert np.array_equal(H, Ho)
+        scale = np.abs(ao).max(axis=1, keepdims=True) + 1e-300
+        assert (np.abs(a - ao) / scale).max() < 1e-11
+
+
+def test_weighted_catalogue_and_normalised_multipoles():
+    G.say("case: weighted random cap")
+    xyz, w, x = pins.random_cap(3000, 4.0, 31)
+    E = pins.small_edges(7, lo=0.05, hi=1.5, log=True)
+    idx = G.build(xyz, x, E, w=w)
+    pm = G.perm(idx)
+    a, W, N, H = G.gpu_multipoles(idx, 6, 0, 3000)
+    ao, Wo, No, _, Ho = G.oracle_multipoles(xyz, x, w, E, 6, pm)
+    assert np.array_equal(N, No) and np.array_equal(H, Ho)
+    assert np.abs(W - Wo).max() <= 1e-13 * np.abs(Wo).max()
+    Xo = G.normalise(ao, Wo)
+    scale = np.abs(Xo).max(axis=1, keepdims=True) + 1e-300
+    assert (np.abs(a - Xo) / scale).max() < 1e-11
+    z, pairs = z3.estimate(idx, 6)
+    zo, po = cpu.estimate(xyz, xyz, w, x, E, 6, w, x)
+    assert pairs == po
+    assert G.err_m(z, zo).max() < 1e-10
+
+
+@pytest.mark.parametrize("m_max", [0, 1, 16])
+def test_m_range_and_single_bin(m_max):
+    G.say("case: m_max", m_max)
+    xyz, w, x = pins.random_cap(1500, 3.0, 40 + m_max)
+    E = pins.small_edges(1 if m_max == 16 else 3, lo=0.1, hi=2.0)
+    idx = G.build(xyz, x, E, w=w)
+    z, pairs = z3.estimate(idx, m_max)
+    zo, po = cpu.estimate(xyz, xyz, w, x, E, m_max, w, x)
+    assert pairs == po
+    assert G.err_m(z, zo).max() < 1e-10
+
+
+def test_full_sky_healpix_poles_and_wrap():
+    """Nside 64 full sky: pivots at the poles and windows wrapping through phi = 0."""
+    G.say("case: healpix nside 64 full sky")
+    xyz = ring_centres(64).numpy()
+    x = make_values(CONFIGS["nside512"], torch.from_numpy(xyz)).numpy()
+    w = np.ones(xyz.shape[1])
+    E = chord2_edges(theta_edges(math.radians(1.0), math.radians(12.0), 6, True))
+    idx = G.build(xyz, x, E)
+    z, pairs = z3.estimate(idx, 10)
+    zo, po = cpu.estimate(xyz, xyz, w, x, E, 10, w, x)
+    assert pairs == po
+    e = G.err_m(z, zo)
+    G.say("err_m", e.max())
+    assert e.max() < 1e-10
+    zm, _ = z3.estimate(idx, 10, prec="mixed")
+    em = G.err_m(zm, zo)
+    G.say("err_m mixed", em)
+    assert em.max() < 1e-6
+    pm = G.perm(idx)
+    for p0, p1 in ((0, 200), (xyz.shape[1] - 200, xyz.shape[1])):
+        a, W, N, H = G.gpu_multipoles(idx, 4, p0, p1)
+        ao, Wo, No, _, Ho = G.oracle_multipoles(xyz, x, w, E, 4, pm[p0:p1])
+        assert np.array_equal(N, No) and np.array_equal(H, Ho)
+
+
+def test_empty_and_degenerate_inputs():
+    G.say("case: empty/degenerate")
+    E = pins.small_edges(3)
+    # empty catalogue
+    idx = z3.Index(torch.zeros((3, 0), dtype=torch.float64, device="cuda"), E)
+    idx.set_values(torch.zeros(0, dtype=torch.float64, device="cuda"))
+    z, pairs = z3.estimate(idx, 3)
+    assert pairs == 0 and np.all(z == 0)
+    # isolated points: no pairs at all
+    xyz = np.array([[1.0, 0, 0], [0, 1.0, 0], [0, 0, 1.0]]).T
+    idx = G.build(xyz, np.array([1.0, 2.0, 3.0]), E)
+    z, pairs = z3.estimate(idx, 3)
+    assert pairs == 0 and np.all(z == 0)
+    # coincident points are never neighbours (E_0 > 0)
+    xyz = np.repeat(np.array([[0.3, 0.4, math.sqrt(0.75)]]).T, 5, axis=1)
+    idx = G.build(xyz, np.arange(5.0), E)
+    z, pairs = z3.estimate(idx, 3)
+    assert pairs == 0
+    # empty pivot range is a no-op
+    zz = torch.zeros((4, 3, 3, 2), dtype=torch.float64, device="cuda")
+    z3.estimate_raw(idx, 3, p0=2, p1=2, zeta=zz)
+    assert float(zz.abs().sum()) == 0.0
+
+
+def test_contract_entry_matches_fused(cap):
+    cfg, xyz, x = cap
+    G.say("case: contract == fused")
+    idx = G.build(xyz, x, cfg.edges_chord2())
+    for prec in ("fp64", "mixed"):
+        A = z3.accumulate(idx, cfg.m_max, prec=prec)["A"]
+        v = torch.from_numpy(x).cuda()[idx.perm()]
+        zc = z3.contract(A, v, cfg.m_max, idx.nbins, prec=prec)
+        zf = z3.estimate_raw(idx, cfg.m_max, prec=prec)
+        torch.cuda.synchronize()
+        assert torch.equal(zc, zf)
+
+
+def test_resum_matches_oracle(cap):
+    cfg, xyz, x = cap
+    G.say("case: resum")
+    from oracle import ref
+    idx = G.build(xyz, x, cfg.edges_chord2())
+    z, _ = z3.estimate(idx, cfg.m_max)
+    phi = np.linspace(-math.pi, math.pi, 17)
+    got = z3.resum(z, phi).cpu().numpy()
+    exp = ref.resum(z, phi)
+    assert np.abs(got - exp).max() <= 1e-13 * np.abs(exp).max()
+
+
+def test_exact_invariants_and_determinism(cap):
+    cfg, xyz, x = cap
+    G.say("case: invariants")
+    E = cfg.edges_chord2()
+    idx = G.build(xyz, x, E)
+    z1, _ = z3.estimate(idx, cfg.m_max)
+    z2, _ = z3.estimate(idx, cfg.m_max)
+    assert np.array_equal(z1, z2)
+    idx.set_values(torch.from_numpy(-x).cuda())
+    zn, _ = z3.estimate(idx, cfg.m_max)
+    assert np.array_equal(zn, -z1)
+    idx.set_values(torch.from_numpy(2.0 * x).cuda())
+    z8, _ = z3.estimate(idx, cfg.m_max)
+    assert np.array_equal(z8, 8.0 * z1)
+
+
+def test_invalid_arguments_on_device():
+    G.say("case: invalid args")
+    xyz, w, x = pins.random_cap(100, 2.0, 3)
+    idx = G.build(xyz, x, pins.small_edges(3))
+    with pytest.raises(z3.zeta3._lib.Zeta3Error):
+        z3.estimate(idx, 3, p0=0, p1=101)
+    with pytest.raises(z3.zeta3._lib.Zeta3Error):
+        z3.estimate(idx, 3, map_index=1)
+    with pytest.raises(z3.zeta3._lib.Zeta3Error):
+        z3.estimate(idx, 17)
