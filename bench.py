@@ -198,7 +198,7 @@ def cpu_baseline(cfg, xyz, x, E, M, prec, nsample, z3, torch):
         sel = perm[p0:p0 + 320]
         _, p320 = cpu.estimate(xyz_h[:, sel], xyz_h, w_h, x_h, E, M, w_h[sel], x_h[sel], nthreads=threads)
         rate = p320 / max(time.perf_counter() - t - t_fixed, 1e-3)
-        nsample = int(min(n - p0, max(320, 15.0 * rate / max(p320 / 320.0, 1.0))))
+        nsample = int(min(n - p0, max(320, 30.0 * rate / max(p320 / 320.0, 1.0))))
         log(f"[bench] cpu_baseline calibration: fixed {t_fixed:.2f}s, {rate:.3g} pairs/s")
     sel = perm[p0:p0 + nsample]
     log(f"[bench] cpu_baseline: oracle on {nsample} pivots x {threads} threads")

@@ -33,22 +33,49 @@ z3_status check_hip(hipError_t e, const char *what)
 
 z3_status check_launch(const char *what) { return check_hip(hipGetLastError(), what); }
 
-z3_status ensure_workspace(Workspace &w, size_t bytes)
+// One private memory pool per device, never trimmed: the fused estimator allocates its
+// chunk workspace stream-ordered on every call, and the pool hands the same memory back
+// without a device-wide synchronisation.
+static std::mutex g_pool_mu;
+static hipMemPool_t g_pools[64] = {};
+
+static z3_status pool_for_current_device(hipMemPool_t *pool)
 {
-    if (w.bytes >= bytes && w.ptr) return Z3_OK;
-    if (w.ptr) {
-        hipError_t e = hipFree(w.ptr);  // waits for outstanding work on the buffer
-        w.ptr = nullptr;
-        w.bytes = 0;
-        if (e != hipSuccess) return check_hip(e, "hipFree(workspace)");
+    int dev = 0;
+    z3_status st = check_hip(hipGetDevice(&dev), "hipGetDevice");
+    if (st != Z3_OK) return st;
+    if (dev < 0 || dev >= 64) return fail(Z3_ERR_UNSUPPORTED, "device ordinal %d", dev);
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    if (!g_pools[dev]) {
+        hipMemPoolProps props = {};
+        props.allocType = hipMemAllocationTypePinned;
+        props.handleTypes = hipMemHandleTypeNone;
+        props.location.type = hipMemLocationTypeDevice;
+        props.location.id = dev;
+        hipMemPool_t p;
+        if ((st = check_hip(hipMemPoolCreate(&p, &props), "hipMemPoolCreate")) != Z3_OK) return st;
+        uint64_t keep = UINT64_MAX;
+        if ((st = check_hip(hipMemPoolSetAttribute(p, hipMemPoolAttrReleaseThreshold, &keep),
+                            "hipMemPoolSetAttribute")) != Z3_OK)
+            return st;
+        g_pools[dev] = p;
     }
-    z3_status st = check_hip(hipMalloc(&w.ptr, bytes), "hipMalloc(workspace)");
-    if (st != Z3_OK) {
-        w.ptr = nullptr;
-        return st;
-    }
-    w.bytes = bytes;
+    *pool = g_pools[dev];
     return Z3_OK;
+}
+
+z3_status scratch_alloc(void **p, size_t bytes, hipStream_t s)
+{
+    *p = nullptr;
+    hipMemPool_t pool;
+    z3_status st = pool_for_current_device(&pool);
+    if (st != Z3_OK) return st;
+    return check_hip(hipMallocFromPoolAsync(p, bytes ? bytes : 1, pool, s), "hipMallocFromPoolAsync");
+}
+
+void scratch_free(void *p, hipStream_t s)
+{
+    if (p) (void)hipFreeAsync(p, s);
 }
 
 // ---- kernel timing -------------------------------------------------------------------
@@ -215,18 +242,18 @@ Z3_API z3_status z3_contract(int64_t npiv, int m_max, int nbins, int prec, const
     if (!A || !piv_v) return fail(Z3_ERR_INVALID_ARG, "z3_contract: A or piv_v is NULL");
     size_t pb = contract_partial_bytes(npiv, m_max, nbins);
     void *part = nullptr;
-    z3_status st = check_hip(hipMallocAsync(&part, pb, as_stream(stream)), "hipMallocAsync(partials)");
+    z3_status st = scratch_alloc(&part, pb, as_stream(stream));
     if (st != Z3_OK) return st;
     st = launch_contract(npiv, m_max, nbins, prec, A, npiv, piv_v, zeta, part, pb, as_stream(stream));
-    z3_status st2 = check_hip(hipFreeAsync(part, as_stream(stream)), "hipFreeAsync(partials)");
-    return st != Z3_OK ? st : st2;
+    scratch_free(part, as_stream(stream));
+    return st;
 }
 
 static int64_t chunk_pivots(const z3_index_s *idx, int m_max, int prec)
 {
     size_t elem = prec == Z3_PREC_FP64 ? 8 : 4;
     size_t per_piv = (size_t)(m_max + 1) * 2 * idx->nbins * elem;
-    size_t budget = (size_t)4 << 30;
+    size_t budget = (size_t)16 << 30;
     if (const char *e = getenv("Z3_WORKSPACE_MB")) {
         long long mb = atoll(e);
         if (mb > 0) budget = (size_t)mb << 20;
@@ -250,19 +277,23 @@ Z3_API z3_status z3_estimate(z3_index idx, int map, int m_max, int prec, int64_t
     size_t elem = prec == Z3_PREC_FP64 ? 8 : 4;
     size_t abytes = (size_t)chunk * (size_t)(m_max + 1) * 2 * idx->nbins * elem;
     size_t pbytes = contract_partial_bytes(chunk, m_max, idx->nbins);
-    if ((st = ensure_workspace(idx->ws_a, abytes)) != Z3_OK) return st;
-    if ((st = ensure_workspace(idx->ws_part, pbytes)) != Z3_OK) return st;
-    const double *v = idx->d_v + (size_t)map * idx->n;
-    for (int64_t c0 = p0; c0 < p1; c0 += chunk) {
-        int64_t c1 = c0 + chunk < p1 ? c0 + chunk : p1;
-        st = launch_multipoles(idx, map, m_max, prec, Z3_NORM_BIN, c0, c1, idx->ws_a.ptr, c1 - c0,
-                               nullptr, nullptr, nullptr, pair_total, s);
-        if (st != Z3_OK) return st;
-        st = launch_contract(c1 - c0, m_max, idx->nbins, prec, idx->ws_a.ptr, c1 - c0, v + c0, zeta,
-                             idx->ws_part.ptr, idx->ws_part.bytes, s);
-        if (st != Z3_OK) return st;
+    void *wa = nullptr, *wp = nullptr;
+    if ((st = scratch_alloc(&wa, abytes, s)) != Z3_OK) return st;
+    if ((st = scratch_alloc(&wp, pbytes, s)) != Z3_OK) {
+        scratch_free(wa, s);
+        return st;
     }
-    return Z3_OK;
+    const double *v = idx->d_v + (size_t)map * idx->n;
+    for (int64_t c0 = p0; c0 < p1 && st == Z3_OK; c0 += chunk) {
+        int64_t c1 = c0 + chunk < p1 ? c0 + chunk : p1;
+        st = launch_multipoles(idx, map, m_max, prec, Z3_NORM_BIN, c0, c1, wa, c1 - c0, nullptr, nullptr,
+                               nullptr, pair_total, s);
+        if (st == Z3_OK)
+            st = launch_contract(c1 - c0, m_max, idx->nbins, prec, wa, c1 - c0, v + c0, zeta, wp, pbytes, s);
+    }
+    scratch_free(wp, s);
+    scratch_free(wa, s);
+    return st;
 }
 
 Z3_API z3_status z3_pivot_weight_sum(z3_index idx, int64_t p0, int64_t p1, double *out, void *stream)

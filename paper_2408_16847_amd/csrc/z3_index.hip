@@ -46,27 +46,66 @@ __device__ __forceinline__ double longitude(double x, double y)
 
 __global__ void k_theta_range(const double *xyz, int64_t n, double *range /* [2]: min, max */)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double th = colatitude(xyz[i], xyz[n + i], xyz[2 * n + i]);
-    atomic_min_pos_double(&range[0], th);
-    atomic_max_pos_double(&range[1], th);
+    __shared__ double smin[256], smax[256];
+    double lo = 4.0, hi = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double th = colatitude(xyz[i], xyz[n + i], xyz[2 * n + i]);
+        lo = fmin(lo, th);
+        hi = fmax(hi, th);
+    }
+    smin[threadIdx.x] = lo;
+    smax[threadIdx.x] = hi;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + o]);
+            smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + o]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        atomic_min_pos_double(&range[0], smin[0]);
+        atomic_max_pos_double(&range[1], smax[0]);
+    }
 }
 
+// Band of every point, with per-band counts and colatitude ranges.  Consecutive points
+// usually share a band, so the lanes of a wave combine their updates per distinct band
+// before touching global memory.
 __global__ void k_band_of_point(const double *xyz, int64_t n, double inv_h, int nbands, int *band,
                                 double *phi_out, int *band_count, double *band_th /* [nbands][2] */)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double x = xyz[i], y = xyz[n + i], z = xyz[2 * n + i];
-    double th = colatitude(x, y, z);
-    int k = (int)(th * inv_h);
-    k = k < 0 ? 0 : (k >= nbands ? nbands - 1 : k);
-    band[i] = k;
-    phi_out[i] = longitude(x, y);
-    atomicAdd(&band_count[k], 1);
-    atomic_min_pos_double(&band_th[2 * k], th);
-    atomic_max_pos_double(&band_th[2 * k + 1], th);
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = i < n;
+    int k = -1;
+    double th = 0.0;
+    if (valid) {
+        const double x = xyz[i], y = xyz[n + i], z = xyz[2 * n + i];
+        th = colatitude(x, y, z);
+        k = (int)(th * inv_h);
+        k = k < 0 ? 0 : (k >= nbands ? nbands - 1 : k);
+        band[i] = k;
+        phi_out[i] = longitude(x, y);
+    }
+    const int lane = threadIdx.x & (kWave - 1);
+    uint64_t todo = __ballot(valid);
+    while (todo) {
+        const int leader = __ffsll((unsigned long long)todo) - 1;
+        const int kl = __shfl(k, leader, kWave);
+        const bool mine = valid && k == kl;
+        const uint64_t grp = __ballot(mine);
+        double lo = mine ? th : 4.0, hi = mine ? th : 0.0;
+        for (int o = 32; o > 0; o >>= 1) {
+            lo = fmin(lo, __shfl_xor(lo, o, kWave));
+            hi = fmax(hi, __shfl_xor(hi, o, kWave));
+        }
+        if (lane == leader) {
+            atomicAdd(&band_count[kl], (int)__popcll(grp));
+            atomic_min_pos_double(&band_th[2 * kl], lo);
+            atomic_max_pos_double(&band_th[2 * kl + 1], hi);
+        }
+        todo &= ~grp;
+    }
 }
 
 __global__ void k_cell_of_point(int64_t n, const int *band, const double *phi, const Band *bands,
@@ -121,17 +160,48 @@ __global__ void k_gather_points(int64_t n, const int *perm, const double *xyz, c
 }
 
 __global__ void k_gather_values(int64_t n, int nmaps, const int *perm, const double *wsorted,
-                                const double *xv, double *v, float *vf)
+                                const double *xv, double *v)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int64_t j = perm[i];
     double w = wsorted[i];
+    for (int m = 0; m < nmaps; ++m) v[(size_t)m * n + i] = w * xv[(size_t)m * n + j];
+}
+
+// Doubled-band layout: index-order point i of band k (first point s_k, n_k points) is
+// stored at 2 s_k + (i - s_k) and again n_k positions later.
+template <class T>
+__global__ void k_double_bands(int64_t n, const int *band, const Band *bands, const T *in, T *out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const Band &bd = bands[band[i]];
+    const int64_t q = 2 * (int64_t)bd.pt_start + (i - bd.pt_start);
+    const T v = in[i];
+    out[q] = v;
+    out[q + bd.npts] = v;
+}
+
+__global__ void k_records(int64_t n, int nmaps, const int *band, const Band *bands, const double *x,
+                          const double *y, const double *z, const double *v, double4 *rec)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const Band &bd = bands[band[i]];
+    const int64_t q = 2 * (int64_t)bd.pt_start + (i - bd.pt_start);
+    const double xi = x[i], yi = y[i], zi = z[i];
     for (int m = 0; m < nmaps; ++m) {
-        double val = w * xv[(size_t)m * n + j];
-        v[(size_t)m * n + i] = val;
-        vf[(size_t)m * n + i] = (float)val;
+        const double4 r = make_double4(xi, yi, zi, v[(size_t)m * n + i]);
+        rec[(size_t)m * 2 * n + q] = r;
+        rec[(size_t)m * 2 * n + q + bd.npts] = r;
     }
+}
+
+__global__ void k_gather_int(int64_t n, const int *perm, const int *in, int *out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = in[perm[i]];
 }
 
 __global__ void k_fill_double(double *p, int64_t n, double v)
@@ -212,7 +282,7 @@ static z3_status exclusive_scan(const int *in, int64_t n, int *out, hipStream_t 
 static void free_ptrs(z3_index idx)
 {
     void *ps[] = {idx->d_edges, idx->d_bands, idx->d_cell_start, idx->d_x, idx->d_y, idx->d_z,
-                  idx->d_w, idx->d_perm, idx->d_v, idx->d_vf, idx->ws_a.ptr, idx->ws_part.ptr};
+                  idx->d_w, idx->d_perm, idx->d_band, idx->d_wdbl, idx->d_permdbl, idx->d_v, idx->d_rec};
     for (void *p : ps)
         if (p) (void)hipFree(p);
 }
@@ -273,7 +343,8 @@ z3_status build_index_impl(int64_t n, const double *xyz, const double *w, int nb
         double init[2] = {kPi, 0.0};
         st = check_hip(hipMemcpyAsync(d_range, init, sizeof(init), hipMemcpyHostToDevice, s), "copy range");
         if (st == Z3_OK && n > 0) {
-            hipLaunchKernelGGL(k_theta_range, dim3(grid_for(n)), dim3(256), 0, s, xyz, n, d_range);
+            unsigned g = grid_for(n) < 2048u ? grid_for(n) : 2048u;
+            hipLaunchKernelGGL(k_theta_range, dim3(g), dim3(256), 0, s, xyz, n, d_range);
             st = check_launch("k_theta_range");
         }
         double rg[2] = {0.0, kPi};
@@ -339,7 +410,7 @@ z3_status build_index_impl(int64_t n, const double *xyz, const double *w, int nb
         std::memset(&b, 0, sizeof(Band));
         b.npts = bcount[k];
         b.pt_start = (int)pt;
-        b.ncell = std::max(1, b.npts);
+        b.ncell = (int)std::max<int64_t>(1, (int64_t)kCellsPerPoint * b.npts);
         b.cell_off = (int)cells;
         b.cells_per_rad = (float)((double)b.ncell / kTwoPi);
         double lo = b.npts ? bth[2 * k] : k * h, hi = b.npts ? bth[2 * k + 1] : k * h;
@@ -355,7 +426,8 @@ z3_status build_index_impl(int64_t n, const double *xyz, const double *w, int nb
         pt += b.npts;
         cells += b.ncell;
     }
-    if (cells >= (int64_t)0x7fffffff) return bail2(fail(Z3_ERR_OVERFLOW, "z3_build_index: too many cells"));
+    if (cells >= (int64_t)0x7fffffff || 2 * n >= (int64_t)0x7fffffff)
+        return bail2(fail(Z3_ERR_OVERFLOW, "z3_build_index: too many points or cells"));
     idx->ncells = cells;
     if ((st = dalloc(&idx->d_bands, nbands, "alloc bands")) != Z3_OK) return bail2(st);
     st = check_hip(hipMemcpyAsync(idx->d_bands, bands.data(), nbands * sizeof(Band), hipMemcpyHostToDevice, s),
@@ -394,9 +466,19 @@ z3_status build_index_impl(int64_t n, const double *xyz, const double *w, int nb
     if ((st = dalloc(&idx->d_y, n, "alloc y")) != Z3_OK) return bail2(st);
     if ((st = dalloc(&idx->d_z, n, "alloc z")) != Z3_OK) return bail2(st);
     if ((st = dalloc(&idx->d_w, n, "alloc w")) != Z3_OK) return bail2(st);
+    idx->unit_w = (w == nullptr);
+    if ((st = dalloc(&idx->d_band, n, "alloc band")) != Z3_OK) return bail2(st);
+    if ((st = dalloc(&idx->d_permdbl, 2 * n, "alloc perm2")) != Z3_OK) return bail2(st);
+    if (!idx->unit_w && (st = dalloc(&idx->d_wdbl, 2 * n, "alloc w2")) != Z3_OK) return bail2(st);
     if (n > 0) {
         hipLaunchKernelGGL(k_gather_points, dim3(grid_for(n)), dim3(256), 0, s, n, idx->d_perm, xyz, w, idx->d_x,
                            idx->d_y, idx->d_z, idx->d_w);
+        hipLaunchKernelGGL(k_gather_int, dim3(grid_for(n)), dim3(256), 0, s, n, idx->d_perm, d_band, idx->d_band);
+        hipLaunchKernelGGL(k_double_bands<int>, dim3(grid_for(n)), dim3(256), 0, s, n, idx->d_band, idx->d_bands,
+                           idx->d_perm, idx->d_permdbl);
+        if (!idx->unit_w)
+            hipLaunchKernelGGL(k_double_bands<double>, dim3(grid_for(n)), dim3(256), 0, s, n, idx->d_band,
+                               idx->d_bands, idx->d_w, idx->d_wdbl);
         if ((st = check_launch("k_gather_points")) != Z3_OK) return bail2(st);
     }
     st = check_hip(hipStreamSynchronize(s), "sync");
@@ -409,16 +491,19 @@ z3_status build_index_impl(int64_t n, const double *xyz, const double *w, int nb
 z3_status set_values_impl(z3_index idx, int nmaps, const double *x, hipStream_t s)
 {
     z3_status st;
+    (void)hipStreamSynchronize(s);  // earlier work may still read the old values
     if (idx->d_v) { (void)hipFree(idx->d_v); idx->d_v = nullptr; }
-    if (idx->d_vf) { (void)hipFree(idx->d_vf); idx->d_vf = nullptr; }
+    if (idx->d_rec) { (void)hipFree(idx->d_rec); idx->d_rec = nullptr; }
     idx->nmaps = 0;
     size_t cnt = (size_t)nmaps * (size_t)idx->n;
     if ((st = dalloc(&idx->d_v, cnt, "alloc values")) != Z3_OK) return st;
-    if ((st = dalloc(&idx->d_vf, cnt, "alloc values32")) != Z3_OK) return st;
+    if ((st = dalloc(&idx->d_rec, 2 * cnt, "alloc records")) != Z3_OK) return st;
     if (idx->n > 0) {
         hipLaunchKernelGGL(k_gather_values, dim3(grid_for(idx->n)), dim3(256), 0, s, idx->n, nmaps, idx->d_perm,
-                           idx->d_w, x, idx->d_v, idx->d_vf);
-        if ((st = check_launch("k_gather_values")) != Z3_OK) return st;
+                           idx->d_w, x, idx->d_v);
+        hipLaunchKernelGGL(k_records, dim3(grid_for(idx->n)), dim3(256), 0, s, idx->n, nmaps, idx->d_band,
+                           idx->d_bands, idx->d_x, idx->d_y, idx->d_z, idx->d_v, idx->d_rec);
+        if ((st = check_launch("k_gather_values/k_records")) != Z3_OK) return st;
     }
     idx->nmaps = nmaps;
     return Z3_OK;

@@ -12,6 +12,7 @@
 namespace z3 {
 
 constexpr int kBlock = 256;      // threads per block of the multipole kernel (4 wave64s)
+constexpr int kCellsPerPoint = 4;  // longitude cells per point of a band
 constexpr int kWave = 64;
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kTwoPi = 6.28318530717958647692;
@@ -39,11 +40,6 @@ struct EdgeTab {
     double rad_out[Z3_MAX_NBINS + 1];  // angular radius 2 asin(sqrt(E)/2), enlarged
 };
 
-struct Workspace {
-    void *ptr = nullptr;
-    size_t bytes = 0;
-};
-
 }  // namespace z3
 
 struct z3_index_s {
@@ -59,10 +55,16 @@ struct z3_index_s {
     int *d_cell_start = nullptr;      // [ncells + 1], index-order point positions
     double *d_x = nullptr, *d_y = nullptr, *d_z = nullptr, *d_w = nullptr;  // [n], index order
     int *d_perm = nullptr;            // [n] original catalogue index
+    int *d_band = nullptr;            // [n] band of each index-order point
+    bool unit_w = true;               // all weights are 1 (W_{p,b} = N_{p,b})
+    // neighbour records in "doubled band" order: band k occupies [2 s_k, 2 s_k + 2 n_k)
+    // and holds its n_k points twice, so every longitude window, wrapped or not, is one
+    // contiguous range
+    double *d_wdbl = nullptr;         // [2n] weights (only when !unit_w)
+    int *d_permdbl = nullptr;         // [2n] original catalogue index
     int nmaps = 0;
     double *d_v = nullptr;            // [nmaps][n] w * x in index order
-    float *d_vf = nullptr;            // [nmaps][n] FP32 copy
-    z3::Workspace ws_a, ws_part;      // fused-estimator workspaces
+    double4 *d_rec = nullptr;         // [nmaps][2n] {x, y, z, w * x}
 };
 
 namespace z3 {
@@ -100,6 +102,8 @@ bool profiling();
 void profile_begin(hipStream_t s, hipEvent_t *ev0);
 void profile_end(hipStream_t s, hipEvent_t ev0);
 
-z3_status ensure_workspace(Workspace &w, size_t bytes);
+// stream-ordered scratch allocations from a library-private pool (memory stays cached)
+z3_status scratch_alloc(void **p, size_t bytes, hipStream_t s);
+void scratch_free(void *p, hipStream_t s);
 
 }  // namespace z3

@@ -27,16 +27,16 @@
 namespace z3 {
 
 struct MultArgs {
-    const double *x, *y, *z, *w;  // index-order neighbour catalogue
-    const double *v;              // w * x of the map, index order
-    const float *vf;              // FP32 copy of v
+    const double *px, *py, *pz;   // index-order positions (the pivots)
+    const double4 *rec;           // doubled-band records {x, y, z, w x} of the map
+    const double *wdbl;           // doubled-band weights, or null when all weights are 1
+    const int *permdbl;           // doubled-band original indices (neighbour fingerprints)
     const int *cell_start;
     const Band *bands;
     int nbands;
     double inv_h;
     const EdgeTab *edges;
     int nb;
-    const int *perm;              // original catalogue index (neighbour fingerprints)
     int64_t p0, p1;
     int norm;
     void *A;
@@ -187,8 +187,34 @@ __device__ __forceinline__ void band_window(const Band &bd, const int *cell_star
     cells_to_points(bd, cell_start, ca1, cb1, s1, l1);
 }
 
+// Unit-length bearing (c, s) = (u1, u2) / |u| with FP64 accuracy: FP32 reciprocal
+// square root refined by one FP64 Newton step (relative error ~1e-14).  For every pair in
+// range |u|^2 >= E_0 (1 - E_nb / 4) > 0, so the clamp only guards non-finite inputs.
+__device__ __forceinline__ void unit_bearing(double u1, double u2, double &c, double &s)
+{
+    const double q = fmax(fma(u1, u1, u2 * u2), 1e-37);
+    const double r0 = (double)__builtin_amdgcn_rsqf((float)q);
+    const double e = fma(-q * r0, r0, 1.0);  // 1 - q r0^2
+    const double r = fma(0.5 * e, r0, r0);
+    c = u1 * r;
+    s = u2 * r;
+}
+
+// Occupancy target of the multipole kernel (waves per SIMD that the register allocation
+// aims for).  Measured on MI355X at m_max = 10: 4 waves beat 3 by ~15% despite a couple
+// of spilled registers; larger m_max needs more accumulators, so the target drops.
+#ifndef Z3_MULT_WAVES_PER_EU
+#define Z3_MULT_WAVES_PER_EU 4
+#endif
+template <int M>
+constexpr int mult_waves_per_eu()
+{
+    return M <= 10 ? Z3_MULT_WAVES_PER_EU : (M <= 13 ? 3 : 2);
+}
+
 template <int M, bool MIXED, bool IDS>
-__global__ __launch_bounds__(kBlock) void k_multipoles(MultArgs a)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(mult_waves_per_eu<M>())))
+void k_multipoles(MultArgs a)
 {
     // XCD-aware order: hardware hands consecutive block ids to the 8 XCDs in turn;
     // give each XCD a contiguous run of pivot tiles so neighbour data stays in its L2.
@@ -198,12 +224,12 @@ __global__ __launch_bounds__(kBlock) void k_multipoles(MultArgs a)
     const int xcd = bid % 8, k8 = bid / 8;
     const int lb = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + k8;
     const int64_t wave0 = a.p0 + (int64_t)lb * kBlock + (threadIdx.x & ~(kWave - 1));
-    if (wave0 >= a.p1) return;  // whole wave past the end
+    if (__builtin_amdgcn_readfirstlane((int)(wave0 >= a.p1))) return;  // whole wave past the end
     const int64_t p = a.p0 + (int64_t)lb * kBlock + threadIdx.x;
     const bool valid = p < a.p1;
     const int64_t pp = valid ? p : a.p1 - 1;  // idle lanes shadow the last pivot
 
-    const double xp = a.x[pp], yp = a.y[pp], zp = a.z[pp];
+    const double xp = a.px[pp], yp = a.py[pp], zp = a.pz[pp];
     const double sinth = sqrt(xp * xp + yp * yp);
     const double th = atan2(sinth, zp);
     double ph = atan2(yp, xp);
@@ -221,11 +247,10 @@ __global__ __launch_bounds__(kBlock) void k_multipoles(MultArgs a)
     }
     nx /= nn; ny /= nn; nz /= nn;
     const double ex = ny * zp - nz * yp, ey = nz * xp - nx * zp, ez = nx * yp - ny * xp;
-    const float nxf = (float)nx, nyf = (float)ny, nzf = (float)nz;
-    const float exf = (float)ex, eyf = (float)ey, ezf = (float)ez;
 
     const int64_t col = p - a.p0;
     const int nb = a.nb;
+    const bool unit_w = a.wdbl == nullptr;
     uint64_t my_pairs = 0;
 
     for (int bin = 0; bin < nb; ++bin) {
@@ -251,75 +276,64 @@ __global__ __launch_bounds__(kBlock) void k_multipoles(MultArgs a)
             if (bd.npts == 0) continue;
             int s0, l0, s1, l1;
             band_window(bd, a.cell_start, th, sh, ch, inv_sp, phf, hav_out, hav_in, s0, l0, s1, l1);
-            const int L = l0 + l1;
+            const int base = 2 * bd.pt_start;
             float Yf[M + 1], Zf[M + 1];
             if constexpr (MIXED) {
 #pragma unroll
                 for (int m = 0; m <= M; ++m) { Yf[m] = 0.0f; Zf[m] = 0.0f; }
             }
-            for (int t = 0; t < L; ++t) {
-                int idx = t < l0 ? s0 + t : s1 + (t - l0);
-                if (idx >= bd.npts) idx -= bd.npts;
-                const int j = bd.pt_start + idx;
-                const double dx = a.x[j] - xp, dy = a.y[j] - yp, dz = a.z[j] - zp;
-                const double d2 = (dx * dx + dy * dy) + dz * dz;
-                if (d2 >= elo && d2 < ehi) {
-                    Wb += a.w[j];
-                    cnt += 1;
-                    if constexpr (IDS) hsum += mix64((uint64_t)a.perm[j]);
-                    if constexpr (!MIXED) {
-                        const double v = a.v[j];
+#pragma unroll
+            for (int seg = 0; seg < 2; ++seg) {
+                int j = base + (seg == 0 ? s0 : s1);
+                const int jend = j + (seg == 0 ? l0 : l1);
+                for (; j < jend; ++j) {
+                    const double4 r = a.rec[j];
+                    const double dx = r.x - xp, dy = r.y - yp, dz = r.z - zp;
+                    const double d2 = (dx * dx + dy * dy) + dz * dz;
+                    if (d2 >= elo && d2 < ehi) {
+                        cnt += 1;
+                        if (!unit_w) Wb += a.wdbl[j];
+                        if constexpr (IDS) hsum += mix64((uint64_t)a.permdbl[j]);
                         const double u1 = fma(dx, nx, fma(dy, ny, dz * nz));
                         const double u2 = fma(dx, ex, fma(dy, ey, dz * ez));
-                        const double q = fma(u1, u1, u2 * u2);
-                        double c = 1.0, s = 0.0;
-                        if (q > 0.0) {
-                            const double r = rsqrt(q);
-                            c = u1 * r;
-                            s = u2 * r;
-                        }
-                        Y[0] += v;
-                        if constexpr (M >= 1) {
-                            const double tc = c + c;
-                            double t2 = v, t1 = v * c, s2 = 0.0, s1 = v * s;
-                            Y[1] += t1;
-                            Z[1] += s1;
+                        double c, sn;
+                        unit_bearing(u1, u2, c, sn);
+                        if constexpr (!MIXED) {
+                            const double v = r.w;
+                            Y[0] += v;
+                            if constexpr (M >= 1) {
+                                const double tc = c + c;
+                                double t2 = v, t1 = v * c, s2 = 0.0, s1 = v * sn;
+                                Y[1] += t1;
+                                Z[1] += s1;
 #pragma unroll
-                            for (int m = 2; m <= M; ++m) {
-                                const double tm = fma(tc, t1, -t2);
-                                const double sm = fma(tc, s1, -s2);
-                                Y[m] += tm;
-                                Z[m] += sm;
-                                t2 = t1; t1 = tm;
-                                s2 = s1; s1 = sm;
+                                for (int m = 2; m <= M; ++m) {
+                                    const double tm = fma(tc, t1, -t2);
+                                    const double sm = fma(tc, s1, -s2);
+                                    Y[m] += tm;
+                                    Z[m] += sm;
+                                    t2 = t1; t1 = tm;
+                                    s2 = s1; s1 = sm;
+                                }
                             }
-                        }
-                    } else {
-                        const float v = a.vf[j];
-                        const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
-                        const float u1 = fmaf(fx, nxf, fmaf(fy, nyf, fz * nzf));
-                        const float u2 = fmaf(fx, exf, fmaf(fy, eyf, fz * ezf));
-                        const float q = fmaf(u1, u1, u2 * u2);
-                        float c = 1.0f, s = 0.0f;
-                        if (q > 0.0f) {
-                            const float r = rsqrtf(q);
-                            c = u1 * r;
-                            s = u2 * r;
-                        }
-                        Yf[0] += v;
-                        if constexpr (M >= 1) {
-                            const float tc = c + c;
-                            float t2 = v, t1 = v * c, s2 = 0.0f, s1 = v * s;
-                            Yf[1] += t1;
-                            Zf[1] += s1;
+                        } else {
+                            const float v = (float)r.w;
+                            const float cf = (float)c, sf = (float)sn;
+                            Yf[0] += v;
+                            if constexpr (M >= 1) {
+                                const float tc = cf + cf;
+                                float t2 = v, t1 = v * cf, s2 = 0.0f, s1 = v * sf;
+                                Yf[1] += t1;
+                                Zf[1] += s1;
 #pragma unroll
-                            for (int m = 2; m <= M; ++m) {
-                                const float tm = fmaf(tc, t1, -t2);
-                                const float sm = fmaf(tc, s1, -s2);
-                                Yf[m] += tm;
-                                Zf[m] += sm;
-                                t2 = t1; t1 = tm;
-                                s2 = s1; s1 = sm;
+                                for (int m = 2; m <= M; ++m) {
+                                    const float tm = fmaf(tc, t1, -t2);
+                                    const float sm = fmaf(tc, s1, -s2);
+                                    Yf[m] += tm;
+                                    Zf[m] += sm;
+                                    t2 = t1; t1 = tm;
+                                    s2 = s1; s1 = sm;
+                                }
                             }
                         }
                     }
@@ -337,6 +351,7 @@ __global__ __launch_bounds__(kBlock) void k_multipoles(MultArgs a)
 
         if (valid) {
             my_pairs += (uint64_t)cnt;
+            if (unit_w) Wb = (double)cnt;
             double inv = 1.0;
             if (a.norm == Z3_NORM_BIN) inv = Wb > 0.0 ? 1.0 / Wb : 0.0;
             if (a.A) {
@@ -388,16 +403,16 @@ z3_status launch_multipoles(const z3_index_s *idx, int map, int m_max, int prec,
     int64_t nblk = (p1 - p0 + kBlock - 1) / kBlock;
     if (nblk > 0x7fffffff) return fail(Z3_ERR_OVERFLOW, "too many pivot blocks");
     MultArgs a;
-    a.x = idx->d_x; a.y = idx->d_y; a.z = idx->d_z; a.w = idx->d_w;
-    a.v = idx->d_v + (size_t)map * idx->n;
-    a.vf = idx->d_vf + (size_t)map * idx->n;
+    a.px = idx->d_x; a.py = idx->d_y; a.pz = idx->d_z;
+    a.rec = idx->d_rec + (size_t)map * 2 * idx->n;
+    a.wdbl = idx->unit_w ? nullptr : idx->d_wdbl;
+    a.permdbl = idx->d_permdbl;
     a.cell_start = idx->d_cell_start;
     a.bands = idx->d_bands;
     a.nbands = idx->nbands;
     a.inv_h = 1.0 / idx->band_h;
     a.edges = idx->d_edges;
     a.nb = idx->nbins;
-    a.perm = idx->d_perm;
     a.p0 = p0; a.p1 = p1;
     a.norm = norm;
     a.A = A; a.ldA = ldA;

@@ -36,7 +36,9 @@ def test_three_point_closed_form_on_gpu():
     z, pairs = z3.estimate(idx, 4)
     exp = pins.three_point_expected(x, 4)
     assert pairs == 4
-    assert np.abs(z - exp).max() < 1e-14
+    # the GPU normalises the bearing with an FP32-seeded, Newton-refined reciprocal
+    # square root (relative error ~1e-14); the oracle uses atan2 and libm trigonometry
+    assert np.abs(z - exp).max() < 1e-12
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("mixed", 1e-6)])
