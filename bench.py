@@ -40,6 +40,22 @@ def cpu_model():
     return "unknown"
 
 
+def measured_traffic(cfg_name, prec):
+    """HBM bytes per k_multipoles launch from the committed rocprofv3 counter passes, if they
+    were taken on this exact kernel source, workload and precision; otherwise None."""
+    import hashlib
+    try:
+        rec = json.load(open(os.path.join(ROOT, "profiles", "k_multipoles_traffic.json")))
+        src = open(os.path.join(ROOT, "paper_2408_16847_amd", "csrc", "z3_multipoles.hip"), "rb").read()
+    except OSError:
+        return None
+    if rec.get("source_sha256") != hashlib.sha256(src).hexdigest():
+        return None
+    if rec.get("workload") != cfg_name or rec.get("precision") != prec:
+        return None
+    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+
+
 def err_m(test, ref):
     out = []
     for m in range(ref.shape[0]):
@@ -156,7 +172,8 @@ def main():
                    "log_bins": cfg.log_bins, "precision": main_prec, "pairs": r["pairs"]},
         "roofline": {"bound": "alu", "kernel": "k_multipoles", "achieved": achieved,
                      "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_VALU_TFLOPS,
-                     "traffic": None, "avg_launch_ms": r["kernel_ms_total"] / max(r["kernel_launches"], 1),
+                     "traffic": measured_traffic(cfg.name, main_prec),
+                     "traffic_unit": "bytes per launch", "avg_launch_ms": r["kernel_ms_total"] / max(r["kernel_launches"], 1),
                      "launches_per_step": launches_per_step, "flops_per_update": FLOPS_PER_UPDATE},
     }
     for prec in res:
