@@ -73,6 +73,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="nside2048")
     ap.add_argument("--prec", default="both", choices=["both", "fp64", "mixed"])
+    ap.add_argument("--approx", action="store_true",
+                    help="approximate search: neighbours from the Nside/2 averaged map, all pivots kept")
+    ap.add_argument("--save-zeta", default="", help="write the zeta_m of each precision to this .npz")
     ap.add_argument("--cpu-sample", type=int, default=-1, help="oracle pivots (-1: automatic, 0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (for HBM counter calibration)")
@@ -104,20 +107,32 @@ def main():
     t0 = time.time()
     xyz = make_positions(cfg, device="cuda")
     x = make_values(cfg, xyz, seed=0)
+    nbr = None
+    if args.approx:
+        from synth import degrade_ring
+        if cfg.kind != "healpix":
+            sys.exit("--approx needs a HEALPix workload")
+        nxyz, nx_, nw = degrade_ring(cfg.n_or_nside, x)
+        nbr = (nxyz, nx_, nw)
     torch.cuda.synchronize()
-    log(f"[bench] inputs {cfg.name}: n={xyz.shape[1]} generated in {time.time() - t0:.1f}s; "
-        f"delta min {float(x.min()):.3g} max {float(x.max()):.3g}")
+    log(f"[bench] inputs {cfg.name}{' approx' if nbr else ''}: n={xyz.shape[1]} generated in "
+        f"{time.time() - t0:.1f}s; delta min {float(x.min()):.3g} max {float(x.max()):.3g}")
     E = cfg.edges_chord2()
     M = cfg.m_max
     n = xyz.shape[1]
 
     def step(prec):
-        idx = z3.Index(xyz, E)
-        idx.set_values(x)
         zeta = torch.zeros((M + 1, cfg.nbins, cfg.nbins, 2), dtype=torch.float64, device="cuda")
         pairs = torch.zeros(1, dtype=torch.int64, device="cuda")
         sw = torch.zeros(1, dtype=torch.float64, device="cuda")
-        z3.estimate_raw(idx, M, prec=prec, zeta=zeta, pair_total=pairs, sum_w=sw)
+        if nbr is None:
+            idx = z3.Index(xyz, E)
+            idx.set_values(x)
+            z3.estimate_raw(idx, M, prec=prec, zeta=zeta, pair_total=pairs, sum_w=sw)
+        else:
+            idx = z3.Index(nbr[0], E, weights=nbr[2])
+            idx.set_values(nbr[1])
+            z3.estimate_pivots_raw(idx, xyz, x, None, M, prec=prec, zeta=zeta, pair_total=pairs, sum_w=sw)
         z3.zeta3._lib.call("z3_finalize", 1, M, cfg.nbins, z3.zeta3._ptr(zeta), z3.zeta3._ptr(sw),
                            z3.zeta3._stream())
         zh = zeta.cpu().numpy()
@@ -167,7 +182,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if main_prec == "fp64" else "f64 geometry + f32 multipoles/MFMA",
         "data": "synthetic",
-        "config": {"workload": cfg.name, "npoints": n, "nbins": cfg.nbins, "m_max": M,
+        "config": {"workload": cfg.name + ("+approx" if nbr else ""), "npoints": n, "nbins": cfg.nbins, "m_max": M,
                    "theta_arcmin": [cfg.theta_min * 10800 / np.pi, cfg.theta_max * 10800 / np.pi],
                    "log_bins": cfg.log_bins, "precision": main_prec, "pairs": r["pairs"]},
         "roofline": {"bound": "alu", "kernel": "k_multipoles", "achieved": achieved,
@@ -186,57 +201,75 @@ def main():
         out["speedup_mixed_vs_fp64"] = res["fp64"]["s_per_step"] / res["mixed"]["s_per_step"]
         out["pairs_equal"] = res["fp64"]["pairs"] == res["mixed"]["pairs"]
 
+    if args.save_zeta:
+        np.savez(args.save_zeta, **{p: res[p]["zeta"] for p in res})
     if args.cpu_sample != 0:
-        out["cpu_baseline"] = cpu_baseline(cfg, xyz, x, E, M, main_prec, args.cpu_sample, z3, torch)
+        out["cpu_baseline"] = cpu_baseline(cfg, xyz, x, nbr, E, M, args.cpu_sample, z3, torch)
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(cfg, xyz, x, E, M, prec, nsample, z3, torch):
-    """Time the FP64 C oracle on a contiguous index-order range of pivots against the full
-    neighbour catalogue, and check the GPU path on the same pivots."""
+def cpu_baseline(cfg, xyz, x, nbr, E, M, nsample, z3, torch):
+    """Time the FP64 C oracle on a contiguous range of pivots against the full neighbour
+    catalogue, and check the GPU path on the same pivots."""
     from oracle import cpu
     n = xyz.shape[1]
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
-    idx = z3.Index(xyz, E)
-    idx.set_values(x)
-    perm = idx.perm().cpu().numpy()
-    # size the sample to ~15 s of oracle work: one call with a single pivot measures the
-    # oracle's fixed cost (its own O(N) grid build), one with 320 pivots its pair rate
+    if nbr is None:
+        idx = z3.Index(xyz, E)
+        idx.set_values(x)
+        order = idx.perm().cpu().numpy()  # GPU pivot ranges are in index order
+        nbr_h = (xyz.cpu().numpy(), x.cpu().numpy(), np.ones(n))
+    else:
+        idx = z3.Index(nbr[0], E, weights=nbr[2])
+        idx.set_values(nbr[1])
+        order = np.arange(n)  # external pivots keep the caller's order
+        nbr_h = (nbr[0].cpu().numpy(), nbr[1].cpu().numpy(), nbr[2].cpu().numpy())
     xyz_h = xyz.cpu().numpy()
     x_h = x.cpu().numpy()
     w_h = np.ones(n)
     p0 = n // 3
+
+    def oracle(sel):
+        return cpu.estimate(xyz_h[:, sel], nbr_h[0], nbr_h[2], nbr_h[1], E, M, w_h[sel], x_h[sel], nthreads=threads)
+
+    # size the sample to ~15 s of oracle work: one call with a single pivot measures the
+    # oracle's fixed cost (its own O(N) grid build), one with 320 pivots its pair rate
     if nsample < 0:
         t = time.perf_counter()
-        sel = perm[p0:p0 + 1]
-        cpu.estimate(xyz_h[:, sel], xyz_h, w_h, x_h, E, M, w_h[sel], x_h[sel], nthreads=threads)
+        oracle(order[p0:p0 + 1])
         t_fixed = time.perf_counter() - t
         t = time.perf_counter()
-        sel = perm[p0:p0 + 320]
-        _, p320 = cpu.estimate(xyz_h[:, sel], xyz_h, w_h, x_h, E, M, w_h[sel], x_h[sel], nthreads=threads)
+        _, p320 = oracle(order[p0:p0 + 320])
         rate = p320 / max(time.perf_counter() - t - t_fixed, 1e-3)
         nsample = int(min(n - p0, max(320, 30.0 * rate / max(p320 / 320.0, 1.0))))
         log(f"[bench] cpu_baseline calibration: fixed {t_fixed:.2f}s, {rate:.3g} pairs/s")
-    sel = perm[p0:p0 + nsample]
+    sel = order[p0:p0 + nsample]
     log(f"[bench] cpu_baseline: oracle on {nsample} pivots x {threads} threads")
     t = time.perf_counter()
-    zo, po = cpu.estimate(xyz_h[:, sel], xyz_h, w_h, x_h, E, M, w_h[sel], x_h[sel], nthreads=threads)
+    zo, po = oracle(sel)
     dt = time.perf_counter() - t
-    zeta = torch.zeros((M + 1, cfg.nbins, cfg.nbins, 2), dtype=torch.float64, device="cuda")
-    pairs = torch.zeros(1, dtype=torch.int64, device="cuda")
-    sw = torch.zeros(1, dtype=torch.float64, device="cuda")
-    z3.estimate_raw(idx, M, prec=prec, p0=p0, p1=p0 + nsample, zeta=zeta, pair_total=pairs, sum_w=sw)
-    zg = (zeta / sw).cpu().numpy()
-    zg = zg[..., 0] + 1j * zg[..., 1]
+    parity = {}
+    for gp in ("fp64", "mixed"):
+        zeta = torch.zeros((M + 1, cfg.nbins, cfg.nbins, 2), dtype=torch.float64, device="cuda")
+        pairs = torch.zeros(1, dtype=torch.int64, device="cuda")
+        sw = torch.zeros(1, dtype=torch.float64, device="cuda")
+        if nbr is None:
+            z3.estimate_raw(idx, M, prec=gp, p0=p0, p1=p0 + nsample, zeta=zeta, pair_total=pairs, sum_w=sw)
+        else:
+            z3.estimate_pivots_raw(idx, xyz, x, None, M, prec=gp, p0=p0, p1=p0 + nsample, zeta=zeta,
+                                   pair_total=pairs, sum_w=sw)
+        zg = (zeta / sw).cpu().numpy()
+        zg = zg[..., 0] + 1j * zg[..., 1]
+        e = err_m(zg, zo)
+        parity[gp] = {"pairs_equal": po == int(pairs.item()), "err_m_max": max(e)}
+        log(f"[bench] cpu_baseline: {dt:.1f}s; {gp} on the sample: pairs oracle {po} gpu {int(pairs.item())}, "
+            f"err_m max {max(e):.2e}")
     idx.free()
-    e = err_m(zg, zo)
-    log(f"[bench] cpu_baseline: {dt:.1f}s, pairs oracle {po} gpu {int(pairs.item())}, err_m max {max(e):.2e}")
     return {"value": po * (M + 1) / dt, "unit": "pair-multipole updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"{nsample} contiguous index-order pivots from position {p0} of the {cfg.name} map "
-                      f"against all {n} neighbours (includes the oracle's O(N) grid build)",
+            "sample": f"{nsample} contiguous pivots from position {p0} of the {cfg.name} map against all "
+                      f"{len(nbr_h[1])} neighbours (includes the oracle's O(N) grid build)",
             "seconds": dt, "cpu_model": cpu_model(),
-            "gpu_parity_on_sample": {"pairs_equal": po == int(pairs.item()), "err_m_max": max(e),
-                                     "precision": prec}}
+            "gpu_parity_on_sample": parity}
 
 
 if __name__ == "__main__":

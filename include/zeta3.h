@@ -32,7 +32,8 @@
  *  - zeta arrays are FP64 [m_max+1][nbins][nbins][2] (re, im), full Hermitian matrices,
  *    and are ACCUMULATED (+=), so pivot ranges can be processed in pieces and summed.
  *  - Pivots are the catalogue's own points, addressed by their position in the index
- *    order (see z3_index_perm), so that pivot ranges [p0, p1) can be streamed.
+ *    order (see z3_index_perm), so that pivot ranges [p0, p1) can be streamed; only
+ *    z3_estimate_pivots takes an external pivot catalogue.
  */
 #ifndef ZETA3_H
 #define ZETA3_H
@@ -73,7 +74,7 @@ enum {
  * Build the sky-cell index of a catalogue of n points (the neighbour search of the
  * binned estimator; it replaces the paper's tree search with a latitude-band x
  * longitude-cell grid, points sorted by cell).
- *   n              number of points, 0 <= n < 2^31
+ *   n              number of points, 0 <= n < 2^29 (Z3_ERR_OVERFLOW above)
  *   xyz            [3][n] FP64 unit vectors (x row, y row, z row)
  *   w              [n] FP64 weights w_i (eq. of the discrete field), or NULL for all 1
  *   nbins          1 .. Z3_MAX_NBINS
@@ -90,8 +91,9 @@ z3_status z3_build_index(int64_t n, const double *xyz, const double *w, int nbin
 
 /*
  * Attach field values: nmaps maps of n values each, x [nmaps][n] FP64 in the
- * catalogue's original order.  The index stores w_i x_i in index order (FP64, and an
- * FP32 copy for the mixed path).  Replaces values attached before.
+ * catalogue's original order.  The index stores w_i x_i in index order and, per map,
+ * 32-byte neighbour records {x, y, z, w x} (2 n records: every latitude band is stored
+ * twice in a row).  Waits for earlier work on `stream`; replaces values attached before.
  */
 z3_status z3_index_set_values(z3_index idx, int nmaps, const double *x, void *stream);
 
@@ -138,6 +140,23 @@ z3_status z3_contract(int64_t npiv, int m_max, int nbins, int prec, const void *
  */
 z3_status z3_estimate(z3_index idx, int map, int m_max, int prec, int64_t p0, int64_t p1,
                       double *zeta, uint64_t *pair_total, void *stream);
+
+/*
+ * Fused estimator for an external pivot catalogue against the index's neighbours (the
+ * pivot field of the cross-correlation remark in the harmonic-decomposition section;
+ * also the approximate search, whose neighbour catalogue is a coarsened map):
+ *   piv_xyz  [3][npiv] FP64 unit vectors in the caller's order (a spatially coherent
+ *            order, such as HEALPix RING, keeps neighbouring pivots in one wave)
+ *   piv_w    [npiv] pivot weights, or NULL for all 1
+ *   piv_x    [npiv] pivot values
+ * Pivots [p0, p1) are processed; zeta += sum_p w_p x_p X(b1) conj X(b2) (unnormalised),
+ * pair_total += pairs (may be NULL), sum_w[0] += sum of the pivots' weights (may be NULL).
+ * A neighbour at the position of a pivot is not a pair (E_0 > 0).
+ */
+z3_status z3_estimate_pivots(z3_index idx, int map, int64_t npiv, const double *piv_xyz,
+                             const double *piv_w, const double *piv_x, int m_max, int prec,
+                             int64_t p0, int64_t p1, double *zeta, uint64_t *pair_total,
+                             double *sum_w, void *stream);
 
 /* sum_p w_p over pivots [p0, p1), FP64, out[0] += . */
 z3_status z3_pivot_weight_sum(z3_index idx, int64_t p0, int64_t p1, double *out, void *stream);

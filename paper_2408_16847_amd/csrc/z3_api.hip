@@ -133,7 +133,7 @@ Z3_API z3_status z3_build_index(int64_t n, const double *xyz, const double *w, i
     if (!out) return fail(Z3_ERR_INVALID_ARG, "z3_build_index: out is NULL");
     *out = nullptr;
     if (n < 0) return fail(Z3_ERR_INVALID_ARG, "z3_build_index: n < 0");
-    if (n >= (int64_t)0x7fffffff) return fail(Z3_ERR_OVERFLOW, "z3_build_index: n >= 2^31 - 1");
+    if (n >= ((int64_t)1 << 29)) return fail(Z3_ERR_OVERFLOW, "z3_build_index: n >= 2^29");
     if (n > 0 && !xyz) return fail(Z3_ERR_INVALID_ARG, "z3_build_index: xyz is NULL");
     if (nbins < 1 || nbins > Z3_MAX_NBINS)
         return fail(Z3_ERR_INVALID_ARG, "z3_build_index: nbins=%d outside 1..%d", nbins, Z3_MAX_NBINS);
@@ -225,8 +225,8 @@ Z3_API z3_status z3_accumulate_multipoles(z3_index idx, int map, int m_max, int 
     if (norm != Z3_NORM_BIN && norm != Z3_NORM_NONE)
         return fail(Z3_ERR_INVALID_ARG, "z3_accumulate_multipoles: unknown norm %d", norm);
     if (p1 == p0) return Z3_OK;
-    return launch_multipoles(idx, map, m_max, prec, norm, p0, p1, A, p1 - p0, W, counts, idhash,
-                             pair_total, as_stream(stream));
+    return launch_multipoles(idx, Pivots{idx->d_x, idx->d_y, idx->d_z}, map, m_max, prec, norm, p0, p1, A,
+                             p1 - p0, W, counts, idhash, pair_total, as_stream(stream));
 }
 
 Z3_API z3_status z3_contract(int64_t npiv, int m_max, int nbins, int prec, const void *A,
@@ -286,11 +286,65 @@ Z3_API z3_status z3_estimate(z3_index idx, int map, int m_max, int prec, int64_t
     const double *v = idx->d_v + (size_t)map * idx->n;
     for (int64_t c0 = p0; c0 < p1 && st == Z3_OK; c0 += chunk) {
         int64_t c1 = c0 + chunk < p1 ? c0 + chunk : p1;
-        st = launch_multipoles(idx, map, m_max, prec, Z3_NORM_BIN, c0, c1, wa, c1 - c0, nullptr, nullptr,
-                               nullptr, pair_total, s);
+        st = launch_multipoles(idx, Pivots{idx->d_x, idx->d_y, idx->d_z}, map, m_max, prec, Z3_NORM_BIN, c0, c1,
+                               wa, c1 - c0, nullptr, nullptr, nullptr, pair_total, s);
         if (st == Z3_OK)
             st = launch_contract(c1 - c0, m_max, idx->nbins, prec, wa, c1 - c0, v + c0, zeta, wp, pbytes, s);
     }
+    scratch_free(wp, s);
+    scratch_free(wa, s);
+    return st;
+}
+
+Z3_API z3_status z3_estimate_pivots(z3_index idx, int map, int64_t npiv, const double *piv_xyz,
+                                    const double *piv_w, const double *piv_x, int m_max, int prec,
+                                    int64_t p0, int64_t p1, double *zeta, uint64_t *pair_total,
+                                    double *sum_w, void *stream)
+{
+    if (!idx) return fail(Z3_ERR_INVALID_ARG, "z3_estimate_pivots: idx is NULL");
+    if (npiv < 0) return fail(Z3_ERR_INVALID_ARG, "z3_estimate_pivots: npiv < 0");
+    if (npiv >= (int64_t)0x7fffffff) return fail(Z3_ERR_OVERFLOW, "z3_estimate_pivots: npiv >= 2^31 - 1");
+    if (m_max < 0 || m_max > Z3_MAX_MMAX)
+        return fail(Z3_ERR_INVALID_ARG, "z3_estimate_pivots: m_max=%d outside 0..%d", m_max, Z3_MAX_MMAX);
+    if (prec != Z3_PREC_FP64 && prec != Z3_PREC_MIXED)
+        return fail(Z3_ERR_INVALID_ARG, "z3_estimate_pivots: unknown precision %d", prec);
+    if (p0 < 0 || p1 < p0 || p1 > npiv)
+        return fail(Z3_ERR_INVALID_ARG, "z3_estimate_pivots: pivot range [%lld, %lld) outside [0, %lld]",
+                    (long long)p0, (long long)p1, (long long)npiv);
+    if (!zeta) return fail(Z3_ERR_INVALID_ARG, "z3_estimate_pivots: zeta is NULL");
+    if (p1 > p0 && (!piv_xyz || !piv_x)) return fail(Z3_ERR_INVALID_ARG, "z3_estimate_pivots: NULL pivots");
+    if (idx->n > 0 && (idx->nmaps < 1 || !idx->d_v))
+        return fail(Z3_ERR_INVALID_ARG, "z3_estimate_pivots: no values attached (z3_index_set_values)");
+    if (idx->n > 0 && (map < 0 || map >= idx->nmaps))
+        return fail(Z3_ERR_INVALID_ARG, "z3_estimate_pivots: map %d outside 0..%d", map, idx->nmaps - 1);
+    if (p1 == p0) return Z3_OK;
+    hipStream_t s = as_stream(stream);
+    z3_status st = Z3_OK;
+    if (sum_w) {
+        st = piv_w ? launch_weight_sum(piv_w + p0, p1 - p0, sum_w, s) : launch_add_scalar(sum_w, (double)(p1 - p0), s);
+        if (st != Z3_OK) return st;
+    }
+    if (idx->n == 0) return Z3_OK;  // no neighbours: no pairs, zeta unchanged
+    int64_t chunk = chunk_pivots(idx, m_max, prec);
+    if (chunk > p1 - p0) chunk = ((p1 - p0 + kBlock - 1) / kBlock) * kBlock;
+    size_t elem = prec == Z3_PREC_FP64 ? 8 : 4;
+    size_t abytes = (size_t)chunk * (size_t)(m_max + 1) * 2 * idx->nbins * elem;
+    size_t pbytes = contract_partial_bytes(chunk, m_max, idx->nbins);
+    void *wa = nullptr, *wp = nullptr, *wv = nullptr;
+    if ((st = scratch_alloc(&wa, abytes, s)) != Z3_OK) return st;
+    if ((st = scratch_alloc(&wp, pbytes, s)) == Z3_OK) st = scratch_alloc(&wv, (size_t)chunk * sizeof(double), s);
+    const Pivots piv{piv_xyz, piv_xyz + npiv, piv_xyz + 2 * npiv};
+    for (int64_t c0 = p0; c0 < p1 && st == Z3_OK; c0 += chunk) {
+        int64_t c1 = c0 + chunk < p1 ? c0 + chunk : p1;
+        st = launch_pivot_values(piv_w ? piv_w + c0 : nullptr, piv_x + c0, c1 - c0, static_cast<double *>(wv), s);
+        if (st == Z3_OK)
+            st = launch_multipoles(idx, piv, map, m_max, prec, Z3_NORM_BIN, c0, c1, wa, c1 - c0, nullptr, nullptr,
+                                   nullptr, pair_total, s);
+        if (st == Z3_OK)
+            st = launch_contract(c1 - c0, m_max, idx->nbins, prec, wa, c1 - c0, static_cast<const double *>(wv),
+                                 zeta, wp, pbytes, s);
+    }
+    scratch_free(wv, s);
     scratch_free(wp, s);
     scratch_free(wa, s);
     return st;

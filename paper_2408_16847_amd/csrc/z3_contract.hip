@@ -203,6 +203,30 @@ z3_status launch_weight_sum(const double *w, int64_t n, double *out, hipStream_t
     return st;
 }
 
+__global__ void k_pivot_values(const double *w, const double *x, int64_t n, double *v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) v[i] = w ? w[i] * x[i] : x[i];
+}
+
+z3_status launch_pivot_values(const double *w, const double *x, int64_t n, double *v, hipStream_t s)
+{
+    if (n <= 0) return Z3_OK;
+    hipLaunchKernelGGL(k_pivot_values, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, w, x, n, v);
+    return check_launch("k_pivot_values");
+}
+
+__global__ void k_add_scalar(double *out, double value)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) out[0] += value;
+}
+
+z3_status launch_add_scalar(double *out, double value, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_add_scalar, dim3(1), dim3(64), 0, s, out, value);
+    return check_launch("k_add_scalar");
+}
+
 __global__ void k_finalize(double *zeta, int64_t count, const double *sum_w)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -81,8 +81,12 @@ z3_status set_values_impl(z3_index idx, int nmaps, const double *x, hipStream_t 
 void free_index(z3_index idx);
 
 // multipole kernels (z3_multipoles.hip)
-z3_status launch_multipoles(const z3_index_s *idx, int map, int m_max, int prec, int norm,
-                            int64_t p0, int64_t p1, void *A, int64_t ldA, double *W,
+// Pivot positions: either the index's own points (index order) or an external catalogue.
+struct Pivots {
+    const double *x, *y, *z;
+};
+z3_status launch_multipoles(const z3_index_s *idx, Pivots piv, int map, int m_max, int prec,
+                            int norm, int64_t p0, int64_t p1, void *A, int64_t ldA, double *W,
                             int64_t *counts, uint64_t *idhash, uint64_t *pair_total,
                             hipStream_t s);
 
@@ -92,6 +96,8 @@ z3_status launch_contract(int64_t npiv, int m_max, int nbins, int prec, const vo
                           size_t partial_bytes, hipStream_t s);
 size_t contract_partial_bytes(int64_t npiv, int m_max, int nbins);
 z3_status launch_weight_sum(const double *w, int64_t n, double *out, hipStream_t s);
+z3_status launch_pivot_values(const double *w, const double *x, int64_t n, double *v, hipStream_t s);
+z3_status launch_add_scalar(double *out, double value, hipStream_t s);
 z3_status launch_finalize(int nmaps, int m_max, int nbins, double *zeta, const double *sum_w,
                           hipStream_t s);
 z3_status launch_resum(int m_max, int nbins, const double *zeta, int nphi, const double *phi,

@@ -396,14 +396,14 @@ static void launch_m(bool mixed, bool ids, const MultArgs &a, hipStream_t s)
     }
 }
 
-z3_status launch_multipoles(const z3_index_s *idx, int map, int m_max, int prec, int norm,
+z3_status launch_multipoles(const z3_index_s *idx, Pivots piv, int map, int m_max, int prec, int norm,
                             int64_t p0, int64_t p1, void *A, int64_t ldA, double *W,
                             int64_t *counts, uint64_t *idhash, uint64_t *pair_total, hipStream_t s)
 {
     int64_t nblk = (p1 - p0 + kBlock - 1) / kBlock;
     if (nblk > 0x7fffffff) return fail(Z3_ERR_OVERFLOW, "too many pivot blocks");
     MultArgs a;
-    a.px = idx->d_x; a.py = idx->d_y; a.pz = idx->d_z;
+    a.px = piv.x; a.py = piv.y; a.pz = piv.z;
     a.rec = idx->d_rec + (size_t)map * 2 * idx->n;
     a.wdbl = idx->unit_w ? nullptr : idx->d_wdbl;
     a.permdbl = idx->d_permdbl;

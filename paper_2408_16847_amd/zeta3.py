@@ -151,6 +151,34 @@ def estimate(idx: Index, m_max: int, prec="fp64", p0: int = 0, p1: int | None = 
     return z[..., 0] + 1j * z[..., 1], int(pairs.item())
 
 
+def estimate_pivots_raw(idx: Index, piv_xyz, piv_x, piv_w=None, m_max: int = 0, prec="fp64", p0: int = 0,
+                        p1: int | None = None, map_index: int = 0, zeta=None, pair_total=None, sum_w=None):
+    """Enqueue the estimator for an external pivot catalogue (piv_xyz [3, P], piv_x [P],
+    piv_w [P] or None) against the index's neighbours: zeta += (unnormalised)."""
+    piv_xyz = _dev(piv_xyz)
+    piv_x = _dev(piv_x)
+    piv_w = None if piv_w is None else _dev(piv_w)
+    P = int(piv_xyz.shape[1])
+    p1 = P if p1 is None else p1
+    if zeta is None:
+        zeta = torch.zeros((m_max + 1, idx.nbins, idx.nbins, 2), dtype=torch.float64, device="cuda")
+    _lib.call("z3_estimate_pivots", idx.handle, map_index, P, _ptr(piv_xyz), _ptr(piv_w), _ptr(piv_x), m_max,
+              PREC[prec], p0, p1, _ptr(zeta), _ptr(pair_total), _ptr(sum_w), _stream())
+    return zeta
+
+
+def estimate_pivots(idx: Index, piv_xyz, piv_x, piv_w=None, m_max: int = 0, prec="fp64", p0: int = 0,
+                    p1: int | None = None, map_index: int = 0):
+    """Normalised zeta_m (complex128 numpy) and the pair count for external pivots."""
+    zeta = torch.zeros((m_max + 1, idx.nbins, idx.nbins, 2), dtype=torch.float64, device="cuda")
+    pairs = torch.zeros(1, dtype=torch.int64, device="cuda")
+    sw = torch.zeros(1, dtype=torch.float64, device="cuda")
+    estimate_pivots_raw(idx, piv_xyz, piv_x, piv_w, m_max, prec, p0, p1, map_index, zeta, pairs, sw)
+    _lib.call("z3_finalize", 1, m_max, idx.nbins, _ptr(zeta), _ptr(sw), _stream())
+    z = zeta.cpu().numpy()
+    return z[..., 0] + 1j * z[..., 1], int(pairs.item())
+
+
 def resum(zeta, phi):
     """zeta(b1, b2, phi) from zeta_m (complex [m+1, nb, nb] or a [m+1, nb, nb, 2] tensor)."""
     if not isinstance(zeta, torch.Tensor):

@@ -207,3 +207,44 @@ def test_invalid_arguments_on_device():
         z3.estimate(idx, 3, map_index=1)
     with pytest.raises(z3.zeta3._lib.Zeta3Error):
         z3.estimate(idx, 17)
+
+
+def test_external_pivots_subset_and_cross_catalogue(cap):
+    cfg, xyz, x = cap
+    G.say("case: external pivots")
+    E = cfg.edges_chord2()
+    w = np.ones(xyz.shape[1])
+    idx = G.build(xyz, x, E)
+    sel = np.arange(5000, 9000)  # pivots drawn from the catalogue itself: no self pairs
+    pxyz = torch.from_numpy(np.ascontiguousarray(xyz[:, sel])).cuda()
+    for prec, tol in (("fp64", 1e-10), ("mixed", 1e-6)):
+        z, pairs = z3.estimate_pivots(idx, pxyz, torch.from_numpy(x[sel]).cuda(), m_max=cfg.m_max, prec=prec)
+        zo, po = cpu.estimate(xyz[:, sel], xyz, w, x, E, cfg.m_max, w[sel], x[sel])
+        assert pairs == po
+        assert G.err_m(z, zo).max() < tol
+    # a different pivot catalogue with its own weights and a pivot sub-range
+    pv, pw, px = pins.random_cap(3000, 9.0, 77)
+    z, pairs = z3.estimate_pivots(idx, torch.from_numpy(pv).cuda(), torch.from_numpy(px).cuda(),
+                                  torch.from_numpy(pw).cuda(), m_max=cfg.m_max, p0=100, p1=2900)
+    zo, po = cpu.estimate(pv[:, 100:2900], xyz, w, x, E, cfg.m_max, pw[100:2900], px[100:2900])
+    assert pairs == po
+    assert G.err_m(z, zo).max() < 1e-10
+
+
+def test_approximate_search_degraded_neighbours():
+    """Full-resolution pivots against the Nside/2 averaged map (weights = 4 children)."""
+    from synth import degrade_ring
+    G.say("case: approximate search nside64 -> 32")
+    xyz_t = ring_centres(64)
+    xf = make_values(CONFIGS["nside512"], xyz_t)
+    cxyz, cx, cw = degrade_ring(64, xf)
+    E = chord2_edges(theta_edges(math.radians(2.0), math.radians(15.0), 5, True))
+    idx = G.build(cxyz.numpy(), cx.numpy(), E, w=cw.numpy())
+    for prec, tol in (("fp64", 1e-10), ("mixed", 1e-6)):
+        z, pairs = z3.estimate_pivots(idx, xyz_t.cuda(), xf.cuda(), m_max=10, prec=prec)
+        zo, po = cpu.estimate(xyz_t.numpy(), cxyz.numpy(), cw.numpy(), cx.numpy(), E, 10,
+                              np.ones(xyz_t.shape[1]), xf.numpy())
+        assert pairs == po
+        e = G.err_m(z, zo)
+        G.say("err_m", prec, e.max())
+        assert e.max() < tol
