@@ -57,6 +57,8 @@ def measured_traffic(cfg_name, prec):
 
 
 def err_m(test, ref):
+    if ref.ndim == 4:  # several maps: the worst map per m
+        return [max(v) for v in zip(*[err_m(t, r) for t, r in zip(test, ref)])]
     out = []
     for m in range(ref.shape[0]):
         r = np.concatenate([ref[m].real.ravel(), ref[m].imag.ravel()])
@@ -106,7 +108,10 @@ def main():
     cfg = CONFIGS[args.config]
     t0 = time.time()
     xyz = make_positions(cfg, device="cuda")
-    x = make_values(cfg, xyz, seed=0)
+    if cfg.nmaps > 1:
+        x = torch.stack([make_values(cfg, xyz, seed=s) for s in range(cfg.nmaps)])
+    else:
+        x = make_values(cfg, xyz, seed=0)
     nbr = None
     if args.approx:
         from synth import degrade_ring
@@ -125,7 +130,12 @@ def main():
         zeta = torch.zeros((M + 1, cfg.nbins, cfg.nbins, 2), dtype=torch.float64, device="cuda")
         pairs = torch.zeros(1, dtype=torch.int64, device="cuda")
         sw = torch.zeros(1, dtype=torch.float64, device="cuda")
-        if nbr is None:
+        if cfg.nmaps > 1:
+            zeta = torch.zeros((cfg.nmaps, M + 1, cfg.nbins, cfg.nbins, 2), dtype=torch.float64, device="cuda")
+            idx = z3.Index(xyz, E)
+            idx.set_values(x)
+            z3.estimate_maps_raw(idx, M, prec=prec, zeta=zeta, pair_total=pairs, sum_w=sw)
+        elif nbr is None:
             idx = z3.Index(xyz, E)
             idx.set_values(x)
             z3.estimate_raw(idx, M, prec=prec, zeta=zeta, pair_total=pairs, sum_w=sw)
@@ -133,7 +143,7 @@ def main():
             idx = z3.Index(nbr[0], E, weights=nbr[2])
             idx.set_values(nbr[1])
             z3.estimate_pivots_raw(idx, xyz, x, None, M, prec=prec, zeta=zeta, pair_total=pairs, sum_w=sw)
-        z3.zeta3._lib.call("z3_finalize", 1, M, cfg.nbins, z3.zeta3._ptr(zeta), z3.zeta3._ptr(sw),
+        z3.zeta3._lib.call("z3_finalize", cfg.nmaps, M, cfg.nbins, z3.zeta3._ptr(zeta), z3.zeta3._ptr(sw),
                            z3.zeta3._stream())
         zh = zeta.cpu().numpy()
         npairs = int(pairs.item())
@@ -164,7 +174,7 @@ def main():
 
     main_prec = "mixed" if "mixed" in res else "fp64"
     r = res[main_prec]
-    updates = r["pairs"] * (M + 1)
+    updates = r["pairs"] * (M + 1) * cfg.nmaps
     value = updates / r["s_per_step"]
     launches_per_step = r["kernel_launches"] / args.steps
     kern_s_per_step = r["kernel_ms_total"] / args.steps / 1e3
@@ -182,7 +192,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if main_prec == "fp64" else "f64 geometry + f32 multipoles/MFMA",
         "data": "synthetic",
-        "config": {"workload": cfg.name + ("+approx" if nbr else ""), "npoints": n, "nbins": cfg.nbins, "m_max": M,
+        "config": {"workload": cfg.name + ("+approx" if nbr else ""), "npoints": n, "nmaps": cfg.nmaps, "nbins": cfg.nbins, "m_max": M,
                    "theta_arcmin": [cfg.theta_min * 10800 / np.pi, cfg.theta_max * 10800 / np.pi],
                    "log_bins": cfg.log_bins, "precision": main_prec, "pairs": r["pairs"]},
         "roofline": {"bound": "alu", "kernel": "k_multipoles", "achieved": achieved,
@@ -193,7 +203,7 @@ def main():
     }
     for prec in res:
         out[f"zeta_wall_ms_{prec}"] = res[prec]["s_per_step"] * 1e3
-        out[f"updates_per_s_{prec}"] = res[prec]["pairs"] * (M + 1) / res[prec]["s_per_step"]
+        out[f"updates_per_s_{prec}"] = res[prec]["pairs"] * (M + 1) * cfg.nmaps / res[prec]["s_per_step"]
     if "fp64" in res and "mixed" in res:
         e = err_m(res["mixed"]["zeta"], res["fp64"]["zeta"])
         out["mixed_vs_fp64_err_m"] = e
@@ -203,7 +213,7 @@ def main():
 
     if args.save_zeta:
         np.savez(args.save_zeta, **{p: res[p]["zeta"] for p in res})
-    if args.cpu_sample != 0:
+    if args.cpu_sample != 0 and cfg.nmaps == 1:
         out["cpu_baseline"] = cpu_baseline(cfg, xyz, x, nbr, E, M, args.cpu_sample, z3, torch)
     print(json.dumps(out), flush=True)
 

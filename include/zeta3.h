@@ -142,6 +142,17 @@ z3_status z3_estimate(z3_index idx, int map, int m_max, int prec, int64_t p0, in
                       double *zeta, uint64_t *pair_total, void *stream);
 
 /*
+ * Fused estimator for ALL attached maps at once (many mock maps over one set of
+ * positions): for every pair the bin test, bearing and cos/sin(m phi) are computed once
+ * and applied to the values of several maps.  zeta [nmaps][m_max+1][nbins][nbins][2] +=
+ * (unnormalised, one block per map, in map order); pair_total += the number of pairs
+ * (counted once, not per map), or NULL.  Multipoles are accumulated in FP64; `prec`
+ * selects the FP64 or the mixed (FP32 storage, split FP32 MFMA) contraction.
+ */
+z3_status z3_estimate_maps(z3_index idx, int m_max, int prec, int64_t p0, int64_t p1,
+                           double *zeta, uint64_t *pair_total, void *stream);
+
+/*
  * Fused estimator for an external pivot catalogue against the index's neighbours (the
  * pivot field of the cross-correlation remark in the harmonic-decomposition section;
  * also the approximate search, whose neighbour catalogue is a coarsened map):

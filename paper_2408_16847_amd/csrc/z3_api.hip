@@ -296,6 +296,52 @@ Z3_API z3_status z3_estimate(z3_index idx, int map, int m_max, int prec, int64_t
     return st;
 }
 
+Z3_API z3_status z3_estimate_maps(z3_index idx, int m_max, int prec, int64_t p0, int64_t p1, double *zeta,
+                                  uint64_t *pair_total, void *stream)
+{
+    z3_status st = check_common("z3_estimate_maps", idx, 0, m_max, prec, p0, p1);
+    if (st != Z3_OK) return st;
+    if (!zeta) return fail(Z3_ERR_INVALID_ARG, "z3_estimate_maps: zeta is NULL");
+    if (p1 == p0) return Z3_OK;
+    hipStream_t s = as_stream(stream);
+    if (idx->nmaps == 1) return z3_estimate(idx, 0, m_max, prec, p0, p1, zeta, pair_total, stream);
+    const size_t elem = prec == Z3_PREC_FP64 ? 8 : 4;
+    const size_t per_map_piv = (size_t)(m_max + 1) * 2 * idx->nbins * elem;
+    int64_t chunk = chunk_pivots(idx, m_max, prec) / kMapGroup;
+    chunk = (chunk / kBlock) * kBlock;
+    if (chunk < 16 * kBlock) chunk = 16 * kBlock;
+    if (chunk > p1 - p0) chunk = ((p1 - p0 + kBlock - 1) / kBlock) * kBlock;
+    const size_t map_stride = (size_t)chunk * (m_max + 1) * 2 * idx->nbins;  // elements
+    size_t pbytes = contract_partial_bytes(chunk, m_max, idx->nbins);
+    void *wa = nullptr, *wp = nullptr;
+    if ((st = scratch_alloc(&wa, (size_t)kMapGroup * chunk * per_map_piv, s)) != Z3_OK) return st;
+    if ((st = scratch_alloc(&wp, pbytes, s)) != Z3_OK) {
+        scratch_free(wa, s);
+        return st;
+    }
+    const size_t zstride = (size_t)(m_max + 1) * idx->nbins * idx->nbins * 2;
+    for (int g = 0; g < idx->ngroups && st == Z3_OK; ++g) {
+        for (int64_t c0 = p0; c0 < p1 && st == Z3_OK; c0 += chunk) {
+            int64_t c1 = c0 + chunk < p1 ? c0 + chunk : p1;
+            // the chunk's multipoles use a leading dimension equal to the chunk length
+            const size_t stride = (size_t)(c1 - c0) * (m_max + 1) * 2 * idx->nbins;
+            st = launch_multipoles_maps(idx, g, m_max, prec, c0, c1, wa, c1 - c0, stride,
+                                        g == 0 ? pair_total : nullptr, s);
+            for (int k = 0; k < kMapGroup && st == Z3_OK; ++k) {
+                const int map = g * kMapGroup + k;
+                if (map >= idx->nmaps) break;
+                const void *Ak = static_cast<const char *>(wa) + k * stride * elem;
+                st = launch_contract(c1 - c0, m_max, idx->nbins, prec, Ak, c1 - c0,
+                                     idx->d_v + (size_t)map * idx->n + c0, zeta + map * zstride, wp, pbytes, s);
+            }
+        }
+    }
+    (void)map_stride;
+    scratch_free(wp, s);
+    scratch_free(wa, s);
+    return st;
+}
+
 Z3_API z3_status z3_estimate_pivots(z3_index idx, int map, int64_t npiv, const double *piv_xyz,
                                     const double *piv_w, const double *piv_x, int m_max, int prec,
                                     int64_t p0, int64_t p1, double *zeta, uint64_t *pair_total,

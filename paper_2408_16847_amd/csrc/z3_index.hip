@@ -198,6 +198,27 @@ __global__ void k_records(int64_t n, int nmaps, const int *band, const Band *ban
     }
 }
 
+// Values of map group g in doubled-band order, kMapGroup maps interleaved per point
+// (missing maps of the last group are 0).
+__global__ void k_group_values(int64_t n, int nmaps, const int *band, const Band *bands, const double *v,
+                               double *out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const Band &bd = bands[band[i]];
+    const int64_t q = 2 * (int64_t)bd.pt_start + (i - bd.pt_start);
+    const int ng = (nmaps + kMapGroup - 1) / kMapGroup;
+    for (int g = 0; g < ng; ++g) {
+        double *o = out + (size_t)g * 2 * n * kMapGroup;
+        for (int k = 0; k < kMapGroup; ++k) {
+            const int m = g * kMapGroup + k;
+            const double val = m < nmaps ? v[(size_t)m * n + i] : 0.0;
+            o[(size_t)q * kMapGroup + k] = val;
+            o[(size_t)(q + bd.npts) * kMapGroup + k] = val;
+        }
+    }
+}
+
 __global__ void k_gather_int(int64_t n, const int *perm, const int *in, int *out)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -282,7 +303,8 @@ static z3_status exclusive_scan(const int *in, int64_t n, int *out, hipStream_t 
 static void free_ptrs(z3_index idx)
 {
     void *ps[] = {idx->d_edges, idx->d_bands, idx->d_cell_start, idx->d_x, idx->d_y, idx->d_z,
-                  idx->d_w, idx->d_perm, idx->d_band, idx->d_wdbl, idx->d_permdbl, idx->d_v, idx->d_rec};
+                  idx->d_w, idx->d_perm, idx->d_band, idx->d_wdbl, idx->d_permdbl, idx->d_v, idx->d_rec,
+                  idx->d_vgrp};
     for (void *p : ps)
         if (p) (void)hipFree(p);
 }
@@ -494,7 +516,9 @@ z3_status set_values_impl(z3_index idx, int nmaps, const double *x, hipStream_t 
     (void)hipStreamSynchronize(s);  // earlier work may still read the old values
     if (idx->d_v) { (void)hipFree(idx->d_v); idx->d_v = nullptr; }
     if (idx->d_rec) { (void)hipFree(idx->d_rec); idx->d_rec = nullptr; }
+    if (idx->d_vgrp) { (void)hipFree(idx->d_vgrp); idx->d_vgrp = nullptr; }
     idx->nmaps = 0;
+    idx->ngroups = 0;
     size_t cnt = (size_t)nmaps * (size_t)idx->n;
     if ((st = dalloc(&idx->d_v, cnt, "alloc values")) != Z3_OK) return st;
     if ((st = dalloc(&idx->d_rec, 2 * cnt, "alloc records")) != Z3_OK) return st;
@@ -504,6 +528,17 @@ z3_status set_values_impl(z3_index idx, int nmaps, const double *x, hipStream_t 
         hipLaunchKernelGGL(k_records, dim3(grid_for(idx->n)), dim3(256), 0, s, idx->n, nmaps, idx->d_band,
                            idx->d_bands, idx->d_x, idx->d_y, idx->d_z, idx->d_v, idx->d_rec);
         if ((st = check_launch("k_gather_values/k_records")) != Z3_OK) return st;
+    }
+    if (nmaps > 1) {
+        const int ng = (nmaps + kMapGroup - 1) / kMapGroup;
+        if ((st = dalloc(&idx->d_vgrp, (size_t)ng * 2 * idx->n * kMapGroup, "alloc grouped values")) != Z3_OK)
+            return st;
+        if (idx->n > 0) {
+            hipLaunchKernelGGL(k_group_values, dim3(grid_for(idx->n)), dim3(256), 0, s, idx->n, nmaps, idx->d_band,
+                               idx->d_bands, idx->d_v, idx->d_vgrp);
+            if ((st = check_launch("k_group_values")) != Z3_OK) return st;
+        }
+        idx->ngroups = ng;
     }
     idx->nmaps = nmaps;
     return Z3_OK;

@@ -13,6 +13,7 @@ namespace z3 {
 
 constexpr int kBlock = 256;      // threads per block of the multipole kernel (4 wave64s)
 constexpr int kCellsPerPoint = 4;  // longitude cells per point of a band
+constexpr int kMapGroup = 4;       // maps carried per lane by the many-map kernel
 constexpr int kWave = 64;
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kTwoPi = 6.28318530717958647692;
@@ -65,6 +66,8 @@ struct z3_index_s {
     int nmaps = 0;
     double *d_v = nullptr;            // [nmaps][n] w * x in index order
     double4 *d_rec = nullptr;         // [nmaps][2n] {x, y, z, w * x}
+    int ngroups = 0;                  // map groups of kMapGroup for the many-map kernel
+    double *d_vgrp = nullptr;         // [ngroups][2n][kMapGroup] w * x, doubled bands
 };
 
 namespace z3 {
@@ -89,6 +92,10 @@ z3_status launch_multipoles(const z3_index_s *idx, Pivots piv, int map, int m_ma
                             int norm, int64_t p0, int64_t p1, void *A, int64_t ldA, double *W,
                             int64_t *counts, uint64_t *idhash, uint64_t *pair_total,
                             hipStream_t s);
+
+z3_status launch_multipoles_maps(const z3_index_s *idx, int group, int m_max, int prec, int64_t p0,
+                                 int64_t p1, void *A, int64_t ldA, size_t map_stride,
+                                 uint64_t *pair_total, hipStream_t s);
 
 // contraction and small kernels (z3_contract.hip)
 z3_status launch_contract(int64_t npiv, int m_max, int nbins, int prec, const void *A,

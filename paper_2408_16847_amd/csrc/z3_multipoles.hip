@@ -383,6 +383,221 @@ void k_multipoles(MultArgs a)
     }
 }
 
+// ---- many maps over one set of positions -------------------------------------------------
+//
+// Same decomposition (one lane per pivot, bins in order, band windows), but every lane
+// carries kMapGroup maps: the pair test, the bearing and the unit harmonics
+// cos(m phi), sin(m phi) (Chebyshev recurrences with unit seed) are computed once per
+// pair, and each map adds v_k cos(m phi) and v_k sin(m phi) with two FMAs per m.
+
+struct MapArgs {
+    const double *px, *py, *pz;   // index-order pivot positions
+    const double4 *rec;           // doubled-band records (x, y, z used)
+    const double *vgrp;           // [2n][kMapGroup] values of the map group
+    const double *wdbl;           // doubled-band weights or null
+    const int *cell_start;
+    const Band *bands;
+    int nbands;
+    double inv_h;
+    const EdgeTab *edges;
+    int nb;
+    int64_t p0, p1;
+    void *A;                      // per map [m+1][2][nb][ldA], maps map_stride elements apart
+    int64_t ldA;
+    size_t map_stride;
+    uint64_t *pair_total;
+    int nblocks;
+};
+
+template <int M>
+constexpr int maps_waves_per_eu()
+{
+    return M <= 6 ? 3 : 2;
+}
+
+template <int M, bool F32OUT>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(maps_waves_per_eu<M>())))
+void k_multipoles_maps(MapArgs a)
+{
+    constexpr int K = kMapGroup;
+    const int nblk = a.nblocks;
+    const int bid = blockIdx.x;
+    const int per = nblk / 8, rem = nblk % 8;
+    const int xcd = bid % 8, k8 = bid / 8;
+    const int lb = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + k8;
+    const int64_t wave0 = a.p0 + (int64_t)lb * kBlock + (threadIdx.x & ~(kWave - 1));
+    if (__builtin_amdgcn_readfirstlane((int)(wave0 >= a.p1))) return;
+    const int64_t p = a.p0 + (int64_t)lb * kBlock + threadIdx.x;
+    const bool valid = p < a.p1;
+    const int64_t pp = valid ? p : a.p1 - 1;
+
+    const double xp = a.px[pp], yp = a.py[pp], zp = a.pz[pp];
+    const double sinth = sqrt(xp * xp + yp * yp);
+    const double th = atan2(sinth, zp);
+    double ph = atan2(yp, xp);
+    if (ph < 0.0) ph += kTwoPi;
+    double sh, ch;
+    sincos(0.5 * th, &sh, &ch);
+    const float inv_sp = sinth > 0.0 ? (float)(1.0 / sinth) : INFINITY;
+    const float phf = (float)ph;
+    double nx = -zp * xp, ny = -zp * yp, nz = 1.0 - zp * zp;
+    double nn = sqrt(nx * nx + ny * ny + nz * nz);
+    if (nn < 1e-12) {
+        nx = 1.0 - xp * xp; ny = -xp * yp; nz = -xp * zp;
+        nn = sqrt(nx * nx + ny * ny + nz * nz);
+    }
+    nx /= nn; ny /= nn; nz /= nn;
+    const double ex = ny * zp - nz * yp, ey = nz * xp - nx * zp, ez = nx * yp - ny * xp;
+
+    const int64_t col = p - a.p0;
+    const int nb = a.nb;
+    const bool unit_w = a.wdbl == nullptr;
+    uint64_t my_pairs = 0;
+
+    for (int bin = 0; bin < nb; ++bin) {
+        const double elo = a.edges->e[bin], ehi = a.edges->e[bin + 1];
+        const double hav_out = a.edges->hav_out[bin + 1], hav_in = a.edges->hav_in[bin];
+        const double rad = a.edges->rad_out[bin + 1];
+        int klo = (int)floor((th - rad) * a.inv_h);
+        int khi = (int)floor((th + rad) * a.inv_h);
+        klo = max(klo, 0);
+        khi = min(khi, a.nbands - 1);
+        klo = __builtin_amdgcn_readfirstlane(wave_min(klo));
+        khi = __builtin_amdgcn_readfirstlane(wave_max(khi));
+
+        double Y[K][M + 1], Z[K][M + 1];
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int m = 0; m <= M; ++m) { Y[k][m] = 0.0; Z[k][m] = 0.0; }
+        double Wb = 0.0;
+        int cnt = 0;
+
+        for (int kb = klo; kb <= khi; ++kb) {
+            const Band bd = a.bands[kb];
+            if (bd.npts == 0) continue;
+            int s0, l0, s1, l1;
+            band_window(bd, a.cell_start, th, sh, ch, inv_sp, phf, hav_out, hav_in, s0, l0, s1, l1);
+            const int base = 2 * bd.pt_start;
+#pragma unroll
+            for (int seg = 0; seg < 2; ++seg) {
+                int j = base + (seg == 0 ? s0 : s1);
+                const int jend = j + (seg == 0 ? l0 : l1);
+                for (; j < jend; ++j) {
+                    const double4 r = a.rec[j];
+                    const double dx = r.x - xp, dy = r.y - yp, dz = r.z - zp;
+                    const double d2 = (dx * dx + dy * dy) + dz * dz;
+                    if (d2 >= elo && d2 < ehi) {
+                        cnt += 1;
+                        if (!unit_w) Wb += a.wdbl[j];
+                        const double4 vv = *reinterpret_cast<const double4 *>(a.vgrp + (size_t)j * K);
+                        const double v[K] = {vv.x, vv.y, vv.z, vv.w};
+                        const double u1 = fma(dx, nx, fma(dy, ny, dz * nz));
+                        const double u2 = fma(dx, ex, fma(dy, ey, dz * ez));
+                        double c, sn;
+                        unit_bearing(u1, u2, c, sn);
+#pragma unroll
+                        for (int k = 0; k < K; ++k) Y[k][0] += v[k];
+                        if constexpr (M >= 1) {
+                            const double tc = c + c;
+                            double t2 = 1.0, t1 = c, s2 = 0.0, s1 = sn;
+#pragma unroll
+                            for (int k = 0; k < K; ++k) {
+                                Y[k][1] = fma(v[k], t1, Y[k][1]);
+                                Z[k][1] = fma(v[k], s1, Z[k][1]);
+                            }
+#pragma unroll
+                            for (int m = 2; m <= M; ++m) {
+                                const double tm = fma(tc, t1, -t2);
+                                const double sm = fma(tc, s1, -s2);
+#pragma unroll
+                                for (int k = 0; k < K; ++k) {
+                                    Y[k][m] = fma(v[k], tm, Y[k][m]);
+                                    Z[k][m] = fma(v[k], sm, Z[k][m]);
+                                }
+                                t2 = t1; t1 = tm;
+                                s2 = s1; s1 = sm;
+                            }
+                        }
+                    }
+                }
+            }
+        }
+
+        if (valid) {
+            my_pairs += (uint64_t)cnt;
+            if (unit_w) Wb = (double)cnt;
+            const double inv = Wb > 0.0 ? 1.0 / Wb : 0.0;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+#pragma unroll
+                for (int m = 0; m <= M; ++m) {
+                    const double re = Y[k][m] * inv;
+                    const double im = m == 0 ? 0.0 : -Z[k][m] * inv;
+                    const size_t ore = k * a.map_stride + ((size_t)(2 * m) * nb + bin) * (size_t)a.ldA + col;
+                    const size_t oim = k * a.map_stride + ((size_t)(2 * m + 1) * nb + bin) * (size_t)a.ldA + col;
+                    if constexpr (F32OUT) {
+                        static_cast<float *>(a.A)[ore] = (float)re;
+                        static_cast<float *>(a.A)[oim] = (float)im;
+                    } else {
+                        static_cast<double *>(a.A)[ore] = re;
+                        static_cast<double *>(a.A)[oim] = im;
+                    }
+                }
+            }
+        }
+    }
+
+    if (a.pair_total) {
+        const uint64_t tot = wave_sum_u64(valid ? my_pairs : 0);
+        if ((threadIdx.x & (kWave - 1)) == 0 && tot) atomicAdd((unsigned long long *)a.pair_total, (unsigned long long)tot);
+    }
+}
+
+template <int M>
+static void launch_maps_m(bool f32out, const MapArgs &a, hipStream_t s)
+{
+    dim3 grid(a.nblocks), block(kBlock);
+    if (f32out) hipLaunchKernelGGL((k_multipoles_maps<M, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_multipoles_maps<M, false>), grid, block, 0, s, a);
+}
+
+z3_status launch_multipoles_maps(const z3_index_s *idx, int group, int m_max, int prec, int64_t p0, int64_t p1,
+                                 void *A, int64_t ldA, size_t map_stride, uint64_t *pair_total, hipStream_t s)
+{
+    int64_t nblk = (p1 - p0 + kBlock - 1) / kBlock;
+    if (nblk > 0x7fffffff) return fail(Z3_ERR_OVERFLOW, "too many pivot blocks");
+    MapArgs a;
+    a.px = idx->d_x; a.py = idx->d_y; a.pz = idx->d_z;
+    a.rec = idx->d_rec;
+    a.vgrp = idx->d_vgrp + (size_t)group * 2 * idx->n * kMapGroup;
+    a.wdbl = idx->unit_w ? nullptr : idx->d_wdbl;
+    a.cell_start = idx->d_cell_start;
+    a.bands = idx->d_bands;
+    a.nbands = idx->nbands;
+    a.inv_h = 1.0 / idx->band_h;
+    a.edges = idx->d_edges;
+    a.nb = idx->nbins;
+    a.p0 = p0; a.p1 = p1;
+    a.A = A; a.ldA = ldA; a.map_stride = map_stride;
+    a.pair_total = pair_total;
+    a.nblocks = (int)nblk;
+    const bool f32 = prec == Z3_PREC_MIXED;
+    hipEvent_t ev0;
+    profile_begin(s, &ev0);
+    switch (m_max) {
+#define Z3_CASE(MM) case MM: launch_maps_m<MM>(f32, a, s); break;
+        Z3_CASE(0) Z3_CASE(1) Z3_CASE(2) Z3_CASE(3) Z3_CASE(4) Z3_CASE(5) Z3_CASE(6) Z3_CASE(7)
+        Z3_CASE(8) Z3_CASE(9) Z3_CASE(10) Z3_CASE(11) Z3_CASE(12) Z3_CASE(13) Z3_CASE(14)
+        Z3_CASE(15) Z3_CASE(16)
+#undef Z3_CASE
+    default: return fail(Z3_ERR_UNSUPPORTED, "m_max=%d not compiled", m_max);
+    }
+    z3_status st = check_launch("k_multipoles_maps");
+    profile_end(s, ev0);
+    return st;
+}
+
 template <int M>
 static void launch_m(bool mixed, bool ids, const MultArgs &a, hipStream_t s)
 {

@@ -151,6 +151,29 @@ def estimate(idx: Index, m_max: int, prec="fp64", p0: int = 0, p1: int | None = 
     return z[..., 0] + 1j * z[..., 1], int(pairs.item())
 
 
+def estimate_maps_raw(idx: Index, m_max: int, prec="fp64", p0: int = 0, p1: int | None = None, zeta=None,
+                      pair_total=None, sum_w=None):
+    """Enqueue the estimator for every attached map at once: zeta [nmaps, m+1, nb, nb, 2] +=."""
+    p1 = idx.n if p1 is None else p1
+    if zeta is None:
+        zeta = torch.zeros((idx.nmaps, m_max + 1, idx.nbins, idx.nbins, 2), dtype=torch.float64, device="cuda")
+    _lib.call("z3_estimate_maps", idx.handle, m_max, PREC[prec], p0, p1, _ptr(zeta), _ptr(pair_total), _stream())
+    if sum_w is not None:
+        _lib.call("z3_pivot_weight_sum", idx.handle, p0, p1, _ptr(sum_w), _stream())
+    return zeta
+
+
+def estimate_maps(idx: Index, m_max: int, prec="fp64", p0: int = 0, p1: int | None = None):
+    """Normalised zeta_m of every attached map: complex128 numpy [nmaps, m+1, nb, nb], and the pair count."""
+    zeta = torch.zeros((idx.nmaps, m_max + 1, idx.nbins, idx.nbins, 2), dtype=torch.float64, device="cuda")
+    pairs = torch.zeros(1, dtype=torch.int64, device="cuda")
+    sw = torch.zeros(1, dtype=torch.float64, device="cuda")
+    estimate_maps_raw(idx, m_max, prec, p0, p1, zeta, pairs, sw)
+    _lib.call("z3_finalize", idx.nmaps, m_max, idx.nbins, _ptr(zeta), _ptr(sw), _stream())
+    z = zeta.cpu().numpy()
+    return z[..., 0] + 1j * z[..., 1], int(pairs.item())
+
+
 def estimate_pivots_raw(idx: Index, piv_xyz, piv_x, piv_w=None, m_max: int = 0, prec="fp64", p0: int = 0,
                         p1: int | None = None, map_index: int = 0, zeta=None, pair_total=None, sum_w=None):
     """Enqueue the estimator for an external pivot catalogue (piv_xyz [3, P], piv_x [P],

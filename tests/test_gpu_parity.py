@@ -248,3 +248,26 @@ def test_approximate_search_degraded_neighbours():
         e = G.err_m(z, zo)
         G.say("err_m", prec, e.max())
         assert e.max() < tol
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("mixed", 1e-6)])
+def test_many_maps_share_geometry(prec, tol):
+    """Six maps over one HEALPix catalogue (a full and a partial map group) against the oracle."""
+    G.say("case: many maps", prec)
+    xyz_t = ring_centres(32)
+    xyz = xyz_t.numpy()
+    cfg = CONFIGS["nside512"]
+    xs = np.stack([make_values(cfg, xyz_t, seed=s).numpy() for s in range(6)])
+    w = np.ones(xyz.shape[1])
+    E = chord2_edges(theta_edges(math.radians(3.0), math.radians(20.0), 5, True))
+    idx = G.build(xyz, xs, E)
+    zs, pairs = z3.estimate_maps(idx, 10, prec=prec)
+    assert zs.shape == (6, 11, 5, 5)
+    for s in range(6):
+        zo, po = cpu.estimate(xyz, xyz, w, xs[s], E, 10, w, xs[s])
+        assert pairs == po
+        e = G.err_m(zs[s], zo)
+        assert e.max() < tol, (s, e)
+    # a single map through the one-map kernel agrees with its slot in the batch
+    z1, _ = z3.estimate(idx, 10, prec=prec, map_index=4)
+    assert G.err_m(zs[4], z1).max() < (1e-12 if prec == "fp64" else 1e-6)
