@@ -78,6 +78,8 @@ def main():
     ap.add_argument("--approx", action="store_true",
                     help="approximate search: neighbours from the Nside/2 averaged map, all pivots kept")
     ap.add_argument("--save-zeta", default="", help="write the zeta_m of each precision to this .npz")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="each step also back-propagates L = sum |zeta - t|^2 (random targets) to the field")
     ap.add_argument("--cpu-sample", type=int, default=-1, help="oracle pivots (-1: automatic, 0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (for HBM counter calibration)")
@@ -126,10 +128,41 @@ def main():
     M = cfg.m_max
     n = xyz.shape[1]
 
+    grads = []
+    _tgt = {}
+    _pairs = {}
+
+    def targets(zt):
+        # random FP64 targets t = N(0,1) * rms(zeta_m) per entry (seeded), fixed across steps
+        if "t" not in _tgt:
+            rng = np.random.default_rng(3_000_000)
+            rms = zt.detach().pow(2).mean(dim=tuple(range(zt.dim() - 3, zt.dim())), keepdim=True).sqrt()
+            _tgt["t"] = torch.from_numpy(rng.normal(size=tuple(zt.shape))).cuda() * rms
+        return _tgt["t"]
+
+    def pairs_of(idx, prec):
+        # pair count of the workload, measured once outside the timed steps' arithmetic
+        if prec not in _pairs:
+            pt = torch.zeros(1, dtype=torch.int64, device="cuda")
+            z3.accumulate(idx, 0, 0, idx.n, prec=prec, want_a=False, pair_total=pt)
+            _pairs[prec] = int(pt.item())
+        return _pairs[prec]
+
     def step(prec):
         zeta = torch.zeros((M + 1, cfg.nbins, cfg.nbins, 2), dtype=torch.float64, device="cuda")
         pairs = torch.zeros(1, dtype=torch.int64, device="cuda")
         sw = torch.zeros(1, dtype=torch.float64, device="cuda")
+        if args.adjoint:
+            idx = z3.Index(xyz, E)
+            xg = x.clone().requires_grad_(True)
+            zt = z3.Zeta3Fn.apply(xg, idx, M, prec)
+            loss = ((zt - targets(zt)) ** 2).sum()
+            loss.backward()
+            grads.append(float(xg.grad.abs().max()))
+            zh = zt.detach().cpu().numpy()
+            npairs = pairs_of(idx, prec)
+            idx.free()
+            return zh[..., 0] + 1j * zh[..., 1], npairs
         if cfg.nmaps > 1:
             zeta = torch.zeros((cfg.nmaps, M + 1, cfg.nbins, cfg.nbins, 2), dtype=torch.float64, device="cuda")
             idx = z3.Index(xyz, E)
@@ -176,6 +209,8 @@ def main():
     r = res[main_prec]
     updates = r["pairs"] * (M + 1) * cfg.nmaps
     value = updates / r["s_per_step"]
+    if args.adjoint:
+        log(f"[bench] adjoint: max |dL/dx| {max(grads):.3g}")
     launches_per_step = r["kernel_launches"] / args.steps
     kern_s_per_step = r["kernel_ms_total"] / args.steps / 1e3
     achieved = FLOPS_PER_UPDATE * updates / kern_s_per_step / 1e12
@@ -192,7 +227,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if main_prec == "fp64" else "f64 geometry + f32 multipoles/MFMA",
         "data": "synthetic",
-        "config": {"workload": cfg.name + ("+approx" if nbr else ""), "npoints": n, "nmaps": cfg.nmaps, "nbins": cfg.nbins, "m_max": M,
+        "config": {"workload": cfg.name + ("+approx" if nbr else "") + ("+adjoint" if args.adjoint else ""),
+                   "npoints": n, "nmaps": cfg.nmaps, "nbins": cfg.nbins, "m_max": M,
                    "theta_arcmin": [cfg.theta_min * 10800 / np.pi, cfg.theta_max * 10800 / np.pi],
                    "log_bins": cfg.log_bins, "precision": main_prec, "pairs": r["pairs"]},
         "roofline": {"bound": "alu", "kernel": "k_multipoles", "achieved": achieved,

@@ -169,6 +169,19 @@ z3_status z3_estimate_pivots(z3_index idx, int map, int64_t npiv, const double *
                              int64_t p0, int64_t p1, double *zeta, uint64_t *pair_total,
                              double *sum_w, void *stream);
 
+/*
+ * Adjoint of the estimator for map `map` and pivots [p0, p1) (derived from eqs.
+ * Xm.binned and zetamEst with the weights held fixed): for a real loss L and
+ *   G [m_max+1][nbins][nbins][2] = (dL/dRe zeta, dL/dIm zeta),
+ * where zeta = scale * sum_p w_p x_p X_p X_p^H over the given pivots,
+ *   grad_x [n] += dL/dx  (catalogue order, FP64).
+ * Pass scale = 1 / sum_p w_p for the normalised estimator.  The multipoles are recomputed
+ * per pivot chunk; neighbour contributions are added with FP64 atomics, so the last bits
+ * may vary between runs.  FP64 throughout.
+ */
+z3_status z3_adjoint(z3_index idx, int map, int m_max, int64_t p0, int64_t p1, const double *G,
+                     double scale, double *grad_x, void *stream);
+
 /* sum_p w_p over pivots [p0, p1), FP64, out[0] += . */
 z3_status z3_pivot_weight_sum(z3_index idx, int64_t p0, int64_t p1, double *out, void *stream);
 

@@ -1,0 +1,254 @@
+// Adjoint of the estimator with respect to the field values (vector-Jacobian product).
+//
+// For a real loss L of zeta and G_m(b1, b2) = dL/dRe zeta + i dL/dIm zeta, with
+// v_p = w_p x_p and X_p(b) = sum_{j in b(p)} c_pj x_j, c_pj = w_j exp(-i m phi_pj) / W_{p,b}
+// (eqs. Xm.binned and zetamEst), the gradient of L(scale * sum_p v_p X_p X_p^H) is
+//
+//   dL/dx_k = scale * w_k Re sum_m sum_{b1 b2} conj(G(b1,b2)) X_k(b1) conj(X_k(b2))       (pivot)
+//           + scale * sum_{p: k in bin a of p} v_p Re sum_m c_pk D_p(a),                     (neighbour)
+//   D_p(a)  = sum_b (conj(G(a,b)) + G(b,a)) conj(X_p(b)).
+//
+// Per pivot chunk: (1) the multipole kernel recomputes X_p and W_{p,b} (nothing is kept
+// between chunks); (2) k_adjoint_prep forms D_p(a) / W_{p,a} and adds the pivot term;
+// (3) k_adjoint_scatter walks the same bin/band windows as the forward kernel, rebuilds
+// cos(m phi), sin(m phi) per pair and adds the neighbour term to the neighbour's gradient
+// with an FP64 atomic (index order; permuted to catalogue order at the end).  The atomics
+// make the last bits of the gradient depend on scheduling.
+#include "z3_internal.h"
+#include "z3_device.h"
+
+namespace z3 {
+
+struct PrepArgs {
+    const double *A;   // [m+1][2][nb][P] X_p (normalised)
+    const double *W;   // [nb][P]
+    const double *G;   // [m+1][nb][nb][2]
+    const double *v;   // [P] pivot w x
+    const double *w;   // [P] pivot weights
+    double *D;         // [m+1][2][nb][P] D_p(a) / W_{p,a}
+    double *grad;      // index-order gradient, pivot term added for p in [p0, p0 + P)
+    int64_t P;
+    int nb, M;
+    double scale;
+};
+
+__global__ __launch_bounds__(256) void k_adjoint_prep(PrepArgs a)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.P) return;
+    const int nb = a.nb;
+    const size_t P = (size_t)a.P;
+    double piv = 0.0;
+    for (int m = 0; m <= a.M; ++m) {
+        const double *xr = a.A + (size_t)(2 * m) * nb * P + p;
+        const double *xi = a.A + (size_t)(2 * m + 1) * nb * P + p;
+        const double *g = a.G + (size_t)m * nb * nb * 2;
+        for (int ai = 0; ai < nb; ++ai) {
+            // E(a) = sum_b conj(G(a,b)) conj(X(b));  F(a) = sum_b G(b,a) conj(X(b))
+            double er = 0.0, ei = 0.0, fr = 0.0, fi = 0.0;
+            for (int b = 0; b < nb; ++b) {
+                const double ur = xr[(size_t)b * P], ui = -xi[(size_t)b * P];  // conj(X(b))
+                const double gr = g[((size_t)ai * nb + b) * 2], gi = -g[((size_t)ai * nb + b) * 2 + 1];
+                er = fma(gr, ur, fma(-gi, ui, er));
+                ei = fma(gr, ui, fma(gi, ur, ei));
+                const double hr = g[((size_t)b * nb + ai) * 2], hi = g[((size_t)b * nb + ai) * 2 + 1];
+                fr = fma(hr, ur, fma(-hi, ui, fr));
+                fi = fma(hr, ui, fma(hi, ur, fi));
+            }
+            const double x_r = xr[(size_t)ai * P], x_i = xi[(size_t)ai * P];
+            piv += x_r * er - x_i * ei;  // Re(X(a) E(a))
+            const double wa = a.W[(size_t)ai * P + p];
+            const double inv = wa > 0.0 ? 1.0 / wa : 0.0;
+            a.D[((size_t)(2 * m) * nb + ai) * P + p] = (er + fr) * inv;
+            a.D[((size_t)(2 * m + 1) * nb + ai) * P + p] = (ei + fi) * inv;
+        }
+    }
+    a.grad[p] += a.scale * a.w[p] * piv;
+}
+
+struct ScatterArgs {
+    const double *px, *py, *pz;   // index-order pivot positions
+    const double *pv;             // index-order w x of the map (pivot values)
+    const double4 *rec;           // doubled-band records
+    const double *wdbl;           // doubled-band weights or null
+    const int *cell_start;
+    const Band *bands;
+    int nbands;
+    double inv_h;
+    const EdgeTab *edges;
+    int nb;
+    int64_t p0, p1;
+    const double *D;              // [m+1][2][nb][ldD] for pivots [p0, p1)
+    int64_t ldD;
+    double *grad;                 // index-order gradient
+    double scale;
+    int nblocks;
+};
+
+template <int M>
+constexpr int adjoint_waves_per_eu()
+{
+    return M <= 10 ? 4 : (M <= 13 ? 3 : 2);
+}
+
+template <int M>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(adjoint_waves_per_eu<M>())))
+void k_adjoint_scatter(ScatterArgs a)
+{
+    const int lb = xcd_block(blockIdx.x, a.nblocks);
+    const int64_t wave0 = a.p0 + (int64_t)lb * kBlock + (threadIdx.x & ~(kWave - 1));
+    if (__builtin_amdgcn_readfirstlane((int)(wave0 >= a.p1))) return;
+    const int64_t p = a.p0 + (int64_t)lb * kBlock + threadIdx.x;
+    const bool valid = p < a.p1;
+    const int64_t pp = valid ? p : a.p1 - 1;
+    const PivotFrame f = pivot_frame(a.px[pp], a.py[pp], a.pz[pp]);
+    const double vp = valid ? a.scale * a.pv[pp] : 0.0;  // idle lanes add nothing
+    const int64_t col = pp - a.p0;
+    const int nb = a.nb;
+    const bool unit_w = a.wdbl == nullptr;
+
+    for (int bin = 0; bin < nb; ++bin) {
+        const double elo = a.edges->e[bin], ehi = a.edges->e[bin + 1];
+        const double hav_out = a.edges->hav_out[bin + 1], hav_in = a.edges->hav_in[bin];
+        int klo, khi;
+        band_range(f.th, a.edges->rad_out[bin + 1], a.inv_h, a.nbands, klo, khi);
+        double Dr[M + 1], Di[M + 1];
+#pragma unroll
+        for (int m = 0; m <= M; ++m) {
+            Dr[m] = vp * a.D[((size_t)(2 * m) * nb + bin) * (size_t)a.ldD + col];
+            Di[m] = vp * a.D[((size_t)(2 * m + 1) * nb + bin) * (size_t)a.ldD + col];
+        }
+        for (int k = klo; k <= khi; ++k) {
+            const Band bd = a.bands[k];
+            if (bd.npts == 0) continue;
+            int s0, l0, s1, l1;
+            band_window(bd, a.cell_start, f.th, f.sh, f.ch, f.inv_sp, f.phf, hav_out, hav_in, s0, l0, s1, l1);
+            const int base = 2 * bd.pt_start;
+#pragma unroll
+            for (int seg = 0; seg < 2; ++seg) {
+                int j = base + (seg == 0 ? s0 : s1);
+                const int jend = j + (seg == 0 ? l0 : l1);
+                for (; j < jend; ++j) {
+                    const double4 r = a.rec[j];
+                    const double dx = r.x - f.xp, dy = r.y - f.yp, dz = r.z - f.zp;
+                    const double d2 = (dx * dx + dy * dy) + dz * dz;
+                    if (d2 >= elo && d2 < ehi) {
+                        const double u1 = fma(dx, f.nx, fma(dy, f.ny, dz * f.nz));
+                        const double u2 = fma(dx, f.ex, fma(dy, f.ey, dz * f.ez));
+                        double c, sn;
+                        unit_bearing(u1, u2, c, sn);
+                        // sum_m Re(exp(-i m phi) D(m)) = sum_m cos(m phi) Re D + sin(m phi) Im D
+                        double acc = Dr[0];
+                        if constexpr (M >= 1) {
+                            const double tc = c + c;
+                            double t2 = 1.0, t1 = c, s2 = 0.0, s1 = sn;
+                            acc = fma(t1, Dr[1], fma(s1, Di[1], acc));
+#pragma unroll
+                            for (int m = 2; m <= M; ++m) {
+                                const double tm = fma(tc, t1, -t2);
+                                const double sm = fma(tc, s1, -s2);
+                                acc = fma(tm, Dr[m], fma(sm, Di[m], acc));
+                                t2 = t1; t1 = tm;
+                                s2 = s1; s1 = sm;
+                            }
+                        }
+                        if (!unit_w) acc *= a.wdbl[j];
+                        int t = j - base;
+                        if (t >= bd.npts) t -= bd.npts;
+                        atomicAdd(&a.grad[bd.pt_start + t], acc);
+                    }
+                }
+            }
+        }
+    }
+}
+
+__global__ void k_grad_to_catalogue(int64_t n, const int *perm, const double *gs, double *grad)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) grad[perm[i]] += gs[i];
+}
+
+template <int M>
+static void launch_scatter_m(const ScatterArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_adjoint_scatter<M>, dim3(a.nblocks), dim3(kBlock), 0, s, a);
+}
+
+z3_status adjoint_impl(z3_index idx, int map, int m_max, int64_t p0, int64_t p1, const double *G, double scale,
+                       double *grad_x, hipStream_t s, int64_t chunk)
+{
+    const int nb = idx->nbins;
+    if (chunk > p1 - p0) chunk = ((p1 - p0 + kBlock - 1) / kBlock) * kBlock;
+    const size_t per_piv = (size_t)(m_max + 1) * 2 * nb;
+    void *wa = nullptr, *wd = nullptr, *ww = nullptr, *wg = nullptr;
+    z3_status st = scratch_alloc(&wa, (size_t)chunk * per_piv * sizeof(double), s);
+    if (st == Z3_OK) st = scratch_alloc(&wd, (size_t)chunk * per_piv * sizeof(double), s);
+    if (st == Z3_OK) st = scratch_alloc(&ww, (size_t)chunk * nb * sizeof(double), s);
+    if (st == Z3_OK) st = scratch_alloc(&wg, (size_t)idx->n * sizeof(double), s);
+    if (st == Z3_OK) st = launch_fill(static_cast<double *>(wg), idx->n, 0.0, s);
+    double *gs = static_cast<double *>(wg);
+    const double *vmap = idx->d_v + (size_t)map * idx->n;
+    for (int64_t c0 = p0; c0 < p1 && st == Z3_OK; c0 += chunk) {
+        const int64_t c1 = c0 + chunk < p1 ? c0 + chunk : p1;
+        const int64_t P = c1 - c0;
+        st = launch_multipoles(idx, Pivots{idx->d_x, idx->d_y, idx->d_z}, map, m_max, Z3_PREC_FP64, Z3_NORM_BIN, c0,
+                               c1, wa, P, static_cast<double *>(ww), nullptr, nullptr, nullptr, s);
+        if (st != Z3_OK) break;
+        PrepArgs pa;
+        pa.A = static_cast<const double *>(wa);
+        pa.W = static_cast<const double *>(ww);
+        pa.G = G;
+        pa.v = vmap + c0;
+        pa.w = idx->d_w + c0;
+        pa.D = static_cast<double *>(wd);
+        pa.grad = gs + c0;
+        pa.P = P;
+        pa.nb = nb;
+        pa.M = m_max;
+        pa.scale = scale;
+        hipLaunchKernelGGL(k_adjoint_prep, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, pa);
+        if ((st = check_launch("k_adjoint_prep")) != Z3_OK) break;
+        ScatterArgs sa;
+        sa.px = idx->d_x; sa.py = idx->d_y; sa.pz = idx->d_z;
+        sa.pv = vmap;
+        sa.rec = idx->d_rec + (size_t)map * 2 * idx->n;
+        sa.wdbl = idx->unit_w ? nullptr : idx->d_wdbl;
+        sa.cell_start = idx->d_cell_start;
+        sa.bands = idx->d_bands;
+        sa.nbands = idx->nbands;
+        sa.inv_h = 1.0 / idx->band_h;
+        sa.edges = idx->d_edges;
+        sa.nb = nb;
+        sa.p0 = c0; sa.p1 = c1;
+        sa.D = static_cast<const double *>(wd);
+        sa.ldD = P;
+        sa.grad = gs;
+        sa.scale = scale;
+        sa.nblocks = (int)((P + kBlock - 1) / kBlock);
+        hipEvent_t ev0;
+        profile_begin(s, &ev0);
+        switch (m_max) {
+#define Z3_CASE(MM) case MM: launch_scatter_m<MM>(sa, s); break;
+            Z3_CASE(0) Z3_CASE(1) Z3_CASE(2) Z3_CASE(3) Z3_CASE(4) Z3_CASE(5) Z3_CASE(6) Z3_CASE(7)
+            Z3_CASE(8) Z3_CASE(9) Z3_CASE(10) Z3_CASE(11) Z3_CASE(12) Z3_CASE(13) Z3_CASE(14)
+            Z3_CASE(15) Z3_CASE(16)
+#undef Z3_CASE
+        default: st = fail(Z3_ERR_UNSUPPORTED, "m_max=%d not compiled", m_max);
+        }
+        if (st == Z3_OK) st = check_launch("k_adjoint_scatter");
+        profile_end(s, ev0);
+    }
+    if (st == Z3_OK && idx->n > 0) {
+        hipLaunchKernelGGL(k_grad_to_catalogue, dim3((unsigned)((idx->n + 255) / 256)), dim3(256), 0, s, idx->n,
+                           idx->d_perm, gs, grad_x);
+        st = check_launch("k_grad_to_catalogue");
+    }
+    scratch_free(wg, s);
+    scratch_free(ww, s);
+    scratch_free(wd, s);
+    scratch_free(wa, s);
+    return st;
+}
+
+}  // namespace z3

@@ -396,6 +396,18 @@ Z3_API z3_status z3_estimate_pivots(z3_index idx, int map, int64_t npiv, const d
     return st;
 }
 
+Z3_API z3_status z3_adjoint(z3_index idx, int map, int m_max, int64_t p0, int64_t p1, const double *G,
+                            double scale, double *grad_x, void *stream)
+{
+    z3_status st = check_common("z3_adjoint", idx, map, m_max, Z3_PREC_FP64, p0, p1);
+    if (st != Z3_OK) return st;
+    if (!std::isfinite(scale)) return fail(Z3_ERR_INVALID_ARG, "z3_adjoint: scale is not finite");
+    if (p1 == p0) return Z3_OK;
+    if (!G || !grad_x) return fail(Z3_ERR_INVALID_ARG, "z3_adjoint: G or grad_x is NULL");
+    return adjoint_impl(idx, map, m_max, p0, p1, G, scale, grad_x, as_stream(stream),
+                        chunk_pivots(idx, m_max, Z3_PREC_FP64) / 2);
+}
+
 Z3_API z3_status z3_pivot_weight_sum(z3_index idx, int64_t p0, int64_t p1, double *out, void *stream)
 {
     if (!idx) return fail(Z3_ERR_INVALID_ARG, "z3_pivot_weight_sum: idx is NULL");

@@ -216,6 +216,20 @@ z3_status launch_pivot_values(const double *w, const double *x, int64_t n, doubl
     return check_launch("k_pivot_values");
 }
 
+__global__ void k_fill_value(double *p, int64_t n, double value)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = value;
+}
+
+// Fills with a kernel rather than a memset, so that the call can sit in a captured graph.
+z3_status launch_fill(double *p, int64_t n, double value, hipStream_t s)
+{
+    if (n <= 0) return Z3_OK;
+    hipLaunchKernelGGL(k_fill_value, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, value);
+    return check_launch("k_fill_value");
+}
+
 __global__ void k_add_scalar(double *out, double value)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) out[0] += value;

@@ -105,6 +105,11 @@ size_t contract_partial_bytes(int64_t npiv, int m_max, int nbins);
 z3_status launch_weight_sum(const double *w, int64_t n, double *out, hipStream_t s);
 z3_status launch_pivot_values(const double *w, const double *x, int64_t n, double *v, hipStream_t s);
 z3_status launch_add_scalar(double *out, double value, hipStream_t s);
+z3_status launch_fill(double *p, int64_t n, double value, hipStream_t s);
+
+// adjoint (z3_adjoint.hip)
+z3_status adjoint_impl(z3_index idx, int map, int m_max, int64_t p0, int64_t p1, const double *G,
+                       double scale, double *grad_x, hipStream_t s, int64_t chunk);
 z3_status launch_finalize(int nmaps, int m_max, int nbins, double *zeta, const double *sum_w,
                           hipStream_t s);
 z3_status launch_resum(int m_max, int nbins, const double *zeta, int nphi, const double *phi,

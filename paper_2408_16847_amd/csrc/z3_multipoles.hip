@@ -23,6 +23,7 @@
 // polynomial families so that no trigonometric function is evaluated per pair.  Scaling
 // both recurrences by w_j x_j folds the field value in: two FMAs and two adds per m.
 #include "z3_internal.h"
+#include "z3_device.h"
 
 namespace z3 {
 
@@ -47,158 +48,6 @@ struct MultArgs {
     uint64_t *pair_total;
     int nblocks;
 };
-
-__device__ __forceinline__ int wave_min(int v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
-    return v;
-}
-
-__device__ __forceinline__ int wave_max(int v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
-    return v;
-}
-
-__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v)
-{
-    unsigned lo = (unsigned)v, hi = (unsigned)(v >> 32);
-    // two 32-bit halves, carried through a 64-bit sum at every step
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        unsigned olo = __shfl_xor(lo, o, 64), ohi = __shfl_xor(hi, o, 64);
-        uint64_t s = ((uint64_t)hi << 32 | lo) + ((uint64_t)ohi << 32 | olo);
-        lo = (unsigned)s;
-        hi = (unsigned)(s >> 32);
-    }
-    return (uint64_t)hi << 32 | lo;
-}
-
-__device__ __forceinline__ uint64_t mix64(uint64_t v)
-{  // SplitMix64 finaliser (Steele, Lea & Flood 2014)
-    v += 0x9E3779B97F4A7C15ull;
-    v = (v ^ (v >> 30)) * 0xBF58476D1CE4E5B9ull;
-    v = (v ^ (v >> 27)) * 0x94D049BB133111EBull;
-    return v ^ (v >> 31);
-}
-
-__device__ __forceinline__ int floor_div(int a, int c) { return a >= 0 ? a / c : -((-a + c - 1) / c); }
-
-// Logical cell range [ca, cb] of a band (indices may run one band-length below 0 or
-// above ncell to express wrap-around) -> start (in [0, npts)) and length in points.
-__device__ __forceinline__ void cells_to_points(const Band &bd, const int *cell_start, int ca, int cb,
-                                                int &s, int &len)
-{
-    if (cb < ca) {
-        s = 0;
-        len = 0;
-        return;
-    }
-    const int C = bd.ncell, np = bd.npts;
-    // windows span at most one band length around [0, C); the clamps only matter for
-    // non-finite inputs and keep every index inside the band regardless
-    ca = max(ca, -C);
-    cb = min(cb, 2 * C - 1);
-    const int q0 = floor_div(ca, C), r0 = ca - q0 * C;
-    const int q1 = floor_div(cb + 1, C), r1 = cb + 1 - q1 * C;
-    const int st = cell_start[bd.cell_off + r0] - bd.pt_start + q0 * np;
-    const int en = cell_start[bd.cell_off + r1] - bd.pt_start + q1 * np;
-    len = min(max(en - st, 0), np);
-    s = st < 0 ? st + np : (st >= np ? st - np : st);
-    s = min(max(s, 0), np - 1);
-}
-
-// Longitude window(s) of band `bd` that can hold points at angular distance in
-// [R_in, R_out) of the pivot, with hav(R) = E/4 (hav_in, hav_out already carry their
-// rounding guards).  Spherical law of haversines, for a point at colatitude t in the
-// band and longitude offset dphi:
-//     hav(d) = hav(t - th_p) + sin(th_p) sin(t) hav(dphi)
-// so d < R_out needs hav(dphi) < (hav_out - min hav(t - th_p)) / (sin th_p * min sin t),
-// and d >= R_in needs hav(dphi) >= (hav_in - max hav(t - th_p)) / (sin th_p * max sin t).
-__device__ __forceinline__ void band_window(const Band &bd, const int *cell_start, double th, double sh,
-                                            double ch, float inv_sp, float phf, double hav_out,
-                                            double hav_in, int &s0, int &l0, int &s1, int &l1)
-{
-    s0 = l0 = s1 = l1 = 0;
-    const double dlo = bd.sh_lo * ch - bd.ch_lo * sh;  // sin((th_lo - th_p) / 2)
-    const double dhi = bd.sh_hi * ch - bd.ch_hi * sh;  // sin((th_hi - th_p) / 2)
-    const double hlo = dlo * dlo, hhi = dhi * dhi;
-    const double hmin = th < bd.th_lo ? hlo : (th > bd.th_hi ? hhi : 0.0);
-    const double hmax = fmax(hlo, hhi);
-    const double num_out = hav_out - hmin;
-    if (!(num_out > 0.0)) return;  // the band lies entirely beyond R_out
-    const double num_in = hav_in - hmax;
-    const int C = bd.ncell;
-    const float cpr = bd.cells_per_rad;
-
-    const float q_out = (float)num_out * inv_sp * bd.inv_smin * (1.0f + 1e-5f);
-    bool full = !(q_out < 1.0f);
-    float dout = 0.0f;
-    if (!full) {
-        dout = 2.0f * asinf(sqrtf(q_out)) * (1.0f + 4e-6f) + 4e-6f;
-        full = dout >= 3.14159265f;
-    }
-    bool excl = false;
-    float din = 0.0f;
-    if (num_in > 0.0) {
-        const float q_in = (float)num_in * inv_sp * bd.inv_smax * (1.0f - 1e-5f);
-        if (!(q_in < 1.0f)) return;  // the whole band lies inside R_in
-        din = 2.0f * asinf(sqrtf(q_in)) * (1.0f - 4e-6f) - 4e-6f;
-        excl = din > 0.0f;
-    }
-    // cells entirely inside the excluded arc (phf - din, phf + din)
-    int es = 0, ee = -1;
-    const float lim = 2.0f * (float)C;  // window bounds stay within +-2 band lengths
-    if (excl) {
-        es = (int)fminf(fmaxf(ceilf((phf - din) * cpr), -lim), lim);
-        ee = (int)fminf(fmaxf(floorf((phf + din) * cpr), -lim), lim) - 1;
-    }
-    int ca0 = 0, cb0 = -1, ca1 = 0, cb1 = -1;
-    if (!full) {
-        const int clo = (int)fminf(fmaxf(floorf((phf - dout) * cpr), -lim), lim);
-        const int chi = (int)fminf(fmaxf(floorf((phf + dout) * cpr), -lim), lim);
-        if (chi - clo + 1 >= C) {
-            full = true;
-        } else {
-            if (excl) {
-                es = max(es, clo);
-                ee = min(ee, chi);
-            }
-            if (excl && es <= ee) {
-                ca0 = clo; cb0 = es - 1;
-                ca1 = ee + 1; cb1 = chi;
-            } else {
-                ca0 = clo; cb0 = chi;
-            }
-        }
-    }
-    if (full) {
-        if (excl && es <= ee) {
-            if (ee - es + 1 >= C) return;
-            ca0 = ee + 1; cb0 = es - 1 + C;
-        } else {
-            ca0 = 0; cb0 = C - 1;
-        }
-        ca1 = 0; cb1 = -1;
-    }
-    cells_to_points(bd, cell_start, ca0, cb0, s0, l0);
-    cells_to_points(bd, cell_start, ca1, cb1, s1, l1);
-}
-
-// Unit-length bearing (c, s) = (u1, u2) / |u| with FP64 accuracy: FP32 reciprocal
-// square root refined by one FP64 Newton step (relative error ~1e-14).  For every pair in
-// range |u|^2 >= E_0 (1 - E_nb / 4) > 0, so the clamp only guards non-finite inputs.
-__device__ __forceinline__ void unit_bearing(double u1, double u2, double &c, double &s)
-{
-    const double q = fmax(fma(u1, u1, u2 * u2), 1e-37);
-    const double r0 = (double)__builtin_amdgcn_rsqf((float)q);
-    const double e = fma(-q * r0, r0, 1.0);  // 1 - q r0^2
-    const double r = fma(0.5 * e, r0, r0);
-    c = u1 * r;
-    s = u2 * r;
-}
 
 // Occupancy target of the multipole kernel (waves per SIMD that the register allocation
 // aims for).  Measured on MI355X at m_max = 10: 4 waves beat 3 by ~15% despite a couple

@@ -202,6 +202,52 @@ def estimate_pivots(idx: Index, piv_xyz, piv_x, piv_w=None, m_max: int = 0, prec
     return z[..., 0] + 1j * z[..., 1], int(pairs.item())
 
 
+def adjoint(idx: Index, G, scale: float, m_max: int, map_index: int = 0, p0: int = 0, p1: int | None = None,
+            grad=None):
+    """grad_x [n] += dL/dx for G = (dL/dRe zeta, dL/dIm zeta) [m+1, nb, nb, 2] of
+    zeta = scale * sum_p v_p X_p X_p^H over pivots [p0, p1)."""
+    p1 = idx.n if p1 is None else p1
+    if grad is None:
+        grad = torch.zeros(idx.n, dtype=torch.float64, device="cuda")
+    G = _dev(G)
+    _lib.call("z3_adjoint", idx.handle, map_index, m_max, p0, p1, _ptr(G), float(scale), _ptr(grad), _stream())
+    return grad
+
+
+class Zeta3Fn(torch.autograd.Function):
+    """zeta_m = estimator(x) as a differentiable torch op.
+
+    forward(x, idx, m_max, prec): x [n] or [nmaps, n] field values (catalogue order) are
+    attached to `idx`, and the normalised zeta [m+1, nb, nb, 2] (or [nmaps, ...]) is
+    returned.  backward runs the library's adjoint kernels (FP64) on the same index, so
+    the index must not receive other values between forward and backward.
+    """
+
+    @staticmethod
+    def forward(ctx, x, idx, m_max, prec="fp64"):
+        idx.set_values(x.detach())
+        sw = torch.zeros(1, dtype=torch.float64, device="cuda")
+        if idx.nmaps > 1:
+            zeta = estimate_maps_raw(idx, m_max, prec, sum_w=sw)
+        else:
+            zeta = estimate_raw(idx, m_max, prec, sum_w=sw)
+        scale = 1.0 / float(sw.item()) if float(sw.item()) != 0.0 else 0.0
+        ctx.idx, ctx.m_max, ctx.scale, ctx.shape = idx, m_max, scale, x.shape
+        return zeta * scale
+
+    @staticmethod
+    def backward(ctx, g):
+        idx = ctx.idx
+        g = g.contiguous()
+        if len(ctx.shape) == 2:
+            grad = torch.zeros(ctx.shape, dtype=torch.float64, device="cuda")
+            for k in range(ctx.shape[0]):
+                adjoint(idx, g[k], ctx.scale, ctx.m_max, map_index=k, grad=grad[k])
+        else:
+            grad = adjoint(idx, g, ctx.scale, ctx.m_max)
+        return grad, None, None, None
+
+
 def resum(zeta, phi):
     """zeta(b1, b2, phi) from zeta_m (complex [m+1, nb, nb] or a [m+1, nb, nb, 2] tensor)."""
     if not isinstance(zeta, torch.Tensor):
