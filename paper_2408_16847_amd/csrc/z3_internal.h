@@ -12,7 +12,10 @@
 namespace z3 {
 
 constexpr int kBlock = 256;      // threads per block of the multipole kernel (4 wave64s)
-constexpr int kCellsPerPoint = 4;  // longitude cells per point of a band
+#ifndef Z3_CELLS_PER_POINT
+#define Z3_CELLS_PER_POINT 4
+#endif
+constexpr int kCellsPerPoint = Z3_CELLS_PER_POINT;  // longitude cells per point of a band (tuning)
 constexpr int kMapGroup = 4;       // maps carried per lane by the many-map kernel
 constexpr int kWave = 64;
 constexpr double kPi = 3.14159265358979323846;
