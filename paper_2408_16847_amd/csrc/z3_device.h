@@ -41,8 +41,6 @@ __device__ __forceinline__ uint64_t mix64(uint64_t v)
     return v ^ (v >> 31);
 }
 
-__device__ __forceinline__ int floor_div(int a, int c) { return a >= 0 ? a / c : -((-a + c - 1) / c); }
-
 // Logical cell range [ca, cb] of a band (indices may run one band-length below 0 or
 // above ncell to express wrap-around) -> start (in [0, npts)) and length in points.
 __device__ __forceinline__ void cells_to_points(const Band &bd, const int *cell_start, int ca, int cb,
@@ -55,11 +53,12 @@ __device__ __forceinline__ void cells_to_points(const Band &bd, const int *cell_
     }
     const int C = bd.ncell, np = bd.npts;
     // windows span at most one band length around [0, C); the clamps only matter for
-    // non-finite inputs and keep every index inside the band regardless
+    // non-finite inputs and keep every index inside the band regardless.  With
+    // ca in [-C, 2C) and cb + 1 in [-C + 1, 2C], the band-length quotients are -1, 0 or 1.
     ca = max(ca, -C);
     cb = min(cb, 2 * C - 1);
-    const int q0 = floor_div(ca, C), r0 = ca - q0 * C;
-    const int q1 = floor_div(cb + 1, C), r1 = cb + 1 - q1 * C;
+    const int q0 = ca < 0 ? -1 : (ca >= C ? 1 : 0), r0 = ca - q0 * C;
+    const int q1 = cb + 1 < 0 ? -1 : (cb + 1 >= C ? 1 : 0), r1 = cb + 1 - q1 * C;
     const int st = cell_start[bd.cell_off + r0] - bd.pt_start + q0 * np;
     const int en = cell_start[bd.cell_off + r1] - bd.pt_start + q1 * np;
     len = min(max(en - st, 0), np);

@@ -15,6 +15,10 @@
 
 #include "z3_internal.h"
 
+#ifndef Z3_BAND_HEIGHT_FACTOR
+#define Z3_BAND_HEIGHT_FACTOR 0.6
+#endif
+
 namespace z3 {
 
 // ---- small device helpers ------------------------------------------------------------
@@ -375,7 +379,10 @@ z3_status build_index_impl(int64_t n, const double *xyz, const double *w, int nb
         if (st != Z3_OK) { (void)hipFree(d_range); return bail(st); }
         double area = 2.0 * kPi * (cos(std::min(rg[0], rg[1])) - cos(std::max(rg[0], rg[1])));
         if (!(area > 0.0)) area = 1e-12;
-        h = 0.35 * sqrt(area / (double)std::max<int64_t>(n, 1));
+        // 0.6 x the mean point spacing: below the smallest HEALPix ring spacing
+        // (2 / (3 Nside) rad against a spacing of ~1.023 / Nside), so a band never
+        // holds two rings, with few empty bands
+        h = Z3_BAND_HEIGHT_FACTOR * sqrt(area / (double)std::max<int64_t>(n, 1));
     }
     (void)hipFree(d_range);
     h = std::min(h, kPi);
