@@ -40,20 +40,64 @@ def cpu_model():
     return "unknown"
 
 
+KERNEL_SOURCES = ("z3_multipoles.hip", "z3_device.h", "z3_internal.h")
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "k_multipoles_traffic.json")
+
+
+def kernel_source_hash():
+    """sha256 over the sources k_multipoles is compiled from."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2408_16847_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
 def measured_traffic(cfg_name, prec):
     """HBM bytes per k_multipoles launch from the committed rocprofv3 counter passes, if they
     were taken on this exact kernel source, workload and precision; otherwise None."""
-    import hashlib
     try:
-        rec = json.load(open(os.path.join(ROOT, "profiles", "k_multipoles_traffic.json")))
-        src = open(os.path.join(ROOT, "paper_2408_16847_amd", "csrc", "z3_multipoles.hip"), "rb").read()
+        rec = json.load(open(TRAFFIC_JSON))
+        digest = kernel_source_hash()
     except OSError:
         return None
-    if rec.get("source_sha256") != hashlib.sha256(src).hexdigest():
+    if rec.get("source_sha256") != digest:
         return None
     if rec.get("workload") != cfg_name or rec.get("precision") != prec:
         return None
     return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+
+
+def _counter_rows(path, counter, name_part):
+    import csv
+    with open(path, newline="") as f:
+        return [float(r["Counter_Value"]) for r in csv.DictReader(f)
+                if r["Counter_Name"] == counter and name_part in r["Kernel_Name"]]
+
+
+def write_traffic_json(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, cfg_name, prec):
+    """Turn rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE passes (KiB per dispatch) over k_multipoles
+    and over the plain copy of `--copy-calibration` into bytes per launch, each counter scaled
+    so that it reads the copy's known size."""
+    copy_bytes = 8 << 28
+    cf = max(_counter_rows(copy_fetch_csv, "FETCH_SIZE", "copyBuffer"))
+    cw = max(_counter_rows(copy_write_csv, "WRITE_SIZE", "copyBuffer"))
+    fs, ws = copy_bytes / (cf * 1024.0), copy_bytes / (cw * 1024.0)
+    f = _counter_rows(fetch_csv, "FETCH_SIZE", "k_multipoles<")
+    w = _counter_rows(write_csv, "WRITE_SIZE", "k_multipoles<")
+    if not f or not w:
+        sys.exit("no k_multipoles dispatch in the counter files")
+    rec = {"kernel": "k_multipoles", "source_sha256": kernel_source_hash(), "workload": cfg_name,
+           "precision": prec, "dispatches": len(f),
+           "fetch_bytes_per_launch": sum(f) / len(f) * 1024.0 * fs,
+           "write_bytes_per_launch": sum(w) / len(w) * 1024.0 * ws,
+           "fetch_scale": round(fs, 4), "write_scale": round(ws, 4),
+           "note": "FETCH_SIZE/WRITE_SIZE KiB averaged over the dispatches (one launch per pivot chunk), scaled by the "
+                   "plain-copy calibration (2 GiB read, 2 GiB written)"}
+    with open(TRAFFIC_JSON, "w") as fo:
+        json.dump(rec, fo, indent=1)
+        fo.write("\n")
+    print(json.dumps(rec))
 
 
 def err_m(test, ref):
@@ -83,7 +127,13 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=-1, help="oracle pivots (-1: automatic, 0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (for HBM counter calibration)")
+    ap.add_argument("--traffic-json", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
+                    help="write the k_multipoles HBM traffic record from rocprofv3 counter CSVs (no GPU needed)")
     args = ap.parse_args()
+
+    if args.traffic_json:
+        write_traffic_json(*args.traffic_json, args.config, "mixed" if args.prec == "both" else args.prec)
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the estimator's pivot sum would shard over GPUs with one "

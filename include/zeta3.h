@@ -182,6 +182,14 @@ z3_status z3_estimate_pivots(z3_index idx, int map, int64_t npiv, const double *
 z3_status z3_adjoint(z3_index idx, int map, int m_max, int64_t p0, int64_t p1, const double *G,
                      double scale, double *grad_x, void *stream);
 
+/*
+ * Adjoint for ALL attached maps: G [nmaps][m_max+1][nbins][nbins][2], grad_x [nmaps][n] +=
+ * (catalogue order), zeta of every map = scale * sum_p w_p x_p X_p X_p^H.  The multipoles
+ * of several maps are recomputed together with shared pair geometry.
+ */
+z3_status z3_adjoint_maps(z3_index idx, int m_max, int64_t p0, int64_t p1, const double *G,
+                          double scale, double *grad_x, void *stream);
+
 /* sum_p w_p over pivots [p0, p1), FP64, out[0] += . */
 z3_status z3_pivot_weight_sum(z3_index idx, int64_t p0, int64_t p1, double *out, void *stream);
 

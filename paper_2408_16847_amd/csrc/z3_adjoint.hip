@@ -91,10 +91,19 @@ constexpr int adjoint_waves_per_eu()
     return M <= 10 ? 4 : (M <= 13 ? 3 : 2);
 }
 
+// Per-wave LDS slice that gathers a window's contributions before they go to HBM: the
+// lanes of a wave walk overlapping ranges of the same band, so one window's pairs touch
+// only ~(window + 64) distinct neighbours.
+constexpr int kAggSlots = 1024;
+
 template <int M>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(adjoint_waves_per_eu<M>())))
 void k_adjoint_scatter(ScatterArgs a)
 {
+    __shared__ double agg_all[kBlock / kWave][kAggSlots];
+    double *agg = agg_all[threadIdx.x / kWave];
+    const int lane = threadIdx.x & (kWave - 1);
+    for (int e = lane; e < kAggSlots; e += kWave) agg[e] = 0.0;
     const int lb = xcd_block(blockIdx.x, a.nblocks);
     const int64_t wave0 = a.p0 + (int64_t)lb * kBlock + (threadIdx.x & ~(kWave - 1));
     if (__builtin_amdgcn_readfirstlane((int)(wave0 >= a.p1))) return;
@@ -128,6 +137,12 @@ void k_adjoint_scatter(ScatterArgs a)
             for (int seg = 0; seg < 2; ++seg) {
                 int j = base + (seg == 0 ? s0 : s1);
                 const int jend = j + (seg == 0 ? l0 : l1);
+                // the wave's span of this segment; inactive lanes do not widen it
+                const bool any = j < jend;
+                const int jlo = __builtin_amdgcn_readfirstlane(wave_min(any ? j : 0x7fffffff));
+                const int jhi = __builtin_amdgcn_readfirstlane(wave_max(any ? jend : -1));
+                if (jhi <= jlo) continue;
+                const bool use_lds = jhi - jlo <= kAggSlots;
                 for (; j < jend; ++j) {
                     const double4 r = a.rec[j];
                     const double dx = r.x - f.xp, dy = r.y - f.yp, dz = r.z - f.zp;
@@ -153,10 +168,30 @@ void k_adjoint_scatter(ScatterArgs a)
                             }
                         }
                         if (!unit_w) acc *= a.wdbl[j];
-                        int t = j - base;
-                        if (t >= bd.npts) t -= bd.npts;
-                        atomicAdd(&a.grad[bd.pt_start + t], acc);
+                        if (use_lds) {
+                            atomicAdd(&agg[j - jlo], acc);
+                        } else {
+                            int t = j - base;
+                            if (t >= bd.npts) t -= bd.npts;
+                            atomicAdd(&a.grad[bd.pt_start + t], acc);
+                        }
                     }
+                }
+                if (use_lds) {
+                    // one global atomic per touched neighbour, and the slice is cleared
+                    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): this wave's LDS adds are done
+                    __builtin_amdgcn_wave_barrier();
+                    for (int e = lane; e < jhi - jlo; e += kWave) {
+                        const double val = agg[e];
+                        if (val != 0.0) {
+                            int t = jlo + e - base;
+                            if (t >= bd.npts) t -= bd.npts;
+                            atomicAdd(&a.grad[bd.pt_start + t], val);
+                            agg[e] = 0.0;
+                        }
+                    }
+                    __builtin_amdgcn_s_waitcnt(0xc07f);
+                    __builtin_amdgcn_wave_barrier();
                 }
             }
         }
@@ -175,11 +210,75 @@ static void launch_scatter_m(const ScatterArgs &a, hipStream_t s)
     hipLaunchKernelGGL(k_adjoint_scatter<M>, dim3(a.nblocks), dim3(kBlock), 0, s, a);
 }
 
+// Prep + scatter of one map for pivots [c0, c1) whose multipoles A (ld = c1 - c0) and
+// weights W are already in the workspace.
+static z3_status adjoint_chunk_map(z3_index idx, int map, int m_max, int64_t c0, int64_t c1, const double *A,
+                                   const double *W, const double *G, double scale, double *D, double *gs,
+                                   hipStream_t s)
+{
+    const int64_t P = c1 - c0;
+    const double *vmap = idx->d_v + (size_t)map * idx->n;
+    PrepArgs pa;
+    pa.A = A;
+    pa.W = W;
+    pa.G = G;
+    pa.v = vmap + c0;
+    pa.w = idx->d_w + c0;
+    pa.D = D;
+    pa.grad = gs + c0;
+    pa.P = P;
+    pa.nb = idx->nbins;
+    pa.M = m_max;
+    pa.scale = scale;
+    hipLaunchKernelGGL(k_adjoint_prep, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, pa);
+    z3_status st = check_launch("k_adjoint_prep");
+    if (st != Z3_OK) return st;
+    ScatterArgs sa;
+    sa.px = idx->d_x; sa.py = idx->d_y; sa.pz = idx->d_z;
+    sa.pv = vmap;
+    sa.rec = idx->d_rec + (size_t)map * 2 * idx->n;
+    sa.wdbl = idx->unit_w ? nullptr : idx->d_wdbl;
+    sa.cell_start = idx->d_cell_start;
+    sa.bands = idx->d_bands;
+    sa.nbands = idx->nbands;
+    sa.inv_h = 1.0 / idx->band_h;
+    sa.edges = idx->d_edges;
+    sa.nb = idx->nbins;
+    sa.p0 = c0; sa.p1 = c1;
+    sa.D = D;
+    sa.ldD = P;
+    sa.grad = gs;
+    sa.scale = scale;
+    sa.nblocks = (int)((P + kBlock - 1) / kBlock);
+    hipEvent_t ev0;
+    profile_begin(s, &ev0);
+    switch (m_max) {
+#define Z3_CASE(MM) case MM: launch_scatter_m<MM>(sa, s); break;
+        Z3_CASE(0) Z3_CASE(1) Z3_CASE(2) Z3_CASE(3) Z3_CASE(4) Z3_CASE(5) Z3_CASE(6) Z3_CASE(7)
+        Z3_CASE(8) Z3_CASE(9) Z3_CASE(10) Z3_CASE(11) Z3_CASE(12) Z3_CASE(13) Z3_CASE(14)
+        Z3_CASE(15) Z3_CASE(16)
+#undef Z3_CASE
+    default: st = fail(Z3_ERR_UNSUPPORTED, "m_max=%d not compiled", m_max);
+    }
+    if (st == Z3_OK) st = check_launch("k_adjoint_scatter");
+    profile_end(s, ev0);
+    return st;
+}
+
+static z3_status grad_to_catalogue(z3_index idx, const double *gs, double *grad_x, hipStream_t s)
+{
+    if (idx->n == 0) return Z3_OK;
+    hipLaunchKernelGGL(k_grad_to_catalogue, dim3((unsigned)((idx->n + 255) / 256)), dim3(256), 0, s, idx->n,
+                       idx->d_perm, gs, grad_x);
+    return check_launch("k_grad_to_catalogue");
+}
+
 z3_status adjoint_impl(z3_index idx, int map, int m_max, int64_t p0, int64_t p1, const double *G, double scale,
                        double *grad_x, hipStream_t s, int64_t chunk)
 {
     const int nb = idx->nbins;
     if (chunk > p1 - p0) chunk = ((p1 - p0 + kBlock - 1) / kBlock) * kBlock;
+    if (chunk < kBlock) chunk = kBlock;
     const size_t per_piv = (size_t)(m_max + 1) * 2 * nb;
     void *wa = nullptr, *wd = nullptr, *ww = nullptr, *wg = nullptr;
     z3_status st = scratch_alloc(&wa, (size_t)chunk * per_piv * sizeof(double), s);
@@ -188,62 +287,57 @@ z3_status adjoint_impl(z3_index idx, int map, int m_max, int64_t p0, int64_t p1,
     if (st == Z3_OK) st = scratch_alloc(&wg, (size_t)idx->n * sizeof(double), s);
     if (st == Z3_OK) st = launch_fill(static_cast<double *>(wg), idx->n, 0.0, s);
     double *gs = static_cast<double *>(wg);
-    const double *vmap = idx->d_v + (size_t)map * idx->n;
     for (int64_t c0 = p0; c0 < p1 && st == Z3_OK; c0 += chunk) {
         const int64_t c1 = c0 + chunk < p1 ? c0 + chunk : p1;
-        const int64_t P = c1 - c0;
         st = launch_multipoles(idx, Pivots{idx->d_x, idx->d_y, idx->d_z}, map, m_max, Z3_PREC_FP64, Z3_NORM_BIN, c0,
-                               c1, wa, P, static_cast<double *>(ww), nullptr, nullptr, nullptr, s);
-        if (st != Z3_OK) break;
-        PrepArgs pa;
-        pa.A = static_cast<const double *>(wa);
-        pa.W = static_cast<const double *>(ww);
-        pa.G = G;
-        pa.v = vmap + c0;
-        pa.w = idx->d_w + c0;
-        pa.D = static_cast<double *>(wd);
-        pa.grad = gs + c0;
-        pa.P = P;
-        pa.nb = nb;
-        pa.M = m_max;
-        pa.scale = scale;
-        hipLaunchKernelGGL(k_adjoint_prep, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, pa);
-        if ((st = check_launch("k_adjoint_prep")) != Z3_OK) break;
-        ScatterArgs sa;
-        sa.px = idx->d_x; sa.py = idx->d_y; sa.pz = idx->d_z;
-        sa.pv = vmap;
-        sa.rec = idx->d_rec + (size_t)map * 2 * idx->n;
-        sa.wdbl = idx->unit_w ? nullptr : idx->d_wdbl;
-        sa.cell_start = idx->d_cell_start;
-        sa.bands = idx->d_bands;
-        sa.nbands = idx->nbands;
-        sa.inv_h = 1.0 / idx->band_h;
-        sa.edges = idx->d_edges;
-        sa.nb = nb;
-        sa.p0 = c0; sa.p1 = c1;
-        sa.D = static_cast<const double *>(wd);
-        sa.ldD = P;
-        sa.grad = gs;
-        sa.scale = scale;
-        sa.nblocks = (int)((P + kBlock - 1) / kBlock);
-        hipEvent_t ev0;
-        profile_begin(s, &ev0);
-        switch (m_max) {
-#define Z3_CASE(MM) case MM: launch_scatter_m<MM>(sa, s); break;
-            Z3_CASE(0) Z3_CASE(1) Z3_CASE(2) Z3_CASE(3) Z3_CASE(4) Z3_CASE(5) Z3_CASE(6) Z3_CASE(7)
-            Z3_CASE(8) Z3_CASE(9) Z3_CASE(10) Z3_CASE(11) Z3_CASE(12) Z3_CASE(13) Z3_CASE(14)
-            Z3_CASE(15) Z3_CASE(16)
-#undef Z3_CASE
-        default: st = fail(Z3_ERR_UNSUPPORTED, "m_max=%d not compiled", m_max);
+                               c1, wa, c1 - c0, static_cast<double *>(ww), nullptr, nullptr, nullptr, s);
+        if (st == Z3_OK)
+            st = adjoint_chunk_map(idx, map, m_max, c0, c1, static_cast<const double *>(wa),
+                                   static_cast<const double *>(ww), G, scale, static_cast<double *>(wd), gs, s);
+    }
+    if (st == Z3_OK) st = grad_to_catalogue(idx, gs, grad_x, s);
+    scratch_free(wg, s);
+    scratch_free(ww, s);
+    scratch_free(wd, s);
+    scratch_free(wa, s);
+    return st;
+}
+
+// All attached maps: the multipoles of kMapGroup maps are recomputed together by the
+// many-map kernel (shared geometry), then each map runs its prep and scatter.
+z3_status adjoint_maps_impl(z3_index idx, int m_max, int64_t p0, int64_t p1, const double *G, double scale,
+                            double *grad_x, hipStream_t s, int64_t chunk)
+{
+    const int nb = idx->nbins;
+    chunk = (chunk / kBlock) * kBlock;
+    if (chunk > p1 - p0) chunk = ((p1 - p0 + kBlock - 1) / kBlock) * kBlock;
+    if (chunk < kBlock) chunk = kBlock;
+    const size_t per_piv = (size_t)(m_max + 1) * 2 * nb;
+    const size_t gstride = (size_t)(m_max + 1) * nb * nb * 2;
+    void *wa = nullptr, *wd = nullptr, *ww = nullptr, *wg = nullptr;
+    z3_status st = scratch_alloc(&wa, (size_t)kMapGroup * chunk * per_piv * sizeof(double), s);
+    if (st == Z3_OK) st = scratch_alloc(&wd, (size_t)chunk * per_piv * sizeof(double), s);
+    if (st == Z3_OK) st = scratch_alloc(&ww, (size_t)chunk * nb * sizeof(double), s);
+    if (st == Z3_OK) st = scratch_alloc(&wg, (size_t)idx->nmaps * idx->n * sizeof(double), s);
+    if (st == Z3_OK) st = launch_fill(static_cast<double *>(wg), (int64_t)idx->nmaps * idx->n, 0.0, s);
+    for (int g = 0; g < idx->ngroups && st == Z3_OK; ++g) {
+        for (int64_t c0 = p0; c0 < p1 && st == Z3_OK; c0 += chunk) {
+            const int64_t c1 = c0 + chunk < p1 ? c0 + chunk : p1;
+            const size_t stride = (size_t)(c1 - c0) * per_piv;
+            st = launch_multipoles_maps(idx, g, m_max, Z3_PREC_FP64, c0, c1, wa, c1 - c0, stride,
+                                        static_cast<double *>(ww), nullptr, s);
+            for (int k = 0; k < kMapGroup && st == Z3_OK; ++k) {
+                const int map = g * kMapGroup + k;
+                if (map >= idx->nmaps) break;
+                st = adjoint_chunk_map(idx, map, m_max, c0, c1, static_cast<const double *>(wa) + k * stride,
+                                       static_cast<const double *>(ww), G + map * gstride, scale,
+                                       static_cast<double *>(wd), static_cast<double *>(wg) + (size_t)map * idx->n,
+                                       s);
+            }
         }
-        if (st == Z3_OK) st = check_launch("k_adjoint_scatter");
-        profile_end(s, ev0);
     }
-    if (st == Z3_OK && idx->n > 0) {
-        hipLaunchKernelGGL(k_grad_to_catalogue, dim3((unsigned)((idx->n + 255) / 256)), dim3(256), 0, s, idx->n,
-                           idx->d_perm, gs, grad_x);
-        st = check_launch("k_grad_to_catalogue");
-    }
+    for (int map = 0; map < idx->nmaps && st == Z3_OK; ++map)
+        st = grad_to_catalogue(idx, static_cast<double *>(wg) + (size_t)map * idx->n, grad_x + (size_t)map * idx->n, s);
     scratch_free(wg, s);
     scratch_free(ww, s);
     scratch_free(wd, s);

@@ -325,7 +325,7 @@ Z3_API z3_status z3_estimate_maps(z3_index idx, int m_max, int prec, int64_t p0,
             int64_t c1 = c0 + chunk < p1 ? c0 + chunk : p1;
             // the chunk's multipoles use a leading dimension equal to the chunk length
             const size_t stride = (size_t)(c1 - c0) * (m_max + 1) * 2 * idx->nbins;
-            st = launch_multipoles_maps(idx, g, m_max, prec, c0, c1, wa, c1 - c0, stride,
+            st = launch_multipoles_maps(idx, g, m_max, prec, c0, c1, wa, c1 - c0, stride, nullptr,
                                         g == 0 ? pair_total : nullptr, s);
             for (int k = 0; k < kMapGroup && st == Z3_OK; ++k) {
                 const int map = g * kMapGroup + k;
@@ -406,6 +406,19 @@ Z3_API z3_status z3_adjoint(z3_index idx, int map, int m_max, int64_t p0, int64_
     if (!G || !grad_x) return fail(Z3_ERR_INVALID_ARG, "z3_adjoint: G or grad_x is NULL");
     return adjoint_impl(idx, map, m_max, p0, p1, G, scale, grad_x, as_stream(stream),
                         chunk_pivots(idx, m_max, Z3_PREC_FP64) / 2);
+}
+
+Z3_API z3_status z3_adjoint_maps(z3_index idx, int m_max, int64_t p0, int64_t p1, const double *G, double scale,
+                                 double *grad_x, void *stream)
+{
+    z3_status st = check_common("z3_adjoint_maps", idx, 0, m_max, Z3_PREC_FP64, p0, p1);
+    if (st != Z3_OK) return st;
+    if (!std::isfinite(scale)) return fail(Z3_ERR_INVALID_ARG, "z3_adjoint_maps: scale is not finite");
+    if (p1 == p0) return Z3_OK;
+    if (!G || !grad_x) return fail(Z3_ERR_INVALID_ARG, "z3_adjoint_maps: G or grad_x is NULL");
+    if (idx->nmaps == 1) return z3_adjoint(idx, 0, m_max, p0, p1, G, scale, grad_x, stream);
+    return adjoint_maps_impl(idx, m_max, p0, p1, G, scale, grad_x, as_stream(stream),
+                             chunk_pivots(idx, m_max, Z3_PREC_FP64) / (2 * kMapGroup));
 }
 
 Z3_API z3_status z3_pivot_weight_sum(z3_index idx, int64_t p0, int64_t p1, double *out, void *stream)

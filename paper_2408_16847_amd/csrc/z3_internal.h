@@ -97,7 +97,7 @@ z3_status launch_multipoles(const z3_index_s *idx, Pivots piv, int map, int m_ma
                             hipStream_t s);
 
 z3_status launch_multipoles_maps(const z3_index_s *idx, int group, int m_max, int prec, int64_t p0,
-                                 int64_t p1, void *A, int64_t ldA, size_t map_stride,
+                                 int64_t p1, void *A, int64_t ldA, size_t map_stride, double *W,
                                  uint64_t *pair_total, hipStream_t s);
 
 // contraction and small kernels (z3_contract.hip)
@@ -113,6 +113,8 @@ z3_status launch_fill(double *p, int64_t n, double value, hipStream_t s);
 // adjoint (z3_adjoint.hip)
 z3_status adjoint_impl(z3_index idx, int map, int m_max, int64_t p0, int64_t p1, const double *G,
                        double scale, double *grad_x, hipStream_t s, int64_t chunk);
+z3_status adjoint_maps_impl(z3_index idx, int m_max, int64_t p0, int64_t p1, const double *G,
+                            double scale, double *grad_x, hipStream_t s, int64_t chunk);
 z3_status launch_finalize(int nmaps, int m_max, int nbins, double *zeta, const double *sum_w,
                           hipStream_t s);
 z3_status launch_resum(int m_max, int nbins, const double *zeta, int nphi, const double *phi,

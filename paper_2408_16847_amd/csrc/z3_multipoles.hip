@@ -254,6 +254,7 @@ struct MapArgs {
     void *A;                      // per map [m+1][2][nb][ldA], maps map_stride elements apart
     int64_t ldA;
     size_t map_stride;
+    double *W;                    // [nb][ldA] W_{p,b} (shared by the maps), or null
     uint64_t *pair_total;
     int nblocks;
 };
@@ -377,6 +378,7 @@ void k_multipoles_maps(MapArgs a)
             my_pairs += (uint64_t)cnt;
             if (unit_w) Wb = (double)cnt;
             const double inv = Wb > 0.0 ? 1.0 / Wb : 0.0;
+            if (a.W) a.W[(size_t)bin * (size_t)a.ldA + col] = Wb;
 #pragma unroll
             for (int k = 0; k < K; ++k) {
 #pragma unroll
@@ -412,7 +414,8 @@ static void launch_maps_m(bool f32out, const MapArgs &a, hipStream_t s)
 }
 
 z3_status launch_multipoles_maps(const z3_index_s *idx, int group, int m_max, int prec, int64_t p0, int64_t p1,
-                                 void *A, int64_t ldA, size_t map_stride, uint64_t *pair_total, hipStream_t s)
+                                 void *A, int64_t ldA, size_t map_stride, double *W, uint64_t *pair_total,
+                                 hipStream_t s)
 {
     int64_t nblk = (p1 - p0 + kBlock - 1) / kBlock;
     if (nblk > 0x7fffffff) return fail(Z3_ERR_OVERFLOW, "too many pivot blocks");
@@ -429,6 +432,7 @@ z3_status launch_multipoles_maps(const z3_index_s *idx, int group, int m_max, in
     a.nb = idx->nbins;
     a.p0 = p0; a.p1 = p1;
     a.A = A; a.ldA = ldA; a.map_stride = map_stride;
+    a.W = W;
     a.pair_total = pair_total;
     a.nblocks = (int)nblk;
     const bool f32 = prec == Z3_PREC_MIXED;

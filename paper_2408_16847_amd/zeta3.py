@@ -214,6 +214,17 @@ def adjoint(idx: Index, G, scale: float, m_max: int, map_index: int = 0, p0: int
     return grad
 
 
+def adjoint_maps(idx: Index, G, scale: float, m_max: int, p0: int = 0, p1: int | None = None, grad=None):
+    """grad_x [nmaps, n] += dL/dx for G [nmaps, m+1, nb, nb, 2], every attached map at once
+    (multipoles of several maps recomputed together)."""
+    p1 = idx.n if p1 is None else p1
+    if grad is None:
+        grad = torch.zeros((idx.nmaps, idx.n), dtype=torch.float64, device="cuda")
+    G = _dev(G)
+    _lib.call("z3_adjoint_maps", idx.handle, m_max, p0, p1, _ptr(G), float(scale), _ptr(grad), _stream())
+    return grad
+
+
 class Zeta3Fn(torch.autograd.Function):
     """zeta_m = estimator(x) as a differentiable torch op.
 
@@ -241,8 +252,7 @@ class Zeta3Fn(torch.autograd.Function):
         g = g.contiguous()
         if len(ctx.shape) == 2:
             grad = torch.zeros(ctx.shape, dtype=torch.float64, device="cuda")
-            for k in range(ctx.shape[0]):
-                adjoint(idx, g[k], ctx.scale, ctx.m_max, map_index=k, grad=grad[k])
+            adjoint_maps(idx, g, ctx.scale, ctx.m_max, grad=grad)
         else:
             grad = adjoint(idx, g, ctx.scale, ctx.m_max)
         return grad, None, None, None

@@ -87,3 +87,24 @@ def test_autograd_quadratic_loss_batch_of_maps():
         Gc = 2.0 * (zc[..., 0] + 1j * zc[..., 1])
         go = ograd.zeta_grad(xyz_t.numpy(), np.ones(xyz_t.shape[1]), xs[s].cpu().numpy(), E, M, Gc)
         assert np.abs(gx[s] - go).max() <= 1e-10 * np.abs(go).max()
+
+
+def test_adjoint_maps_matches_per_map_adjoint(monkeypatch):
+    """z3_adjoint_maps (multipoles of four maps recomputed together, several pivot chunks,
+    a partial last group, a pivot sub-range) against z3_adjoint map by map."""
+    G.say("case: adjoint_maps vs per-map adjoint")
+    monkeypatch.setenv("Z3_WORKSPACE_MB", "1")
+    xyz, w, _ = pins.random_cap(3000, 5.0, 17)
+    E = pins.small_edges(6, lo=0.1, hi=2.5, log=True)
+    M = 6
+    rng = np.random.default_rng(4)
+    xs = rng.normal(size=(6, xyz.shape[1]))
+    idx = G.build(xyz, xs, E, w=w)
+    Gs = torch.stack([_G_tensor(_rand_G(20 + k, M, 6)) for k in range(6)])
+    p0, p1 = 37, 2811
+    got = z3.adjoint_maps(idx, Gs, 0.5, M, p0=p0, p1=p1).cpu().numpy()
+    for k in range(6):
+        ref = z3.adjoint(idx, Gs[k], 0.5, M, map_index=k, p0=p0, p1=p1).cpu().numpy()
+        err = np.abs(got[k] - ref).max() / np.abs(ref).max()
+        G.say("map", k, "rel err", err)
+        assert err < 1e-12
