@@ -329,16 +329,22 @@ def cpu_baseline(cfg, xyz, x, nbr, E, M, nsample, z3, torch):
         return cpu.estimate(xyz_h[:, sel], nbr_h[0], nbr_h[2], nbr_h[1], E, M, w_h[sel], x_h[sel], nthreads=threads)
 
     # size the sample to ~15 s of oracle work: one call with a single pivot measures the
-    # oracle's fixed cost (its own O(N) grid build), one with 320 pivots its pair rate
+    # oracle's fixed cost (its own O(N) grid build); its pair rate is measured on 320 pivots,
+    # then again on ~2 s worth of pivots (small calls under-use the threads)
     if nsample < 0:
         t = time.perf_counter()
         oracle(order[p0:p0 + 1])
         t_fixed = time.perf_counter() - t
-        t = time.perf_counter()
-        _, p320 = oracle(order[p0:p0 + 320])
-        rate = p320 / max(time.perf_counter() - t - t_fixed, 1e-3)
-        nsample = int(min(n - p0, max(320, 30.0 * rate / max(p320 / 320.0, 1.0))))
-        log(f"[bench] cpu_baseline calibration: fixed {t_fixed:.2f}s, {rate:.3g} pairs/s")
+        k, rate = 320, 0.0
+        for target in (None, 2.0):
+            if target is not None:
+                k = int(min(n - p0, max(320, target * rate / per_pivot)))
+            t = time.perf_counter()
+            _, pk = oracle(order[p0:p0 + k])
+            rate = pk / max(time.perf_counter() - t - t_fixed, 1e-3)
+            per_pivot = max(pk / k, 1.0)
+            log(f"[bench] cpu_baseline calibration: fixed {t_fixed:.2f}s, {k} pivots at {rate:.3g} pairs/s")
+        nsample = int(min(n - p0, max(320, 15.0 * rate / per_pivot)))
     sel = order[p0:p0 + nsample]
     log(f"[bench] cpu_baseline: oracle on {nsample} pivots x {threads} threads")
     t = time.perf_counter()

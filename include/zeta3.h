@@ -104,6 +104,20 @@ z3_status z3_index_info(z3_index idx, int64_t *n, int *nbins, int *nmaps, int *n
 /* perm [n] int64: original catalogue index of the point at index position i. */
 z3_status z3_index_perm(z3_index idx, int64_t *perm, void *stream);
 
+/*
+ * Block shape of the MFMA many-map kernel (z3_estimate_maps, z3_adjoint_maps with more
+ * than 4 maps): one block per pivot with `waves` wave64s, each owning `maps_per_wave`
+ * maps; compiled shapes are (4, 16), (2, 32), (2, 16) and (4, 32).  (0, 0), the default,
+ * lets the library time every compiled shape on a 4096-pivot sample of the first eager
+ * call for each (m_max, prec) and keep the fastest for this index.  Every shape gives
+ * bit-identical results.  Attaching new values (z3_index_set_values) forgets the tuned
+ * shapes.  Z3_ERR_INVALID_ARG for a shape that is not compiled.
+ */
+z3_status z3_index_set_batch_shape(z3_index idx, int waves, int maps_per_wave);
+
+/* [host] The fixed or tuned shape for (m_max, prec); (0, 0) if not tuned yet. */
+z3_status z3_index_batch_shape(z3_index idx, int m_max, int prec, int *waves, int *maps_per_wave);
+
 /* Release an index and its device memory (NULL is ignored).  Waits for its work. */
 void z3_index_free(z3_index idx);
 
@@ -143,11 +157,17 @@ z3_status z3_estimate(z3_index idx, int map, int m_max, int prec, int64_t p0, in
 
 /*
  * Fused estimator for ALL attached maps at once (many mock maps over one set of
- * positions): for every pair the bin test, bearing and cos/sin(m phi) are computed once
- * and applied to the values of several maps.  zeta [nmaps][m_max+1][nbins][nbins][2] +=
- * (unnormalised, one block per map, in map order); pair_total += the number of pairs
- * (counted once, not per map), or NULL.  Multipoles are accumulated in FP64; `prec`
+ * positions, eqs. Xm.binned and zetamEst for each map): for every pair the bin test,
+ * bearing and cos/sin(m phi) are computed once and applied to the values of all maps.
+ * zeta [nmaps][m_max+1][nbins][nbins][2] += (unnormalised, one block per map, in map
+ * order); pair_total += the number of pairs (counted once, not per map), or NULL.
+ * Up to 4 maps: register-tiled kernel, FP64 multipole sums.  More maps: the per-pair
+ * harmonics of a group of 64 candidates form the B operand of an MFMA product with the
+ * maps' values (block shape: see z3_index_set_batch_shape); FP64 path in
+ * FP64 MFMA, mixed path in FP32 MFMA with FP64 sums per 64 candidates.  `prec` also
  * selects the FP64 or the mixed (FP32 storage, split FP32 MFMA) contraction.
+ * Synchronous on `stream` the first time an (m_max, prec) is used with more than 4
+ * maps and an automatic shape (the shapes are timed then), unless the stream is capturing.
  */
 z3_status z3_estimate_maps(z3_index idx, int m_max, int prec, int64_t p0, int64_t p1,
                            double *zeta, uint64_t *pair_total, void *stream);

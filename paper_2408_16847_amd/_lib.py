@@ -21,6 +21,8 @@ SIGNATURES = {
     "z3_index_set_values": (_I, [_P, _I, _P, _P]),
     "z3_index_info": (_I, [_P, _P, _P, _P, _P, _P]),
     "z3_index_perm": (_I, [_P, _P, _P]),
+    "z3_index_set_batch_shape": (_I, [_P, _I, _I]),
+    "z3_index_batch_shape": (_I, [_P, _I, _I, _P, _P]),
     "z3_index_free": (None, [_P]),
     "z3_accumulate_multipoles": (_I, [_P, _I, _I, _I, _I, _I64, _I64, _P, _P, _P, _P, _P, _P]),
     "z3_contract": (_I, [_I64, _I, _I, _I, _P, _P, _P, _P]),

@@ -9,7 +9,8 @@
 //   D_p(a)  = sum_b (conj(G(a,b)) + G(b,a)) conj(X_p(b)).
 //
 // Per pivot chunk: (1) the multipole kernel recomputes X_p and W_{p,b} (nothing is kept
-// between chunks); (2) k_adjoint_prep forms D_p(a) / W_{p,a} and adds the pivot term;
+// between chunks); (2) k_adjoint_prep forms D_p(a) / W_{p,a} and adds the pivot term
+// (grid y: the maps of the pass);
 // (3) k_adjoint_scatter walks the same bin/band windows as the forward kernel, rebuilds
 // cos(m phi), sin(m phi) per pair and adds the neighbour term to the neighbour's gradient
 // with an FP64 atomic (index order; permuted to catalogue order at the end).  The atomics
@@ -30,12 +31,20 @@ struct PrepArgs {
     int64_t P;
     int nb, M;
     double scale;
+    // map blockIdx.y: A and D advance by ad_stride, G by g_stride, v and grad by n_stride
+    size_t ad_stride, g_stride, n_stride;
 };
 
 __global__ __launch_bounds__(256) void k_adjoint_prep(PrepArgs a)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= a.P) return;
+    const size_t mp = blockIdx.y;
+    a.A += mp * a.ad_stride;
+    a.D += mp * a.ad_stride;
+    a.G += mp * a.g_stride;
+    a.v += mp * a.n_stride;
+    a.grad += mp * a.n_stride;
     const int nb = a.nb;
     const size_t P = (size_t)a.P;
     double piv = 0.0;
@@ -83,6 +92,8 @@ struct ScatterArgs {
     double *grad;                 // index-order gradient
     double scale;
     int nblocks;
+    // map blockIdx.y: pv and grad advance by n_stride, rec by rec_stride, D by d_stride
+    size_t n_stride, rec_stride, d_stride;
 };
 
 template <int M>
@@ -110,6 +121,13 @@ void k_adjoint_scatter(ScatterArgs a)
     const int64_t p = a.p0 + (int64_t)lb * kBlock + threadIdx.x;
     const bool valid = p < a.p1;
     const int64_t pp = valid ? p : a.p1 - 1;
+    {
+        const size_t mp = blockIdx.y;
+        a.pv += mp * a.n_stride;
+        a.grad += mp * a.n_stride;
+        a.rec += mp * a.rec_stride;
+        a.D += mp * a.d_stride;
+    }
     const PivotFrame f = pivot_frame(a.px[pp], a.py[pp], a.pz[pp]);
     const double vp = valid ? a.scale * a.pv[pp] : 0.0;  // idle lanes add nothing
     const int64_t col = pp - a.p0;
@@ -205,19 +223,21 @@ __global__ void k_grad_to_catalogue(int64_t n, const int *perm, const double *gs
 }
 
 template <int M>
-static void launch_scatter_m(const ScatterArgs &a, hipStream_t s)
+static void launch_scatter_m(const ScatterArgs &a, int nm, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_adjoint_scatter<M>, dim3(a.nblocks), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_adjoint_scatter<M>, dim3(a.nblocks, nm), dim3(kBlock), 0, s, a);
 }
 
-// Prep + scatter of one map for pivots [c0, c1) whose multipoles A (ld = c1 - c0) and
-// weights W are already in the workspace.
-static z3_status adjoint_chunk_map(z3_index idx, int map, int m_max, int64_t c0, int64_t c1, const double *A,
-                                   const double *W, const double *G, double scale, double *D, double *gs,
-                                   hipStream_t s)
+// Prep + scatter of maps [map, map + nm) for pivots [c0, c1) whose multipoles A (ld =
+// c1 - c0, maps `stride` elements apart) and weights W are already in the workspace; D has
+// the layout of A.  G and gs (index-order gradients, idx->n apart) start at map `map`.
+static z3_status adjoint_chunk_maps(z3_index idx, int map, int nm, int m_max, int64_t c0, int64_t c1,
+                                    const double *A, size_t stride, const double *W, const double *G, double scale,
+                                    double *D, double *gs, hipStream_t s)
 {
     const int64_t P = c1 - c0;
     const double *vmap = idx->d_v + (size_t)map * idx->n;
+    const size_t gstride = (size_t)(m_max + 1) * idx->nbins * idx->nbins * 2;
     PrepArgs pa;
     pa.A = A;
     pa.W = W;
@@ -230,7 +250,10 @@ static z3_status adjoint_chunk_map(z3_index idx, int map, int m_max, int64_t c0,
     pa.nb = idx->nbins;
     pa.M = m_max;
     pa.scale = scale;
-    hipLaunchKernelGGL(k_adjoint_prep, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, pa);
+    pa.ad_stride = stride;
+    pa.g_stride = gstride;
+    pa.n_stride = (size_t)idx->n;
+    hipLaunchKernelGGL(k_adjoint_prep, dim3((unsigned)((P + 255) / 256), nm), dim3(256), 0, s, pa);
     z3_status st = check_launch("k_adjoint_prep");
     if (st != Z3_OK) return st;
     ScatterArgs sa;
@@ -250,10 +273,13 @@ static z3_status adjoint_chunk_map(z3_index idx, int map, int m_max, int64_t c0,
     sa.grad = gs;
     sa.scale = scale;
     sa.nblocks = (int)((P + kBlock - 1) / kBlock);
+    sa.n_stride = (size_t)idx->n;
+    sa.rec_stride = (size_t)2 * idx->n;
+    sa.d_stride = stride;
     hipEvent_t ev0;
     profile_begin(s, &ev0);
     switch (m_max) {
-#define Z3_CASE(MM) case MM: launch_scatter_m<MM>(sa, s); break;
+#define Z3_CASE(MM) case MM: launch_scatter_m<MM>(sa, nm, s); break;
         Z3_CASE(0) Z3_CASE(1) Z3_CASE(2) Z3_CASE(3) Z3_CASE(4) Z3_CASE(5) Z3_CASE(6) Z3_CASE(7)
         Z3_CASE(8) Z3_CASE(9) Z3_CASE(10) Z3_CASE(11) Z3_CASE(12) Z3_CASE(13) Z3_CASE(14)
         Z3_CASE(15) Z3_CASE(16)
@@ -292,8 +318,8 @@ z3_status adjoint_impl(z3_index idx, int map, int m_max, int64_t p0, int64_t p1,
         st = launch_multipoles(idx, Pivots{idx->d_x, idx->d_y, idx->d_z}, map, m_max, Z3_PREC_FP64, Z3_NORM_BIN, c0,
                                c1, wa, c1 - c0, static_cast<double *>(ww), nullptr, nullptr, nullptr, s);
         if (st == Z3_OK)
-            st = adjoint_chunk_map(idx, map, m_max, c0, c1, static_cast<const double *>(wa),
-                                   static_cast<const double *>(ww), G, scale, static_cast<double *>(wd), gs, s);
+            st = adjoint_chunk_maps(idx, map, 1, m_max, c0, c1, static_cast<const double *>(wa), 0,
+                                    static_cast<const double *>(ww), G, scale, static_cast<double *>(wd), gs, s);
     }
     if (st == Z3_OK) st = grad_to_catalogue(idx, gs, grad_x, s);
     scratch_free(wg, s);
@@ -303,37 +329,49 @@ z3_status adjoint_impl(z3_index idx, int map, int m_max, int64_t p0, int64_t p1,
     return st;
 }
 
-// All attached maps: the multipoles of kMapGroup maps are recomputed together by the
-// many-map kernel (shared geometry), then each map runs its prep and scatter.
+// All attached maps.  Up to kMapGroup maps: their multipoles are recomputed together by the
+// register-tiled many-map kernel; more maps: by the MFMA many-map kernel, all maps of a pivot
+// chunk at once.  Then one prep and one scatter launch cover every map of the pass.
+// `budget` is the pivot count whose single-map FP64 multipoles fill the workspace budget.
 z3_status adjoint_maps_impl(z3_index idx, int m_max, int64_t p0, int64_t p1, const double *G, double scale,
-                            double *grad_x, hipStream_t s, int64_t chunk)
+                            double *grad_x, hipStream_t s, int64_t budget)
 {
     const int nb = idx->nbins;
+    const bool batch = idx->nmaps > kMapGroup;
+    int shape = 0;
+    z3_status st = Z3_OK;
+    if (batch && (st = batch_shape(idx, m_max, Z3_PREC_FP64, p0, p1, s, &shape)) != Z3_OK) return st;
+    const int per_pass = batch ? idx->nmaps : kMapGroup;  // multipole sets held at once
+    int64_t chunk = budget / (2 * per_pass);               // A and D of every map of the pass
     chunk = (chunk / kBlock) * kBlock;
-    if (chunk > p1 - p0) chunk = ((p1 - p0 + kBlock - 1) / kBlock) * kBlock;
     if (chunk < kBlock) chunk = kBlock;
+    if (chunk > p1 - p0) chunk = ((p1 - p0 + kBlock - 1) / kBlock) * kBlock;
     const size_t per_piv = (size_t)(m_max + 1) * 2 * nb;
     const size_t gstride = (size_t)(m_max + 1) * nb * nb * 2;
     void *wa = nullptr, *wd = nullptr, *ww = nullptr, *wg = nullptr;
-    z3_status st = scratch_alloc(&wa, (size_t)kMapGroup * chunk * per_piv * sizeof(double), s);
-    if (st == Z3_OK) st = scratch_alloc(&wd, (size_t)chunk * per_piv * sizeof(double), s);
+    st = scratch_alloc(&wa, (size_t)per_pass * chunk * per_piv * sizeof(double), s);
+    if (st == Z3_OK) st = scratch_alloc(&wd, (size_t)per_pass * chunk * per_piv * sizeof(double), s);
     if (st == Z3_OK) st = scratch_alloc(&ww, (size_t)chunk * nb * sizeof(double), s);
     if (st == Z3_OK) st = scratch_alloc(&wg, (size_t)idx->nmaps * idx->n * sizeof(double), s);
     if (st == Z3_OK) st = launch_fill(static_cast<double *>(wg), (int64_t)idx->nmaps * idx->n, 0.0, s);
-    for (int g = 0; g < idx->ngroups && st == Z3_OK; ++g) {
+    const int ngroups = batch ? 1 : idx->ngroups;
+    for (int g = 0; g < ngroups && st == Z3_OK; ++g) {
+        const int map0 = g * kMapGroup;
+        const int nm = batch ? idx->nmaps : (idx->nmaps - map0 < kMapGroup ? idx->nmaps - map0 : kMapGroup);
         for (int64_t c0 = p0; c0 < p1 && st == Z3_OK; c0 += chunk) {
             const int64_t c1 = c0 + chunk < p1 ? c0 + chunk : p1;
             const size_t stride = (size_t)(c1 - c0) * per_piv;
-            st = launch_multipoles_maps(idx, g, m_max, Z3_PREC_FP64, c0, c1, wa, c1 - c0, stride,
-                                        static_cast<double *>(ww), nullptr, s);
-            for (int k = 0; k < kMapGroup && st == Z3_OK; ++k) {
-                const int map = g * kMapGroup + k;
-                if (map >= idx->nmaps) break;
-                st = adjoint_chunk_map(idx, map, m_max, c0, c1, static_cast<const double *>(wa) + k * stride,
-                                       static_cast<const double *>(ww), G + map * gstride, scale,
-                                       static_cast<double *>(wd), static_cast<double *>(wg) + (size_t)map * idx->n,
-                                       s);
-            }
+            if (batch)
+                st = launch_multipoles_batch(idx, m_max, Z3_PREC_FP64, shape, c0, c1, wa, c1 - c0, stride,
+                                             static_cast<double *>(ww), nullptr, s);
+            else
+                st = launch_multipoles_maps(idx, g, m_max, Z3_PREC_FP64, c0, c1, wa, c1 - c0, stride,
+                                            static_cast<double *>(ww), nullptr, s);
+            if (st == Z3_OK)
+                st = adjoint_chunk_maps(idx, map0, nm, m_max, c0, c1, static_cast<const double *>(wa), stride,
+                                        static_cast<const double *>(ww), G + map0 * gstride, scale,
+                                        static_cast<double *>(wd), static_cast<double *>(wg) + (size_t)map0 * idx->n,
+                                        s);
         }
     }
     for (int map = 0; map < idx->nmaps && st == Z3_OK; ++map)

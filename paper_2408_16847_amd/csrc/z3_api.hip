@@ -264,6 +264,100 @@ static int64_t chunk_pivots(const z3_index_s *idx, int m_max, int prec)
     return c;
 }
 
+// Block shape of the MFMA many-map kernel (waves per block x 16-map tiles per wave).
+// Unless the caller fixed it, the first eager call for an (m_max, precision) times every
+// compiled shape on a 4096-pivot sample from the middle of the call's pivot range and
+// keeps the fastest for the index.  All shapes give bit-identical results; a call made
+// while its stream is being captured into a graph does not tune (it uses the tuned shape,
+// else shape 0).
+z3_status z3::batch_shape(z3_index idx, int m_max, int prec, int64_t p0, int64_t p1, hipStream_t s, int *out)
+{
+    if (idx->batch_shape_forced >= 0) {
+        *out = idx->batch_shape_forced;
+        return Z3_OK;
+    }
+    int &slot = idx->batch_shape_tuned[prec == Z3_PREC_MIXED ? 1 : 0][m_max];
+    if (slot) {
+        *out = slot - 1;
+        return Z3_OK;
+    }
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    z3_status st = check_hip(hipStreamIsCapturing(s, &cs), "hipStreamIsCapturing");
+    if (st != Z3_OK) return st;
+    if (cs != hipStreamCaptureStatusNone || p1 <= p0) {
+        *out = 0;
+        return Z3_OK;
+    }
+    const int64_t S = p1 - p0 < 4096 ? p1 - p0 : 4096;
+    const int64_t q0 = p0 + (p1 - p0 - S) / 2;
+    const size_t elem = prec == Z3_PREC_FP64 ? 8 : 4;
+    const size_t stride = (size_t)S * (m_max + 1) * 2 * idx->nbins;
+    void *wa = nullptr;
+    if ((st = scratch_alloc(&wa, (size_t)idx->nmaps * stride * elem, s)) != Z3_OK) return st;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    st = check_hip(hipEventCreate(&e0), "hipEventCreate");
+    if (st == Z3_OK) st = check_hip(hipEventCreate(&e1), "hipEventCreate");
+    float best_ms = 0.0f;
+    int best = 0;
+    for (int c = 0; c < batch_num_shapes() && st == Z3_OK; ++c) {
+        // one untimed launch (code object load, caches), then one timed
+        st = launch_multipoles_batch(idx, m_max, prec, c, q0, q0 + S, wa, S, stride, nullptr, nullptr, s);
+        if (st == Z3_OK) st = check_hip(hipEventRecord(e0, s), "hipEventRecord");
+        if (st == Z3_OK) st = launch_multipoles_batch(idx, m_max, prec, c, q0, q0 + S, wa, S, stride, nullptr, nullptr, s);
+        if (st == Z3_OK) st = check_hip(hipEventRecord(e1, s), "hipEventRecord");
+        if (st == Z3_OK) st = check_hip(hipEventSynchronize(e1), "hipEventSynchronize");
+        float ms = 0.0f;
+        if (st == Z3_OK) st = check_hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+        if (st == Z3_OK && (c == 0 || ms < best_ms)) {
+            best_ms = ms;
+            best = c;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    scratch_free(wa, s);
+    if (st != Z3_OK) return st;
+    slot = best + 1;
+    *out = best;
+    return Z3_OK;
+}
+
+Z3_API z3_status z3_index_set_batch_shape(z3_index idx, int waves, int maps_per_wave)
+{
+    if (!idx) return fail(Z3_ERR_INVALID_ARG, "z3_index_set_batch_shape: idx is NULL");
+    if (waves == 0 && maps_per_wave == 0) {
+        idx->batch_shape_forced = -1;
+        return Z3_OK;
+    }
+    for (int c = 0; c < batch_num_shapes(); ++c) {
+        int w, t;
+        batch_shape_dims(c, &w, &t);
+        if (w == waves && 16 * t == maps_per_wave) {
+            idx->batch_shape_forced = c;
+            return Z3_OK;
+        }
+    }
+    return fail(Z3_ERR_INVALID_ARG, "z3_index_set_batch_shape: no compiled shape of %d waves x %d maps", waves,
+                maps_per_wave);
+}
+
+Z3_API z3_status z3_index_batch_shape(z3_index idx, int m_max, int prec, int *waves, int *maps_per_wave)
+{
+    if (!idx || !waves || !maps_per_wave) return fail(Z3_ERR_INVALID_ARG, "z3_index_batch_shape: NULL argument");
+    if (m_max < 0 || m_max > Z3_MAX_MMAX) return fail(Z3_ERR_INVALID_ARG, "z3_index_batch_shape: m_max=%d", m_max);
+    if (prec != Z3_PREC_FP64 && prec != Z3_PREC_MIXED)
+        return fail(Z3_ERR_INVALID_ARG, "z3_index_batch_shape: unknown precision %d", prec);
+    const int c = idx->batch_shape_forced >= 0 ? idx->batch_shape_forced
+                                                : idx->batch_shape_tuned[prec == Z3_PREC_MIXED ? 1 : 0][m_max] - 1;
+    *waves = *maps_per_wave = 0;
+    if (c >= 0) {
+        int t;
+        batch_shape_dims(c, waves, &t);
+        *maps_per_wave = 16 * t;
+    }
+    return Z3_OK;
+}
+
 Z3_API z3_status z3_estimate(z3_index idx, int map, int m_max, int prec, int64_t p0, int64_t p1,
                              double *zeta, uint64_t *pair_total, void *stream)
 {
@@ -307,6 +401,37 @@ Z3_API z3_status z3_estimate_maps(z3_index idx, int m_max, int prec, int64_t p0,
     if (idx->nmaps == 1) return z3_estimate(idx, 0, m_max, prec, p0, p1, zeta, pair_total, stream);
     const size_t elem = prec == Z3_PREC_FP64 ? 8 : 4;
     const size_t per_map_piv = (size_t)(m_max + 1) * 2 * idx->nbins * elem;
+    const size_t zstride = (size_t)(m_max + 1) * idx->nbins * idx->nbins * 2;
+    if (idx->nmaps > kMapGroup) {
+        // MFMA many-map kernel: all maps of a pivot chunk in one launch, then one
+        // contraction per map
+        int shape = 0;
+        if ((st = batch_shape(idx, m_max, prec, p0, p1, s, &shape)) != Z3_OK) return st;
+        int64_t chunk = chunk_pivots(idx, m_max, prec) / idx->nmaps;
+        chunk = (chunk / kBlock) * kBlock;
+        if (chunk < 4 * kBlock) chunk = 4 * kBlock;
+        if (chunk > p1 - p0) chunk = p1 - p0;
+        const size_t pbytes = contract_partial_bytes(chunk, m_max, idx->nbins);
+        void *wa = nullptr, *wp = nullptr;
+        if ((st = scratch_alloc(&wa, (size_t)idx->nmaps * chunk * per_map_piv, s)) != Z3_OK) return st;
+        if ((st = scratch_alloc(&wp, pbytes, s)) != Z3_OK) {
+            scratch_free(wa, s);
+            return st;
+        }
+        for (int64_t c0 = p0; c0 < p1 && st == Z3_OK; c0 += chunk) {
+            const int64_t c1 = c0 + chunk < p1 ? c0 + chunk : p1;
+            const size_t stride = (size_t)(c1 - c0) * (m_max + 1) * 2 * idx->nbins;
+            st = launch_multipoles_batch(idx, m_max, prec, shape, c0, c1, wa, c1 - c0, stride, nullptr, pair_total, s);
+            for (int map = 0; map < idx->nmaps && st == Z3_OK; ++map) {
+                const void *Ak = static_cast<const char *>(wa) + map * stride * elem;
+                st = launch_contract(c1 - c0, m_max, idx->nbins, prec, Ak, c1 - c0,
+                                     idx->d_v + (size_t)map * idx->n + c0, zeta + map * zstride, wp, pbytes, s);
+            }
+        }
+        scratch_free(wp, s);
+        scratch_free(wa, s);
+        return st;
+    }
     int64_t chunk = chunk_pivots(idx, m_max, prec) / kMapGroup;
     chunk = (chunk / kBlock) * kBlock;
     if (chunk < 16 * kBlock) chunk = 16 * kBlock;
@@ -319,7 +444,6 @@ Z3_API z3_status z3_estimate_maps(z3_index idx, int m_max, int prec, int64_t p0,
         scratch_free(wa, s);
         return st;
     }
-    const size_t zstride = (size_t)(m_max + 1) * idx->nbins * idx->nbins * 2;
     for (int g = 0; g < idx->ngroups && st == Z3_OK; ++g) {
         for (int64_t c0 = p0; c0 < p1 && st == Z3_OK; c0 += chunk) {
             int64_t c1 = c0 + chunk < p1 ? c0 + chunk : p1;
@@ -418,7 +542,7 @@ Z3_API z3_status z3_adjoint_maps(z3_index idx, int m_max, int64_t p0, int64_t p1
     if (!G || !grad_x) return fail(Z3_ERR_INVALID_ARG, "z3_adjoint_maps: G or grad_x is NULL");
     if (idx->nmaps == 1) return z3_adjoint(idx, 0, m_max, p0, p1, G, scale, grad_x, stream);
     return adjoint_maps_impl(idx, m_max, p0, p1, G, scale, grad_x, as_stream(stream),
-                             chunk_pivots(idx, m_max, Z3_PREC_FP64) / (2 * kMapGroup));
+                             chunk_pivots(idx, m_max, Z3_PREC_FP64));
 }
 
 Z3_API z3_status z3_pivot_weight_sum(z3_index idx, int64_t p0, int64_t p1, double *out, void *stream)

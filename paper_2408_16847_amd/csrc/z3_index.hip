@@ -223,6 +223,25 @@ __global__ void k_group_values(int64_t n, int nmaps, const int *band, const Band
     }
 }
 
+// Per-record value matrix of the MFMA many-map kernel: row q of the doubled-band order
+// holds the ldv map values of its point (maps >= nmaps are 0).  One thread per (point, map).
+__global__ void k_value_matrix(int64_t n, int nmaps, int ldv, const int *band, const Band *bands, const double *v,
+                               double *out64, float *out32)
+{
+    const int64_t total = n * ldv;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = t / ldv;
+        const int m = (int)(t - i * ldv);
+        const Band &bd = bands[band[i]];
+        const int64_t q = 2 * (int64_t)bd.pt_start + (i - bd.pt_start);
+        const double val = m < nmaps ? v[(size_t)m * n + i] : 0.0;
+        out64[q * ldv + m] = val;
+        out64[(q + bd.npts) * ldv + m] = val;
+        out32[q * ldv + m] = (float)val;
+        out32[(q + bd.npts) * ldv + m] = (float)val;
+    }
+}
+
 __global__ void k_gather_int(int64_t n, const int *perm, const int *in, int *out)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -308,7 +327,7 @@ static void free_ptrs(z3_index idx)
 {
     void *ps[] = {idx->d_edges, idx->d_bands, idx->d_cell_start, idx->d_x, idx->d_y, idx->d_z,
                   idx->d_w, idx->d_perm, idx->d_band, idx->d_wdbl, idx->d_permdbl, idx->d_v, idx->d_rec,
-                  idx->d_vgrp};
+                  idx->d_vgrp, idx->d_vmat64, idx->d_vmat32};
     for (void *p : ps)
         if (p) (void)hipFree(p);
 }
@@ -524,8 +543,12 @@ z3_status set_values_impl(z3_index idx, int nmaps, const double *x, hipStream_t 
     if (idx->d_v) { (void)hipFree(idx->d_v); idx->d_v = nullptr; }
     if (idx->d_rec) { (void)hipFree(idx->d_rec); idx->d_rec = nullptr; }
     if (idx->d_vgrp) { (void)hipFree(idx->d_vgrp); idx->d_vgrp = nullptr; }
+    if (idx->d_vmat64) { (void)hipFree(idx->d_vmat64); idx->d_vmat64 = nullptr; }
+    if (idx->d_vmat32) { (void)hipFree(idx->d_vmat32); idx->d_vmat32 = nullptr; }
     idx->nmaps = 0;
     idx->ngroups = 0;
+    for (auto &row : idx->batch_shape_tuned)
+        for (int &t : row) t = 0;
     size_t cnt = (size_t)nmaps * (size_t)idx->n;
     if ((st = dalloc(&idx->d_v, cnt, "alloc values")) != Z3_OK) return st;
     if ((st = dalloc(&idx->d_rec, 2 * cnt, "alloc records")) != Z3_OK) return st;
@@ -546,6 +569,16 @@ z3_status set_values_impl(z3_index idx, int nmaps, const double *x, hipStream_t 
             if ((st = check_launch("k_group_values")) != Z3_OK) return st;
         }
         idx->ngroups = ng;
+        const int ldv = batch_ldv(nmaps);
+        if ((st = dalloc(&idx->d_vmat64, (size_t)2 * idx->n * ldv, "alloc value matrix")) != Z3_OK) return st;
+        if ((st = dalloc(&idx->d_vmat32, (size_t)2 * idx->n * ldv, "alloc value matrix")) != Z3_OK) return st;
+        if (idx->n > 0) {
+            const int64_t nt = idx->n * ldv;
+            const int64_t g = (nt + 255) / 256 < (1 << 20) ? (nt + 255) / 256 : (1 << 20);
+            hipLaunchKernelGGL(k_value_matrix, dim3((unsigned)g), dim3(256), 0, s, idx->n, nmaps, ldv,
+                               idx->d_band, idx->d_bands, idx->d_v, idx->d_vmat64, idx->d_vmat32);
+            if ((st = check_launch("k_value_matrix")) != Z3_OK) return st;
+        }
     }
     idx->nmaps = nmaps;
     return Z3_OK;

@@ -71,6 +71,12 @@ struct z3_index_s {
     double4 *d_rec = nullptr;         // [nmaps][2n] {x, y, z, w * x}
     int ngroups = 0;                  // map groups of kMapGroup for the many-map kernel
     double *d_vgrp = nullptr;         // [ngroups][2n][kMapGroup] w * x, doubled bands
+    // per-record value matrices of the MFMA many-map kernel: [2n][ldv] w * x, doubled
+    // bands, maps padded with zeros to ldv = a multiple of 32
+    double *d_vmat64 = nullptr;
+    float *d_vmat32 = nullptr;
+    int batch_shape_forced = -1;      // -1: autotune; else a block shape id
+    int batch_shape_tuned[2][Z3_MAX_MMAX + 1] = {};  // [prec][m_max] -> shape id + 1 (0 = not yet)
 };
 
 namespace z3 {
@@ -96,6 +102,13 @@ z3_status launch_multipoles(const z3_index_s *idx, Pivots piv, int map, int m_ma
                             int64_t *counts, uint64_t *idhash, uint64_t *pair_total,
                             hipStream_t s);
 
+int batch_ldv(int nmaps);
+int batch_num_shapes();
+void batch_shape_dims(int shape, int *waves, int *tiles_per_wave);
+z3_status batch_shape(z3_index idx, int m_max, int prec, int64_t p0, int64_t p1, hipStream_t s, int *shape);
+z3_status launch_multipoles_batch(const z3_index_s *idx, int m_max, int prec, int shape, int64_t p0, int64_t p1,
+                                  void *A, int64_t ldA, size_t map_stride, double *W, uint64_t *pair_total,
+                                  hipStream_t s);
 z3_status launch_multipoles_maps(const z3_index_s *idx, int group, int m_max, int prec, int64_t p0,
                                  int64_t p1, void *A, int64_t ldA, size_t map_stride, double *W,
                                  uint64_t *pair_total, hipStream_t s);

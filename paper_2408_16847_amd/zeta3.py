@@ -82,6 +82,16 @@ class Index:
         _lib.call("z3_index_perm", self._h, _ptr(out), _stream())
         return out
 
+    def set_batch_shape(self, waves: int = 0, maps_per_wave: int = 0):
+        """MFMA many-map kernel block shape: (waves per block, maps per wave), (0, 0) to autotune."""
+        _lib.call("z3_index_set_batch_shape", self._h, int(waves), int(maps_per_wave))
+
+    def batch_shape(self, m_max: int, prec: str = "mixed"):
+        """The fixed or tuned (waves, maps per wave) for (m_max, prec); (0, 0) if not tuned yet."""
+        w, t = ctypes.c_int(), ctypes.c_int()
+        _lib.call("z3_index_batch_shape", self._h, m_max, PREC[prec], ctypes.byref(w), ctypes.byref(t))
+        return w.value, t.value
+
     def free(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             torch.cuda.current_stream().synchronize()

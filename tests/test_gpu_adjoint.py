@@ -89,21 +89,23 @@ def test_autograd_quadratic_loss_batch_of_maps():
         assert np.abs(gx[s] - go).max() <= 1e-10 * np.abs(go).max()
 
 
-def test_adjoint_maps_matches_per_map_adjoint(monkeypatch):
-    """z3_adjoint_maps (multipoles of four maps recomputed together, several pivot chunks,
-    a partial last group, a pivot sub-range) against z3_adjoint map by map."""
-    G.say("case: adjoint_maps vs per-map adjoint")
+@pytest.mark.parametrize("nmaps", [3, 6])
+def test_adjoint_maps_matches_per_map_adjoint(monkeypatch, nmaps):
+    """z3_adjoint_maps (multipoles of several maps recomputed together: the register-tiled
+    kernel for 3 maps, the MFMA kernel for 6; several pivot chunks, a pivot sub-range)
+    against z3_adjoint map by map."""
+    G.say("case: adjoint_maps vs per-map adjoint", nmaps)
     monkeypatch.setenv("Z3_WORKSPACE_MB", "1")
     xyz, w, _ = pins.random_cap(3000, 5.0, 17)
     E = pins.small_edges(6, lo=0.1, hi=2.5, log=True)
     M = 6
     rng = np.random.default_rng(4)
-    xs = rng.normal(size=(6, xyz.shape[1]))
+    xs = rng.normal(size=(nmaps, xyz.shape[1]))
     idx = G.build(xyz, xs, E, w=w)
-    Gs = torch.stack([_G_tensor(_rand_G(20 + k, M, 6)) for k in range(6)])
+    Gs = torch.stack([_G_tensor(_rand_G(20 + k, M, 6)) for k in range(nmaps)])
     p0, p1 = 37, 2811
     got = z3.adjoint_maps(idx, Gs, 0.5, M, p0=p0, p1=p1).cpu().numpy()
-    for k in range(6):
+    for k in range(nmaps):
         ref = z3.adjoint(idx, Gs[k], 0.5, M, map_index=k, p0=p0, p1=p1).cpu().numpy()
         err = np.abs(got[k] - ref).max() / np.abs(ref).max()
         G.say("map", k, "rel err", err)
