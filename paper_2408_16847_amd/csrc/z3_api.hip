@@ -404,14 +404,14 @@ Z3_API z3_status z3_estimate_maps(z3_index idx, int m_max, int prec, int64_t p0,
     const size_t zstride = (size_t)(m_max + 1) * idx->nbins * idx->nbins * 2;
     if (idx->nmaps > kMapGroup) {
         // MFMA many-map kernel: all maps of a pivot chunk in one launch, then one
-        // contraction per map
+        // contraction launch for all maps
         int shape = 0;
         if ((st = batch_shape(idx, m_max, prec, p0, p1, s, &shape)) != Z3_OK) return st;
         int64_t chunk = chunk_pivots(idx, m_max, prec) / idx->nmaps;
         chunk = (chunk / kBlock) * kBlock;
         if (chunk < 4 * kBlock) chunk = 4 * kBlock;
         if (chunk > p1 - p0) chunk = p1 - p0;
-        const size_t pbytes = contract_partial_bytes(chunk, m_max, idx->nbins);
+        const size_t pbytes = contract_partial_bytes(chunk, m_max, idx->nbins) * idx->nmaps;
         void *wa = nullptr, *wp = nullptr;
         if ((st = scratch_alloc(&wa, (size_t)idx->nmaps * chunk * per_map_piv, s)) != Z3_OK) return st;
         if ((st = scratch_alloc(&wp, pbytes, s)) != Z3_OK) {
@@ -422,11 +422,9 @@ Z3_API z3_status z3_estimate_maps(z3_index idx, int m_max, int prec, int64_t p0,
             const int64_t c1 = c0 + chunk < p1 ? c0 + chunk : p1;
             const size_t stride = (size_t)(c1 - c0) * (m_max + 1) * 2 * idx->nbins;
             st = launch_multipoles_batch(idx, m_max, prec, shape, c0, c1, wa, c1 - c0, stride, nullptr, pair_total, s);
-            for (int map = 0; map < idx->nmaps && st == Z3_OK; ++map) {
-                const void *Ak = static_cast<const char *>(wa) + map * stride * elem;
-                st = launch_contract(c1 - c0, m_max, idx->nbins, prec, Ak, c1 - c0,
-                                     idx->d_v + (size_t)map * idx->n + c0, zeta + map * zstride, wp, pbytes, s);
-            }
+            if (st == Z3_OK)
+                st = launch_contract_maps(c1 - c0, m_max, idx->nbins, prec, idx->nmaps, wa, c1 - c0, stride,
+                                          idx->d_v + c0, (size_t)idx->n, zeta, zstride, wp, pbytes, s);
         }
         scratch_free(wp, s);
         scratch_free(wa, s);
@@ -437,7 +435,7 @@ Z3_API z3_status z3_estimate_maps(z3_index idx, int m_max, int prec, int64_t p0,
     if (chunk < 16 * kBlock) chunk = 16 * kBlock;
     if (chunk > p1 - p0) chunk = ((p1 - p0 + kBlock - 1) / kBlock) * kBlock;
     const size_t map_stride = (size_t)chunk * (m_max + 1) * 2 * idx->nbins;  // elements
-    size_t pbytes = contract_partial_bytes(chunk, m_max, idx->nbins);
+    size_t pbytes = contract_partial_bytes(chunk, m_max, idx->nbins) * kMapGroup;
     void *wa = nullptr, *wp = nullptr;
     if ((st = scratch_alloc(&wa, (size_t)kMapGroup * chunk * per_map_piv, s)) != Z3_OK) return st;
     if ((st = scratch_alloc(&wp, pbytes, s)) != Z3_OK) {
@@ -451,13 +449,12 @@ Z3_API z3_status z3_estimate_maps(z3_index idx, int m_max, int prec, int64_t p0,
             const size_t stride = (size_t)(c1 - c0) * (m_max + 1) * 2 * idx->nbins;
             st = launch_multipoles_maps(idx, g, m_max, prec, c0, c1, wa, c1 - c0, stride, nullptr,
                                         g == 0 ? pair_total : nullptr, s);
-            for (int k = 0; k < kMapGroup && st == Z3_OK; ++k) {
-                const int map = g * kMapGroup + k;
-                if (map >= idx->nmaps) break;
-                const void *Ak = static_cast<const char *>(wa) + k * stride * elem;
-                st = launch_contract(c1 - c0, m_max, idx->nbins, prec, Ak, c1 - c0,
-                                     idx->d_v + (size_t)map * idx->n + c0, zeta + map * zstride, wp, pbytes, s);
-            }
+            const int map0 = g * kMapGroup;
+            const int nm = idx->nmaps - map0 < kMapGroup ? idx->nmaps - map0 : kMapGroup;
+            if (st == Z3_OK)
+                st = launch_contract_maps(c1 - c0, m_max, idx->nbins, prec, nm, wa, c1 - c0, stride,
+                                          idx->d_v + (size_t)map0 * idx->n + c0, (size_t)idx->n, zeta + map0 * zstride,
+                                          zstride, wp, pbytes, s);
         }
     }
     (void)map_stride;

@@ -38,13 +38,18 @@ struct ContractArgs {
     int64_t npiv;
     const double *v;
     int nb, T, ntp;
-    double *part;
+    int M1;              // m_max + 1; blockIdx.z = map * M1 + m
+    size_t a_stride;     // elements between the maps' multipoles
+    size_t v_stride;     // elements between the maps' pivot values
+    double *part;        // [seg][map][m][tile pair][256]
 };
 
 template <bool F32>
 __global__ __launch_bounds__(64) void k_gram_tiles(ContractArgs c)
 {
-    const int tp = blockIdx.x, seg = blockIdx.y, m = blockIdx.z;
+    const int tp = blockIdx.x, seg = blockIdx.y, m = blockIdx.z % c.M1;
+    const size_t map = blockIdx.z / c.M1;
+    c.v += map * c.v_stride;
     int I = 0, r = tp;
     while (r >= c.T - I) { r -= c.T - I; ++I; }
     const int J = I + r;
@@ -60,7 +65,7 @@ __global__ __launch_bounds__(64) void k_gram_tiles(ContractArgs c)
     const int64_t pend = min(c.npiv, pbeg + kSeg);
 
     if constexpr (!F32) {
-        const double *A = static_cast<const double *>(c.A);
+        const double *A = static_cast<const double *>(c.A) + map * c.a_stride;
         v4d acc = {0.0, 0.0, 0.0, 0.0};
         for (int64_t s = pbeg; s < pend; s += 16) {
 #pragma unroll
@@ -74,11 +79,11 @@ __global__ __launch_bounds__(64) void k_gram_tiles(ContractArgs c)
             }
         }
         // v_mfma_f64_16x16x4f64 result layout: register k of lane l holds D[4k + l/16][l % 16]
-        double *out = c.part + ((size_t)(seg * gridDim.z + m) * c.ntp + tp) * 256;
+        double *out = c.part + ((size_t)(seg * gridDim.z + blockIdx.z) * c.ntp + tp) * 256;
 #pragma unroll
         for (int k = 0; k < 4; ++k) out[(4 * k + kq) * 16 + row] = acc[k];
     } else {
-        const float *A = static_cast<const float *>(c.A);
+        const float *A = static_cast<const float *>(c.A) + map * c.a_stride;
         v4d acc = {0.0, 0.0, 0.0, 0.0};
         for (int64_t s = pbeg; s < pend; s += 16) {
             // FP32 products and sums over 16 pivots, then into the FP64 segment sum
@@ -101,7 +106,7 @@ __global__ __launch_bounds__(64) void k_gram_tiles(ContractArgs c)
             for (int k = 0; k < 4; ++k) acc[k] += (double)part[k];
         }
         // v_mfma_f32_16x16x4f32 result layout: register k of lane l holds D[4 (l/16) + k][l % 16]
-        double *out = c.part + ((size_t)(seg * gridDim.z + m) * c.ntp + tp) * 256;
+        double *out = c.part + ((size_t)(seg * gridDim.z + blockIdx.z) * c.ntp + tp) * 256;
 #pragma unroll
         for (int k = 0; k < 4; ++k) out[(4 * kq + k) * 16 + row] = (double)acc[k];
     }
@@ -116,48 +121,61 @@ __device__ __forceinline__ double gram_at(const double *seg_m, int T, int u, int
     return seg_m[(size_t)tp * 256 + (u & 15) * 16 + (v & 15)];
 }
 
-__global__ void k_gram_reduce(const double *part, int64_t nseg, int M1, int nb, int T, int ntp, double *zeta)
+__global__ void k_gram_reduce(const double *part, int64_t nseg, int nmaps, int M1, int nb, int T, int ntp,
+                              double *zeta, size_t z_stride)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    const int total = M1 * nb * nb;
+    const int total = nmaps * M1 * nb * nb;
     if (t >= total) return;
-    const int m = t / (nb * nb), rem = t % (nb * nb), b1 = rem / nb, b2 = rem % nb;
+    const int mm = t / (nb * nb), rem = t % (nb * nb), b1 = rem / nb, b2 = rem % nb;
+    const int map = mm / M1, m = mm % M1;
     const int r1 = b1, r2 = b2, i1 = nb + b1, i2 = nb + b2;
     double rr = 0.0, ii = 0.0, ir = 0.0, ri = 0.0;
     for (int64_t s = 0; s < nseg; ++s) {
-        const double *g = part + (size_t)(s * M1 + m) * ntp * 256;
+        const double *g = part + (size_t)((s * nmaps + map) * M1 + m) * ntp * 256;
         rr += gram_at(g, T, r1, r2);
         ii += gram_at(g, T, i1, i2);
         ir += gram_at(g, T, i1, r2);
         ri += gram_at(g, T, r1, i2);
     }
-    double *z = zeta + ((size_t)(m * nb + b1) * nb + b2) * 2;
+    double *z = zeta + map * z_stride + ((size_t)(m * nb + b1) * nb + b2) * 2;
     z[0] += rr + ii;
     z[1] += ir - ri;
+}
+
+z3_status launch_contract_maps(int64_t npiv, int m_max, int nbins, int prec, int nmaps, const void *A, int64_t ldA,
+                               size_t a_stride, const double *piv_v, size_t v_stride, double *zeta, size_t z_stride,
+                               void *partials, size_t partial_bytes, hipStream_t s)
+{
+    if (npiv <= 0 || nmaps <= 0) return Z3_OK;
+    const int T = tiles_for(nbins), ntp = T * (T + 1) / 2;
+    const int64_t nseg = (npiv + kSeg - 1) / kSeg;
+    if (contract_partial_bytes(npiv, m_max, nbins) * (size_t)nmaps > partial_bytes)
+        return fail(Z3_ERR_INVALID_ARG, "contraction workspace too small");
+    if (nseg > 65535) return fail(Z3_ERR_OVERFLOW, "too many pivots for one contraction (%lld)", (long long)npiv);
+    if ((int64_t)nmaps * (m_max + 1) > 65535) return fail(Z3_ERR_OVERFLOW, "too many maps for one contraction");
+    ContractArgs c;
+    c.A = A; c.ldA = ldA; c.npiv = npiv; c.v = piv_v; c.nb = nbins; c.T = T; c.ntp = ntp;
+    c.M1 = m_max + 1;
+    c.a_stride = a_stride;
+    c.v_stride = v_stride;
+    c.part = static_cast<double *>(partials);
+    dim3 grid(ntp, (unsigned)nseg, (unsigned)(nmaps * (m_max + 1)));
+    if (prec == Z3_PREC_MIXED) hipLaunchKernelGGL(k_gram_tiles<true>, grid, dim3(64), 0, s, c);
+    else hipLaunchKernelGGL(k_gram_tiles<false>, grid, dim3(64), 0, s, c);
+    z3_status st = check_launch("k_gram_tiles");
+    if (st != Z3_OK) return st;
+    const int total = nmaps * (m_max + 1) * nbins * nbins;
+    hipLaunchKernelGGL(k_gram_reduce, dim3((total + 127) / 128), dim3(128), 0, s,
+                       static_cast<const double *>(partials), nseg, nmaps, m_max + 1, nbins, T, ntp, zeta, z_stride);
+    return check_launch("k_gram_reduce");
 }
 
 z3_status launch_contract(int64_t npiv, int m_max, int nbins, int prec, const void *A, int64_t ldA,
                           const double *piv_v, double *zeta, void *partials, size_t partial_bytes,
                           hipStream_t s)
 {
-    if (npiv <= 0) return Z3_OK;
-    const int T = tiles_for(nbins), ntp = T * (T + 1) / 2;
-    const int64_t nseg = (npiv + kSeg - 1) / kSeg;
-    if (contract_partial_bytes(npiv, m_max, nbins) > partial_bytes)
-        return fail(Z3_ERR_INVALID_ARG, "contraction workspace too small");
-    if (nseg > 65535) return fail(Z3_ERR_OVERFLOW, "too many pivots for one contraction (%lld)", (long long)npiv);
-    ContractArgs c;
-    c.A = A; c.ldA = ldA; c.npiv = npiv; c.v = piv_v; c.nb = nbins; c.T = T; c.ntp = ntp;
-    c.part = static_cast<double *>(partials);
-    dim3 grid(ntp, (unsigned)nseg, m_max + 1);
-    if (prec == Z3_PREC_MIXED) hipLaunchKernelGGL(k_gram_tiles<true>, grid, dim3(64), 0, s, c);
-    else hipLaunchKernelGGL(k_gram_tiles<false>, grid, dim3(64), 0, s, c);
-    z3_status st = check_launch("k_gram_tiles");
-    if (st != Z3_OK) return st;
-    const int total = (m_max + 1) * nbins * nbins;
-    hipLaunchKernelGGL(k_gram_reduce, dim3((total + 127) / 128), dim3(128), 0, s,
-                       static_cast<const double *>(partials), nseg, m_max + 1, nbins, T, ntp, zeta);
-    return check_launch("k_gram_reduce");
+    return launch_contract_maps(npiv, m_max, nbins, prec, 1, A, ldA, 0, piv_v, 0, zeta, 0, partials, partial_bytes, s);
 }
 
 // ---- sum of pivot weights (fixed order) ------------------------------------------------

@@ -117,6 +117,11 @@ z3_status launch_multipoles_maps(const z3_index_s *idx, int group, int m_max, in
 z3_status launch_contract(int64_t npiv, int m_max, int nbins, int prec, const void *A,
                           int64_t ldA, const double *piv_v, double *zeta, void *partials,
                           size_t partial_bytes, hipStream_t s);
+// nmaps contractions in one launch: map k reads A + k a_stride, piv_v + k v_stride and adds
+// into zeta + k z_stride; partials hold nmaps x contract_partial_bytes
+z3_status launch_contract_maps(int64_t npiv, int m_max, int nbins, int prec, int nmaps, const void *A, int64_t ldA,
+                               size_t a_stride, const double *piv_v, size_t v_stride, double *zeta, size_t z_stride,
+                               void *partials, size_t partial_bytes, hipStream_t s);
 size_t contract_partial_bytes(int64_t npiv, int m_max, int nbins);
 z3_status launch_weight_sum(const double *w, int64_t n, double *out, hipStream_t s);
 z3_status launch_pivot_values(const double *w, const double *x, int64_t n, double *v, hipStream_t s);
