@@ -23,6 +23,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "pair-multipole updates/s; ζ_m wall time Nside=2048, mixed vs FP64 at 1e-6"
 PEAK_VALU_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz (non-packed FP32 or FP64 FMA)
+PEAK_MFMA_TFLOPS = {"mixed": 157.3, "fp64": 78.6}  # dense FP32 / FP64 matrix cores
 FLOPS_PER_UPDATE = 12.5  # algorithmic flops per (pair, m) at m_max = 10: 10 per m + ~35 per pair / 11
 
 
@@ -124,6 +125,12 @@ def main():
     ap.add_argument("--save-zeta", default="", help="write the zeta_m of each precision to this .npz")
     ap.add_argument("--adjoint", action="store_true",
                     help="each step also back-propagates L = sum |zeta - t|^2 (random targets) to the field")
+    ap.add_argument("--graph", action="store_true",
+                    help="with --adjoint: positions fixed, index built once; each step replays one captured HIP "
+                         "graph (new values, forward of all maps, adjoint)")
+    ap.add_argument("--fd-check", type=int, default=0,
+                    help="with --adjoint: check the gradient at this many random (map, pixel) entries against "
+                         "central differences of the FP64 forward (after the timed steps)")
     ap.add_argument("--cpu-sample", type=int, default=-1, help="oracle pivots (-1: automatic, 0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (for HBM counter calibration)")
@@ -198,7 +205,34 @@ def main():
             _pairs[prec] = int(pt.item())
         return _pairs[prec]
 
+    if args.graph and not args.adjoint:
+        sys.exit("--graph needs --adjoint")
+    graphs = {}
+    last = {}
+
+    def graph_step(prec):
+        # index and captured graph built once per precision (outside the timed steps)
+        if prec not in graphs:
+            idx = z3.Index(xyz, E)
+            idx.set_values(x)
+            z0 = z3.estimate_maps_raw(idx, M, prec) if cfg.nmaps > 1 else z3.estimate_raw(idx, M, prec).unsqueeze(0)
+            sw = torch.zeros(1, dtype=torch.float64, device="cuda")
+            z3.zeta3._lib.call("z3_pivot_weight_sum", idx.handle, 0, idx.n, z3.zeta3._ptr(sw), z3.zeta3._stream())
+            t = targets((z0 / sw).reshape((cfg.nmaps,) + tuple(z0.shape[1:])))
+            graphs[prec] = (idx, z3.GraphStep(idx, M, t, prec=prec))
+            log(f"[bench] {prec}: graph captured, workspace {graphs[prec][1].workspace_bytes / 2**30:.2f} GiB")
+        idx, gs = graphs[prec]
+        zt, g = gs.run(x.reshape(cfg.nmaps, n))
+        grads.append(float(g.abs().max()))
+        last["x"], last["zeta"], last["grad"], last["target"] = x, zt, g, gs.target
+        zh = zt.cpu().numpy()
+        if cfg.nmaps == 1:
+            zh = zh[0]
+        return zh[..., 0] + 1j * zh[..., 1], pairs_of(idx, prec)
+
     def step(prec):
+        if args.graph:
+            return graph_step(prec)
         zeta = torch.zeros((M + 1, cfg.nbins, cfg.nbins, 2), dtype=torch.float64, device="cuda")
         pairs = torch.zeros(1, dtype=torch.int64, device="cuda")
         sw = torch.zeros(1, dtype=torch.float64, device="cuda")
@@ -209,6 +243,7 @@ def main():
             loss = ((zt - targets(zt)) ** 2).sum()
             loss.backward()
             grads.append(float(xg.grad.abs().max()))
+            last["x"], last["zeta"], last["grad"], last["target"] = x, zt.detach(), xg.grad, targets(zt)
             zh = zt.detach().cpu().numpy()
             npairs = pairs_of(idx, prec)
             idx.free()
@@ -263,7 +298,16 @@ def main():
         log(f"[bench] adjoint: max |dL/dx| {max(grads):.3g}")
     launches_per_step = r["kernel_launches"] / args.steps
     kern_s_per_step = r["kernel_ms_total"] / args.steps / 1e3
-    achieved = FLOPS_PER_UPDATE * updates / kern_s_per_step / 1e12
+    if cfg.nmaps > 4:
+        # MFMA many-map kernel: one FMA per (pair, map, harmonic column) is the useful work
+        rf_kernel, rf_bound, rf_peak = "k_multipoles_batch", "mfma", PEAK_MFMA_TFLOPS[main_prec]
+        rf_flops = 2.0 * (2 * M + 1) * r["pairs"] * cfg.nmaps
+        rf_unit_note = "2 (2 m_max + 1) flop per (pair, map)"
+    else:
+        rf_kernel, rf_bound, rf_peak = "k_multipoles", "alu", PEAK_VALU_TFLOPS
+        rf_flops = FLOPS_PER_UPDATE * updates
+        rf_unit_note = f"{FLOPS_PER_UPDATE} flop per pair-multipole update"
+    achieved = rf_flops / kern_s_per_step / 1e12 if kern_s_per_step > 0 else None
     out = {
         "metric": METRIC,
         "value": value,
@@ -281,11 +325,13 @@ def main():
                    "npoints": n, "nmaps": cfg.nmaps, "nbins": cfg.nbins, "m_max": M,
                    "theta_arcmin": [cfg.theta_min * 10800 / np.pi, cfg.theta_max * 10800 / np.pi],
                    "log_bins": cfg.log_bins, "precision": main_prec, "pairs": r["pairs"]},
-        "roofline": {"bound": "alu", "kernel": "k_multipoles", "achieved": achieved,
-                     "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_VALU_TFLOPS,
-                     "traffic": measured_traffic(cfg.name, main_prec),
-                     "traffic_unit": "bytes per launch", "avg_launch_ms": r["kernel_ms_total"] / max(r["kernel_launches"], 1),
-                     "launches_per_step": launches_per_step, "flops_per_update": FLOPS_PER_UPDATE},
+        "roofline": {"bound": rf_bound, "kernel": rf_kernel, "achieved": achieved,
+                     "peak": rf_peak, "unit": "TFLOP/s", "frac": achieved / rf_peak if achieved else None,
+                     "traffic": measured_traffic(cfg.name, main_prec) if rf_kernel == "k_multipoles" else None,
+                     "traffic_unit": "bytes per launch",
+                     "avg_launch_ms": r["kernel_ms_total"] / r["kernel_launches"] if r["kernel_launches"] else None,
+                     "launches_per_step": launches_per_step, "flops": rf_unit_note,
+                     **({"note": "kernel time is not measurable inside a graph replay"} if not achieved else {})},
     }
     for prec in res:
         out[f"zeta_wall_ms_{prec}"] = res[prec]["s_per_step"] * 1e3
@@ -297,11 +343,59 @@ def main():
         out["speedup_mixed_vs_fp64"] = res["fp64"]["s_per_step"] / res["mixed"]["s_per_step"]
         out["pairs_equal"] = res["fp64"]["pairs"] == res["mixed"]["pairs"]
 
+    if args.adjoint and args.fd_check > 0:
+        out["fd_check"] = fd_check(cfg, xyz, E, M, last, args.fd_check, z3, torch)
+        log(f"[bench] fd check: {out['fd_check']}")
+    if args.graph:
+        out["config"]["graph"] = "index built once; each step = one replay of a captured HIP graph " \
+                                 "(value update, forward of all maps, loss gradient, adjoint)"
+        out["config"]["workload"] += "+graph"
     if args.save_zeta:
         np.savez(args.save_zeta, **{p: res[p]["zeta"] for p in res})
     if args.cpu_sample != 0 and cfg.nmaps == 1:
         out["cpu_baseline"] = cpu_baseline(cfg, xyz, x, nbr, E, M, args.cpu_sample, z3, torch)
     print(json.dumps(out), flush=True)
+
+
+def fd_check(cfg, xyz, E, M, last, k, z3, torch):
+    """Gradient of L = sum (zeta - t)^2 at k random (map, pixel) entries against central
+    differences of the FP64 forward.  zeta is a quadratic function of any single value x_i
+    (x_i enters as a pivot value and through the multipoles of its neighbours' bins), so
+    the central difference of zeta is exact up to rounding for any step h; the adjoint
+    computes sum_G G . dzeta/dx_i with G = 2 (zeta - t) at the evaluated forward."""
+    x = last["x"].reshape(cfg.nmaps, -1)
+    n = x.shape[1]
+    G = (2.0 * (last["zeta"] - last["target"])).reshape(cfg.nmaps, M + 1, cfg.nbins, cfg.nbins, 2)
+    grad = last["grad"].reshape(cfg.nmaps, n)
+    rng = np.random.default_rng(4_000_000)
+    maps = rng.integers(0, cfg.nmaps, size=k)
+    pix = rng.choice(n, size=k, replace=False)
+    idx = z3.Index(xyz, E)
+    idx.set_values(x[0].contiguous())
+    sw = torch.zeros(1, dtype=torch.float64, device="cuda")
+    z3.zeta3._lib.call("z3_pivot_weight_sum", idx.handle, 0, n, z3.zeta3._ptr(sw), z3.zeta3._stream())
+    scale = 1.0 / float(sw.item())
+    fd, ad = [], []
+    t0 = time.perf_counter()
+    for s_, i in zip(maps, pix):
+        xm = x[s_].clone()
+        h = 32.0 * float(xm.std())
+        zs = []
+        for sign in (1.0, -1.0):
+            xp = xm.clone()
+            xp[i] += sign * h
+            idx.update_values(xp)
+            zs.append(z3.estimate_raw(idx, M, "fp64") * scale)
+        dz = (zs[0] - zs[1]) / (2.0 * h)
+        fd.append(float((G[s_] * dz).sum()))
+        ad.append(float(grad[s_, i]))
+    idx.free()
+    fd, ad = np.array(fd), np.array(ad)
+    err = np.abs(ad - fd) / np.abs(fd).max()
+    return {"entries": k, "max_rel_err": float(err.max()), "median_rel_err": float(np.median(err)),
+            "max_abs_grad": float(np.abs(fd).max()), "seconds": time.perf_counter() - t0,
+            "note": "relative to the largest sampled gradient; FP64 forward differences, exact for the "
+                    "quadratic dependence of zeta on one value"}
 
 
 def cpu_baseline(cfg, xyz, x, nbr, E, M, nsample, z3, torch):

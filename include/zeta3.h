@@ -97,6 +97,31 @@ z3_status z3_build_index(int64_t n, const double *xyz, const double *w, int nbin
  */
 z3_status z3_index_set_values(z3_index idx, int nmaps, const double *x, void *stream);
 
+/*
+ * Replace the values of the attached maps in place: x [nmaps][n] FP64 (catalogue order),
+ * nmaps as attached by z3_index_set_values.  Enqueues kernels only on `stream` (no host
+ * synchronisation, no allocation), so it can be captured in a HIP graph with the estimator
+ * and the adjoint; work already queued on other streams that reads the old values must be
+ * ordered before it by the caller.  Tuned block shapes are kept.
+ */
+z3_status z3_index_update_values(z3_index idx, const double *x, void *stream);
+
+/*
+ * Graph capture.  The estimator and adjoint calls take their chunk workspaces from the
+ * library's stream-ordered memory pool; while their stream is being captured into a HIP
+ * graph they take them instead from a workspace held by the index, so that the captured
+ * kernels point at memory that stays valid for every replay.  This call reserves that
+ * workspace: max(min_bytes, the largest total any eager call on this index has used so
+ * far) bytes, kept until z3_index_free; [host] reserved (may be NULL) receives the size.
+ * Run each call once eagerly with the arguments it will be captured with, then prepare,
+ * then capture.  A captured call whose needs exceed the reservation fails with
+ * Z3_ERR_INVALID_ARG (and the capture is then unusable).  Synchronises the device; growing
+ * the workspace frees the previous one, which invalidates graphs captured before.  Graphs
+ * captured on one index share the workspace: their replays must not overlap in time.
+ * z3_contract and z3_build_index / z3_index_set_values cannot be captured.
+ */
+z3_status z3_index_prepare_capture(z3_index idx, size_t min_bytes, size_t *reserved);
+
 /* Sizes of an index ([host] outputs, any may be NULL). */
 z3_status z3_index_info(z3_index idx, int64_t *n, int *nbins, int *nmaps, int *nbands,
                         int64_t *ncells);
@@ -233,8 +258,10 @@ const char *z3_last_error(void);
 
 /*
  * Kernel timing for measurement: when enabled, the library brackets every launch of
- * its multipole kernel with HIP events on the launch stream.  z3_profile_read waits
- * for those events and returns the number of launches and their summed duration.
+ * its forward multipole kernels (one-map, register-tiled many-map and MFMA many-map)
+ * with HIP events on the launch stream.  Launches made inside the adjoint calls and
+ * calls on a stream that is being captured into a graph are not timed.  z3_profile_read
+ * waits for those events and returns the number of launches and their summed duration.
  */
 z3_status z3_profile_enable(int on);
 z3_status z3_profile_read(int64_t *launches, double *total_ms, int reset);

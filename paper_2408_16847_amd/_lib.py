@@ -20,6 +20,8 @@ SIGNATURES = {
     "z3_build_index": (_I, [_I64, _P, _P, _I, _P, _D, _P, ctypes.POINTER(_P)]),
     "z3_index_set_values": (_I, [_P, _I, _P, _P]),
     "z3_index_info": (_I, [_P, _P, _P, _P, _P, _P]),
+    "z3_index_update_values": (_I, [_P, _P, _P]),
+    "z3_index_prepare_capture": (_I, [_P, ctypes.c_size_t, _P]),
     "z3_index_perm": (_I, [_P, _P, _P]),
     "z3_index_set_batch_shape": (_I, [_P, _I, _I]),
     "z3_index_batch_shape": (_I, [_P, _I, _I, _P, _P]),

@@ -276,8 +276,6 @@ static z3_status adjoint_chunk_maps(z3_index idx, int map, int nm, int m_max, in
     sa.n_stride = (size_t)idx->n;
     sa.rec_stride = (size_t)2 * idx->n;
     sa.d_stride = stride;
-    hipEvent_t ev0;
-    profile_begin(s, &ev0);
     switch (m_max) {
 #define Z3_CASE(MM) case MM: launch_scatter_m<MM>(sa, nm, s); break;
         Z3_CASE(0) Z3_CASE(1) Z3_CASE(2) Z3_CASE(3) Z3_CASE(4) Z3_CASE(5) Z3_CASE(6) Z3_CASE(7)
@@ -287,7 +285,6 @@ static z3_status adjoint_chunk_maps(z3_index idx, int map, int nm, int m_max, in
     default: st = fail(Z3_ERR_UNSUPPORTED, "m_max=%d not compiled", m_max);
     }
     if (st == Z3_OK) st = check_launch("k_adjoint_scatter");
-    profile_end(s, ev0);
     return st;
 }
 
@@ -302,6 +299,7 @@ static z3_status grad_to_catalogue(z3_index idx, const double *gs, double *grad_
 z3_status adjoint_impl(z3_index idx, int map, int m_max, int64_t p0, int64_t p1, const double *G, double scale,
                        double *grad_x, hipStream_t s, int64_t chunk)
 {
+    ProfileMute mute;  // the recomputed multipoles are not forward launches
     const int nb = idx->nbins;
     if (chunk > p1 - p0) chunk = ((p1 - p0 + kBlock - 1) / kBlock) * kBlock;
     if (chunk < kBlock) chunk = kBlock;
@@ -336,6 +334,7 @@ z3_status adjoint_impl(z3_index idx, int map, int m_max, int64_t p0, int64_t p1,
 z3_status adjoint_maps_impl(z3_index idx, int m_max, int64_t p0, int64_t p1, const double *G, double scale,
                             double *grad_x, hipStream_t s, int64_t budget)
 {
+    ProfileMute mute;  // the recomputed multipoles are not forward launches
     const int nb = idx->nbins;
     const bool batch = idx->nmaps > kMapGroup;
     int shape = 0;

@@ -64,17 +64,49 @@ static z3_status pool_for_current_device(hipMemPool_t *pool)
     return Z3_OK;
 }
 
+static thread_local CallScope *t_scope = nullptr;
+
+CallScope::CallScope(z3_index i, hipStream_t s) : idx(i), prev(t_scope)
+{
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) == hipSuccess) capturing = cs != hipStreamCaptureStatusNone;
+    t_scope = this;
+}
+
+CallScope::~CallScope()
+{
+    if (idx && !capturing && used > idx->ws_peak) idx->ws_peak = used;
+    t_scope = prev;
+}
+
 z3_status scratch_alloc(void **p, size_t bytes, hipStream_t s)
 {
     *p = nullptr;
+    const size_t aligned = ((bytes ? bytes : 1) + 255) / 256 * 256;
+    CallScope *sc = t_scope;
+    if (sc && sc->capturing) {
+        z3_index idx = sc->idx;
+        if (!idx) return fail(Z3_ERR_UNSUPPORTED, "this call needs scratch memory and cannot be captured in a graph");
+        if (sc->used + aligned > idx->cap_bytes)
+            return fail(Z3_ERR_INVALID_ARG,
+                        "graph capture needs %zu bytes of index workspace, %zu reserved: run the same call once "
+                        "eagerly, then z3_index_prepare_capture, before capturing",
+                        sc->used + aligned, idx->cap_bytes);
+        *p = static_cast<char *>(idx->cap_ws) + sc->used;
+        sc->used += aligned;
+        return Z3_OK;
+    }
     hipMemPool_t pool;
     z3_status st = pool_for_current_device(&pool);
     if (st != Z3_OK) return st;
-    return check_hip(hipMallocFromPoolAsync(p, bytes ? bytes : 1, pool, s), "hipMallocFromPoolAsync");
+    st = check_hip(hipMallocFromPoolAsync(p, aligned, pool, s), "hipMallocFromPoolAsync");
+    if (st == Z3_OK && sc) sc->used += aligned;
+    return st;
 }
 
 void scratch_free(void *p, hipStream_t s)
 {
+    if (t_scope && t_scope->capturing) return;  // a slice of the index's capture workspace
     if (p) (void)hipFreeAsync(p, s);
 }
 
@@ -85,12 +117,16 @@ static std::vector<std::pair<hipEvent_t, hipEvent_t>> g_prof_events;
 static int64_t g_prof_launches = 0;
 static double g_prof_ms = 0.0;
 
+static thread_local int t_prof_mute = 0;
+ProfileMute::ProfileMute() { ++t_prof_mute; }
+ProfileMute::~ProfileMute() { --t_prof_mute; }
+
 bool profiling() { return g_prof_on; }
 
 void profile_begin(hipStream_t s, hipEvent_t *ev0)
 {
     *ev0 = nullptr;
-    if (!g_prof_on) return;
+    if (!g_prof_on || t_prof_mute > 0 || (t_scope && t_scope->capturing)) return;
     if (hipEventCreate(ev0) != hipSuccess) { *ev0 = nullptr; return; }
     (void)hipEventRecord(*ev0, s);
 }
@@ -163,6 +199,33 @@ Z3_API z3_status z3_index_set_values(z3_index idx, int nmaps, const double *x, v
     return set_values_impl(idx, nmaps, x, as_stream(stream));
 }
 
+Z3_API z3_status z3_index_update_values(z3_index idx, const double *x, void *stream)
+{
+    if (!idx) return fail(Z3_ERR_INVALID_ARG, "z3_index_update_values: idx is NULL");
+    if (idx->n > 0 && (idx->nmaps < 1 || !idx->d_v))
+        return fail(Z3_ERR_INVALID_ARG, "z3_index_update_values: no values attached (z3_index_set_values)");
+    if (idx->n > 0 && !x) return fail(Z3_ERR_INVALID_ARG, "z3_index_update_values: x is NULL");
+    return update_values_impl(idx, x, as_stream(stream));
+}
+
+Z3_API z3_status z3_index_prepare_capture(z3_index idx, size_t min_bytes, size_t *reserved)
+{
+    if (!idx) return fail(Z3_ERR_INVALID_ARG, "z3_index_prepare_capture: idx is NULL");
+    const size_t want = idx->ws_peak > min_bytes ? idx->ws_peak : min_bytes;
+    if (want > idx->cap_bytes) {
+        z3_status st = check_hip(hipSetDevice(idx->device), "hipSetDevice");
+        if (st == Z3_OK) st = check_hip(hipDeviceSynchronize(), "hipDeviceSynchronize");
+        if (st != Z3_OK) return st;
+        if (idx->cap_ws) (void)hipFree(idx->cap_ws);
+        idx->cap_ws = nullptr;
+        idx->cap_bytes = 0;
+        if ((st = check_hip(hipMalloc(&idx->cap_ws, want), "hipMalloc (capture workspace)")) != Z3_OK) return st;
+        idx->cap_bytes = want;
+    }
+    if (reserved) *reserved = idx->cap_bytes;
+    return Z3_OK;
+}
+
 Z3_API z3_status z3_index_info(z3_index idx, int64_t *n, int *nbins, int *nmaps, int *nbands,
                                int64_t *ncells)
 {
@@ -232,6 +295,7 @@ Z3_API z3_status z3_accumulate_multipoles(z3_index idx, int map, int m_max, int 
 Z3_API z3_status z3_contract(int64_t npiv, int m_max, int nbins, int prec, const void *A,
                              const double *piv_v, double *zeta, void *stream)
 {
+    CallScope scope(nullptr, as_stream(stream));
     if (npiv < 0) return fail(Z3_ERR_INVALID_ARG, "z3_contract: npiv < 0");
     if (m_max < 0 || m_max > Z3_MAX_MMAX) return fail(Z3_ERR_INVALID_ARG, "z3_contract: bad m_max");
     if (nbins < 1 || nbins > Z3_MAX_NBINS) return fail(Z3_ERR_INVALID_ARG, "z3_contract: bad nbins");
@@ -361,6 +425,7 @@ Z3_API z3_status z3_index_batch_shape(z3_index idx, int m_max, int prec, int *wa
 Z3_API z3_status z3_estimate(z3_index idx, int map, int m_max, int prec, int64_t p0, int64_t p1,
                              double *zeta, uint64_t *pair_total, void *stream)
 {
+    CallScope scope(idx, as_stream(stream));
     z3_status st = check_common("z3_estimate", idx, map, m_max, prec, p0, p1);
     if (st != Z3_OK) return st;
     if (!zeta) return fail(Z3_ERR_INVALID_ARG, "z3_estimate: zeta is NULL");
@@ -393,6 +458,7 @@ Z3_API z3_status z3_estimate(z3_index idx, int map, int m_max, int prec, int64_t
 Z3_API z3_status z3_estimate_maps(z3_index idx, int m_max, int prec, int64_t p0, int64_t p1, double *zeta,
                                   uint64_t *pair_total, void *stream)
 {
+    CallScope scope(idx, as_stream(stream));
     z3_status st = check_common("z3_estimate_maps", idx, 0, m_max, prec, p0, p1);
     if (st != Z3_OK) return st;
     if (!zeta) return fail(Z3_ERR_INVALID_ARG, "z3_estimate_maps: zeta is NULL");
@@ -468,6 +534,7 @@ Z3_API z3_status z3_estimate_pivots(z3_index idx, int map, int64_t npiv, const d
                                     int64_t p0, int64_t p1, double *zeta, uint64_t *pair_total,
                                     double *sum_w, void *stream)
 {
+    CallScope scope(idx, as_stream(stream));
     if (!idx) return fail(Z3_ERR_INVALID_ARG, "z3_estimate_pivots: idx is NULL");
     if (npiv < 0) return fail(Z3_ERR_INVALID_ARG, "z3_estimate_pivots: npiv < 0");
     if (npiv >= (int64_t)0x7fffffff) return fail(Z3_ERR_OVERFLOW, "z3_estimate_pivots: npiv >= 2^31 - 1");
@@ -520,6 +587,7 @@ Z3_API z3_status z3_estimate_pivots(z3_index idx, int map, int64_t npiv, const d
 Z3_API z3_status z3_adjoint(z3_index idx, int map, int m_max, int64_t p0, int64_t p1, const double *G,
                             double scale, double *grad_x, void *stream)
 {
+    CallScope scope(idx, as_stream(stream));
     z3_status st = check_common("z3_adjoint", idx, map, m_max, Z3_PREC_FP64, p0, p1);
     if (st != Z3_OK) return st;
     if (!std::isfinite(scale)) return fail(Z3_ERR_INVALID_ARG, "z3_adjoint: scale is not finite");
@@ -532,6 +600,7 @@ Z3_API z3_status z3_adjoint(z3_index idx, int map, int m_max, int64_t p0, int64_
 Z3_API z3_status z3_adjoint_maps(z3_index idx, int m_max, int64_t p0, int64_t p1, const double *G, double scale,
                                  double *grad_x, void *stream)
 {
+    CallScope scope(idx, as_stream(stream));
     z3_status st = check_common("z3_adjoint_maps", idx, 0, m_max, Z3_PREC_FP64, p0, p1);
     if (st != Z3_OK) return st;
     if (!std::isfinite(scale)) return fail(Z3_ERR_INVALID_ARG, "z3_adjoint_maps: scale is not finite");
@@ -544,6 +613,7 @@ Z3_API z3_status z3_adjoint_maps(z3_index idx, int m_max, int64_t p0, int64_t p1
 
 Z3_API z3_status z3_pivot_weight_sum(z3_index idx, int64_t p0, int64_t p1, double *out, void *stream)
 {
+    CallScope scope(idx, as_stream(stream));
     if (!idx) return fail(Z3_ERR_INVALID_ARG, "z3_pivot_weight_sum: idx is NULL");
     if (p0 < 0 || p1 < p0 || p1 > idx->n) return fail(Z3_ERR_INVALID_ARG, "z3_pivot_weight_sum: bad range");
     if (!out) return fail(Z3_ERR_INVALID_ARG, "z3_pivot_weight_sum: out is NULL");

@@ -211,13 +211,14 @@ z3_status launch_weight_sum(const double *w, int64_t n, double *out, hipStream_t
     int nblk = (int)(want < 1024 ? want : 1024);
     if (nblk < 1) nblk = 1;
     const int64_t per = (n + nblk - 1) / nblk;
-    double *partial = nullptr;
-    z3_status st = check_hip(hipMallocAsync((void **)&partial, nblk * sizeof(double), s), "hipMallocAsync");
+    void *part = nullptr;
+    z3_status st = scratch_alloc(&part, nblk * sizeof(double), s);
     if (st != Z3_OK) return st;
+    double *partial = static_cast<double *>(part);
     hipLaunchKernelGGL(k_sum_partials, dim3(nblk), dim3(256), 0, s, w, n, per, partial);
     hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(64), 0, s, partial, nblk, out);
     st = check_launch("k_sum");
-    (void)hipFreeAsync(partial, s);
+    scratch_free(part, s);
     return st;
 }
 

@@ -327,7 +327,7 @@ static void free_ptrs(z3_index idx)
 {
     void *ps[] = {idx->d_edges, idx->d_bands, idx->d_cell_start, idx->d_x, idx->d_y, idx->d_z,
                   idx->d_w, idx->d_perm, idx->d_band, idx->d_wdbl, idx->d_permdbl, idx->d_v, idx->d_rec,
-                  idx->d_vgrp, idx->d_vmat64, idx->d_vmat32};
+                  idx->d_vgrp, idx->d_vmat64, idx->d_vmat32, idx->cap_ws};
     for (void *p : ps)
         if (p) (void)hipFree(p);
 }
@@ -536,6 +536,35 @@ z3_status build_index_impl(int64_t n, const double *xyz, const double *w, int nb
     return Z3_OK;
 }
 
+// Rebuild every per-map array from new values x [nmaps][n] (catalogue order) into the
+// buffers already attached: kernels only, on `s`.
+static z3_status fill_values(z3_index idx, int nmaps, const double *x, hipStream_t s)
+{
+    z3_status st;
+    if (idx->n == 0) return Z3_OK;
+    hipLaunchKernelGGL(k_gather_values, dim3(grid_for(idx->n)), dim3(256), 0, s, idx->n, nmaps, idx->d_perm,
+                       idx->d_w, x, idx->d_v);
+    hipLaunchKernelGGL(k_records, dim3(grid_for(idx->n)), dim3(256), 0, s, idx->n, nmaps, idx->d_band,
+                       idx->d_bands, idx->d_x, idx->d_y, idx->d_z, idx->d_v, idx->d_rec);
+    if ((st = check_launch("k_gather_values/k_records")) != Z3_OK) return st;
+    if (nmaps > 1) {
+        hipLaunchKernelGGL(k_group_values, dim3(grid_for(idx->n)), dim3(256), 0, s, idx->n, nmaps, idx->d_band,
+                           idx->d_bands, idx->d_v, idx->d_vgrp);
+        const int ldv = batch_ldv(nmaps);
+        const int64_t nt = idx->n * ldv;
+        const int64_t g = (nt + 255) / 256 < (1 << 20) ? (nt + 255) / 256 : (1 << 20);
+        hipLaunchKernelGGL(k_value_matrix, dim3((unsigned)g), dim3(256), 0, s, idx->n, nmaps, ldv, idx->d_band,
+                           idx->d_bands, idx->d_v, idx->d_vmat64, idx->d_vmat32);
+        if ((st = check_launch("k_group_values/k_value_matrix")) != Z3_OK) return st;
+    }
+    return Z3_OK;
+}
+
+z3_status update_values_impl(z3_index idx, const double *x, hipStream_t s)
+{
+    return fill_values(idx, idx->nmaps, x, s);
+}
+
 z3_status set_values_impl(z3_index idx, int nmaps, const double *x, hipStream_t s)
 {
     z3_status st;
@@ -552,34 +581,16 @@ z3_status set_values_impl(z3_index idx, int nmaps, const double *x, hipStream_t 
     size_t cnt = (size_t)nmaps * (size_t)idx->n;
     if ((st = dalloc(&idx->d_v, cnt, "alloc values")) != Z3_OK) return st;
     if ((st = dalloc(&idx->d_rec, 2 * cnt, "alloc records")) != Z3_OK) return st;
-    if (idx->n > 0) {
-        hipLaunchKernelGGL(k_gather_values, dim3(grid_for(idx->n)), dim3(256), 0, s, idx->n, nmaps, idx->d_perm,
-                           idx->d_w, x, idx->d_v);
-        hipLaunchKernelGGL(k_records, dim3(grid_for(idx->n)), dim3(256), 0, s, idx->n, nmaps, idx->d_band,
-                           idx->d_bands, idx->d_x, idx->d_y, idx->d_z, idx->d_v, idx->d_rec);
-        if ((st = check_launch("k_gather_values/k_records")) != Z3_OK) return st;
-    }
     if (nmaps > 1) {
         const int ng = (nmaps + kMapGroup - 1) / kMapGroup;
         if ((st = dalloc(&idx->d_vgrp, (size_t)ng * 2 * idx->n * kMapGroup, "alloc grouped values")) != Z3_OK)
             return st;
-        if (idx->n > 0) {
-            hipLaunchKernelGGL(k_group_values, dim3(grid_for(idx->n)), dim3(256), 0, s, idx->n, nmaps, idx->d_band,
-                               idx->d_bands, idx->d_v, idx->d_vgrp);
-            if ((st = check_launch("k_group_values")) != Z3_OK) return st;
-        }
         idx->ngroups = ng;
         const int ldv = batch_ldv(nmaps);
         if ((st = dalloc(&idx->d_vmat64, (size_t)2 * idx->n * ldv, "alloc value matrix")) != Z3_OK) return st;
         if ((st = dalloc(&idx->d_vmat32, (size_t)2 * idx->n * ldv, "alloc value matrix")) != Z3_OK) return st;
-        if (idx->n > 0) {
-            const int64_t nt = idx->n * ldv;
-            const int64_t g = (nt + 255) / 256 < (1 << 20) ? (nt + 255) / 256 : (1 << 20);
-            hipLaunchKernelGGL(k_value_matrix, dim3((unsigned)g), dim3(256), 0, s, idx->n, nmaps, ldv,
-                               idx->d_band, idx->d_bands, idx->d_v, idx->d_vmat64, idx->d_vmat32);
-            if ((st = check_launch("k_value_matrix")) != Z3_OK) return st;
-        }
     }
+    if ((st = fill_values(idx, nmaps, x, s)) != Z3_OK) return st;
     idx->nmaps = nmaps;
     return Z3_OK;
 }

@@ -77,9 +77,36 @@ struct z3_index_s {
     float *d_vmat32 = nullptr;
     int batch_shape_forced = -1;      // -1: autotune; else a block shape id
     int batch_shape_tuned[2][Z3_MAX_MMAX + 1] = {};  // [prec][m_max] -> shape id + 1 (0 = not yet)
+    // workspace of calls captured into a HIP graph (z3_index_prepare_capture): captured calls
+    // take their chunk buffers from here instead of allocating
+    void *cap_ws = nullptr;
+    size_t cap_bytes = 0;
+    size_t ws_peak = 0;               // largest scratch total of one eager call on this index
 };
 
 namespace z3 {
+
+// Scratch accounting of one API call on an index (z3_api.hip).  While it is alive,
+// scratch_alloc either allocates from the library's stream-ordered pool (eager calls; the
+// total is recorded in idx->ws_peak) or, when the stream is being captured into a graph,
+// hands out consecutive slices of idx->cap_ws (nothing is allocated, scratch_free is a
+// no-op), so that the captured kernels point at memory that stays valid for every replay.
+struct CallScope {
+    CallScope(z3_index idx, hipStream_t s);
+    ~CallScope();
+    CallScope(const CallScope &) = delete;
+    CallScope &operator=(const CallScope &) = delete;
+    z3_index idx;
+    bool capturing = false;
+    size_t used = 0;
+    CallScope *prev = nullptr;
+};
+
+// While alive on a thread, kernel timing (z3_profile_enable) skips that thread's launches.
+struct ProfileMute {
+    ProfileMute();
+    ~ProfileMute();
+};
 
 // error reporting (z3_api.hip)
 z3_status fail(z3_status s, const char *fmt, ...);
@@ -89,6 +116,7 @@ z3_status check_launch(const char *what);
 // index kernels (z3_index.hip)
 z3_status build_index_impl(int64_t n, const double *xyz, const double *w, int nbins,
                            const double *edges, double cell_size, hipStream_t s, z3_index *out);
+z3_status update_values_impl(z3_index idx, const double *x, hipStream_t s);
 z3_status set_values_impl(z3_index idx, int nmaps, const double *x, hipStream_t s);
 void free_index(z3_index idx);
 

@@ -67,6 +67,17 @@ class Index:
         self._values = x  # keep alive until the gather has run
         return self
 
+    def update_values(self, x):
+        """Replace the attached maps' values in place (same [nmaps, n] shape): kernels only,
+        no host synchronisation or allocation, so it can sit in a captured HIP graph.  The
+        caller keeps `x` alive until the stream has run."""
+        if not isinstance(x, torch.Tensor) or not x.is_cuda or x.dtype != torch.float64 or not x.is_contiguous():
+            raise TypeError("update_values needs a contiguous float64 CUDA tensor")
+        if x.numel() != self.nmaps * self.n:
+            raise ValueError("values must be [nmaps, n] with the attached nmaps")
+        _lib.call("z3_index_update_values", self._h, _ptr(x), _stream())
+        return self
+
     def info(self):
         n = ctypes.c_int64()
         nb = ctypes.c_int()
@@ -233,6 +244,64 @@ def adjoint_maps(idx: Index, G, scale: float, m_max: int, p0: int = 0, p1: int |
     G = _dev(G)
     _lib.call("z3_adjoint_maps", idx.handle, m_max, p0, p1, _ptr(G), float(scale), _ptr(grad), _stream())
     return grad
+
+
+class GraphStep:
+    """One field-level inference step captured in a HIP graph and replayed: new values of
+    every attached map, zeta of all maps (eq. zetamEst, normalised by 1/sum_p w_p), and
+    the gradient of L = sum (zeta - target)^2 with respect to the values (the adjoint).
+
+    The index must already hold values of the right shape ([nmaps, n]); the constructor
+    runs the step once eagerly (which also tunes the many-map block shape), then captures
+    it.  `run(x)` copies x into the static input and replays the graph; the returned zeta
+    [nmaps, m+1, nb, nb, 2] and grad [nmaps, n] are the graph's own buffers, overwritten by
+    the next run.  Everything inside is kernels (the library's value update, estimator,
+    contraction, adjoint, and torch elementwise ops); the library's chunk workspaces are a
+    fixed reservation held by the index (z3_index_prepare_capture), so nothing is allocated
+    inside the graph.  Replays of graphs captured on one index must not overlap.
+    """
+
+    def __init__(self, idx: "Index", m_max: int, target, prec: str = "mixed", stream=None):
+        self.idx, self.m_max, self.prec = idx, m_max, prec
+        nm, n, nb = idx.nmaps, idx.n, idx.nbins
+        self.x = torch.zeros((nm, n), dtype=torch.float64, device="cuda")
+        self.target = _dev(target).reshape(nm, m_max + 1, nb, nb, 2).clone()
+        self.zeta_raw = torch.zeros((nm, m_max + 1, nb, nb, 2), dtype=torch.float64, device="cuda")
+        self.zeta = torch.zeros_like(self.zeta_raw)
+        self.grad = torch.zeros((nm, n), dtype=torch.float64, device="cuda")
+        sw = torch.zeros(1, dtype=torch.float64, device="cuda")
+        _lib.call("z3_pivot_weight_sum", idx.handle, 0, n, _ptr(sw), _stream())
+        s = float(sw.item())
+        self.scale = 1.0 / s if s != 0.0 else 0.0
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        self.stream.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(self.stream):
+            self._body()  # eager: tunes the block shape, measures the workspace the calls use
+        torch.cuda.current_stream().wait_stream(self.stream)
+        torch.cuda.synchronize()
+        # the captured calls take their workspace from the index, reserved here
+        reserved = ctypes.c_size_t()
+        _lib.call("z3_index_prepare_capture", idx.handle, 0, ctypes.byref(reserved))
+        self.workspace_bytes = reserved.value
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph, stream=self.stream):
+            self._body()
+
+    def _body(self):
+        self.idx.update_values(self.x)
+        self.zeta_raw.zero_()
+        _lib.call("z3_estimate_maps", self.idx.handle, self.m_max, PREC[self.prec], 0, self.idx.n,
+                  _ptr(self.zeta_raw), _ptr(None), _stream())
+        torch.mul(self.zeta_raw, self.scale, out=self.zeta)
+        g = 2.0 * (self.zeta - self.target)  # dL/dzeta
+        self.grad.zero_()
+        _lib.call("z3_adjoint_maps", self.idx.handle, self.m_max, 0, self.idx.n, _ptr(g), float(self.scale),
+                  _ptr(self.grad), _stream())
+
+    def run(self, x):
+        self.x.copy_(x.reshape(self.x.shape))
+        self.graph.replay()
+        return self.zeta, self.grad
 
 
 class Zeta3Fn(torch.autograd.Function):

@@ -1,0 +1,60 @@
+"""Forward + adjoint captured in one HIP graph (GraphStep): every replay, with new field
+values and eager work between replays, against the same computation run eagerly."""
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2408_16847_amd as z3
+from synth import CONFIGS, make_values
+from tests import gpu_helpers as G
+from tests import pins
+
+pytestmark = pytest.mark.gpu
+
+
+def _maps(xyz, nmaps, seed0):
+    xyz_t = torch.from_numpy(np.ascontiguousarray(xyz))
+    return torch.stack([make_values(CONFIGS["cap20k"], xyz_t, seed=seed0 + s) for s in range(nmaps)])
+
+
+def _eager(idx, x, M, prec, t):
+    """zeta (normalised) and dL/dx for L = sum (zeta - t)^2, by the eager calls."""
+    idx.set_values(x.cuda())
+    zr = z3.estimate_maps_raw(idx, M, prec)
+    sw = torch.zeros(1, dtype=torch.float64, device="cuda")
+    z3._lib.call("z3_pivot_weight_sum", idx.handle, 0, idx.n, z3.zeta3._ptr(sw), z3.zeta3._stream())
+    scale = 1.0 / float(sw.item())
+    zeta = zr * scale
+    g = (2.0 * (zeta - t)).contiguous()
+    if idx.nmaps > 1:
+        grad = z3.adjoint_maps(idx, g, scale, M)
+    else:
+        grad = z3.adjoint(idx, g[0], scale, M).unsqueeze(0)
+    torch.cuda.synchronize()
+    return zeta.cpu().numpy(), grad.cpu().numpy()
+
+
+@pytest.mark.parametrize("nmaps,prec", [(6, "mixed"), (6, "fp64"), (1, "mixed")])
+def test_graph_replays_match_eager(nmaps, prec):
+    G.say("case: graph step", nmaps, prec)
+    xyz, w, _ = pins.random_cap(3000, 5.0, 31)
+    E = pins.small_edges(5, lo=0.1, hi=2.0, log=True)
+    M = 6
+    x0 = _maps(xyz, nmaps, 100)
+    idx = G.build(xyz, x0.numpy(), E, w=w)
+    ref_idx = G.build(xyz, x0.numpy(), E, w=w)
+    t = torch.from_numpy(np.random.default_rng(5).normal(size=(nmaps, M + 1, 5, 5, 2))).cuda() * 1e-3
+    step = z3.GraphStep(idx, M, t, prec=prec)
+    for r in range(3):
+        x = _maps(xyz, nmaps, 200 + 10 * r)
+        zeta_g, grad_g = step.run(x.cuda())
+        torch.cuda.synchronize()
+        zg, gg = zeta_g.cpu().numpy(), grad_g.cpu().numpy()
+        ze, ge = _eager(ref_idx, x, M, prec, t)  # eager work between the replays
+        G.say("replay", r, "zeta max", np.abs(ze).max(), "grad max", np.abs(ge).max())
+        assert np.array_equal(zg, ze), r
+        # the adjoint's FP64 atomics make its last bits depend on scheduling
+        assert np.abs(gg - ge).max() <= 1e-12 * np.abs(ge).max(), r
+    idx.free()
+    ref_idx.free()
