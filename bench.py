@@ -41,7 +41,7 @@ def cpu_model():
     return "unknown"
 
 
-KERNEL_SOURCES = ("z3_multipoles.hip", "z3_device.h", "z3_internal.h")
+KERNEL_SOURCES = ("z3_multipoles.hip", "z3_device.h")  # the kernel and its device helpers
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "k_multipoles_traffic.json")
 
 
@@ -422,23 +422,20 @@ def cpu_baseline(cfg, xyz, x, nbr, E, M, nsample, z3, torch):
     def oracle(sel):
         return cpu.estimate(xyz_h[:, sel], nbr_h[0], nbr_h[2], nbr_h[1], E, M, w_h[sel], x_h[sel], nthreads=threads)
 
-    # size the sample to ~15 s of oracle work: one call with a single pivot measures the
-    # oracle's fixed cost (its own O(N) grid build); its pair rate is measured on 320 pivots,
-    # then again on ~2 s worth of pivots (small calls under-use the threads)
+    # size the sample to ~15 s of oracle work: the oracle's time per pivot falls as the
+    # sample grows (its O(N) grid build, thread start-up and load balance amortise), so the
+    # pivot count is grown until one call takes >= 3 s and then scaled to 15 s
     if nsample < 0:
-        t = time.perf_counter()
-        oracle(order[p0:p0 + 1])
-        t_fixed = time.perf_counter() - t
-        k, rate = 320, 0.0
-        for target in (None, 2.0):
-            if target is not None:
-                k = int(min(n - p0, max(320, target * rate / per_pivot)))
+        k = 256
+        while True:
             t = time.perf_counter()
-            _, pk = oracle(order[p0:p0 + k])
-            rate = pk / max(time.perf_counter() - t - t_fixed, 1e-3)
-            per_pivot = max(pk / k, 1.0)
-            log(f"[bench] cpu_baseline calibration: fixed {t_fixed:.2f}s, {k} pivots at {rate:.3g} pairs/s")
-        nsample = int(min(n - p0, max(320, 15.0 * rate / per_pivot)))
+            oracle(order[p0:p0 + k])
+            dt = time.perf_counter() - t
+            log(f"[bench] cpu_baseline calibration: {k} pivots in {dt:.2f}s")
+            if dt >= 3.0 or k >= n - p0:
+                break
+            k = int(min(n - p0, k * max(2.0, min(8.0, 3.5 / max(dt, 1e-3)))))
+        nsample = int(min(n - p0, max(256, k * 15.0 / max(dt, 1e-3))))
     sel = order[p0:p0 + nsample]
     log(f"[bench] cpu_baseline: oracle on {nsample} pivots x {threads} threads")
     t = time.perf_counter()
