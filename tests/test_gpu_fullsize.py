@@ -1,0 +1,116 @@
+"""GPU parity at the full workload sizes the bench times (HEALPix Nside 2048 and 4096, 64
+maps at Nside 512), on sampled pivots the oracle computes one by one: ragged pivot ranges
+at the north pole, across a band boundary near the equator (the 0 / 2 pi wrap of the
+longitude windows) and at the south pole.  Per-pivot pair counts, bin weights and neighbour
+fingerprints bit-exact; per-pivot multipoles within 1e-11 (FP64) of each bin's scale, and
+1e-5 on the mixed path (its FP32 Chebyshev recurrence turns the FP32 rounding of cos phi
+into errors up to ~m^2 x 6e-8 for a single pair near phi = 0 or pi, and the inner bins hold
+only a few pairs); zeta over all sampled pivots within 1e-10 / 1e-6."""
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2408_16847_amd as z3
+from oracle import cpu
+from synth import CONFIGS, make_positions, make_values
+from tests import gpu_helpers as G
+
+pytestmark = pytest.mark.gpu
+
+
+def _ranges(xyz_h, perm):
+    """Ragged pivot ranges in index order (latitude bands from the north pole, longitude
+    cells within a band): the first band(s), a range across a band boundary near the
+    equator (the end of one band at phi near 2 pi, the start of the next at phi near 0),
+    and the last band(s)."""
+    n = len(perm)
+    lo = max(n // 2 - 20000, 0)
+    seg = perm[lo:n // 2 + 20000]
+    phi = np.arctan2(xyz_h[1, seg], xyz_h[0, seg]) % (2 * np.pi)
+    jumps = np.nonzero(phi[1:] < phi[:-1] - np.pi)[0]
+    wrap = lo + int(jumps[0]) + 1 if len(jumps) else n // 2
+    return [(0, 397), (wrap - 150, wrap + 251), (n - 430, n)]
+
+
+def _check_multipoles(idx, xyz_h, x_h, E, M, p0, p1, perm):
+    pm = perm[p0:p1]
+    w = np.ones(xyz_h.shape[1])
+    ao, Wo, No, _, Ho = cpu.multipoles(xyz_h[:, pm], xyz_h, w, x_h, E, M, ids=True)
+    scale = np.abs(ao).max(axis=1, keepdims=True) + 1e-300
+    for prec, tol in (("fp64", 1e-11), ("mixed", 1e-5)):
+        a, W, N, H = G.gpu_multipoles(idx, M, p0, p1, prec=prec, norm="none")
+        assert np.array_equal(N, No), prec
+        assert np.array_equal(W, Wo), prec
+        assert np.array_equal(H, Ho), prec
+        err = (np.abs(a - ao) / scale).max()
+        G.say("  multipoles", prec, "pivots", p0, p1, "err", err)
+        assert err < tol, (prec, err)
+
+
+def _check_zeta(idx, xyz_h, x_h, E, M, ranges, perm):
+    pm = np.concatenate([perm[p0:p1] for p0, p1 in ranges])
+    w = np.ones(xyz_h.shape[1])
+    zo, po = cpu.estimate(xyz_h[:, pm], xyz_h, w, x_h, E, M, np.ones(len(pm)), x_h[pm])
+    for prec, tol in (("fp64", 1e-10), ("mixed", 1e-6)):
+        zeta = torch.zeros((M + 1, idx.nbins, idx.nbins, 2), dtype=torch.float64, device="cuda")
+        pairs = torch.zeros(1, dtype=torch.int64, device="cuda")
+        for p0, p1 in ranges:
+            z3.estimate_raw(idx, M, prec, p0, p1, zeta=zeta, pair_total=pairs)
+        torch.cuda.synchronize()
+        zg = zeta.cpu().numpy() / len(pm)
+        assert int(pairs.item()) == po
+        e = G.err_m(zg[..., 0] + 1j * zg[..., 1], zo).max()
+        G.say("  zeta", prec, len(pm), "pivots, err", e)
+        assert e < tol, (prec, e)
+
+
+@pytest.mark.parametrize("name", ["nside2048", "nside4096"])
+def test_fullsize_healpix_sampled_pivots(name):
+    cfg = CONFIGS[name]
+    G.say("case: full size", name)
+    xyz = make_positions(cfg, device="cuda")
+    x = make_values(cfg, xyz, seed=0)
+    E = cfg.edges_chord2()
+    idx = z3.Index(xyz, E)
+    idx.set_values(x)
+    perm = idx.perm().cpu().numpy()
+    xyz_h, x_h = xyz.cpu().numpy(), x.cpu().numpy()
+    del xyz
+    ranges = _ranges(xyz_h, perm)
+    for p0, p1 in ranges:
+        _check_multipoles(idx, xyz_h, x_h, E, cfg.m_max, p0, p1, perm)
+    _check_zeta(idx, xyz_h, x_h, E, cfg.m_max, ranges, perm)
+    idx.free()
+
+
+def test_fullsize_batch64_sampled_pivots():
+    """The MFMA many-map kernel over all 64 maps at Nside 512, on sampled pivots, for the
+    first, a middle and the last map."""
+    cfg = CONFIGS["batch64"]
+    G.say("case: full size batch64")
+    xyz = make_positions(cfg, device="cuda")
+    x = torch.stack([make_values(cfg, xyz, seed=s) for s in range(cfg.nmaps)])
+    E = cfg.edges_chord2()
+    M = cfg.m_max
+    idx = z3.Index(xyz, E)
+    idx.set_values(x)
+    perm = idx.perm().cpu().numpy()
+    xyz_h, x_h = xyz.cpu().numpy(), x.cpu().numpy()
+    w = np.ones(xyz_h.shape[1])
+    ranges = _ranges(xyz_h, perm)
+    pm = np.concatenate([perm[p0:p1] for p0, p1 in ranges])
+    for prec, tol in (("fp64", 1e-10), ("mixed", 1e-6)):
+        zeta = torch.zeros((cfg.nmaps, M + 1, cfg.nbins, cfg.nbins, 2), dtype=torch.float64, device="cuda")
+        pairs = torch.zeros(1, dtype=torch.int64, device="cuda")
+        for p0, p1 in ranges:
+            z3.estimate_maps_raw(idx, M, prec, p0, p1, zeta, pairs)
+        torch.cuda.synchronize()
+        zg = zeta.cpu().numpy() / len(pm)
+        for s in (0, 31, 63):
+            zo, po = cpu.estimate(xyz_h[:, pm], xyz_h, w, x_h[s], E, M, np.ones(len(pm)), x_h[s][pm])
+            assert int(pairs.item()) == po
+            e = G.err_m(zg[s, ..., 0] + 1j * zg[s, ..., 1], zo).max()
+            G.say("  map", s, prec, len(pm), "pivots, err", e)
+            assert e < tol, (s, prec, e)
+    idx.free()
