@@ -422,25 +422,26 @@ def cpu_baseline(cfg, xyz, x, nbr, E, M, nsample, z3, torch):
     def oracle(sel):
         return cpu.estimate(xyz_h[:, sel], nbr_h[0], nbr_h[2], nbr_h[1], E, M, w_h[sel], x_h[sel], nthreads=threads)
 
-    # size the sample to ~15 s of oracle work: the oracle's time per pivot falls as the
-    # sample grows (its O(N) grid build, thread start-up and load balance amortise), so the
-    # pivot count is grown until one call takes >= 3 s and then scaled to 15 s
+    # sample size: the oracle's time per pivot falls as the sample grows (its O(N) grid
+    # build, thread start-up and load balance amortise), so the pivot count is grown
+    # geometrically and the first call that takes >= 10 s is the measurement
+    def timed(k):
+        t = time.perf_counter()
+        zo_, po_ = oracle(order[p0:p0 + k])
+        return zo_, po_, time.perf_counter() - t
+
     if nsample < 0:
         k = 256
         while True:
-            t = time.perf_counter()
-            oracle(order[p0:p0 + k])
-            dt = time.perf_counter() - t
-            log(f"[bench] cpu_baseline calibration: {k} pivots in {dt:.2f}s")
-            if dt >= 3.0 or k >= n - p0:
+            zo, po, dt = timed(k)
+            log(f"[bench] cpu_baseline: {k} pivots in {dt:.2f}s")
+            if dt >= 10.0 or k >= n - p0:
                 break
-            k = int(min(n - p0, k * max(2.0, min(8.0, 3.5 / max(dt, 1e-3)))))
-        nsample = int(min(n - p0, max(256, k * 15.0 / max(dt, 1e-3))))
-    sel = order[p0:p0 + nsample]
-    log(f"[bench] cpu_baseline: oracle on {nsample} pivots x {threads} threads")
-    t = time.perf_counter()
-    zo, po = oracle(sel)
-    dt = time.perf_counter() - t
+            k = int(min(n - p0, k * max(1.5, min(8.0, 12.0 / max(dt, 1e-3)))))
+        nsample = k
+    else:
+        log(f"[bench] cpu_baseline: oracle on {nsample} pivots x {threads} threads")
+        zo, po, dt = timed(nsample)
     parity = {}
     for gp in ("fp64", "mixed"):
         zeta = torch.zeros((M + 1, cfg.nbins, cfg.nbins, 2), dtype=torch.float64, device="cuda")

@@ -22,6 +22,12 @@
 // for sin(m phi) = U_{m-1}(c) sin(phi) (second kind); the paper's code uses the same two
 // polynomial families so that no trigonometric function is evaluated per pair.  Scaling
 // both recurrences by w_j x_j folds the field value in: two FMAs and two adds per m.
+//
+// Precision: the FP64 path normalises the bearing with an FP32-seeded reciprocal square
+// root refined by one FP64 Newton step and runs everything in FP64.  The mixed path keeps
+// the separations and bin decisions in FP64, forms the bearing in FP32 (tangent components
+// rounded once, hardware reciprocal square root), runs the recurrences in FP32 and adds the
+// FP32 sums of each band window into FP64 bin sums.
 #include "z3_internal.h"
 #include "z3_device.h"
 
@@ -145,9 +151,9 @@ void k_multipoles(MultArgs a)
                         if constexpr (IDS) hsum += mix64((uint64_t)a.permdbl[j]);
                         const double u1 = fma(dx, nx, fma(dy, ny, dz * nz));
                         const double u2 = fma(dx, ex, fma(dy, ey, dz * ez));
-                        double c, sn;
-                        unit_bearing(u1, u2, c, sn);
                         if constexpr (!MIXED) {
+                            double c, sn;
+                            unit_bearing(u1, u2, c, sn);
                             const double v = r.w;
                             Y[0] += v;
                             if constexpr (M >= 1) {
@@ -167,7 +173,12 @@ void k_multipoles(MultArgs a)
                             }
                         } else {
                             const float v = (float)r.w;
-                            const float cf = (float)c, sf = (float)sn;
+                            // the bearing in FP32: the tangent components rounded once, then
+                            // the hardware reciprocal square root (the FP32 harmonics that
+                            // follow carry errors of the same order)
+                            const float u1f = (float)u1, u2f = (float)u2;
+                            const float rq = __builtin_amdgcn_rsqf(fmaxf(fmaf(u1f, u1f, u2f * u2f), 1e-30f));
+                            const float cf = u1f * rq, sf = u2f * rq;
                             Yf[0] += v;
                             if constexpr (M >= 1) {
                                 const float tc = cf + cf;
