@@ -87,6 +87,16 @@ def test_other_entry_points_reject_bad_arguments():
     assert _status("z3_resum", 4, 65, P(1), 3, P(1), P(1), P(0))[0] == 1
     assert _status("z3_finalize", 0, 4, 4, P(1), P(1), P(0))[0] == 1
     assert _status("z3_index_info", P(0), P(0), P(0), P(0), P(0), P(0))[0] == 1
+    # index-based calls with a NULL index
+    assert _status("z3_estimate_maps", P(0), 4, 0, 0, 1, P(1), P(0), P(0))[0] == 1
+    assert _status("z3_estimate_pivots", P(0), 0, 1, P(1), P(0), P(1), 4, 0, 0, 1, P(1), P(0), P(0), P(0))[0] == 1
+    assert _status("z3_adjoint", P(0), 0, 4, 0, 1, P(1), 1.0, P(1), P(0))[0] == 1
+    assert _status("z3_adjoint_maps", P(0), 4, 0, 1, P(1), 1.0, P(1), P(0))[0] == 1
+    assert _status("z3_pivot_weight_sum", P(0), 0, 1, P(1), P(0))[0] == 1
+    assert _status("z3_index_update_values", P(0), P(1), P(0))[0] == 1
+    assert _status("z3_index_prepare_capture", P(0), 0, P(0))[0] == 1
+    assert _status("z3_index_set_batch_shape", P(0), 0, 0)[0] == 1
+    assert _status("z3_index_batch_shape", P(0), 10, 0, P(1), P(1))[0] == 1
     # empty work is a successful no-op
     assert _status("z3_contract", 0, 4, 4, 0, P(0), P(0), P(1), P(0))[0] == 0
     assert _status("z3_resum", 4, 4, P(0), 0, P(0), P(0), P(0))[0] == 0
