@@ -361,7 +361,8 @@ z3_status adjoint_maps_impl(z3_index idx, int m_max, int64_t p0, int64_t p1, con
             const int64_t c1 = c0 + chunk < p1 ? c0 + chunk : p1;
             const size_t stride = (size_t)(c1 - c0) * per_piv;
             if (batch)
-                st = launch_multipoles_batch(idx, m_max, Z3_PREC_FP64, shape, c0, c1, wa, c1 - c0, stride,
+                // wd (written later by the prep) stages the pivot-major multipoles
+                st = launch_multipoles_batch(idx, m_max, Z3_PREC_FP64, shape, c0, c1, wd, wa, c1 - c0, stride,
                                              static_cast<double *>(ww), nullptr, s);
             else
                 st = launch_multipoles_maps(idx, g, m_max, Z3_PREC_FP64, c0, c1, wa, c1 - c0, stride,

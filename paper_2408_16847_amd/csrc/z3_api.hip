@@ -356,7 +356,7 @@ z3_status z3::batch_shape(z3_index idx, int m_max, int prec, int64_t p0, int64_t
     const int64_t q0 = p0 + (p1 - p0 - S) / 2;
     const size_t elem = prec == Z3_PREC_FP64 ? 8 : 4;
     const size_t stride = (size_t)S * (m_max + 1) * 2 * idx->nbins;
-    void *wa = nullptr;
+    void *wa = nullptr;  // pivot-major staging only: the transpose is the same for every shape
     if ((st = scratch_alloc(&wa, (size_t)idx->nmaps * stride * elem, s)) != Z3_OK) return st;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     st = check_hip(hipEventCreate(&e0), "hipEventCreate");
@@ -365,9 +365,9 @@ z3_status z3::batch_shape(z3_index idx, int m_max, int prec, int64_t p0, int64_t
     int best = 0;
     for (int c = 0; c < batch_num_shapes() && st == Z3_OK; ++c) {
         // one untimed launch (code object load, caches), then one timed
-        st = launch_multipoles_batch(idx, m_max, prec, c, q0, q0 + S, wa, S, stride, nullptr, nullptr, s);
+        st = launch_multipoles_batch(idx, m_max, prec, c, q0, q0 + S, wa, nullptr, S, stride, nullptr, nullptr, s);
         if (st == Z3_OK) st = check_hip(hipEventRecord(e0, s), "hipEventRecord");
-        if (st == Z3_OK) st = launch_multipoles_batch(idx, m_max, prec, c, q0, q0 + S, wa, S, stride, nullptr, nullptr, s);
+        if (st == Z3_OK) st = launch_multipoles_batch(idx, m_max, prec, c, q0, q0 + S, wa, nullptr, S, stride, nullptr, nullptr, s);
         if (st == Z3_OK) st = check_hip(hipEventRecord(e1, s), "hipEventRecord");
         if (st == Z3_OK) st = check_hip(hipEventSynchronize(e1), "hipEventSynchronize");
         float ms = 0.0f;
@@ -473,26 +473,26 @@ Z3_API z3_status z3_estimate_maps(z3_index idx, int m_max, int prec, int64_t p0,
         // contraction launch for all maps
         int shape = 0;
         if ((st = batch_shape(idx, m_max, prec, p0, p1, s, &shape)) != Z3_OK) return st;
-        int64_t chunk = chunk_pivots(idx, m_max, prec) / idx->nmaps;
+        int64_t chunk = chunk_pivots(idx, m_max, prec) / (2 * idx->nmaps);  // multipoles + staging
         chunk = (chunk / kBlock) * kBlock;
         if (chunk < 4 * kBlock) chunk = 4 * kBlock;
         if (chunk > p1 - p0) chunk = p1 - p0;
         const size_t pbytes = contract_partial_bytes(chunk, m_max, idx->nbins) * idx->nmaps;
-        void *wa = nullptr, *wp = nullptr;
-        if ((st = scratch_alloc(&wa, (size_t)idx->nmaps * chunk * per_map_piv, s)) != Z3_OK) return st;
-        if ((st = scratch_alloc(&wp, pbytes, s)) != Z3_OK) {
-            scratch_free(wa, s);
-            return st;
-        }
+        void *wa = nullptr, *wst = nullptr, *wp = nullptr;
+        st = scratch_alloc(&wa, (size_t)idx->nmaps * chunk * per_map_piv, s);
+        if (st == Z3_OK) st = scratch_alloc(&wst, (size_t)idx->nmaps * chunk * per_map_piv, s);
+        if (st == Z3_OK) st = scratch_alloc(&wp, pbytes, s);
         for (int64_t c0 = p0; c0 < p1 && st == Z3_OK; c0 += chunk) {
             const int64_t c1 = c0 + chunk < p1 ? c0 + chunk : p1;
             const size_t stride = (size_t)(c1 - c0) * (m_max + 1) * 2 * idx->nbins;
-            st = launch_multipoles_batch(idx, m_max, prec, shape, c0, c1, wa, c1 - c0, stride, nullptr, pair_total, s);
+            st = launch_multipoles_batch(idx, m_max, prec, shape, c0, c1, wst, wa, c1 - c0, stride, nullptr,
+                                         pair_total, s);
             if (st == Z3_OK)
                 st = launch_contract_maps(c1 - c0, m_max, idx->nbins, prec, idx->nmaps, wa, c1 - c0, stride,
                                           idx->d_v + c0, (size_t)idx->n, zeta, zstride, wp, pbytes, s);
         }
         scratch_free(wp, s);
+        scratch_free(wst, s);
         scratch_free(wa, s);
         return st;
     }

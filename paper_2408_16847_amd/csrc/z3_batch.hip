@@ -44,10 +44,9 @@ struct BatchArgs {
     int64_t p0, p1;
     int nmaps;                    // maps written (rows >= nmaps are padding)
     int ntiles;                   // map tiles of one pivot (blocks per pivot)
-    void *A;                      // per map [m+1][2][nb][ldA], maps map_stride elements apart
-    int64_t ldA;
-    size_t map_stride;
+    void *stage;                  // [P][nb][nmaps][2 (m+1)] pivot-major multipoles (re, im per m)
     double *W;                    // [nb][ldA] W_{p,b}, or null
+    int64_t ldA;
     uint64_t *pair_total;
     int nblocks;
 };
@@ -305,9 +304,10 @@ void k_multipoles_batch(BatchArgs a)
                         else if (c == 0) { m = 0; part = 0; val = s * inv; }
                         else if (c <= M) { m = c; part = 0; val = s * inv; }
                         else { m = c - M; part = 1; val = -s * inv; }        // e^{-i m phi}
-                        const size_t o =
-                            (size_t)map * a.map_stride + ((size_t)(2 * m + part) * nb + bin) * (size_t)a.ldA + col;
-                        static_cast<T *>(a.A)[o] = (T)val;
+                        // pivot-major staging: the bin's values of all maps are one contiguous
+                        // run, so the block's stores fill whole cache lines
+                        const size_t o = (((size_t)col * nb + bin) * (size_t)a.nmaps + map) * (2 * (M + 1)) + 2 * m + part;
+                        static_cast<T *>(a.stage)[o] = (T)val;
                     }
         }
         if (mt == 0 && tid == 0 && a.W) a.W[(size_t)bin * (size_t)a.ldA + col] = Wb;
@@ -344,33 +344,63 @@ void batch_shape_dims(int shape, int *wpb, int *ti)
     *ti = kBatchShapes[shape].ti;
 }
 
+// Pivot-major staging [P][nb][nmaps][R] -> A [map][R][nb][ldA] (R = 2 (m+1) rows re/im per
+// m; row r of bin b is row r nb + b): one block per (64 pivots, bin, map), through LDS, so
+// both the reads (runs of R values per pivot) and the writes (runs of 64 pivots) are
+// contiguous.
+constexpr int kMaxRows = 2 * (Z3_MAX_MMAX + 1);
+
+template <class T>
+__global__ __launch_bounds__(256) void k_batch_transpose(const T *stage, T *A, int64_t P, int nb, int nmaps, int R,
+                                                         int64_t ldA, size_t map_stride)
+{
+    __shared__ T tile[kMaxRows][65];
+    const int64_t pt0 = (int64_t)blockIdx.x * 64;
+    const int b = blockIdx.y, map = blockIdx.z;
+    const int np = (int)(P - pt0 < 64 ? P - pt0 : 64);
+    for (int e = threadIdx.x; e < np * R; e += 256) {
+        const int pl = e / R, r = e - pl * R;
+        tile[r][pl] = stage[(((size_t)(pt0 + pl) * nb + b) * nmaps + map) * R + r];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < R * 64; e += 256) {
+        const int r = e / 64, pl = e - r * 64;
+        if (pl < np) A[(size_t)map * map_stride + ((size_t)r * nb + b) * ldA + pt0 + pl] = tile[r][pl];
+    }
+}
+
 z3_status launch_multipoles_batch(const z3_index_s *idx, int m_max, int prec, int shape, int64_t p0, int64_t p1,
-                                  void *A, int64_t ldA, size_t map_stride, double *W, uint64_t *pair_total,
-                                  hipStream_t s)
+                                  void *stage, void *A, int64_t ldA, size_t map_stride, double *W,
+                                  uint64_t *pair_total, hipStream_t s)
 {
     if (shape < 0 || shape >= kNumBatchShapes) return fail(Z3_ERR_INVALID_ARG, "batch shape %d", shape);
     const int per_block = 16 * kBatchShapes[shape].ti * kBatchShapes[shape].wpb;
     const int ntiles = (batch_ldv(idx->nmaps) + per_block - 1) / per_block;
+    const int R = 2 * (m_max + 1);
+    const bool f32 = prec == Z3_PREC_MIXED;
     if (p1 <= p0) return Z3_OK;
+    if (idx->nmaps > 65535) return fail(Z3_ERR_UNSUPPORTED, "more than 65535 maps");
     // one launch stays well below 2^32 work-items: at most 2^22 blocks
     const int64_t max_piv = ((int64_t)1 << 22) / ntiles;
     if (p1 - p0 > max_piv) {
         for (int64_t c0 = p0; c0 < p1; c0 += max_piv) {
             const int64_t c1 = c0 + max_piv < p1 ? c0 + max_piv : p1;
             const size_t off = (size_t)(c0 - p0);
+            const size_t soff = off * idx->nbins * idx->nmaps * R;
             z3_status st;
-            if (prec == Z3_PREC_MIXED)
-                st = launch_multipoles_batch(idx, m_max, prec, shape, c0, c1, static_cast<float *>(A) + off, ldA,
-                                             map_stride, W ? W + off : nullptr, pair_total, s);
+            if (f32)
+                st = launch_multipoles_batch(idx, m_max, prec, shape, c0, c1, static_cast<float *>(stage) + soff,
+                                             A ? static_cast<float *>(A) + off : nullptr, ldA, map_stride,
+                                             W ? W + off : nullptr, pair_total, s);
             else
-                st = launch_multipoles_batch(idx, m_max, prec, shape, c0, c1, static_cast<double *>(A) + off, ldA,
-                                             map_stride, W ? W + off : nullptr, pair_total, s);
+                st = launch_multipoles_batch(idx, m_max, prec, shape, c0, c1, static_cast<double *>(stage) + soff,
+                                             A ? static_cast<double *>(A) + off : nullptr, ldA, map_stride,
+                                             W ? W + off : nullptr, pair_total, s);
             if (st != Z3_OK) return st;
         }
         return Z3_OK;
     }
     const int64_t nblk = (p1 - p0) * ntiles;
-    const bool f32 = prec == Z3_PREC_MIXED;
     BatchArgs a;
     a.rec = idx->d_rec;
     a.vmat = f32 ? static_cast<const void *>(idx->d_vmat32) : static_cast<const void *>(idx->d_vmat64);
@@ -386,8 +416,9 @@ z3_status launch_multipoles_batch(const z3_index_s *idx, int m_max, int prec, in
     a.p0 = p0; a.p1 = p1;
     a.nmaps = idx->nmaps;
     a.ntiles = ntiles;
-    a.A = A; a.ldA = ldA; a.map_stride = map_stride;
+    a.stage = stage;
     a.W = W;
+    a.ldA = ldA;
     a.pair_total = pair_total;
     a.nblocks = (int)nblk;
     hipEvent_t ev0;
@@ -404,7 +435,15 @@ z3_status launch_multipoles_batch(const z3_index_s *idx, int m_max, int prec, in
     }
     if (st == Z3_OK) st = check_launch("k_multipoles_batch");
     profile_end(s, ev0);
-    return st;
+    if (st != Z3_OK || !A) return st;
+    const dim3 tgrid((unsigned)((p1 - p0 + 63) / 64), (unsigned)idx->nbins, (unsigned)idx->nmaps);
+    if (f32)
+        hipLaunchKernelGGL(k_batch_transpose<float>, tgrid, dim3(256), 0, s, static_cast<const float *>(stage),
+                           static_cast<float *>(A), p1 - p0, idx->nbins, idx->nmaps, R, ldA, map_stride);
+    else
+        hipLaunchKernelGGL(k_batch_transpose<double>, tgrid, dim3(256), 0, s, static_cast<const double *>(stage),
+                           static_cast<double *>(A), p1 - p0, idx->nbins, idx->nmaps, R, ldA, map_stride);
+    return check_launch("k_batch_transpose");
 }
 
 }  // namespace z3

@@ -134,9 +134,11 @@ int batch_ldv(int nmaps);
 int batch_num_shapes();
 void batch_shape_dims(int shape, int *waves, int *tiles_per_wave);
 z3_status batch_shape(z3_index idx, int m_max, int prec, int64_t p0, int64_t p1, hipStream_t s, int *shape);
+// stage: [P][nb][nmaps][2 (m+1)] pivot-major buffer the kernel writes (required); A (or
+// null): transposed into [map][2 (m+1)][nb][ldA], maps map_stride elements apart
 z3_status launch_multipoles_batch(const z3_index_s *idx, int m_max, int prec, int shape, int64_t p0, int64_t p1,
-                                  void *A, int64_t ldA, size_t map_stride, double *W, uint64_t *pair_total,
-                                  hipStream_t s);
+                                  void *stage, void *A, int64_t ldA, size_t map_stride, double *W,
+                                  uint64_t *pair_total, hipStream_t s);
 z3_status launch_multipoles_maps(const z3_index_s *idx, int group, int m_max, int prec, int64_t p0,
                                  int64_t p1, void *A, int64_t ldA, size_t map_stride, double *W,
                                  uint64_t *pair_total, hipStream_t s);
