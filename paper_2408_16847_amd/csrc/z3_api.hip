@@ -473,21 +473,28 @@ Z3_API z3_status z3_estimate_maps(z3_index idx, int m_max, int prec, int64_t p0,
         // contraction launch for all maps
         int shape = 0;
         if ((st = batch_shape(idx, m_max, prec, p0, p1, s, &shape)) != Z3_OK) return st;
-        int64_t chunk = chunk_pivots(idx, m_max, prec) / (2 * idx->nmaps);  // multipoles + staging
+        // the contraction reads the kernel's pivot-major staging directly when its LDS tile
+        // fits; otherwise the staging is transposed into the pivot-minor layout first
+        const bool direct = gram_lds_fits(m_max, idx->nbins, prec);
+        int64_t chunk = chunk_pivots(idx, m_max, prec) / ((direct ? 1 : 2) * idx->nmaps);
         chunk = (chunk / kBlock) * kBlock;
         if (chunk < 4 * kBlock) chunk = 4 * kBlock;
         if (chunk > p1 - p0) chunk = p1 - p0;
         const size_t pbytes = contract_partial_bytes(chunk, m_max, idx->nbins) * idx->nmaps;
         void *wa = nullptr, *wst = nullptr, *wp = nullptr;
-        st = scratch_alloc(&wa, (size_t)idx->nmaps * chunk * per_map_piv, s);
-        if (st == Z3_OK) st = scratch_alloc(&wst, (size_t)idx->nmaps * chunk * per_map_piv, s);
+        st = scratch_alloc(&wst, (size_t)idx->nmaps * chunk * per_map_piv, s);
+        if (st == Z3_OK && !direct) st = scratch_alloc(&wa, (size_t)idx->nmaps * chunk * per_map_piv, s);
         if (st == Z3_OK) st = scratch_alloc(&wp, pbytes, s);
         for (int64_t c0 = p0; c0 < p1 && st == Z3_OK; c0 += chunk) {
             const int64_t c1 = c0 + chunk < p1 ? c0 + chunk : p1;
             const size_t stride = (size_t)(c1 - c0) * (m_max + 1) * 2 * idx->nbins;
             st = launch_multipoles_batch(idx, m_max, prec, shape, c0, c1, wst, wa, c1 - c0, stride, nullptr,
                                          pair_total, s);
-            if (st == Z3_OK)
+            if (st != Z3_OK) break;
+            if (direct)
+                st = launch_contract_staged(c1 - c0, m_max, idx->nbins, prec, idx->nmaps, wst, idx->d_v + c0,
+                                            (size_t)idx->n, zeta, zstride, wp, pbytes, s);
+            else
                 st = launch_contract_maps(c1 - c0, m_max, idx->nbins, prec, idx->nmaps, wa, c1 - c0, stride,
                                           idx->d_v + c0, (size_t)idx->n, zeta, zstride, wp, pbytes, s);
         }

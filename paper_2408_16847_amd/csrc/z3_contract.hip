@@ -13,6 +13,7 @@
 // mirror, so zeta(b2, b1) is exactly conj(zeta(b1, b2)) and Im zeta(b, b) is exactly 0.
 // Segment partials are summed in FP64 in segment order (deterministic).
 #include <algorithm>
+#include <type_traits>
 
 #include "z3_internal.h"
 
@@ -143,9 +144,184 @@ __global__ void k_gram_reduce(const double *part, int64_t nseg, int nmaps, int M
     z[1] += ir - ri;
 }
 
-z3_status launch_contract_maps(int64_t npiv, int m_max, int nbins, int prec, int nmaps, const void *A, int64_t ldA,
-                               size_t a_stride, const double *piv_v, size_t v_stride, double *zeta, size_t z_stride,
-                               void *partials, size_t partial_bytes, hipStream_t s)
+// ---- LDS-staged contraction -------------------------------------------------------------
+// One block of kGramWaves waves per (pivot segment, map).  Tiles of kGramKP pivots are
+// staged in LDS as [pivot][bin][row] (row = 2 m + comp) from either multipole layout (the
+// many-map kernel's pivot-major staging, or the pivot-minor [row][bin][pivot] layout), with
+// the layout's contiguous dimension on consecutive lanes.  Every wave then runs its
+// (m, tile pair) units over the tile out of LDS, so each multipole is fetched once per block
+// rather than once per tile pair, and the pivot-major staging needs no transpose.
+constexpr int kGramWaves = 8;
+constexpr int kGramThreads = kGramWaves * 64;
+constexpr int kGramKP = 16;                      // pivots per LDS tile (4 MFMA k-steps)
+constexpr size_t kGramLdsMax = 64 * 1024 - 256;  // tile + pivot values
+
+static size_t gram_tile_bytes(int nb, int R, bool f32)
+{
+    return ((size_t)kGramKP * nb * R * (f32 ? 4 : 8) + 15) / 16 * 16;
+}
+
+// units per wave: the smallest compiled bound covering M1 x (tile pairs) units, else 0 (more
+// accumulators than a wave can hold at two waves per SIMD without spilling)
+static int gram_upw(int nunits)
+{
+    for (int u : {5, 9})
+        if (kGramWaves * u >= nunits) return u;
+    return 0;
+}
+
+bool gram_lds_fits(int m_max, int nbins, int prec)
+{
+    const int T = tiles_for(nbins), ntp = T * (T + 1) / 2;
+    const int R = 2 * (m_max + 1);
+    return gram_upw((m_max + 1) * ntp) > 0 && R <= 64 &&
+           gram_tile_bytes(nbins, R, prec == Z3_PREC_MIXED) + kGramKP * sizeof(double) <= kGramLdsMax;
+}
+
+// element (pivot p, bin b, row r) of map j at base + j map_stride + p sp + b sb + r sr
+struct GramSrc {
+    const void *base;
+    int64_t sp, sb, sr;
+    size_t map_stride;
+};
+
+struct GramArgs {
+    GramSrc src;
+    int64_t npiv;
+    const double *v;
+    size_t v_stride;
+    int nb, R, T, ntp, M1, nmaps, nunits;
+    int lpr_shift;       // PM staging: log2 of the lanes per (pivot, bin) run of R rows
+    size_t tile_bytes;
+    double *part;        // [seg][map][m][tile pair][256]
+};
+
+template <bool F32, bool PM, int UPW>
+__global__ __launch_bounds__(kGramThreads) void k_gram_lds(GramArgs g)
+{
+    typedef typename std::conditional<F32, float, double>::type T;
+    extern __shared__ __align__(16) unsigned char smem[];
+    T *tile = reinterpret_cast<T *>(smem);                          // [kGramKP][nb][R]
+    double *vt = reinterpret_cast<double *>(smem + g.tile_bytes);   // [kGramKP]
+    const int nb = g.nb, R = g.R, rowlen = nb * R;
+    // blocks are dealt round-robin to the 8 XCDs: each XCD gets a contiguous run of
+    // (segment, map) units, so blocks reading neighbouring maps' runs share its L2
+    const int64_t nblk = gridDim.x, bi = blockIdx.x, per = nblk / 8;
+    const int64_t unit = bi < per * 8 ? (bi % 8) * per + bi / 8 : bi;
+    const int64_t seg = unit / g.nmaps;
+    const int map = (int)(unit - seg * g.nmaps);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int row = lane & 15, kq = lane >> 4;
+    const T *src = static_cast<const T *>(g.src.base) + (size_t)map * g.src.map_stride;
+    const double *v = g.v + (size_t)map * g.v_stride;
+
+    // this wave's units (m, tile pair) and, for each, the offsets within one pivot's LDS row
+    // of the A-operand and B-operand entries this lane supplies (-1: a padding row)
+    int um[UPW], offa[UPW], offb[UPW];
+    v4d acc[UPW];
+#pragma unroll
+    for (int j = 0; j < UPW; ++j) {
+        const int uu = wave + kGramWaves * j;
+        um[j] = offa[j] = offb[j] = -1;
+        acc[j] = v4d{0.0, 0.0, 0.0, 0.0};
+        if (uu < g.nunits) {
+            const int m = uu / g.ntp;
+            int r = uu - m * g.ntp, I = 0;
+            while (r >= g.T - I) { r -= g.T - I; ++I; }
+            const int J = I + r;
+            const int ua = I * 16 + row, ub = J * 16 + row;
+            um[j] = m;
+            if (ua < 2 * nb) { const int c = ua >= nb; offa[j] = (ua - c * nb) * R + 2 * m + c; }
+            if (ub < 2 * nb) { const int c = ub >= nb; offb[j] = (ub - c * nb) * R + 2 * m + c; }
+        }
+    }
+
+    const int64_t pbeg = seg * kSeg;
+    const int64_t pend = min(g.npiv, pbeg + kSeg);
+    for (int64_t p0 = pbeg; p0 < pend; p0 += kGramKP) {
+        const int np = (int)min((int64_t)kGramKP, pend - p0);
+        __syncthreads();  // the previous tile is consumed
+        if constexpr (PM) {
+            // runs of R rows per (pivot, bin), contiguous in memory: lanes along the run
+            const int lpr = 1 << g.lpr_shift, step = kGramThreads >> g.lpr_shift;
+            const int r = tid & (lpr - 1);
+            int kb = tid >> g.lpr_shift, k = kb / nb, b = kb - k * nb;
+            while (k < kGramKP) {
+                if (r < R)
+                    tile[(k * nb + b) * R + r] =
+                        k < np ? src[(size_t)(p0 + k) * g.src.sp + (size_t)b * g.src.sb + r] : T(0);
+                b += step;
+                while (b >= nb) { b -= nb; ++k; }
+            }
+        } else {
+            // runs of kGramKP pivots per (row, bin): lanes along the pivots
+            const int k = tid & (kGramKP - 1), step = kGramThreads / kGramKP;
+            int rb = tid / kGramKP, r = rb / nb, b = rb - r * nb;
+            while (r < R) {
+                tile[(k * nb + b) * R + r] =
+                    k < np ? src[(size_t)(p0 + k) * g.src.sp + (size_t)b * g.src.sb + (size_t)r * g.src.sr] : T(0);
+                b += step;
+                while (b >= nb) { b -= nb; ++r; }
+            }
+        }
+        if (tid < kGramKP) vt[tid] = tid < np ? v[p0 + tid] : 0.0;
+        __syncthreads();
+        double vk[4];
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) vk[ks] = vt[4 * ks + kq];
+#pragma unroll
+        for (int j = 0; j < UPW; ++j) {
+            if (um[j] < 0) continue;  // wave-uniform
+            if constexpr (F32) {
+                // FP32 products and sums over the tile's pivots, then into the FP64 sum; the
+                // scaled operand v_p U_i is formed in FP64 and carried as FP32 hi + lo
+                v4f part = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks) {
+                    const int base = (4 * ks + kq) * rowlen;
+                    const float ua = offa[j] >= 0 ? tile[base + offa[j]] : 0.0f;
+                    const float ub = offb[j] >= 0 ? tile[base + offb[j]] : 0.0f;
+                    const double av = (double)ua * vk[ks];
+                    const float ahi = (float)av;
+                    const float alo = (float)(av - (double)ahi);
+                    part = __builtin_amdgcn_mfma_f32_16x16x4f32(ahi, ub, part, 0, 0, 0);
+                    part = __builtin_amdgcn_mfma_f32_16x16x4f32(alo, ub, part, 0, 0, 0);
+                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k) acc[j][k] += (double)part[k];
+            } else {
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks) {
+                    const int base = (4 * ks + kq) * rowlen;
+                    const double ua = offa[j] >= 0 ? tile[base + offa[j]] : 0.0;
+                    const double ub = offb[j] >= 0 ? tile[base + offb[j]] : 0.0;
+                    acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ua * vk[ks], ub, acc[j], 0, 0, 0);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < UPW; ++j) {
+        if (um[j] < 0) continue;
+        const int tp = wave + kGramWaves * j - um[j] * g.ntp;
+        double *out = g.part + ((((size_t)seg * g.nmaps + map) * g.M1 + um[j]) * g.ntp + tp) * 256;
+        // f64 16x16x4 result: register k of lane l is D[4k + l/16][l % 16];
+        // f32 16x16x4 result: register k of lane l is D[4 (l/16) + k][l % 16]
+#pragma unroll
+        for (int k = 0; k < 4; ++k) out[(F32 ? 4 * kq + k : 4 * k + kq) * 16 + row] = acc[j][k];
+    }
+}
+
+template <bool F32, bool PM>
+static void launch_gram_lds(int upw, dim3 grid, size_t lds, const GramArgs &g, hipStream_t s)
+{
+    if (upw == 5) hipLaunchKernelGGL((k_gram_lds<F32, PM, 5>), grid, dim3(kGramThreads), lds, s, g);
+    else hipLaunchKernelGGL((k_gram_lds<F32, PM, 9>), grid, dim3(kGramThreads), lds, s, g);
+}
+
+static z3_status contract_src(int64_t npiv, int m_max, int nbins, int prec, int nmaps, const GramSrc &src, bool pm,
+                              const double *piv_v, size_t v_stride, double *zeta, size_t z_stride, void *partials,
+                              size_t partial_bytes, hipStream_t s)
 {
     if (npiv <= 0 || nmaps <= 0) return Z3_OK;
     const int T = tiles_for(nbins), ntp = T * (T + 1) / 2;
@@ -154,21 +330,67 @@ z3_status launch_contract_maps(int64_t npiv, int m_max, int nbins, int prec, int
         return fail(Z3_ERR_INVALID_ARG, "contraction workspace too small");
     if (nseg > 65535) return fail(Z3_ERR_OVERFLOW, "too many pivots for one contraction (%lld)", (long long)npiv);
     if ((int64_t)nmaps * (m_max + 1) > 65535) return fail(Z3_ERR_OVERFLOW, "too many maps for one contraction");
-    ContractArgs c;
-    c.A = A; c.ldA = ldA; c.npiv = npiv; c.v = piv_v; c.nb = nbins; c.T = T; c.ntp = ntp;
-    c.M1 = m_max + 1;
-    c.a_stride = a_stride;
-    c.v_stride = v_stride;
-    c.part = static_cast<double *>(partials);
-    dim3 grid(ntp, (unsigned)nseg, (unsigned)(nmaps * (m_max + 1)));
-    if (prec == Z3_PREC_MIXED) hipLaunchKernelGGL(k_gram_tiles<true>, grid, dim3(64), 0, s, c);
-    else hipLaunchKernelGGL(k_gram_tiles<false>, grid, dim3(64), 0, s, c);
-    z3_status st = check_launch("k_gram_tiles");
+    const bool f32 = prec == Z3_PREC_MIXED;
+    z3_status st;
+    if (gram_lds_fits(m_max, nbins, prec)) {
+        GramArgs g;
+        g.src = src;
+        g.npiv = npiv;
+        g.v = piv_v;
+        g.v_stride = v_stride;
+        g.nb = nbins;
+        g.R = 2 * (m_max + 1);
+        g.T = T;
+        g.ntp = ntp;
+        g.M1 = m_max + 1;
+        g.nmaps = nmaps;
+        g.nunits = (m_max + 1) * ntp;
+        g.lpr_shift = g.R <= 32 ? 5 : 6;
+        g.tile_bytes = gram_tile_bytes(nbins, g.R, f32);
+        g.part = static_cast<double *>(partials);
+        const int upw = gram_upw(g.nunits);
+        const dim3 grid((unsigned)(nseg * nmaps));
+        const size_t lds = g.tile_bytes + kGramKP * sizeof(double);
+        if (f32) pm ? launch_gram_lds<true, true>(upw, grid, lds, g, s) : launch_gram_lds<true, false>(upw, grid, lds, g, s);
+        else pm ? launch_gram_lds<false, true>(upw, grid, lds, g, s) : launch_gram_lds<false, false>(upw, grid, lds, g, s);
+        st = check_launch("k_gram_lds");
+    } else {
+        if (pm) return fail(Z3_ERR_UNSUPPORTED, "pivot-major contraction for m_max=%d, %d bins", m_max, nbins);
+        ContractArgs c;
+        c.A = src.base; c.ldA = src.sb; c.npiv = npiv; c.v = piv_v; c.nb = nbins; c.T = T; c.ntp = ntp;
+        c.M1 = m_max + 1;
+        c.a_stride = src.map_stride;
+        c.v_stride = v_stride;
+        c.part = static_cast<double *>(partials);
+        dim3 grid(ntp, (unsigned)nseg, (unsigned)(nmaps * (m_max + 1)));
+        if (f32) hipLaunchKernelGGL(k_gram_tiles<true>, grid, dim3(64), 0, s, c);
+        else hipLaunchKernelGGL(k_gram_tiles<false>, grid, dim3(64), 0, s, c);
+        st = check_launch("k_gram_tiles");
+    }
     if (st != Z3_OK) return st;
     const int total = nmaps * (m_max + 1) * nbins * nbins;
     hipLaunchKernelGGL(k_gram_reduce, dim3((total + 127) / 128), dim3(128), 0, s,
                        static_cast<const double *>(partials), nseg, nmaps, m_max + 1, nbins, T, ntp, zeta, z_stride);
     return check_launch("k_gram_reduce");
+}
+
+z3_status launch_contract_maps(int64_t npiv, int m_max, int nbins, int prec, int nmaps, const void *A, int64_t ldA,
+                               size_t a_stride, const double *piv_v, size_t v_stride, double *zeta, size_t z_stride,
+                               void *partials, size_t partial_bytes, hipStream_t s)
+{
+    const GramSrc src{A, 1, ldA, (int64_t)nbins * ldA, a_stride};
+    return contract_src(npiv, m_max, nbins, prec, nmaps, src, false, piv_v, v_stride, zeta, z_stride, partials,
+                        partial_bytes, s);
+}
+
+z3_status launch_contract_staged(int64_t npiv, int m_max, int nbins, int prec, int nmaps, const void *stage,
+                                 const double *piv_v, size_t v_stride, double *zeta, size_t z_stride, void *partials,
+                                 size_t partial_bytes, hipStream_t s)
+{
+    const int64_t R = 2 * (m_max + 1);
+    const GramSrc src{stage, (int64_t)nbins * nmaps * R, (int64_t)nmaps * R, 1, (size_t)R};
+    return contract_src(npiv, m_max, nbins, prec, nmaps, src, true, piv_v, v_stride, zeta, z_stride, partials,
+                        partial_bytes, s);
 }
 
 z3_status launch_contract(int64_t npiv, int m_max, int nbins, int prec, const void *A, int64_t ldA,

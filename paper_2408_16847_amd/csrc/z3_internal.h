@@ -152,6 +152,12 @@ z3_status launch_contract(int64_t npiv, int m_max, int nbins, int prec, const vo
 z3_status launch_contract_maps(int64_t npiv, int m_max, int nbins, int prec, int nmaps, const void *A, int64_t ldA,
                                size_t a_stride, const double *piv_v, size_t v_stride, double *zeta, size_t z_stride,
                                void *partials, size_t partial_bytes, hipStream_t s);
+// the same contraction reading the many-map kernel's pivot-major staging
+// [P][nb][nmaps][2 (m+1)]; needs gram_lds_fits
+z3_status launch_contract_staged(int64_t npiv, int m_max, int nbins, int prec, int nmaps, const void *stage,
+                                 const double *piv_v, size_t v_stride, double *zeta, size_t z_stride, void *partials,
+                                 size_t partial_bytes, hipStream_t s);
+bool gram_lds_fits(int m_max, int nbins, int prec);
 size_t contract_partial_bytes(int64_t npiv, int m_max, int nbins);
 z3_status launch_weight_sum(const double *w, int64_t n, double *out, hipStream_t s);
 z3_status launch_pivot_values(const double *w, const double *x, int64_t n, double *v, hipStream_t s);

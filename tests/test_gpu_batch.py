@@ -158,3 +158,26 @@ def test_batch_pivot_subranges_compose(weighted_cap64):
     part = acc.cpu().numpy()
     assert np.abs(part - whole).max() <= 1e-12 * np.abs(whole).max()
     idx.free()
+
+
+@pytest.mark.parametrize("nb,M", [(20, 10), (25, 8)])
+@pytest.mark.parametrize("nmaps", [1, 3, 6])
+def test_contraction_unit_budgets(nb, M, nmaps):
+    """The contraction at both sides of its register budget: 20 bins with m <= 10 (66
+    (m, tile pair) units, the LDS-staged kernel at 9 units per wave) and 25 bins with m <= 8
+    (90 units, beyond it: the tile-pair kernel, after a transpose on the many-map path), for
+    the one-map, register-tiled (3 maps) and MFMA (6 maps) multipole kernels."""
+    G.say("case: contraction units, nb", nb, "M", M, "maps", nmaps)
+    xyz, w, _ = pins.random_cap(1500, 4.0, 11)
+    xs = _lognormal_maps(xyz, nmaps)
+    E = pins.small_edges(nb, lo=0.05, hi=2.0, log=True)
+    idx = G.build(xyz, xs if nmaps > 1 else xs[0], E, w=w)
+    for prec, tol in (("fp64", 1e-10), ("mixed", 1e-6)):
+        zs, pairs = z3.estimate_maps(idx, M, prec=prec)
+        for s in sorted({0, nmaps - 1}):
+            zo, po = cpu.estimate(xyz, xyz, w, xs[s], E, M, w, xs[s])
+            assert po == pairs
+            e = G.err_m(zs[s], zo)
+            G.say("  map", s, prec, "err", e.max())
+            assert e.max() < tol, (prec, s, e)
+    idx.free()
