@@ -33,6 +33,27 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v)
     return (uint64_t)hi << 32 | lo;
 }
 
+// Buffer view of one band's doubled records: a gfx9 buffer resource on a wave-uniform
+// base, addressed by 32-bit per-lane byte offsets (one add and one compare per loop step
+// instead of 64-bit address arithmetic).  Loads past `bytes` return zeros.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_view(const void *base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+__device__ __forceinline__ double4 load_record(__amdgpu_buffer_rsrc_t v, uint32_t off)
+{
+    typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+    const u4 a = __builtin_amdgcn_raw_buffer_load_b128(v, off, 0, 0);
+    const u4 b = __builtin_amdgcn_raw_buffer_load_b128(v, off + 16u, 0, 0);
+    double4 r;
+    r.x = __builtin_bit_cast(double, (uint64_t)a.x | (uint64_t)a.y << 32);
+    r.y = __builtin_bit_cast(double, (uint64_t)a.z | (uint64_t)a.w << 32);
+    r.z = __builtin_bit_cast(double, (uint64_t)b.x | (uint64_t)b.y << 32);
+    r.w = __builtin_bit_cast(double, (uint64_t)b.z | (uint64_t)b.w << 32);
+    return r;
+}
+
 __device__ __forceinline__ uint64_t mix64(uint64_t v)
 {  // SplitMix64 finaliser (Steele, Lea & Flood 2014)
     v += 0x9E3779B97F4A7C15ull;

@@ -132,6 +132,8 @@ void k_multipoles(MultArgs a)
             int s0, l0, s1, l1;
             band_window(bd, a.cell_start, th, sh, ch, inv_sp, phf, hav_out, hav_in, s0, l0, s1, l1);
             const int base = 2 * bd.pt_start;
+            // the band's doubled records (wave-uniform base), walked by byte offset
+            const __amdgpu_buffer_rsrc_t rband = buffer_view(a.rec + base, (uint32_t)bd.npts * 64u);
             float Yf[M + 1], Zf[M + 1];
             if constexpr (MIXED) {
 #pragma unroll
@@ -139,14 +141,19 @@ void k_multipoles(MultArgs a)
             }
 #pragma unroll
             for (int seg = 0; seg < 2; ++seg) {
-                int j = base + (seg == 0 ? s0 : s1);
-                const int jend = j + (seg == 0 ? l0 : l1);
-                for (; j < jend; ++j) {
-                    const double4 r = a.rec[j];
+                uint32_t off = (uint32_t)(seg == 0 ? s0 : s1) * 32u;
+                const uint32_t oend = off + (uint32_t)(seg == 0 ? l0 : l1) * 32u;
+                for (; off < oend; off += 32u) {
+                    const double4 r = load_record(rband, off);
                     const double dx = r.x - xp, dy = r.y - yp, dz = r.z - zp;
                     const double d2 = (dx * dx + dy * dy) + dz * dz;
                     if (d2 >= elo && d2 < ehi) {
                         cnt += 1;
+                        // record index from the byte offset, as an opaque shift so that the
+                        // compiler keeps no second induction variable for this rare use
+                        uint32_t jo;
+                        asm("v_lshrrev_b32 %0, 5, %1" : "=v"(jo) : "v"(off));
+                        const int j = base + (int)jo;
                         if (!unit_w) Wb += a.wdbl[j];
                         if constexpr (IDS) hsum += mix64((uint64_t)a.permdbl[j]);
                         const double u1 = fma(dx, nx, fma(dy, ny, dz * nz));
