@@ -110,19 +110,25 @@ __device__ __forceinline__ void band_window(const Band &bd, const int *cell_star
     const int C = bd.ncell;
     const float cpr = bd.cells_per_rad;
 
+    // The half-widths asin(sqrt(q)) are bounded rather than evaluated: with a = asin(x),
+    // x <= a <= tan(a) = x / sqrt(1 - x^2), so sqrt(q) bounds the excluded arc from below
+    // and sqrt(q / (1 - q)) the window from above (relative excess ~a^2 / 3, a few extra
+    // candidates that the d2 test rejects).  Hardware square root and reciprocal square
+    // root (~1 ulp) sit far inside the guard factors.
     const float q_out = (float)num_out * inv_sp * bd.inv_smin * (1.0f + 1e-5f);
     bool full = !(q_out < 1.0f);
     float dout = 0.0f;
     if (!full) {
-        dout = 2.0f * asinf(sqrtf(q_out)) * (1.0f + 4e-6f) + 4e-6f;
-        full = dout >= 3.14159265f;
+        const float t = __builtin_amdgcn_sqrtf(q_out) * __builtin_amdgcn_rsqf(1.0f - q_out);
+        dout = 2.0f * t * (1.0f + 4e-6f) + 4e-6f;
+        full = !(dout < 3.14159265f);
     }
     bool excl = false;
     float din = 0.0f;
     if (num_in > 0.0) {
         const float q_in = (float)num_in * inv_sp * bd.inv_smax * (1.0f - 1e-5f);
         if (!(q_in < 1.0f)) return;  // the whole band lies inside R_in
-        din = 2.0f * asinf(sqrtf(q_in)) * (1.0f - 4e-6f) - 4e-6f;
+        din = 2.0f * __builtin_amdgcn_sqrtf(q_in) * (1.0f - 4e-6f) - 4e-6f;
         excl = din > 0.0f;
     }
     // cells entirely inside the excluded arc (phf - din, phf + din)
