@@ -333,6 +333,9 @@ static z3_status contract_src(int64_t npiv, int m_max, int nbins, int prec, int 
     const bool f32 = prec == Z3_PREC_MIXED;
     z3_status st;
     if (gram_lds_fits(m_max, nbins, prec)) {
+        // one block per (segment, map): the dispatch stays below 2^32 work-items
+        if (nseg * nmaps > (int64_t)(UINT32_MAX / kGramThreads))
+            return fail(Z3_ERR_OVERFLOW, "contraction of %lld pivots x %d maps in one launch", (long long)npiv, nmaps);
         GramArgs g;
         g.src = src;
         g.npiv = npiv;
