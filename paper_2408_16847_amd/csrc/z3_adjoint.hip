@@ -35,44 +35,100 @@ struct PrepArgs {
     size_t ad_stride, g_stride, n_stride;
 };
 
+// One thread per (pivot, map); for each m the block first forms
+//     H(a, b) = conj(G(a, b)) + G(b, a)
+// in LDS (G is shared by the block's map), then every thread keeps its X(b) in registers:
+//     D(a) = sum_b H(a, b) conj(X(b)),
+// and the pivot term is Re sum_a X(a) E(a) = Re sum_a X(a) D(a) / 2, since
+// sum_a X(a) F(a) = conj(sum_a X(a) E(a)) (swap a and b).  NBT bounds nb (registers).
+template <int NBT>
 __global__ __launch_bounds__(256) void k_adjoint_prep(PrepArgs a)
+{
+    __shared__ double2 sH[NBT * NBT];
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool act = p < a.P;
+    const size_t mp = blockIdx.y;
+    const double *A = a.A + mp * a.ad_stride;
+    double *D = a.D + mp * a.ad_stride;
+    const double *G = a.G + mp * a.g_stride;
+    const int nb = a.nb;
+    const size_t P = (size_t)a.P;
+    const size_t pc = act ? (size_t)p : 0;
+    double piv = 0.0;
+    for (int m = 0; m <= a.M; ++m) {
+        __syncthreads();  // the previous m's H is consumed
+        const double *g = G + (size_t)m * nb * nb * 2;
+        for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
+            const int ai = e / nb, b = e - ai * nb;
+            const double gr = g[((size_t)ai * nb + b) * 2], gi = g[((size_t)ai * nb + b) * 2 + 1];
+            const double tr = g[((size_t)b * nb + ai) * 2], ti = g[((size_t)b * nb + ai) * 2 + 1];
+            sH[ai * NBT + b] = make_double2(gr + tr, ti - gi);
+        }
+        __syncthreads();
+        if (!act) continue;
+        const double *xr = A + (size_t)(2 * m) * nb * P + pc;
+        const double *xi = A + (size_t)(2 * m + 1) * nb * P + pc;
+        double ur[NBT], ui[NBT];  // conj(X(b))
+#pragma unroll
+        for (int b = 0; b < NBT; ++b) {
+            ur[b] = b < nb ? xr[(size_t)b * P] : 0.0;
+            ui[b] = b < nb ? -xi[(size_t)b * P] : 0.0;
+        }
+        for (int ai = 0; ai < nb; ++ai) {
+            double dr = 0.0, di = 0.0;
+#pragma unroll
+            for (int b = 0; b < NBT; ++b) {
+                if (b < nb) {  // uniform
+                    const double2 h = sH[ai * NBT + b];
+                    dr = fma(h.x, ur[b], fma(-h.y, ui[b], dr));
+                    di = fma(h.x, ui[b], fma(h.y, ur[b], di));
+                }
+            }
+            const double x_r = xr[(size_t)ai * P], x_i = xi[(size_t)ai * P];
+            piv += 0.5 * (x_r * dr - x_i * di);
+            const double wa = a.W[(size_t)ai * P + pc];
+            const double inv = wa > 0.0 ? 1.0 / wa : 0.0;
+            D[((size_t)(2 * m) * nb + ai) * P + pc] = dr * inv;
+            D[((size_t)(2 * m + 1) * nb + ai) * P + pc] = di * inv;
+        }
+    }
+    if (act) a.grad[mp * a.n_stride + pc] += a.scale * a.w[pc] * piv;
+}
+
+// The same for any nb: X(b) read from memory in the inner loop.
+__global__ __launch_bounds__(256) void k_adjoint_prep_any(PrepArgs a)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= a.P) return;
     const size_t mp = blockIdx.y;
-    a.A += mp * a.ad_stride;
-    a.D += mp * a.ad_stride;
-    a.G += mp * a.g_stride;
-    a.v += mp * a.n_stride;
-    a.grad += mp * a.n_stride;
+    const double *A = a.A + mp * a.ad_stride;
+    double *D = a.D + mp * a.ad_stride;
+    const double *G = a.G + mp * a.g_stride;
     const int nb = a.nb;
     const size_t P = (size_t)a.P;
     double piv = 0.0;
     for (int m = 0; m <= a.M; ++m) {
-        const double *xr = a.A + (size_t)(2 * m) * nb * P + p;
-        const double *xi = a.A + (size_t)(2 * m + 1) * nb * P + p;
-        const double *g = a.G + (size_t)m * nb * nb * 2;
+        const double *xr = A + (size_t)(2 * m) * nb * P + p;
+        const double *xi = A + (size_t)(2 * m + 1) * nb * P + p;
+        const double *g = G + (size_t)m * nb * nb * 2;
         for (int ai = 0; ai < nb; ++ai) {
-            // E(a) = sum_b conj(G(a,b)) conj(X(b));  F(a) = sum_b G(b,a) conj(X(b))
-            double er = 0.0, ei = 0.0, fr = 0.0, fi = 0.0;
+            double dr = 0.0, di = 0.0;
             for (int b = 0; b < nb; ++b) {
-                const double ur = xr[(size_t)b * P], ui = -xi[(size_t)b * P];  // conj(X(b))
-                const double gr = g[((size_t)ai * nb + b) * 2], gi = -g[((size_t)ai * nb + b) * 2 + 1];
-                er = fma(gr, ur, fma(-gi, ui, er));
-                ei = fma(gr, ui, fma(gi, ur, ei));
-                const double hr = g[((size_t)b * nb + ai) * 2], hi = g[((size_t)b * nb + ai) * 2 + 1];
-                fr = fma(hr, ur, fma(-hi, ui, fr));
-                fi = fma(hr, ui, fma(hi, ur, fi));
+                const double ur = xr[(size_t)b * P], ui = -xi[(size_t)b * P];
+                const double hr = g[((size_t)ai * nb + b) * 2] + g[((size_t)b * nb + ai) * 2];
+                const double hi = g[((size_t)b * nb + ai) * 2 + 1] - g[((size_t)ai * nb + b) * 2 + 1];
+                dr = fma(hr, ur, fma(-hi, ui, dr));
+                di = fma(hr, ui, fma(hi, ur, di));
             }
             const double x_r = xr[(size_t)ai * P], x_i = xi[(size_t)ai * P];
-            piv += x_r * er - x_i * ei;  // Re(X(a) E(a))
+            piv += 0.5 * (x_r * dr - x_i * di);
             const double wa = a.W[(size_t)ai * P + p];
             const double inv = wa > 0.0 ? 1.0 / wa : 0.0;
-            a.D[((size_t)(2 * m) * nb + ai) * P + p] = (er + fr) * inv;
-            a.D[((size_t)(2 * m + 1) * nb + ai) * P + p] = (ei + fi) * inv;
+            D[((size_t)(2 * m) * nb + ai) * P + p] = dr * inv;
+            D[((size_t)(2 * m + 1) * nb + ai) * P + p] = di * inv;
         }
     }
-    a.grad[p] += a.scale * a.w[p] * piv;
+    a.grad[mp * a.n_stride + p] += a.scale * a.w[p] * piv;
 }
 
 struct ScatterArgs {
@@ -253,7 +309,10 @@ static z3_status adjoint_chunk_maps(z3_index idx, int map, int nm, int m_max, in
     pa.ad_stride = stride;
     pa.g_stride = gstride;
     pa.n_stride = (size_t)idx->n;
-    hipLaunchKernelGGL(k_adjoint_prep, dim3((unsigned)((P + 255) / 256), nm), dim3(256), 0, s, pa);
+    const dim3 pgrid((unsigned)((P + 255) / 256), nm);
+    if (idx->nbins <= 16) hipLaunchKernelGGL(k_adjoint_prep<16>, pgrid, dim3(256), 0, s, pa);
+    else if (idx->nbins <= 32) hipLaunchKernelGGL(k_adjoint_prep<32>, pgrid, dim3(256), 0, s, pa);
+    else hipLaunchKernelGGL(k_adjoint_prep_any, pgrid, dim3(256), 0, s, pa);
     z3_status st = check_launch("k_adjoint_prep");
     if (st != Z3_OK) return st;
     ScatterArgs sa;

@@ -26,16 +26,18 @@ def _G_tensor(Gc):
     return torch.from_numpy(np.stack([Gc.real, Gc.imag], -1)).cuda()
 
 
-@pytest.mark.parametrize("weighted", [False, True])
-def test_adjoint_matches_oracle_gradient(weighted):
-    G.say("case: adjoint vs oracle, weighted", weighted)
+# 6 and 20 bins: the prep kernel's register paths (up to 16 and 32 bins); 40: its
+# general path
+@pytest.mark.parametrize("weighted,nb", [(False, 6), (True, 6), (False, 20), (True, 40)])
+def test_adjoint_matches_oracle_gradient(weighted, nb):
+    G.say("case: adjoint vs oracle, weighted", weighted, "bins", nb)
     xyz, w, x = pins.random_cap(1500, 4.0, 91)
     if not weighted:
         w = np.ones_like(w)
-    E = pins.small_edges(6, lo=0.1, hi=2.0, log=True)
+    E = pins.small_edges(nb, lo=0.1, hi=2.0, log=True)
     M = 6
     idx = G.build(xyz, x, E, w=w if weighted else None)
-    Gc = _rand_G(5, M, 6)
+    Gc = _rand_G(5, M, nb)
     g = z3.adjoint(idx, _G_tensor(Gc), 1.0 / w.sum(), M).cpu().numpy()
     go = ograd.zeta_grad(xyz, w, x, E, M, Gc)
     err = np.abs(g - go).max() / np.abs(go).max()
