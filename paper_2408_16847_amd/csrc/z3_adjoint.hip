@@ -152,40 +152,43 @@ struct ScatterArgs {
     size_t n_stride, rec_stride, d_stride;
 };
 
-template <int M>
+// K maps per lane share each pair's geometry and harmonics; their D coefficients take
+// 2 (M + 1) K registers, so the occupancy target drops with K.
+template <int M, int K>
 constexpr int adjoint_waves_per_eu()
 {
-    return M <= 10 ? 4 : (M <= 13 ? 3 : 2);
+    return K == 1 ? (M <= 10 ? 4 : (M <= 13 ? 3 : 2)) : (M <= 10 ? 3 : 2);
 }
 
 // Per-wave LDS slice that gathers a window's contributions before they go to HBM: the
 // lanes of a wave walk overlapping ranges of the same band, so one window's pairs touch
-// only ~(window + 64) distinct neighbours.
+// only ~(window + 64) distinct neighbours.  kAggSlots doubles per wave, split among the K
+// maps.
 constexpr int kAggSlots = 1024;
 
-template <int M>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(adjoint_waves_per_eu<M>())))
+template <int M, int K>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(adjoint_waves_per_eu<M, K>())))
 void k_adjoint_scatter(ScatterArgs a)
 {
-    __shared__ double agg_all[kBlock / kWave][kAggSlots];
-    double *agg = agg_all[threadIdx.x / kWave];
+    constexpr int SLOTS = kAggSlots / K;
+    __shared__ double agg_all[kBlock / kWave][K][SLOTS];
+    double(*agg)[SLOTS] = agg_all[threadIdx.x / kWave];
     const int lane = threadIdx.x & (kWave - 1);
-    for (int e = lane; e < kAggSlots; e += kWave) agg[e] = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        for (int e = lane; e < SLOTS; e += kWave) agg[k][e] = 0.0;
     const int lb = xcd_block(blockIdx.x, a.nblocks);
     const int64_t wave0 = a.p0 + (int64_t)lb * kBlock + (threadIdx.x & ~(kWave - 1));
     if (__builtin_amdgcn_readfirstlane((int)(wave0 >= a.p1))) return;
     const int64_t p = a.p0 + (int64_t)lb * kBlock + threadIdx.x;
     const bool valid = p < a.p1;
     const int64_t pp = valid ? p : a.p1 - 1;
-    {
-        const size_t mp = blockIdx.y;
-        a.pv += mp * a.n_stride;
-        a.grad += mp * a.n_stride;
-        a.rec += mp * a.rec_stride;
-        a.D += mp * a.d_stride;
-    }
+    const size_t mp0 = (size_t)blockIdx.y * K;  // first map of this block
+    a.rec += mp0 * a.rec_stride;  // positions (the same for every map)
     const PivotFrame f = pivot_frame(a.px[pp], a.py[pp], a.pz[pp]);
-    const double vp = valid ? a.scale * a.pv[pp] : 0.0;  // idle lanes add nothing
+    double vp[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) vp[k] = valid ? a.scale * a.pv[(mp0 + k) * a.n_stride + pp] : 0.0;  // idle lanes add nothing
     const int64_t col = pp - a.p0;
     const int nb = a.nb;
     const bool unit_w = a.wdbl == nullptr;
@@ -195,14 +198,18 @@ void k_adjoint_scatter(ScatterArgs a)
         const double hav_out = a.edges->hav_out[bin + 1], hav_in = a.edges->hav_in[bin];
         int klo, khi;
         band_range(f.th, a.edges->rad_out[bin + 1], a.inv_h, a.nbands, klo, khi);
-        double Dr[M + 1], Di[M + 1];
+        double Dr[K][M + 1], Di[K][M + 1];
 #pragma unroll
-        for (int m = 0; m <= M; ++m) {
-            Dr[m] = vp * a.D[((size_t)(2 * m) * nb + bin) * (size_t)a.ldD + col];
-            Di[m] = vp * a.D[((size_t)(2 * m + 1) * nb + bin) * (size_t)a.ldD + col];
+        for (int k = 0; k < K; ++k) {
+            const double *Dk = a.D + (mp0 + k) * a.d_stride;
+#pragma unroll
+            for (int m = 0; m <= M; ++m) {
+                Dr[k][m] = vp[k] * Dk[((size_t)(2 * m) * nb + bin) * (size_t)a.ldD + col];
+                Di[k][m] = vp[k] * Dk[((size_t)(2 * m + 1) * nb + bin) * (size_t)a.ldD + col];
+            }
         }
-        for (int k = klo; k <= khi; ++k) {
-            const Band bd = a.bands[k];
+        for (int kb = klo; kb <= khi; ++kb) {
+            const Band bd = a.bands[kb];
             if (bd.npts == 0) continue;
             int s0, l0, s1, l1;
             band_window(bd, a.cell_start, f.th, f.sh, f.ch, f.inv_sp, f.phf, hav_out, hav_in, s0, l0, s1, l1);
@@ -216,7 +223,7 @@ void k_adjoint_scatter(ScatterArgs a)
                 const int jlo = __builtin_amdgcn_readfirstlane(wave_min(any ? j : 0x7fffffff));
                 const int jhi = __builtin_amdgcn_readfirstlane(wave_max(any ? jend : -1));
                 if (jhi <= jlo) continue;
-                const bool use_lds = jhi - jlo <= kAggSlots;
+                const bool use_lds = jhi - jlo <= SLOTS;
                 for (; j < jend; ++j) {
                     const double4 r = a.rec[j];
                     const double dx = r.x - f.xp, dy = r.y - f.yp, dz = r.z - f.zp;
@@ -227,41 +234,55 @@ void k_adjoint_scatter(ScatterArgs a)
                         double c, sn;
                         unit_bearing(u1, u2, c, sn);
                         // sum_m Re(exp(-i m phi) D(m)) = sum_m cos(m phi) Re D + sin(m phi) Im D
-                        double acc = Dr[0];
+                        double acc[K];
+#pragma unroll
+                        for (int k = 0; k < K; ++k) acc[k] = Dr[k][0];
                         if constexpr (M >= 1) {
                             const double tc = c + c;
                             double t2 = 1.0, t1 = c, s2 = 0.0, s1 = sn;
-                            acc = fma(t1, Dr[1], fma(s1, Di[1], acc));
+#pragma unroll
+                            for (int k = 0; k < K; ++k) acc[k] = fma(t1, Dr[k][1], fma(s1, Di[k][1], acc[k]));
 #pragma unroll
                             for (int m = 2; m <= M; ++m) {
                                 const double tm = fma(tc, t1, -t2);
                                 const double sm = fma(tc, s1, -s2);
-                                acc = fma(tm, Dr[m], fma(sm, Di[m], acc));
+#pragma unroll
+                                for (int k = 0; k < K; ++k) acc[k] = fma(tm, Dr[k][m], fma(sm, Di[k][m], acc[k]));
                                 t2 = t1; t1 = tm;
                                 s2 = s1; s1 = sm;
                             }
                         }
-                        if (!unit_w) acc *= a.wdbl[j];
+                        if (!unit_w) {
+                            const double wj = a.wdbl[j];
+#pragma unroll
+                            for (int k = 0; k < K; ++k) acc[k] *= wj;
+                        }
                         if (use_lds) {
-                            atomicAdd(&agg[j - jlo], acc);
+#pragma unroll
+                            for (int k = 0; k < K; ++k) atomicAdd(&agg[k][j - jlo], acc[k]);
                         } else {
                             int t = j - base;
                             if (t >= bd.npts) t -= bd.npts;
-                            atomicAdd(&a.grad[bd.pt_start + t], acc);
+#pragma unroll
+                            for (int k = 0; k < K; ++k)
+                                atomicAdd(&a.grad[(mp0 + k) * a.n_stride + bd.pt_start + t], acc[k]);
                         }
                     }
                 }
                 if (use_lds) {
-                    // one global atomic per touched neighbour, and the slice is cleared
+                    // one global atomic per touched neighbour and map, and the slice is cleared
                     __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): this wave's LDS adds are done
                     __builtin_amdgcn_wave_barrier();
                     for (int e = lane; e < jhi - jlo; e += kWave) {
-                        const double val = agg[e];
-                        if (val != 0.0) {
-                            int t = jlo + e - base;
-                            if (t >= bd.npts) t -= bd.npts;
-                            atomicAdd(&a.grad[bd.pt_start + t], val);
-                            agg[e] = 0.0;
+                        int t = jlo + e - base;
+                        if (t >= bd.npts) t -= bd.npts;
+#pragma unroll
+                        for (int k = 0; k < K; ++k) {
+                            const double val = agg[k][e];
+                            if (val != 0.0) {
+                                atomicAdd(&a.grad[(mp0 + k) * a.n_stride + bd.pt_start + t], val);
+                                agg[k][e] = 0.0;
+                            }
                         }
                     }
                     __builtin_amdgcn_s_waitcnt(0xc07f);
@@ -278,10 +299,20 @@ __global__ void k_grad_to_catalogue(int64_t n, const int *perm, const double *gs
     if (i < n) grad[perm[i]] += gs[i];
 }
 
+// Maps in pairs (geometry shared by two maps per lane), an odd last map alone.
 template <int M>
 static void launch_scatter_m(const ScatterArgs &a, int nm, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_adjoint_scatter<M>, dim3(a.nblocks, nm), dim3(kBlock), 0, s, a);
+    if (nm >= 2) hipLaunchKernelGGL((k_adjoint_scatter<M, 2>), dim3(a.nblocks, nm / 2), dim3(kBlock), 0, s, a);
+    if (nm & 1) {
+        ScatterArgs b = a;
+        const size_t last = (size_t)(nm - 1);
+        b.pv += last * a.n_stride;
+        b.grad += last * a.n_stride;
+        b.rec += last * a.rec_stride;
+        b.D += last * a.d_stride;
+        hipLaunchKernelGGL((k_adjoint_scatter<M, 1>), dim3(a.nblocks, 1), dim3(kBlock), 0, s, b);
+    }
 }
 
 // Prep + scatter of maps [map, map + nm) for pivots [c0, c1) whose multipoles A (ld =
