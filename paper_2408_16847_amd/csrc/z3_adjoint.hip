@@ -157,7 +157,7 @@ struct ScatterArgs {
 template <int M, int K>
 constexpr int adjoint_waves_per_eu()
 {
-    return K == 1 ? (M <= 10 ? 4 : (M <= 13 ? 3 : 2)) : (M <= 10 ? 3 : 2);
+    return K == 1 ? (M <= 10 ? 4 : (M <= 13 ? 3 : 2)) : (K == 2 && M <= 10 ? 3 : 2);
 }
 
 // Per-wave LDS slice that gathers a window's contributions before they go to HBM: the
@@ -303,7 +303,16 @@ __global__ void k_grad_to_catalogue(int64_t n, const int *perm, const double *gs
 template <int M>
 static void launch_scatter_m(const ScatterArgs &a, int nm, hipStream_t s)
 {
-    if (nm >= 2) hipLaunchKernelGGL((k_adjoint_scatter<M, 2>), dim3(a.nblocks, nm / 2), dim3(kBlock), 0, s, a);
+    if (nm >= 4) hipLaunchKernelGGL((k_adjoint_scatter<M, 4>), dim3(a.nblocks, nm / 4), dim3(kBlock), 0, s, a);
+    if (nm & 2) {
+        ScatterArgs b = a;
+        const size_t first = (size_t)(nm & ~3);
+        b.pv += first * a.n_stride;
+        b.grad += first * a.n_stride;
+        b.rec += first * a.rec_stride;
+        b.D += first * a.d_stride;
+        hipLaunchKernelGGL((k_adjoint_scatter<M, 2>), dim3(a.nblocks, 1), dim3(kBlock), 0, s, b);
+    }
     if (nm & 1) {
         ScatterArgs b = a;
         const size_t last = (size_t)(nm - 1);
