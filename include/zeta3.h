@@ -187,10 +187,11 @@ z3_status z3_estimate(z3_index idx, int map, int m_max, int prec, int64_t p0, in
  * zeta [nmaps][m_max+1][nbins][nbins][2] += (unnormalised, one block per map, in map
  * order); pair_total += the number of pairs (counted once, not per map), or NULL.
  * Up to 4 maps: register-tiled kernel, FP64 multipole sums.  More maps: the per-pair
- * harmonics of a group of 64 candidates form the B operand of an MFMA product with the
- * maps' values (block shape: see z3_index_set_batch_shape); FP64 path in
- * FP64 MFMA, mixed path in FP32 MFMA with FP64 sums per 64 candidates.  `prec` also
- * selects the FP64 or the mixed (FP32 storage, split FP32 MFMA) contraction.
+ * harmonics of a group of 64 x (waves per block) candidates form the B operand of MFMA
+ * products with the maps' values (block shape: see z3_index_set_batch_shape); FP64 path
+ * in FP64 MFMA, mixed path in FP32 MFMA with the FP32 sums added into FP64 every 128
+ * candidates.  `prec` also selects the FP64 or the mixed (FP32 storage, split FP32 MFMA)
+ * contraction.
  * Synchronous on `stream` the first time an (m_max, prec) is used with more than 4
  * maps and an automatic shape (the shapes are timed then), unless the stream is capturing.
  */
