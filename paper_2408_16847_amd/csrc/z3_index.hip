@@ -454,6 +454,11 @@ z3_status build_index_impl(int64_t n, const double *xyz, const double *w, int nb
     if (st == Z3_OK) st = check_hip(hipStreamSynchronize(s), "sync");
     if (st != Z3_OK) return bail2(st);
 
+    // the multipole kernel addresses a band's doubled records (64 B per point) with 32-bit
+    // byte offsets
+    for (int k = 0; k < nbands; ++k)
+        if ((int64_t)bcount[k] * 64 > (int64_t)UINT32_MAX)
+            return bail2(fail(Z3_ERR_UNSUPPORTED, "z3_build_index: %d points in one latitude band", bcount[k]));
     std::vector<Band> bands(nbands);
     int64_t pt = 0, cells = 0;
     for (int k = 0; k < nbands; ++k) {
