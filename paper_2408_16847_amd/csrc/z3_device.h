@@ -172,10 +172,12 @@ __device__ __forceinline__ void band_window(const Band &bd, const int *cell_star
 
 // Unit-length bearing (c, s) = (u1, u2) / |u| with FP64 accuracy: FP32 reciprocal
 // square root refined by one FP64 Newton step (relative error ~1e-14).  For every pair in
-// range |u|^2 >= E_0 (1 - E_nb / 4) > 0, so the clamp only guards non-finite inputs.
+// range |u|^2 >= E_0 (1 - E_nb / 4) > 0; the addend below only matters for |u| = 0.
 __device__ __forceinline__ void unit_bearing(double u1, double u2, double &c, double &s)
 {
-    const double q = fmax(fma(u1, u1, u2 * u2), 1e-37);
+    // the tiny addend keeps q > 0 (coincident points) at the cost of no instruction: it is
+    // below the rounding of u2^2 for every pair in range
+    const double q = fma(u1, u1, fma(u2, u2, 1e-37));
     const double r0 = (double)__builtin_amdgcn_rsqf((float)q);
     const double e = fma(-q * r0, r0, 1.0);  // 1 - q r0^2
     const double r = fma(0.5 * e, r0, r0);

@@ -243,7 +243,8 @@ void k_multipoles(MultArgs a)
                             // the hardware reciprocal square root (the FP32 harmonics that
                             // follow carry errors of the same order)
                             const float u1f = (float)u1, u2f = (float)u2;
-                            const float rq = __builtin_amdgcn_rsqf(fmaxf(fmaf(u1f, u1f, u2f * u2f), 1e-30f));
+                            // + 1e-30: q > 0 for coincident points, below the rounding otherwise
+                            const float rq = __builtin_amdgcn_rsqf(fmaf(u1f, u1f, fmaf(u2f, u2f, 1e-30f)));
                             const float cf = u1f * rq, sf = u2f * rq;
                             Yf[0] += v;
                             if constexpr (M >= 1) {
