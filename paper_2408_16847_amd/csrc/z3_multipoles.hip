@@ -200,44 +200,29 @@ void k_multipoles(MultArgs a)
                         }
                     }
                 }
-                for (; off < oend; off += 32u) {
-                    const double4 r = load_record(rband, off);
-                    const double dx = r.x - xp, dy = r.y - yp, dz = r.z - zp;
-                    const double d2 = (dx * dx + dy * dy) + dz * dz;
-                    if (d2 >= elo && d2 < ehi) {
-                        cnt += 1;
-                        if (IDS || !unit_w) {  // wave-uniform
-                            // record index from the byte offset, as an opaque shift so that
-                            // the compiler keeps no second induction variable for this use
-                            uint32_t jo;
-                            asm("v_lshrrev_b32 %0, 5, %1" : "=v"(jo) : "v"(off));
-                            const int j = base + (int)jo;
-                            if (!unit_w) Wb += a.wdbl[j];
-                            if constexpr (IDS) hsum += mix64((uint64_t)a.permdbl[j]);
-                        }
-                        const double u1 = fma(dx, nx, fma(dy, ny, dz * nz));
-                        const double u2 = fma(dx, ex, fma(dy, ey, dz * ez));
-                        if constexpr (!MIXED) {
-                            double c, sn;
-                            unit_bearing(u1, u2, c, sn);
-                            const double v = r.w;
-                            Y[0] += v;
-                            if constexpr (M >= 1) {
-                                const double tc = c + c;
-                                double t2 = v, t1 = v * c, s2 = 0.0, s1 = v * sn;
-                                Y[1] += t1;
-                                Z[1] += s1;
-#pragma unroll
-                                for (int m = 2; m <= M; ++m) {
-                                    const double tm = fma(tc, t1, -t2);
-                                    const double sm = fma(tc, s1, -s2);
-                                    Y[m] += tm;
-                                    Z[m] += sm;
-                                    t2 = t1; t1 = tm;
-                                    s2 = s1; s1 = sm;
-                                }
+                if constexpr (MIXED) {
+                    // one candidate per step; the next record is requested before this one
+                    // is processed, so that its latency (an L2 or HBM miss now and then)
+                    // overlaps this candidate's work
+                    double4 rn = load_record(rband, off < oend ? off : 0u);
+                    for (; off < oend; off += 32u) {
+                        const double4 r = rn;
+                        rn = load_record(rband, off + 32u < oend ? off + 32u : off);
+                        const double dx = r.x - xp, dy = r.y - yp, dz = r.z - zp;
+                        const double d2 = (dx * dx + dy * dy) + dz * dz;
+                        if (d2 >= elo && d2 < ehi) {
+                            cnt += 1;
+                            if (IDS || !unit_w) {  // wave-uniform
+                                // record index from the byte offset, as an opaque shift so
+                                // that the compiler keeps no second induction variable
+                                uint32_t jo;
+                                asm("v_lshrrev_b32 %0, 5, %1" : "=v"(jo) : "v"(off));
+                                const int j = base + (int)jo;
+                                if (!unit_w) Wb += a.wdbl[j];
+                                if constexpr (IDS) hsum += mix64((uint64_t)a.permdbl[j]);
                             }
-                        } else {
+                            const double u1 = fma(dx, nx, fma(dy, ny, dz * nz));
+                            const double u2 = fma(dx, ex, fma(dy, ey, dz * ez));
                             const float v = (float)r.w;
                             // the bearing in FP32: the tangent components rounded once, then
                             // the hardware reciprocal square root (the FP32 harmonics that
