@@ -1,5 +1,6 @@
-"""GPU parity at the full workload sizes the bench times (HEALPix Nside 2048 and 4096, 64
-maps at Nside 512), on sampled pivots the oracle computes one by one: ragged pivot ranges
+"""GPU parity at the full workload sizes the bench times (HEALPix Nside 2048 and 4096, the
+approximate Nside 4096 search, 64 maps at Nside 512), on sampled pivots the oracle computes
+one by one: ragged pivot ranges
 at the north pole, across a band boundary near the equator (the 0 / 2 pi wrap of the
 longitude windows) and at the south pole.  Per-pivot pair counts, bin weights and neighbour
 fingerprints bit-exact; per-pivot multipoles within 1e-11 (FP64) of each bin's scale, and
@@ -113,4 +114,39 @@ def test_fullsize_batch64_sampled_pivots():
             e = G.err_m(zg[s, ..., 0] + 1j * zg[s, ..., 1], zo).max()
             G.say("  map", s, prec, len(pm), "pivots, err", e)
             assert e < tol, (s, prec, e)
+    idx.free()
+
+
+def test_fullsize_approx_nside4096_sampled_pivots():
+    """The approximate search at full size: Nside 4096 pivots (external catalogue, RING
+    order) against the Nside 2048 averaged neighbour map, on pivot ranges at the north pole,
+    across the equator and at the south pole, against the oracle run on the same coarse
+    neighbour catalogue."""
+    from synth import degrade_ring
+    cfg = CONFIGS["nside4096"]
+    G.say("case: full size approx nside4096")
+    xyz = make_positions(cfg, device="cuda")
+    x = make_values(cfg, xyz, seed=0)
+    nxyz, nx, nw = degrade_ring(cfg.n_or_nside, x)
+    E = cfg.edges_chord2()
+    M = cfg.m_max
+    idx = z3.Index(nxyz, E, weights=nw)
+    idx.set_values(nx)
+    n = xyz.shape[1]
+    ranges = [(0, 300), (n // 2 - 150, n // 2 + 151), (n - 300, n)]
+    piv_h = np.concatenate([xyz[:, a:b].cpu().numpy() for a, b in ranges], axis=1)
+    pxv_h = np.concatenate([x[a:b].cpu().numpy() for a, b in ranges])
+    nbr_h, nx_h, nw_h = nxyz.cpu().numpy(), nx.cpu().numpy(), nw.cpu().numpy()
+    zo, po = cpu.estimate(piv_h, nbr_h, nw_h, nx_h, E, M, np.ones(piv_h.shape[1]), pxv_h)
+    for prec, tol in (("fp64", 1e-10), ("mixed", 1e-6)):
+        zeta = torch.zeros((M + 1, idx.nbins, idx.nbins, 2), dtype=torch.float64, device="cuda")
+        pairs = torch.zeros(1, dtype=torch.int64, device="cuda")
+        for a, b in ranges:
+            z3.estimate_pivots_raw(idx, xyz, x, None, M, prec=prec, p0=a, p1=b, zeta=zeta, pair_total=pairs)
+        torch.cuda.synchronize()
+        zg = zeta.cpu().numpy() / piv_h.shape[1]
+        assert int(pairs.item()) == po, (prec, int(pairs.item()), po)
+        e = G.err_m(zg[..., 0] + 1j * zg[..., 1], zo).max()
+        G.say("  approx zeta", prec, piv_h.shape[1], "pivots, err", e)
+        assert e < tol, (prec, e)
     idx.free()
