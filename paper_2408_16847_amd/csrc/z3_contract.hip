@@ -241,27 +241,63 @@ __global__ __launch_bounds__(kGramThreads) void k_gram_lds(GramArgs g)
     for (int64_t p0 = pbeg; p0 < pend; p0 += kGramKP) {
         const int np = (int)min((int64_t)kGramKP, pend - p0);
         __syncthreads();  // the previous tile is consumed
+        // Each thread walks its elements (inner index b by `step`, wrapping into the outer
+        // index) with incremental addresses, and issues the global loads of 8 elements
+        // before it writes any of them to LDS, so their latencies overlap.
         if constexpr (PM) {
             // runs of R rows per (pivot, bin), contiguous in memory: lanes along the run
-            const int lpr = 1 << g.lpr_shift, step = kGramThreads >> g.lpr_shift;
-            const int r = tid & (lpr - 1);
-            int kb = tid >> g.lpr_shift, k = kb / nb, b = kb - k * nb;
+            const int step = kGramThreads >> g.lpr_shift;
+            const int r = tid & ((1 << g.lpr_shift) - 1);
+            const int kb0 = tid >> g.lpr_shift;
+            int k = kb0 / nb, b = kb0 - k * nb;
+            const T *ptr = src + (size_t)(p0 + k) * g.src.sp + (size_t)b * g.src.sb + r;
+            int li = kb0 * R + r;
+            const int64_t d_in = (int64_t)step * g.src.sb, d_wrap = g.src.sp - (int64_t)nb * g.src.sb;
             while (k < kGramKP) {
-                if (r < R)
-                    tile[(k * nb + b) * R + r] =
-                        k < np ? src[(size_t)(p0 + k) * g.src.sp + (size_t)b * g.src.sb + r] : T(0);
-                b += step;
-                while (b >= nb) { b -= nb; ++k; }
+                T val[8];
+                int at[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    at[i] = -1;
+                    if (k < kGramKP) {
+                        if (r < R) at[i] = li;
+                        val[i] = (k < np && r < R) ? *ptr : T(0);
+                        b += step;
+                        ptr += d_in;
+                        li += step * R;
+                        while (b >= nb) { b -= nb; ++k; ptr += d_wrap; }
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+                    if (at[i] >= 0) tile[at[i]] = val[i];
             }
         } else {
             // runs of kGramKP pivots per (row, bin): lanes along the pivots
             const int k = tid & (kGramKP - 1), step = kGramThreads / kGramKP;
-            int rb = tid / kGramKP, r = rb / nb, b = rb - r * nb;
+            const int rb0 = tid / kGramKP;
+            int r = rb0 / nb, b = rb0 - r * nb;
+            const T *ptr = src + (size_t)(p0 + k) * g.src.sp + (size_t)b * g.src.sb + (size_t)r * g.src.sr;
+            int li = (k * nb + b) * R + r;
+            const int64_t d_in = (int64_t)step * g.src.sb, d_wrap = g.src.sr - (int64_t)nb * g.src.sb;
             while (r < R) {
-                tile[(k * nb + b) * R + r] =
-                    k < np ? src[(size_t)(p0 + k) * g.src.sp + (size_t)b * g.src.sb + (size_t)r * g.src.sr] : T(0);
-                b += step;
-                while (b >= nb) { b -= nb; ++r; }
+                T val[8];
+                int at[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    at[i] = -1;
+                    if (r < R) {
+                        at[i] = li;
+                        val[i] = k < np ? *ptr : T(0);
+                        b += step;
+                        ptr += d_in;
+                        li += step * R;
+                        while (b >= nb) { b -= nb; ++r; ptr += d_wrap; li += 1 - nb * R; }
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+                    if (at[i] >= 0) tile[at[i]] = val[i];
             }
         }
         if (tid < kGramKP) vt[tid] = tid < np ? v[p0 + tid] : 0.0;
