@@ -55,6 +55,17 @@ __global__ __launch_bounds__(256) void k_adjoint_prep(PrepArgs a)
     const size_t P = (size_t)a.P;
     const size_t pc = act ? (size_t)p : 0;
     double piv = 0.0;
+    // up to 16 bins the a-loop is unrolled too: 1 / W_{p,a} is loaded once, and X(a) comes
+    // from the registers instead of a second load
+    constexpr bool UNROLL_A = NBT <= 16;
+    double inv_w[UNROLL_A ? NBT : 1];
+    if constexpr (UNROLL_A) {
+#pragma unroll
+        for (int ai = 0; ai < NBT; ++ai) {
+            const double wa = ai < nb ? a.W[(size_t)ai * P + pc] : 0.0;
+            inv_w[ai] = wa > 0.0 ? 1.0 / wa : 0.0;
+        }
+    }
     for (int m = 0; m <= a.M; ++m) {
         __syncthreads();  // the previous m's H is consumed
         const double *g = G + (size_t)m * nb * nb * 2;
@@ -73,6 +84,25 @@ __global__ __launch_bounds__(256) void k_adjoint_prep(PrepArgs a)
         for (int b = 0; b < NBT; ++b) {
             ur[b] = b < nb ? xr[(size_t)b * P] : 0.0;
             ui[b] = b < nb ? -xi[(size_t)b * P] : 0.0;
+        }
+        if constexpr (UNROLL_A) {
+#pragma unroll
+            for (int ai = 0; ai < NBT; ++ai) {
+                if (ai >= nb) continue;  // uniform
+                double dr = 0.0, di = 0.0;
+#pragma unroll
+                for (int b = 0; b < NBT; ++b) {
+                    if (b < nb) {
+                        const double2 h = sH[ai * NBT + b];
+                        dr = fma(h.x, ur[b], fma(-h.y, ui[b], dr));
+                        di = fma(h.x, ui[b], fma(h.y, ur[b], di));
+                    }
+                }
+                piv += 0.5 * (ur[ai] * dr + ui[ai] * di);  // Re(X(a) D(a)) / 2, X = (ur, -ui)
+                D[((size_t)(2 * m) * nb + ai) * P + pc] = dr * inv_w[ai];
+                D[((size_t)(2 * m + 1) * nb + ai) * P + pc] = di * inv_w[ai];
+            }
+            continue;
         }
         for (int ai = 0; ai < nb; ++ai) {
             double dr = 0.0, di = 0.0;
