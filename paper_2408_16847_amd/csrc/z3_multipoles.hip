@@ -25,9 +25,9 @@
 //
 // Precision: the FP64 path normalises the bearing with an FP32-seeded reciprocal square
 // root refined by one FP64 Newton step and runs everything in FP64.  The mixed path keeps
-// the separations and bin decisions in FP64, forms the bearing in FP32 (tangent components
-// rounded once, hardware reciprocal square root), runs the recurrences in FP32 and adds the
-// FP32 sums of each band window into FP64 bin sums.
+// the separations and bin decisions in FP64, forms the bearing in FP32 (the separation
+// rounded once, an FP32 frame, hardware reciprocal square root), runs the recurrences in
+// FP32 and adds the FP32 sums of each band window into FP64 bin sums.
 #include "z3_internal.h"
 #include "z3_device.h"
 
@@ -102,6 +102,9 @@ void k_multipoles(MultArgs a)
     }
     nx /= nn; ny /= nn; nz /= nn;
     const double ex = ny * zp - nz * yp, ey = nz * xp - nx * zp, ez = nx * yp - ny * xp;
+    // the mixed path's frame, rounded once
+    const float nxf = (float)nx, nyf = (float)ny, nzf = (float)nz;
+    const float exf = (float)ex, eyf = (float)ey, ezf = (float)ez;
 
     const int64_t col = p - a.p0;
     const int nb = a.nb;
@@ -221,13 +224,14 @@ void k_multipoles(MultArgs a)
                                 if (!unit_w) Wb += a.wdbl[j];
                                 if constexpr (IDS) hsum += mix64((uint64_t)a.permdbl[j]);
                             }
-                            const double u1 = fma(dx, nx, fma(dy, ny, dz * nz));
-                            const double u2 = fma(dx, ex, fma(dy, ey, dz * ez));
+                            // the bearing in FP32: the separation rounded once, the tangent
+                            // components against the FP32 frame, then the hardware reciprocal
+                            // square root (the FP32 harmonics that follow carry errors of the
+                            // same order; the FP32 frame also frees six registers)
+                            const float dxf = (float)dx, dyf = (float)dy, dzf = (float)dz;
                             const float v = (float)r.w;
-                            // the bearing in FP32: the tangent components rounded once, then
-                            // the hardware reciprocal square root (the FP32 harmonics that
-                            // follow carry errors of the same order)
-                            const float u1f = (float)u1, u2f = (float)u2;
+                            const float u1f = fmaf(dxf, nxf, fmaf(dyf, nyf, dzf * nzf));
+                            const float u2f = fmaf(dxf, exf, fmaf(dyf, eyf, dzf * ezf));
                             // + 1e-30: q > 0 for coincident points, below the rounding otherwise
                             const float rq = __builtin_amdgcn_rsqf(fmaf(u1f, u1f, fmaf(u2f, u2f, 1e-30f)));
                             const float cf = u1f * rq, sf = u2f * rq;
