@@ -7,6 +7,8 @@ AssertionError otherwise, so a planted mistake can be shown to fail it.
 from __future__ import annotations
 
 import math
+import os
+from fractions import Fraction
 
 import numpy as np
 
@@ -46,6 +48,30 @@ def three_point_expected(x, m_max):
         z[m, 0, 0] = (xp * xa * xa + xa * xp * xp) / 3.0
         z[m, 2, 2] = (xp * xb * xb + xb * xp * xp) / 3.0
     return z
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def golden_three_point():
+    """Hand-derived three-point values of ``golden/three_point.txt`` (exact rationals).
+
+    Returns (ordered pair count, zeta[m][b1][b2] complex128 for m = 0..4).
+    """
+    z = np.zeros((5, 3, 3), dtype=np.complex128)
+    pairs = None
+    with open(os.path.join(GOLDEN, "three_point.txt")) as f:
+        for line in f:
+            tok = line.split()
+            if not tok or tok[0].startswith("#"):
+                continue
+            if tok[0] == "pairs":
+                pairs = int(tok[1])
+                continue
+            m, b1, b2 = (int(t) for t in tok[:3])
+            re, im = (float(Fraction(t)) for t in tok[3:5])
+            z[m, b1, b2] = complex(re, im)
+    return pairs, z
 
 
 def check_three_point(m_max=4, tol=1e-14):

@@ -34,8 +34,8 @@ def test_three_point_closed_form_on_gpu():
     xyz, E, x = pins.three_point_case()
     idx = G.build(xyz, x, E)
     z, pairs = z3.estimate(idx, 4)
-    exp = pins.three_point_expected(x, 4)
-    assert pairs == 4
+    gold_pairs, exp = pins.golden_three_point()
+    assert pairs == gold_pairs
     # the GPU normalises the bearing with an FP32-seeded, Newton-refined reciprocal
     # square root (relative error ~1e-14); the oracle uses atan2 and libm trigonometry
     assert np.abs(z - exp).max() < 1e-12

@@ -29,6 +29,18 @@ def test_p2_three_point_values_printed_in_the_derivation():
     assert abs(z[0, 2, 2].real - (-0.468 / 3.0)) < 1e-14
 
 
+def test_p2_three_point_golden_fixture():
+    # the closed form used by the other checks against the hand-derived rationals
+    pairs, gold = pins.golden_three_point()
+    xyz, E, x = pins.three_point_case()
+    w = np.ones(3)
+    assert pairs == 4
+    assert np.abs(pins.three_point_expected(x, 4) - gold).max() < 1e-15
+    z, p = ref.estimate(xyz, xyz, w, x, E, 4, w, x)
+    assert p == pairs
+    assert np.abs(z - gold).max() < 1e-14
+
+
 def test_p2_three_point_c_oracle_and_brute():
     xyz, E, x = pins.three_point_case()
     w = np.ones(3)
