@@ -28,6 +28,10 @@ Ym/Zm.binned, zetamEst2), with the readings listed in the design doc:
 4. normalise: X_m(b; p) = a_{m,b}(p) / W_{p,b}, and 0 where W_{p,b} = 0;
 5. contract: zeta_m(b1, b2) = (1 / sum_p w_p) sum_p w_p x_p X_m(b1; p) conj(X_m(b2; p)),
    over all pivots, keeping the j = k terms;
+   optionally without them (the diagonal overcount that the paper flags in the
+   kappa^3 multipole-signal subsection): each pivot's product X(b) conj X(b) holds the
+   terms k = j, sum_{j in b} (w_j x_j / W_{p,b})^2 for every m, which are then
+   subtracted; brute.py drops them from the triplet sum directly (k != j);
 6. resum: zeta(b1, b2, phi) = sum_{m=-M}^{M} zeta_m exp(i m phi), zeta_{-m} = conj(zeta_m).
 
 Parity of every function here is pinned by tests that do not re-type its formulas

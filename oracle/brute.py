@@ -7,7 +7,9 @@ in bin a, neighbour k in bin b), without any per-pivot reference direction:
                    sum_{j in a(p)} sum_{k in b(p)} (w_j x_j / W_{p,a}) (w_k x_k / W_{p,b})
                    exp(-i m (phi_j - phi_k))
 
-which is eq. zetamEst with X_m expanded (the j = k terms included).  The opening angle
+which is eq. zetamEst with X_m expanded (the j = k terms included; with
+self_pairs=False the triangles with k = j are left out of the sum, the correction of
+the diagonal overcount noted in the kappa^3 multipole-signal subsection).  The opening angle
 phi_j - phi_k is taken from the tangent vectors t = delta - (delta . r_p) r_p:
 cos = t_j . t_k / |t_j||t_k|, sin = r_p . (t_j x t_k) / |t_j||t_k| (angles growing from
 north through east).  Because the angle between two neighbours does not depend on n_hat,
@@ -27,7 +29,7 @@ def _bins_by_loop(d2: np.ndarray, edges: np.ndarray) -> np.ndarray:
     return b
 
 
-def zeta_brute(piv, nbr, w, x, edges, m_max, wp, xp):
+def zeta_brute(piv, nbr, w, x, edges, m_max, wp, xp, self_pairs=True):
     piv = np.asarray(piv, dtype=np.float64)
     nbr = np.asarray(nbr, dtype=np.float64)
     nb = len(edges) - 1
@@ -52,6 +54,8 @@ def zeta_brute(piv, nbr, w, x, edges, m_max, wp, xp):
         sind = np.cross(t.T[:, None, :], t.T[None, :, :], axis=2) @ r
         dphi = np.arctan2(sind, cosd)
         gg = np.outer(g, g) * (wp[p] * xp[p])
+        if not self_pairs:
+            np.fill_diagonal(gg, 0.0)  # no triangle with k = j
         key = (bj[:, None] * nb + bj[None, :]).ravel()
         for m in range(m_max + 1):
             ph = np.exp(-1j * m * dphi) * gg

@@ -8,6 +8,7 @@ import os
 import numpy as np
 
 from . import build as _build
+from . import ref
 
 _lib = None
 
@@ -67,8 +68,12 @@ def multipoles(piv, nbr, w, x, edges, m_max, ids=False, nthreads=0):
     return a, W, N
 
 
-def estimate(piv, nbr, w, x, edges, m_max, wp, xp, nthreads=0):
-    """zeta [m_max+1, nb, nb] complex (normalised by sum w_p) and the pair total."""
+def estimate(piv, nbr, w, x, edges, m_max, wp, xp, nthreads=0, self_pairs=True):
+    """zeta [m_max+1, nb, nb] complex (normalised by sum w_p) and the pair total.
+
+    self_pairs=False removes the k = j terms of the diagonal (ref.self_pair_term), with
+    Q_{p,b} taken as the m = 0 multipole of the field w x^2.
+    """
     lib = _load()
     nbr = _c(nbr)
     piv = _c(piv)
@@ -86,7 +91,14 @@ def estimate(piv, nbr, w, x, edges, m_max, wp, xp, nthreads=0):
                      _ptr(wp), _ptr(pv), nb, _ptr(edges), m_max, _ptr(zeta), _ptr(pairs), nthreads)
     if rc:
         raise RuntimeError("zo_zeta failed")
-    return zeta[..., 0] + 1j * zeta[..., 1], int(pairs[0])
+    z = zeta[..., 0] + 1j * zeta[..., 1]
+    if not self_pairs:
+        wn = np.asarray(w, np.float64)
+        xn = np.asarray(x, np.float64)
+        q, W, _ = multipoles(piv, nbr, wn, wn * xn * xn, edges, 0, nthreads=nthreads)
+        d = ref.self_pair_term(W, q[:, 0, :].real, np.asarray(pv, np.float64))
+        z[:, np.arange(nb), np.arange(nb)] -= d[None, :] / np.sum(wp)
+    return z, int(pairs[0])
 
 
 def mix64(j):

@@ -117,12 +117,36 @@ def contract(X, vp):
     return re + 1j * im
 
 
-def estimate(piv, nbr, w, x, edges, m_max, wp, xp):
-    """zeta_m(b1, b2) for the given pivot set, normalised by sum_p w_p; plus the pair total."""
+def self_pair_term(W, Q, vp):
+    """The k = j terms of sum_p v_p X_m(b; p) conj(X_m(b; p)), per bin b ([nb], real).
+
+    With X_m(b; p) = sum_{j in b} g_j exp(-i m phi_j), g_j = w_j x_j / W_{p,b}, the product
+    X conj X holds sum_j g_j^2 (the same for every m): summed over pivots with the weight
+    v_p this is sum_p v_p Q_{p,b} / W_{p,b}^2, Q_{p,b} = sum_{j in b} (w_j x_j)^2 (0 where
+    W_{p,b} = 0).  This is the overcount on the diagonal that the paper notes in the kappa^3
+    multipole-signal subsection.
+    """
+    safe = np.where(W > 0, W, 1.0)
+    return np.where(W > 0, Q / (safe * safe), 0.0).T @ vp
+
+
+def estimate(piv, nbr, w, x, edges, m_max, wp, xp, self_pairs=True):
+    """zeta_m(b1, b2) for the given pivot set, normalised by sum_p w_p; plus the pair total.
+
+    self_pairs=False removes the k = j terms from the diagonal b1 = b2 (self_pair_term).
+    """
     a, W, N = multipoles(piv, nbr, w, x, edges, m_max)
     X = normalise(a, W)
-    z = contract(X, wp * xp) / np.sum(wp)
-    return z, int(N.sum())
+    z = contract(X, wp * xp)
+    if not self_pairs:
+        w = np.asarray(w, dtype=np.float64)
+        x = np.asarray(x, dtype=np.float64)
+        # Q_{p,b} = sum_{j in b} w_j (w_j x_j^2): the m = 0 sum of the field w x^2
+        q, _, _ = multipoles(piv, nbr, w, w * x * x, edges, 0)
+        d = self_pair_term(W, q[:, 0, :].real, wp * xp)
+        nb = W.shape[1]
+        z[:, np.arange(nb), np.arange(nb)] -= d[None, :]
+    return z / np.sum(wp), int(N.sum())
 
 
 def resum(zeta, phi):

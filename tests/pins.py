@@ -110,6 +110,32 @@ def check_brute(n=250, seed=1, m_max=5, tol=1e-12, log=False):
     assert err <= tol, err
 
 
+def check_brute_no_self(n=250, seed=5, m_max=5, tol=1e-12, log=False):
+    """Removal of the k = j terms: ref's subtraction against the triplet sum over k != j."""
+    xyz, w, x = random_cap(n, 3.0, seed)
+    E = small_edges(6, log=log)
+    z, pairs = ref.estimate(xyz, xyz, w, x, E, m_max, w, x, self_pairs=False)
+    zb, pb = brute.zeta_brute(xyz, xyz, w, x, E, m_max, w, x, self_pairs=False)
+    zs, _ = ref.estimate(xyz, xyz, w, x, E, m_max, w, x)
+    assert pairs == pb, (pairs, pb)
+    err = rel_err(z, zb)
+    assert err <= tol, err
+    # the option changes the diagonal only
+    nb = len(E) - 1
+    off = ~np.eye(nb, dtype=bool)
+    assert np.array_equal(z[:, off], zs[:, off])
+    assert rel_err(z, zs) > 1e-6
+
+
+def golden_three_point_no_self():
+    """The hand-derived three-point values without the k = j terms: every non-empty bin
+    of every pivot holds one point, so the diagonal entries vanish and the rest stays."""
+    pairs, z = golden_three_point()
+    for b in range(z.shape[1]):
+        z[:, b, b] = 0.0
+    return pairs, z
+
+
 def check_weight_invariance(seed=2, m_max=4):
     """w -> 2w leaves zeta unchanged exactly (per-bin average and 1/sum w_p)."""
     xyz, w, x = random_cap(200, 3.0, seed)

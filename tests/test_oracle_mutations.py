@@ -3,7 +3,7 @@
 Each test swaps one oracle function for a plausibly wrong version and checks that a
 pin from tests/pins.py raises.  This shows the pins constrain every step: the bearing
 (sign and handedness), the exponent sign, the bin rule, the normaliser, the
-contraction's operand order and the pivot weight.
+contraction's operand order, the pivot weight and the removal of the k = j terms.
 """
 
 import numpy as np
@@ -91,3 +91,26 @@ def test_unweighted_pivots_fail_brute(monkeypatch):
     monkeypatch.setattr(ref, "contract", lambda X, vp: orig(X, np.sign(vp)))
     with pytest.raises(AssertionError):
         pins.check_brute(n=120, seed=4, m_max=3)
+
+
+def test_self_term_with_one_normaliser_fails_brute(monkeypatch):
+    # k = j terms divided by W instead of W^2
+    def wrong(W, Q, vp):
+        safe = np.where(W > 0, W, 1.0)
+        return np.where(W > 0, Q / safe, 0.0).T @ vp
+    monkeypatch.setattr(ref, "self_pair_term", wrong)
+    with pytest.raises(AssertionError):
+        pins.check_brute_no_self()
+
+
+def test_self_term_of_the_plain_field_fails_brute(monkeypatch):
+    # Q taken as sum w |x| instead of sum (w x)^2 (the square dropped from the field)
+    orig = ref.multipoles
+
+    def wrong(piv, nbr, w, x, edges, m_max, block=128):
+        if m_max == 0:
+            x = np.sqrt(np.abs(x / w)) * np.sign(x)
+        return orig(piv, nbr, w, x, edges, m_max, block)
+    monkeypatch.setattr(ref, "multipoles", wrong)
+    with pytest.raises(AssertionError):
+        pins.check_brute_no_self()

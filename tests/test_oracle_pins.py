@@ -70,6 +70,29 @@ def test_p1_brute_random_catalogues(seed, log):
     pins.check_brute(seed=seed, log=log)
 
 
+@pytest.mark.parametrize("seed,log", [(5, False), (13, True)])
+def test_no_self_pairs_brute(seed, log):
+    pins.check_brute_no_self(seed=seed, log=log)
+
+
+def test_no_self_pairs_three_point_and_c_oracle():
+    pairs, gold = pins.golden_three_point_no_self()
+    xyz, E, x = pins.three_point_case()
+    w = np.ones(3)
+    for z, p in (ref.estimate(xyz, xyz, w, x, E, 4, w, x, self_pairs=False),
+                 cpu.estimate(xyz, xyz, w, x, E, 4, w, x, self_pairs=False),
+                 brute.zeta_brute(xyz, xyz, w, x, E, 4, w, x, self_pairs=False)):
+        assert p == pairs
+        assert np.abs(z - gold).max() < 1e-14
+    # weighted random catalogue: the C oracle's removal equals the NumPy one
+    xyz, w, x = pins.random_cap(400, 3.0, 17)
+    E = pins.small_edges(5)
+    zc, pc = cpu.estimate(xyz, xyz, w, x, E, 4, w, x, self_pairs=False)
+    zr, pr = ref.estimate(xyz, xyz, w, x, E, 4, w, x, self_pairs=False)
+    assert pc == pr
+    assert pins.rel_err(zc, zr) < 1e-12
+
+
 @pytest.mark.parametrize("n", [50, 120, 500])
 def test_p1_brute_sizes(n):
     pins.check_brute(n=n, seed=100 + n, m_max=3)
