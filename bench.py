@@ -122,6 +122,8 @@ def main():
     ap.add_argument("--prec", default="both", choices=["both", "fp64", "mixed"])
     ap.add_argument("--approx", action="store_true",
                     help="approximate search: neighbours from the Nside/2 averaged map, all pivots kept")
+    ap.add_argument("--exclude-self", action="store_true",
+                    help="leave out the k = j terms of the diagonal (one-map exact search only)")
     ap.add_argument("--save-zeta", default="", help="write the zeta_m of each precision to this .npz")
     ap.add_argument("--adjoint", action="store_true",
                     help="each step also back-propagates L = sum |zeta - t|^2 (random targets) to the field")
@@ -165,6 +167,10 @@ def main():
         return
 
     cfg = CONFIGS[args.config]
+    if args.exclude_self and (args.approx or args.adjoint or cfg.nmaps > 1):
+        print("--exclude-self applies to the one-map exact search only", file=sys.stderr)
+        sys.exit(2)
+    self_pairs = not args.exclude_self
     t0 = time.time()
     xyz = make_positions(cfg, device="cuda")
     if cfg.nmaps > 1:
@@ -256,7 +262,7 @@ def main():
         elif nbr is None:
             idx = z3.Index(xyz, E)
             idx.set_values(x)
-            z3.estimate_raw(idx, M, prec=prec, zeta=zeta, pair_total=pairs, sum_w=sw)
+            z3.estimate_raw(idx, M, prec=prec, zeta=zeta, pair_total=pairs, sum_w=sw, self_pairs=self_pairs)
         else:
             idx = z3.Index(nbr[0], E, weights=nbr[2])
             idx.set_values(nbr[1])
@@ -321,13 +327,15 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if main_prec == "fp64" else "f64 geometry + f32 multipoles/MFMA",
         "data": "synthetic",
-        "config": {"workload": cfg.name + ("+approx" if nbr else "") + ("+adjoint" if args.adjoint else ""),
+        "config": {"workload": cfg.name + ("+approx" if nbr else "") + ("+adjoint" if args.adjoint else "")
+                   + ("+noself" if not self_pairs else ""),
                    "npoints": n, "nmaps": cfg.nmaps, "nbins": cfg.nbins, "m_max": M,
                    "theta_arcmin": [cfg.theta_min * 10800 / np.pi, cfg.theta_max * 10800 / np.pi],
                    "log_bins": cfg.log_bins, "precision": main_prec, "pairs": r["pairs"]},
         "roofline": {"bound": rf_bound, "kernel": rf_kernel, "achieved": achieved,
                      "peak": rf_peak, "unit": "TFLOP/s", "frac": achieved / rf_peak if achieved else None,
-                     "traffic": measured_traffic(cfg.name, main_prec) if rf_kernel == "k_multipoles" else None,
+                     "traffic": measured_traffic(cfg.name, main_prec)
+                     if rf_kernel == "k_multipoles" and self_pairs else None,
                      "traffic_unit": "bytes per launch",
                      "avg_launch_ms": r["kernel_ms_total"] / r["kernel_launches"] if r["kernel_launches"] else None,
                      "launches_per_step": launches_per_step, "flops": rf_unit_note,
@@ -353,7 +361,7 @@ def main():
     if args.save_zeta:
         np.savez(args.save_zeta, **{p: res[p]["zeta"] for p in res})
     if args.cpu_sample != 0 and cfg.nmaps == 1:
-        out["cpu_baseline"] = cpu_baseline(cfg, xyz, x, nbr, E, M, args.cpu_sample, z3, torch)
+        out["cpu_baseline"] = cpu_baseline(cfg, xyz, x, nbr, E, M, args.cpu_sample, z3, torch, self_pairs)
     print(json.dumps(out), flush=True)
 
 
@@ -398,7 +406,7 @@ def fd_check(cfg, xyz, E, M, last, k, z3, torch):
                     "quadratic dependence of zeta on one value"}
 
 
-def cpu_baseline(cfg, xyz, x, nbr, E, M, nsample, z3, torch):
+def cpu_baseline(cfg, xyz, x, nbr, E, M, nsample, z3, torch, self_pairs=True):
     """Time the FP64 C oracle on a contiguous range of pivots against the full neighbour
     catalogue, and check the GPU path on the same pivots."""
     from oracle import cpu
@@ -420,7 +428,8 @@ def cpu_baseline(cfg, xyz, x, nbr, E, M, nsample, z3, torch):
     p0 = n // 3
 
     def oracle(sel):
-        return cpu.estimate(xyz_h[:, sel], nbr_h[0], nbr_h[2], nbr_h[1], E, M, w_h[sel], x_h[sel], nthreads=threads)
+        return cpu.estimate(xyz_h[:, sel], nbr_h[0], nbr_h[2], nbr_h[1], E, M, w_h[sel], x_h[sel], nthreads=threads,
+                            self_pairs=self_pairs)
 
     # sample size: the oracle's time per pivot falls as the sample grows (its O(N) grid
     # build, thread start-up and load balance amortise), so the pivot count is grown
@@ -448,7 +457,8 @@ def cpu_baseline(cfg, xyz, x, nbr, E, M, nsample, z3, torch):
         pairs = torch.zeros(1, dtype=torch.int64, device="cuda")
         sw = torch.zeros(1, dtype=torch.float64, device="cuda")
         if nbr is None:
-            z3.estimate_raw(idx, M, prec=gp, p0=p0, p1=p0 + nsample, zeta=zeta, pair_total=pairs, sum_w=sw)
+            z3.estimate_raw(idx, M, prec=gp, p0=p0, p1=p0 + nsample, zeta=zeta, pair_total=pairs, sum_w=sw,
+                            self_pairs=self_pairs)
         else:
             z3.estimate_pivots_raw(idx, xyz, x, None, M, prec=gp, p0=p0, p1=p0 + nsample, zeta=zeta,
                                    pair_total=pairs, sum_w=sw)

@@ -66,6 +66,13 @@ enum {
     Z3_NORM_NONE = 1  /* raw sums a_{m,b}; callers can apply any other normaliser       */
 };
 
+enum {
+    /* z3_estimate_ex: leave out the triangles whose two neighbours are the same point
+       (k = j), which the product X_m(b) conj X_m(b) of eq. zetamEst otherwise holds on the
+       diagonal b1 = b2 (the overcount noted in the kappa^3 multipole-signal subsection) */
+    Z3_EST_EXCLUDE_SELF = 1u << 0
+};
+
 /* Largest supported multipole and bin count. */
 #define Z3_MAX_MMAX 16
 #define Z3_MAX_NBINS 64
@@ -179,6 +186,18 @@ z3_status z3_contract(int64_t npiv, int m_max, int nbins, int prec, const void *
  */
 z3_status z3_estimate(z3_index idx, int map, int m_max, int prec, int64_t p0, int64_t p1,
                       double *zeta, uint64_t *pair_total, void *stream);
+
+/*
+ * z3_estimate with options.  flags: 0 or Z3_EST_EXCLUDE_SELF (other bits:
+ * Z3_ERR_INVALID_ARG).  With Z3_EST_EXCLUDE_SELF the k = j terms are removed:
+ *   zeta_m[b][b] re -= sum_p w_p x_p Q_{p,b} / W_{p,b}^2,  Q_{p,b} = sum_{j in b} (w_j x_j)^2
+ * for every m (0 where W_{p,b} = 0), accumulated in FP64 on either precision path, so that
+ * zeta holds the triplet sum over k != j; the other entries are those of z3_estimate.
+ * Same arguments, chunking and accumulation (zeta +=, unnormalised) as z3_estimate;
+ * the removal adds a workspace of 8 x nbins bytes per 64 pivots of a chunk.
+ */
+z3_status z3_estimate_ex(z3_index idx, int map, int m_max, int prec, unsigned flags, int64_t p0,
+                         int64_t p1, double *zeta, uint64_t *pair_total, void *stream);
 
 /*
  * Fused estimator for ALL attached maps at once (many mock maps over one set of

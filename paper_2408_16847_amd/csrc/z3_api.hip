@@ -425,10 +425,18 @@ Z3_API z3_status z3_index_batch_shape(z3_index idx, int m_max, int prec, int *wa
 Z3_API z3_status z3_estimate(z3_index idx, int map, int m_max, int prec, int64_t p0, int64_t p1,
                              double *zeta, uint64_t *pair_total, void *stream)
 {
+    return z3_estimate_ex(idx, map, m_max, prec, 0u, p0, p1, zeta, pair_total, stream);
+}
+
+Z3_API z3_status z3_estimate_ex(z3_index idx, int map, int m_max, int prec, unsigned flags, int64_t p0,
+                                int64_t p1, double *zeta, uint64_t *pair_total, void *stream)
+{
     CallScope scope(idx, as_stream(stream));
     z3_status st = check_common("z3_estimate", idx, map, m_max, prec, p0, p1);
     if (st != Z3_OK) return st;
     if (!zeta) return fail(Z3_ERR_INVALID_ARG, "z3_estimate: zeta is NULL");
+    if (flags & ~(unsigned)Z3_EST_EXCLUDE_SELF) return fail(Z3_ERR_INVALID_ARG, "z3_estimate_ex: unknown flags 0x%x", flags);
+    const bool no_self = (flags & Z3_EST_EXCLUDE_SELF) != 0;
     if (p1 == p0) return Z3_OK;
     hipStream_t s = as_stream(stream);
     int64_t chunk = chunk_pivots(idx, m_max, prec);
@@ -436,20 +444,25 @@ Z3_API z3_status z3_estimate(z3_index idx, int map, int m_max, int prec, int64_t
     size_t elem = prec == Z3_PREC_FP64 ? 8 : 4;
     size_t abytes = (size_t)chunk * (size_t)(m_max + 1) * 2 * idx->nbins * elem;
     size_t pbytes = contract_partial_bytes(chunk, m_max, idx->nbins);
-    void *wa = nullptr, *wp = nullptr;
+    // with the self-pair removal: one FP64 sum per (wave, bin) of the chunk
+    const int64_t nw_max = (chunk + kWave - 1) / kWave;
+    void *wa = nullptr, *wp = nullptr, *wsf = nullptr;
     if ((st = scratch_alloc(&wa, abytes, s)) != Z3_OK) return st;
-    if ((st = scratch_alloc(&wp, pbytes, s)) != Z3_OK) {
-        scratch_free(wa, s);
-        return st;
-    }
+    st = scratch_alloc(&wp, pbytes, s);
+    if (st == Z3_OK && no_self) st = scratch_alloc(&wsf, (size_t)nw_max * idx->nbins * sizeof(double), s);
     const double *v = idx->d_v + (size_t)map * idx->n;
+    double *self_part = static_cast<double *>(wsf);
     for (int64_t c0 = p0; c0 < p1 && st == Z3_OK; c0 += chunk) {
         int64_t c1 = c0 + chunk < p1 ? c0 + chunk : p1;
         st = launch_multipoles(idx, Pivots{idx->d_x, idx->d_y, idx->d_z}, map, m_max, prec, Z3_NORM_BIN, c0, c1,
-                               wa, c1 - c0, nullptr, nullptr, nullptr, pair_total, s);
+                               wa, c1 - c0, nullptr, nullptr, nullptr, pair_total, s, no_self ? v : nullptr,
+                               self_part);
         if (st == Z3_OK)
             st = launch_contract(c1 - c0, m_max, idx->nbins, prec, wa, c1 - c0, v + c0, zeta, wp, pbytes, s);
+        if (st == Z3_OK && no_self)
+            st = launch_self_subtract(self_part, (c1 - c0 + kWave - 1) / kWave, m_max, idx->nbins, zeta, s);
     }
+    scratch_free(wsf, s);
     scratch_free(wp, s);
     scratch_free(wa, s);
     return st;

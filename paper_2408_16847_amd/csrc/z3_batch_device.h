@@ -15,13 +15,6 @@ __device__ __forceinline__ int wave_incl_scan(int v, int lane)
     return v;
 }
 
-__device__ __forceinline__ double wave_sum_f64(double v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-    return v;
-}
-
 __device__ __forceinline__ int wave_sum_i32(int v)
 {
 #pragma unroll

@@ -535,6 +535,31 @@ z3_status launch_finalize(int nmaps, int m_max, int nbins, double *zeta, const d
     return check_launch("k_finalize");
 }
 
+// Removal of the k = j terms: one block per bin adds the bin's column of the per-wave
+// sums v_p Q / W^2 in a fixed order and subtracts the total from Re zeta_m(b, b) for every
+// m (those terms are real and the same for every m).
+__global__ void k_self_subtract(const double *part, int64_t nw, int nb, int M, double *zeta)
+{
+    __shared__ double sh[256];
+    const int b = blockIdx.x;
+    double acc = 0.0;
+    for (int64_t w = threadIdx.x; w < nw; w += 256) acc += part[w * nb + b];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if ((int)threadIdx.x <= M) zeta[(((size_t)threadIdx.x * nb + b) * nb + b) * 2] -= sh[0];
+}
+
+z3_status launch_self_subtract(const double *part, int64_t nw, int m_max, int nbins, double *zeta, hipStream_t s)
+{
+    if (nw <= 0) return Z3_OK;
+    hipLaunchKernelGGL(k_self_subtract, dim3(nbins), dim3(256), 0, s, part, nw, nbins, m_max, zeta);
+    return check_launch("k_self_subtract");
+}
+
 // zeta(b1, b2, phi) = Re zeta_0 + 2 sum_{m>=1} (Re zeta_m cos(m phi) - Im zeta_m sin(m phi))
 __global__ void k_resum(int M, int nb, const double *zeta, int nphi, const double *phi, double *out)
 {

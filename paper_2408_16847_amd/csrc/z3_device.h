@@ -33,6 +33,15 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v)
     return (uint64_t)hi << 32 | lo;
 }
 
+// Butterfly sum over the wave; the order of the additions is fixed, so the result is
+// reproducible from run to run.
+__device__ __forceinline__ double wave_sum_f64(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
 // Buffer view of one band's doubled records: a gfx9 buffer resource on a wave-uniform
 // base, addressed by 32-bit per-lane byte offsets (one add and one compare per loop step
 // instead of 64-bit address arithmetic).  Loads past `bytes` return zeros.

@@ -128,7 +128,8 @@ struct Pivots {
 z3_status launch_multipoles(const z3_index_s *idx, Pivots piv, int map, int m_max, int prec,
                             int norm, int64_t p0, int64_t p1, void *A, int64_t ldA, double *W,
                             int64_t *counts, uint64_t *idhash, uint64_t *pair_total,
-                            hipStream_t s);
+                            hipStream_t s, const double *self_pv = nullptr,
+                            double *self_part = nullptr);
 
 int batch_ldv(int nmaps);
 int batch_num_shapes();
@@ -163,6 +164,9 @@ z3_status launch_weight_sum(const double *w, int64_t n, double *out, hipStream_t
 z3_status launch_pivot_values(const double *w, const double *x, int64_t n, double *v, hipStream_t s);
 z3_status launch_add_scalar(double *out, double value, hipStream_t s);
 z3_status launch_fill(double *p, int64_t n, double value, hipStream_t s);
+// zeta[m][b][b] re -= sum over the nw rows of part [nw][nbins] (column b), for m <= m_max
+z3_status launch_self_subtract(const double *part, int64_t nw, int m_max, int nbins, double *zeta,
+                               hipStream_t s);
 
 // adjoint (z3_adjoint.hip)
 z3_status adjoint_impl(z3_index idx, int map, int m_max, int64_t p0, int64_t p1, const double *G,

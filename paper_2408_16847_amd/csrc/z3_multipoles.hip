@@ -23,6 +23,11 @@
 // polynomial families so that no trigonometric function is evaluated per pair.  Scaling
 // both recurrences by w_j x_j folds the field value in: two FMAs and two adds per m.
 //
+// Optionally (SELF) the kernel also removes the k = j terms of the contraction's diagonal
+// (the overcount the paper points out in the kappa^3 multipole-signal subsection): per
+// (pivot, bin) it sums Q = sum_j (w_j x_j)^2 in FP64, forms v_p Q / W^2 (v_p Q for raw
+// sums), adds that over the wave in a fixed order and writes one value per (wave, bin).
+//
 // Precision: the FP64 path normalises the bearing with an FP32-seeded reciprocal square
 // root refined by one FP64 Newton step and runs everything in FP64.  The mixed path keeps
 // the separations and bin decisions in FP64, forms the bearing in FP32 (the separation
@@ -52,6 +57,8 @@ struct MultArgs {
     int64_t *counts;
     uint64_t *idhash;
     uint64_t *pair_total;
+    const double *pv;             // SELF: index-order pivot products w_p x_p
+    double *self_part;            // SELF: [waves of the launch][nb] sums of v_p Q / W^2
     int nblocks;
 };
 
@@ -67,7 +74,7 @@ constexpr int mult_waves_per_eu()
     return M <= 10 ? Z3_MULT_WAVES_PER_EU : (M <= 13 ? 3 : 2);
 }
 
-template <int M, bool MIXED, bool IDS>
+template <int M, bool MIXED, bool IDS, bool SELF>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(mult_waves_per_eu<M>())))
 void k_multipoles(MultArgs a)
 {
@@ -125,7 +132,7 @@ void k_multipoles(MultArgs a)
         double Y[M + 1], Z[M + 1];
 #pragma unroll
         for (int m = 0; m <= M; ++m) { Y[m] = 0.0; Z[m] = 0.0; }
-        double Wb = 0.0;
+        double Wb = 0.0, Qb = 0.0;
         int cnt = 0;
         uint64_t hsum = 0;
 
@@ -183,6 +190,7 @@ void k_multipoles(MultArgs a)
                             unit_bearing(u10, u20, c0, sn0);
                             unit_bearing(u11, u21, c1, sn1);
                             const double v0 = in0 ? r0.w : 0.0, v1 = in1 ? r1.w : 0.0;
+                            if constexpr (SELF) Qb = fma(v1, v1, fma(v0, v0, Qb));
                             Y[0] += v0 + v1;
                             if constexpr (M >= 1) {
                                 const double tc0 = c0 + c0, tc1 = c1 + c1;
@@ -224,6 +232,7 @@ void k_multipoles(MultArgs a)
                                 if (!unit_w) Wb += a.wdbl[j];
                                 if constexpr (IDS) hsum += mix64((uint64_t)a.permdbl[j]);
                             }
+                            if constexpr (SELF) Qb = fma(r.w, r.w, Qb);
                             // the bearing in FP32: the separation rounded once, the tangent
                             // components against the FP32 frame, then the hardware reciprocal
                             // square root (the FP32 harmonics that follow carry errors of the
@@ -265,11 +274,13 @@ void k_multipoles(MultArgs a)
             }
         }
 
+        double self_t = 0.0;
         if (valid) {
             my_pairs += (uint64_t)cnt;
             if (unit_w) Wb = (double)cnt;
             double inv = 1.0;
             if (a.norm == Z3_NORM_BIN) inv = Wb > 0.0 ? 1.0 / Wb : 0.0;
+            if constexpr (SELF) self_t = a.pv[p] * Qb * inv * inv;
             if (a.A) {
 #pragma unroll
                 for (int m = 0; m <= M; ++m) {
@@ -290,6 +301,11 @@ void k_multipoles(MultArgs a)
             if (a.W) a.W[ob] = Wb;
             if (a.counts) a.counts[ob] = cnt;
             if constexpr (IDS) a.idhash[ob] = hsum;
+        }
+        if constexpr (SELF) {
+            const double t = wave_sum_f64(self_t);
+            if ((threadIdx.x & (kWave - 1)) == 0)
+                a.self_part[(size_t)((wave0 - a.p0) / kWave) * nb + bin] = t;
         }
     }
 
@@ -519,24 +535,29 @@ z3_status launch_multipoles_maps(const z3_index_s *idx, int group, int m_max, in
 }
 
 template <int M>
-static void launch_m(bool mixed, bool ids, const MultArgs &a, hipStream_t s)
+static void launch_m(bool mixed, bool ids, bool self, const MultArgs &a, hipStream_t s)
 {
     dim3 grid(a.nblocks), block(kBlock);
     if (mixed) {
-        if (ids) hipLaunchKernelGGL((k_multipoles<M, true, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_multipoles<M, true, false>), grid, block, 0, s, a);
+        if (ids) hipLaunchKernelGGL((k_multipoles<M, true, true, false>), grid, block, 0, s, a);
+        else if (self) hipLaunchKernelGGL((k_multipoles<M, true, false, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_multipoles<M, true, false, false>), grid, block, 0, s, a);
     } else {
-        if (ids) hipLaunchKernelGGL((k_multipoles<M, false, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_multipoles<M, false, false>), grid, block, 0, s, a);
+        if (ids) hipLaunchKernelGGL((k_multipoles<M, false, true, false>), grid, block, 0, s, a);
+        else if (self) hipLaunchKernelGGL((k_multipoles<M, false, false, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_multipoles<M, false, false, false>), grid, block, 0, s, a);
     }
 }
 
 z3_status launch_multipoles(const z3_index_s *idx, Pivots piv, int map, int m_max, int prec, int norm,
                             int64_t p0, int64_t p1, void *A, int64_t ldA, double *W,
-                            int64_t *counts, uint64_t *idhash, uint64_t *pair_total, hipStream_t s)
+                            int64_t *counts, uint64_t *idhash, uint64_t *pair_total, hipStream_t s,
+                            const double *self_pv, double *self_part)
 {
     int64_t nblk = (p1 - p0 + kBlock - 1) / kBlock;
     if (nblk > 0x7fffffff) return fail(Z3_ERR_OVERFLOW, "too many pivot blocks");
+    if ((self_part != nullptr) != (self_pv != nullptr) || (self_part && idhash))
+        return fail(Z3_ERR_INVALID_ARG, "k_multipoles: the self-pair sums need pivot values and no fingerprints");
     MultArgs a;
     a.px = piv.x; a.py = piv.y; a.pz = piv.z;
     a.rec = idx->d_rec + (size_t)map * 2 * idx->n;
@@ -552,12 +573,13 @@ z3_status launch_multipoles(const z3_index_s *idx, Pivots piv, int map, int m_ma
     a.norm = norm;
     a.A = A; a.ldA = ldA;
     a.W = W; a.counts = counts; a.idhash = idhash; a.pair_total = pair_total;
+    a.pv = self_pv; a.self_part = self_part;
     a.nblocks = (int)nblk;
-    const bool mixed = prec == Z3_PREC_MIXED, ids = idhash != nullptr;
+    const bool mixed = prec == Z3_PREC_MIXED, ids = idhash != nullptr, self = self_part != nullptr;
     hipEvent_t ev0;
     profile_begin(s, &ev0);
     switch (m_max) {
-#define Z3_CASE(MM) case MM: launch_m<MM>(mixed, ids, a, s); break;
+#define Z3_CASE(MM) case MM: launch_m<MM>(mixed, ids, self, a, s); break;
         Z3_CASE(0) Z3_CASE(1) Z3_CASE(2) Z3_CASE(3) Z3_CASE(4) Z3_CASE(5) Z3_CASE(6) Z3_CASE(7)
         Z3_CASE(8) Z3_CASE(9) Z3_CASE(10) Z3_CASE(11) Z3_CASE(12) Z3_CASE(13) Z3_CASE(14)
         Z3_CASE(15) Z3_CASE(16)

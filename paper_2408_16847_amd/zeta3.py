@@ -18,6 +18,7 @@ from . import _lib
 
 PREC = {"fp64": 0, "mixed": 1}
 NORM = {"bin": 0, "none": 1}
+EST_EXCLUDE_SELF = 1  # Z3_EST_EXCLUDE_SELF
 
 
 def _ptr(t):
@@ -147,26 +148,29 @@ def contract(A, piv_v, m_max: int, nbins: int, prec="fp64", zeta=None):
 
 
 def estimate_raw(idx: Index, m_max: int, prec="fp64", p0: int = 0, p1: int | None = None, map_index: int = 0,
-                 zeta=None, pair_total=None, sum_w=None):
+                 zeta=None, pair_total=None, sum_w=None, self_pairs: bool = True):
     """Enqueue the fused estimator for pivots [p0, p1): zeta += (unnormalised),
-    pair_total += pairs, sum_w += sum of pivot weights. All CUDA tensors; no sync."""
+    pair_total += pairs, sum_w += sum of pivot weights. All CUDA tensors; no sync.
+    self_pairs=False leaves out the k = j terms of the diagonal (Z3_EST_EXCLUDE_SELF)."""
     p1 = idx.n if p1 is None else p1
     if zeta is None:
         zeta = torch.zeros((m_max + 1, idx.nbins, idx.nbins, 2), dtype=torch.float64, device="cuda")
-    _lib.call("z3_estimate", idx.handle, map_index, m_max, PREC[prec], p0, p1, _ptr(zeta), _ptr(pair_total),
-              _stream())
+    flags = 0 if self_pairs else EST_EXCLUDE_SELF
+    _lib.call("z3_estimate_ex", idx.handle, map_index, m_max, PREC[prec], flags, p0, p1, _ptr(zeta),
+              _ptr(pair_total), _stream())
     if sum_w is not None:
         _lib.call("z3_pivot_weight_sum", idx.handle, p0, p1, _ptr(sum_w), _stream())
     return zeta
 
 
-def estimate(idx: Index, m_max: int, prec="fp64", p0: int = 0, p1: int | None = None, map_index: int = 0):
+def estimate(idx: Index, m_max: int, prec="fp64", p0: int = 0, p1: int | None = None, map_index: int = 0,
+             self_pairs: bool = True):
     """zeta_m(b1, b2) normalised by the pivots' total weight, as complex128 numpy [m+1, nb, nb],
-    and the number of pairs."""
+    and the number of pairs (self_pairs=False: without the k = j terms)."""
     zeta = torch.zeros((m_max + 1, idx.nbins, idx.nbins, 2), dtype=torch.float64, device="cuda")
     pairs = torch.zeros(1, dtype=torch.int64, device="cuda")
     sw = torch.zeros(1, dtype=torch.float64, device="cuda")
-    estimate_raw(idx, m_max, prec, p0, p1, map_index, zeta, pairs, sw)
+    estimate_raw(idx, m_max, prec, p0, p1, map_index, zeta, pairs, sw, self_pairs)
     _lib.call("z3_finalize", 1, m_max, idx.nbins, _ptr(zeta), _ptr(sw), _stream())
     z = zeta.cpu().numpy()
     return z[..., 0] + 1j * z[..., 1], int(pairs.item())
