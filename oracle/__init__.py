@@ -32,6 +32,9 @@ Ym/Zm.binned, zetamEst2), with the readings listed in the design doc:
    kappa^3 multipole-signal subsection): each pivot's product X(b) conj X(b) holds the
    terms k = j, sum_{j in b} (w_j x_j / W_{p,b})^2 for every m, which are then
    subtracted; brute.py drops them from the triplet sum directly (k != j);
+   multi-field form (remark after eq. ubEstimator): the pivot carries field A, X(b1) is
+   taken from field B and X(b2) from field C; optionally summed over the cyclic
+   permutations of (A, B, C);
 6. resum: zeta(b1, b2, phi) = sum_{m=-M}^{M} zeta_m exp(i m phi), zeta_{-m} = conj(zeta_m).
 
 Parity of every function here is pinned by tests that do not re-type its formulas

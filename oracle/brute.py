@@ -65,6 +65,49 @@ def zeta_brute(piv, nbr, w, x, edges, m_max, wp, xp, self_pairs=True):
     return acc / np.sum(wp), pairs
 
 
+def zeta_cross_brute(piv, nbr, w, fields, edges, m_max, wp, pivot_fields, cyclic=False):
+    """Multi-field triplet sum: pivot p carries field A, neighbour j (bin a) field B and
+    neighbour k (bin b) field C,
+
+        zeta_m(a, b) = (1/sum_p w_p) sum_p w_p x^A_p sum_{j in a} sum_{k in b}
+                       (w_j x^B_j / W_{p,a}) (w_k x^C_k / W_{p,b}) exp(-i m (phi_j - phi_k)),
+
+    plus, with cyclic=True, the same with (B, C, A) and (C, A, B).  Angles as in zeta_brute.
+    """
+    piv = np.asarray(piv, dtype=np.float64)
+    nbr = np.asarray(nbr, dtype=np.float64)
+    nb = len(edges) - 1
+    terms = [(0, 1, 2), (1, 2, 0), (2, 0, 1)] if cyclic else [(0, 1, 2)]
+    acc = np.zeros((m_max + 1, nb, nb), dtype=np.complex128)
+    pairs = 0
+    for p in range(piv.shape[1]):
+        r = piv[:, p]
+        d = nbr - r[:, None]
+        d2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]
+        b = _bins_by_loop(d2, edges)
+        sel = b >= 0
+        if not sel.any():
+            continue
+        pairs += int(sel.sum())
+        bj = b[sel]
+        t = d[:, sel] - np.outer(r, r @ d[:, sel])
+        t = t / np.linalg.norm(t, axis=0)
+        Wb = np.zeros(nb)
+        np.add.at(Wb, bj, w[sel])
+        dphi = np.arctan2(np.cross(t.T[:, None, :], t.T[None, :, :], axis=2) @ r, t.T @ t)
+        key = (bj[:, None] * nb + bj[None, :]).ravel()
+        for ia, ib, ic in terms:
+            gj = w[sel] * fields[ib][sel] / Wb[bj]
+            gk = w[sel] * fields[ic][sel] / Wb[bj]
+            gg = np.outer(gj, gk) * (wp[p] * pivot_fields[ia][p])
+            for m in range(m_max + 1):
+                ph = np.exp(-1j * m * dphi) * gg
+                re = np.bincount(key, weights=ph.real.ravel(), minlength=nb * nb)
+                im = np.bincount(key, weights=ph.imag.ravel(), minlength=nb * nb)
+                acc[m] += (re + 1j * im).reshape(nb, nb)
+    return acc / np.sum(wp), pairs
+
+
 def dirichlet_resum_brute(piv, nbr, w, x, edges, M, wp, xp, phi):
     """Triplet density smoothed by the Dirichlet kernel D_M(phi - (phi_j - phi_k)).
 

@@ -101,6 +101,20 @@ def estimate(piv, nbr, w, x, edges, m_max, wp, xp, nthreads=0, self_pairs=True):
     return z, int(pairs[0])
 
 
+def estimate_cross(piv, nbr, w, fields, edges, m_max, wp, pivot_fields, cyclic=False, nthreads=0):
+    """Multi-field estimator (ref.estimate_cross) with the C oracle's multipoles per field."""
+    X = []
+    for xf in fields:
+        a, W, N = multipoles(piv, nbr, w, xf, edges, m_max, nthreads=nthreads)
+        X.append(ref.normalise(a, W))
+    terms = [(0, 1, 2), (1, 2, 0), (2, 0, 1)] if cyclic else [(0, 1, 2)]
+    wp = np.asarray(wp, np.float64)
+    z = 0
+    for ia, ib, ic in terms:
+        z = z + ref.contract_cross(X[ib], X[ic], wp * np.asarray(pivot_fields[ia], np.float64))
+    return z / np.sum(wp), int(N.sum())
+
+
 def mix64(j):
     """SplitMix64 finaliser of uint64 array j (matches oracle_cpu.c)."""
     v = np.asarray(j, dtype=np.uint64) + np.uint64(0x9E3779B97F4A7C15)

@@ -149,6 +149,37 @@ def estimate(piv, nbr, w, x, edges, m_max, wp, xp, self_pairs=True):
     return z / np.sum(wp), int(N.sum())
 
 
+def contract_cross(Xa, Xb, vp):
+    """Unnormalised sum_p v_p Xa_m(b1; p) conj(Xb_m(b2; p)) -> [m_max+1, nb, nb]: the
+    contraction of eq. zetamEst with the two neighbour fields of a cross-correlation."""
+    M1, nb = Xa.shape[1], Xa.shape[2]
+    out = np.zeros((M1, nb, nb), dtype=np.complex128)
+    for p in range(Xa.shape[0]):
+        out += vp[p] * (Xa[p][:, :, None] * np.conj(Xb[p][:, None, :]))
+    return out
+
+
+def estimate_cross(piv, nbr, w, fields, edges, m_max, wp, pivot_fields, cyclic=False):
+    """Multi-field estimator (remark after eq. ubEstimator): the pivot carries field A, the
+    bin b1 field B and the bin b2 field C,
+
+        zeta^{A;BC}_m(b1, b2) = (1/sum_p w_p) sum_p w_p x^A_p X^B_m(b1; p) conj(X^C_m(b2; p));
+
+    with cyclic=True the sum over the cyclic permutations (A;BC) + (B;CA) + (C;AB).
+    fields = (xA, xB, xC) on the neighbour catalogue, pivot_fields the same on the pivots.
+    Returns (zeta [m_max+1, nb, nb], pair total).
+    """
+    X = []
+    for xf in fields:
+        a, W, N = multipoles(piv, nbr, w, xf, edges, m_max)
+        X.append(normalise(a, W))
+    terms = [(0, 1, 2), (1, 2, 0), (2, 0, 1)] if cyclic else [(0, 1, 2)]
+    z = 0
+    for ia, ib, ic in terms:
+        z = z + contract_cross(X[ib], X[ic], wp * pivot_fields[ia])
+    return z / np.sum(wp), int(N.sum())
+
+
 def resum(zeta, phi):
     """zeta(b1, b2, phi) = sum_{m=-M}^{M} zeta_m exp(i m phi), zeta_{-m} = conj(zeta_m).
 

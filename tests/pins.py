@@ -127,6 +127,20 @@ def check_brute_no_self(n=250, seed=5, m_max=5, tol=1e-12, log=False):
     assert rel_err(z, zs) > 1e-6
 
 
+def check_cross_brute(n=220, seed=21, m_max=4, tol=1e-12, cyclic=False):
+    """Multi-field estimator: ref's per-field multipoles and cross contraction against the
+    triplet sum with the pivot, first and second neighbour carrying fields A, B, C."""
+    xyz, w, xa = random_cap(n, 3.0, seed)
+    rng = np.random.default_rng(seed + 1)
+    fields = (xa, rng.normal(size=n), rng.lognormal(size=n) - 1.0)
+    E = small_edges(5)
+    z, pairs = ref.estimate_cross(xyz, xyz, w, fields, E, m_max, w, fields, cyclic=cyclic)
+    zb, pb = brute.zeta_cross_brute(xyz, xyz, w, fields, E, m_max, w, fields, cyclic=cyclic)
+    assert pairs == pb, (pairs, pb)
+    err = rel_err(z, zb)
+    assert err <= tol, err
+
+
 def golden_three_point_no_self():
     """The hand-derived three-point values without the k = j terms: every non-empty bin
     of every pivot holds one point, so the diagonal entries vanish and the rest stays."""

@@ -3,7 +3,7 @@
 Each test swaps one oracle function for a plausibly wrong version and checks that a
 pin from tests/pins.py raises.  This shows the pins constrain every step: the bearing
 (sign and handedness), the exponent sign, the bin rule, the normaliser, the
-contraction's operand order, the pivot weight and the removal of the k = j terms.
+contraction's operand order, the pivot weight and the removal of the k = j terms and the operand order of the multi-field contraction.
 """
 
 import numpy as np
@@ -114,3 +114,27 @@ def test_self_term_of_the_plain_field_fails_brute(monkeypatch):
     monkeypatch.setattr(ref, "multipoles", wrong)
     with pytest.raises(AssertionError):
         pins.check_brute_no_self()
+
+
+def test_cross_conjugate_on_the_wrong_field_fails_brute(monkeypatch):
+    def wrong(Xa, Xb, vp):
+        M1, nb = Xa.shape[1], Xa.shape[2]
+        out = np.zeros((M1, nb, nb), dtype=np.complex128)
+        for p in range(Xa.shape[0]):
+            out += vp[p] * (np.conj(Xa[p][:, :, None]) * Xb[p][:, None, :])
+        return out
+    monkeypatch.setattr(ref, "contract_cross", wrong)
+    with pytest.raises(AssertionError):
+        pins.check_cross_brute()
+
+
+def test_cross_pivot_field_swapped_fails_brute(monkeypatch):
+    orig = ref.estimate_cross
+
+    def wrong(piv, nbr, w, fields, edges, m_max, wp, pivot_fields, cyclic=False):
+        # the pivot takes field B instead of A
+        pf = (pivot_fields[1], pivot_fields[1], pivot_fields[2])
+        return orig(piv, nbr, w, fields, edges, m_max, wp, pf, cyclic)
+    monkeypatch.setattr(ref, "estimate_cross", wrong)
+    with pytest.raises(AssertionError):
+        pins.check_cross_brute()

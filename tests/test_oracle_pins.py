@@ -75,6 +75,27 @@ def test_no_self_pairs_brute(seed, log):
     pins.check_brute_no_self(seed=seed, log=log)
 
 
+@pytest.mark.parametrize("cyclic", [False, True])
+def test_cross_fields_brute(cyclic):
+    pins.check_cross_brute(cyclic=cyclic)
+
+
+def test_cross_fields_special_cases():
+    # one field in all three roles: the single term is zeta, the cyclic sum 3 zeta; exchanging
+    # the two neighbour fields conjugates and transposes
+    xyz, w, x = pins.random_cap(300, 3.0, 23)
+    y = np.random.default_rng(24).normal(size=300)
+    E = pins.small_edges(5)
+    z, p = ref.estimate(xyz, xyz, w, x, E, 4, w, x)
+    z1, p1 = ref.estimate_cross(xyz, xyz, w, (x, x, x), E, 4, w, (x, x, x))
+    z3_, p3 = ref.estimate_cross(xyz, xyz, w, (x, x, x), E, 4, w, (x, x, x), cyclic=True)
+    assert p == p1 == p3
+    assert pins.rel_err(z1, z) < 1e-13 and pins.rel_err(z3_, 3.0 * z) < 1e-13
+    zbc, _ = ref.estimate_cross(xyz, xyz, w, (x, y, x), E, 4, w, (x, y, x))
+    zcb, _ = ref.estimate_cross(xyz, xyz, w, (x, x, y), E, 4, w, (x, x, y))
+    assert pins.rel_err(zcb, np.conj(np.swapaxes(zbc, 1, 2))) < 1e-13
+
+
 def test_no_self_pairs_three_point_and_c_oracle():
     pairs, gold = pins.golden_three_point_no_self()
     xyz, E, x = pins.three_point_case()
