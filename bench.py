@@ -122,6 +122,9 @@ def main():
     ap.add_argument("--prec", default="both", choices=["both", "fp64", "mixed"])
     ap.add_argument("--approx", action="store_true",
                     help="approximate search: neighbours from the Nside/2 averaged map, all pivots kept")
+    ap.add_argument("--cross", action="store_true",
+                    help="multi-field estimator: three correlated fields on the positions, summed over the "
+                         "cyclic permutations of (pivot; b1, b2) fields (one-map workloads)")
     ap.add_argument("--exclude-self", action="store_true",
                     help="leave out the k = j terms of the diagonal (one-map exact search only)")
     ap.add_argument("--save-zeta", default="", help="write the zeta_m of each precision to this .npz")
@@ -167,8 +170,11 @@ def main():
         return
 
     cfg = CONFIGS[args.config]
-    if args.exclude_self and (args.approx or args.adjoint or cfg.nmaps > 1):
-        print("--exclude-self applies to the one-map exact search only", file=sys.stderr)
+    if (args.exclude_self or args.cross) and (args.approx or args.adjoint or cfg.nmaps > 1):
+        print("--exclude-self and --cross apply to the one-map exact search only", file=sys.stderr)
+        sys.exit(2)
+    if args.exclude_self and args.cross:
+        print("--exclude-self and --cross are separate options", file=sys.stderr)
         sys.exit(2)
     self_pairs = not args.exclude_self
     t0 = time.time()
@@ -177,6 +183,12 @@ def main():
         x = torch.stack([make_values(cfg, xyz, seed=s) for s in range(cfg.nmaps)])
     else:
         x = make_values(cfg, xyz, seed=0)
+    x3 = None
+    if args.cross:
+        # three correlated fields (as for redshift bins of one sky): x0, x0 + x1 / 2, x0 - 0.3 x2
+        x1, x2 = make_values(cfg, xyz, seed=1), make_values(cfg, xyz, seed=2)
+        x3 = torch.stack([x, x + 0.5 * x1, x - 0.3 * x2])
+        del x1, x2
     nbr = None
     if args.approx:
         from synth import degrade_ring
@@ -259,6 +271,10 @@ def main():
             idx = z3.Index(xyz, E)
             idx.set_values(x)
             z3.estimate_maps_raw(idx, M, prec=prec, zeta=zeta, pair_total=pairs, sum_w=sw)
+        elif x3 is not None:
+            idx = z3.Index(xyz, E)
+            idx.set_values(x3)
+            z3.estimate_cross_raw(idx, (0, 1, 2), M, prec, True, zeta=zeta, pair_total=pairs, sum_w=sw)
         elif nbr is None:
             idx = z3.Index(xyz, E)
             idx.set_values(x)
@@ -298,7 +314,7 @@ def main():
 
     main_prec = "mixed" if "mixed" in res else "fp64"
     r = res[main_prec]
-    updates = r["pairs"] * (M + 1) * cfg.nmaps
+    updates = r["pairs"] * (M + 1) * (3 if args.cross else cfg.nmaps)
     value = updates / r["s_per_step"]
     if args.adjoint:
         log(f"[bench] adjoint: max |dL/dx| {max(grads):.3g}")
@@ -328,14 +344,14 @@ def main():
         "dtype": "f64" if main_prec == "fp64" else "f64 geometry + f32 multipoles/MFMA",
         "data": "synthetic",
         "config": {"workload": cfg.name + ("+approx" if nbr else "") + ("+adjoint" if args.adjoint else "")
-                   + ("+noself" if not self_pairs else ""),
+                   + ("+noself" if not self_pairs else "") + ("+cross3" if args.cross else ""),
                    "npoints": n, "nmaps": cfg.nmaps, "nbins": cfg.nbins, "m_max": M,
                    "theta_arcmin": [cfg.theta_min * 10800 / np.pi, cfg.theta_max * 10800 / np.pi],
                    "log_bins": cfg.log_bins, "precision": main_prec, "pairs": r["pairs"]},
         "roofline": {"bound": rf_bound, "kernel": rf_kernel, "achieved": achieved,
                      "peak": rf_peak, "unit": "TFLOP/s", "frac": achieved / rf_peak if achieved else None,
                      "traffic": measured_traffic(cfg.name, main_prec)
-                     if rf_kernel == "k_multipoles" and self_pairs else None,
+                     if rf_kernel == "k_multipoles" and self_pairs and not args.cross else None,
                      "traffic_unit": "bytes per launch",
                      "avg_launch_ms": r["kernel_ms_total"] / r["kernel_launches"] if r["kernel_launches"] else None,
                      "launches_per_step": launches_per_step, "flops": rf_unit_note,
@@ -360,7 +376,7 @@ def main():
         out["config"]["workload"] += "+graph"
     if args.save_zeta:
         np.savez(args.save_zeta, **{p: res[p]["zeta"] for p in res})
-    if args.cpu_sample != 0 and cfg.nmaps == 1:
+    if args.cpu_sample != 0 and cfg.nmaps == 1 and not args.cross:
         out["cpu_baseline"] = cpu_baseline(cfg, xyz, x, nbr, E, M, args.cpu_sample, z3, torch, self_pairs)
     print(json.dumps(out), flush=True)
 

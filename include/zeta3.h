@@ -200,6 +200,21 @@ z3_status z3_estimate_ex(z3_index idx, int map, int m_max, int prec, unsigned fl
                          int64_t p1, double *zeta, uint64_t *pair_total, void *stream);
 
 /*
+ * Multi-field estimator (the remark after eq. ubEstimator): three attached maps A, B, C of
+ * one index (fields on the same positions and weights, e.g. several redshift bins of one
+ * pixel grid).  The pivot carries field A, the bin b1 field B and the bin b2 field C:
+ *   zeta[m][b1][b2] += sum_p w_p x^A_p X^B_m(b1; p) conj(X^C_m(b2; p))          (cyclic = 0)
+ * or the sum of that term over the cyclic permutations (A;B,C) + (B;C,A) + (C;A,B)
+ * (cyclic = 1).  Unnormalised like z3_estimate (divide by sum_p w_p, z3_finalize); the
+ * result is not Hermitian unless B = C.  map_a, map_b, map_c in [0, nmaps); they may repeat.
+ * The multipoles of each distinct field needed are computed once per pivot chunk (one
+ * search pass per field, the chunk shrinks accordingly); pair_total += pairs counted once.
+ */
+z3_status z3_estimate_cross(z3_index idx, int map_a, int map_b, int map_c, int cyclic, int m_max,
+                            int prec, int64_t p0, int64_t p1, double *zeta, uint64_t *pair_total,
+                            void *stream);
+
+/*
  * Fused estimator for ALL attached maps at once (many mock maps over one set of
  * positions, eqs. Xm.binned and zetamEst for each map): for every pair the bin test,
  * bearing and cos/sin(m phi) are computed once and applied to the values of all maps.

@@ -468,6 +468,61 @@ Z3_API z3_status z3_estimate_ex(z3_index idx, int map, int m_max, int prec, unsi
     return st;
 }
 
+Z3_API z3_status z3_estimate_cross(z3_index idx, int map_a, int map_b, int map_c, int cyclic, int m_max,
+                                   int prec, int64_t p0, int64_t p1, double *zeta, uint64_t *pair_total,
+                                   void *stream)
+{
+    CallScope scope(idx, as_stream(stream));
+    z3_status st = check_common("z3_estimate_cross", idx, map_a, m_max, prec, p0, p1);
+    if (st == Z3_OK) st = check_common("z3_estimate_cross", idx, map_b, m_max, prec, p0, p1);
+    if (st == Z3_OK) st = check_common("z3_estimate_cross", idx, map_c, m_max, prec, p0, p1);
+    if (st != Z3_OK) return st;
+    if (!zeta) return fail(Z3_ERR_INVALID_ARG, "z3_estimate_cross: zeta is NULL");
+    if (cyclic != 0 && cyclic != 1) return fail(Z3_ERR_INVALID_ARG, "z3_estimate_cross: cyclic must be 0 or 1");
+    if (p1 == p0) return Z3_OK;
+    hipStream_t s = as_stream(stream);
+    // the terms (pivot field; b1 field, b2 field) and the distinct fields whose multipoles they read
+    const int fa[3] = {map_a, map_b, map_c};
+    const int nterms = cyclic ? 3 : 1;
+    int need[3], nneed = 0, slot_of[3];
+    for (int t = 0; t < 3; ++t) {
+        const int f = fa[t];
+        if (!cyclic && t == 0) { slot_of[t] = -1; continue; }  // the single term reads B and C only
+        int k = 0;
+        while (k < nneed && need[k] != f) ++k;
+        if (k == nneed) need[nneed++] = f;
+        slot_of[t] = k;
+    }
+    int64_t chunk = chunk_pivots(idx, m_max, prec) / nneed;
+    chunk = (chunk / kBlock) * kBlock;
+    if (chunk < 16 * kBlock) chunk = 16 * kBlock;
+    if (chunk > p1 - p0) chunk = ((p1 - p0 + kBlock - 1) / kBlock) * kBlock;
+    const size_t elem = prec == Z3_PREC_FP64 ? 8 : 4;
+    const size_t slot_elems = (size_t)chunk * (size_t)(m_max + 1) * 2 * idx->nbins;
+    const size_t pbytes = cross_partial_bytes(chunk, m_max, idx->nbins);
+    void *wa = nullptr, *wp = nullptr;
+    if ((st = scratch_alloc(&wa, slot_elems * elem * nneed, s)) != Z3_OK) return st;
+    st = scratch_alloc(&wp, pbytes, s);
+    for (int64_t c0 = p0; c0 < p1 && st == Z3_OK; c0 += chunk) {
+        const int64_t c1 = c0 + chunk < p1 ? c0 + chunk : p1;
+        for (int k = 0; k < nneed && st == Z3_OK; ++k)
+            st = launch_multipoles(idx, Pivots{idx->d_x, idx->d_y, idx->d_z}, need[k], m_max, prec, Z3_NORM_BIN, c0,
+                                   c1, static_cast<char *>(wa) + (size_t)k * slot_elems * elem, c1 - c0, nullptr,
+                                   nullptr, nullptr, k == 0 ? pair_total : nullptr, s);
+        for (int t = 0; t < nterms && st == Z3_OK; ++t) {
+            // term t: pivot field fa[t], b1 field fa[t+1], b2 field fa[t+2] (cyclically)
+            const int t1 = (t + 1) % 3, t2 = (t + 2) % 3;
+            const void *X1 = static_cast<char *>(wa) + (size_t)slot_of[t1] * slot_elems * elem;
+            const void *X2 = static_cast<char *>(wa) + (size_t)slot_of[t2] * slot_elems * elem;
+            const double *v = idx->d_v + (size_t)fa[t] * idx->n + c0;
+            st = launch_contract_cross(c1 - c0, m_max, idx->nbins, prec, X1, X2, c1 - c0, v, zeta, wp, pbytes, s);
+        }
+    }
+    scratch_free(wp, s);
+    scratch_free(wa, s);
+    return st;
+}
+
 Z3_API z3_status z3_estimate_maps(z3_index idx, int m_max, int prec, int64_t p0, int64_t p1, double *zeta,
                                   uint64_t *pair_total, void *stream)
 {

@@ -439,6 +439,135 @@ z3_status launch_contract(int64_t npiv, int m_max, int nbins, int prec, const vo
     return launch_contract_maps(npiv, m_max, nbins, prec, 1, A, ldA, 0, piv_v, 0, zeta, 0, partials, partial_bytes, s);
 }
 
+// ---- multi-field contraction ------------------------------------------------------------
+// For the pivot field's values v_p and two neighbour fields with multipoles U1 and U2 (same
+// pivots, same bins):  G = sum_p v_p U1_p U2_p^T, a full 2nb x 2nb matrix (no symmetry), and
+//     Re zeta_m(b1, b2) = G(r1, r2) + G(i1, i2),   Im zeta_m(b1, b2) = G(i1, r2) - G(r1, i2),
+// i.e. sum_p v_p X1(b1) conj(X2(b2)).  One wave per (16 x 16 tile, pivot segment, m), MFMA
+// as in k_gram_tiles (split FP32 operand on the mixed path), fixed-order FP64 sums.
+
+struct CrossArgs {
+    const void *A1, *A2;  // [m+1][2][nb][ldA] multipoles of the b1 field and of the b2 field
+    int64_t ldA;
+    int64_t npiv;
+    const double *v;      // pivot products w_p x_p of the pivot field
+    int nb, T;
+    double *part;         // [seg][m][T * T][256]
+};
+
+template <bool F32>
+__global__ __launch_bounds__(64) void k_cross_tiles(CrossArgs c)
+{
+    const int tp = blockIdx.x, seg = blockIdx.y, m = blockIdx.z;
+    const int I = tp / c.T, J = tp % c.T;
+    const int lane = threadIdx.x;
+    const int row = lane & 15, kq = lane >> 4;
+    const int ui = I * 16 + row, uj = J * 16 + row;
+    const int two_nb = 2 * c.nb;
+    const bool vi = ui < two_nb, vj = uj < two_nb;
+    const size_t oi = vi ? ((size_t)2 * m * c.nb + ui) * (size_t)c.ldA : 0;
+    const size_t oj = vj ? ((size_t)2 * m * c.nb + uj) * (size_t)c.ldA : 0;
+    const int64_t pbeg = (int64_t)seg * kSeg;
+    const int64_t pend = min(c.npiv, pbeg + kSeg);
+    double *out = c.part + ((size_t)(seg * gridDim.z + m) * (size_t)(c.T * c.T) + tp) * 256;
+
+    if constexpr (!F32) {
+        const double *A1 = static_cast<const double *>(c.A1), *A2 = static_cast<const double *>(c.A2);
+        v4d acc = {0.0, 0.0, 0.0, 0.0};
+        for (int64_t s = pbeg; s < pend; s += 16) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t p = s + 4 * kq + q;
+                const bool in = p < pend;
+                const double vp = in ? c.v[p] : 0.0;
+                const double ai = (vi && in) ? A1[oi + p] : 0.0;
+                const double bj = (vj && in) ? A2[oj + p] : 0.0;
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ai * vp, bj, acc, 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) out[(4 * k + kq) * 16 + row] = acc[k];
+    } else {
+        const float *A1 = static_cast<const float *>(c.A1), *A2 = static_cast<const float *>(c.A2);
+        v4d acc = {0.0, 0.0, 0.0, 0.0};
+        for (int64_t s = pbeg; s < pend; s += 16) {
+            v4f part = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t p = s + 4 * kq + q;
+                const bool in = p < pend;
+                const double vp = in ? c.v[p] : 0.0;
+                const float ui = (vi && in) ? A1[oi + p] : 0.0f;
+                const float bj = (vj && in) ? A2[oj + p] : 0.0f;
+                const double a = (double)ui * vp;
+                const float ahi = (float)a;
+                const float alo = (float)(a - (double)ahi);
+                part = __builtin_amdgcn_mfma_f32_16x16x4f32(ahi, bj, part, 0, 0, 0);
+                part = __builtin_amdgcn_mfma_f32_16x16x4f32(alo, bj, part, 0, 0, 0);
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) acc[k] += (double)part[k];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) out[(4 * kq + k) * 16 + row] = acc[k];
+    }
+}
+
+__device__ __forceinline__ double cross_at(const double *seg_m, int T, int u, int v)
+{
+    return seg_m[(size_t)((u >> 4) * T + (v >> 4)) * 256 + (u & 15) * 16 + (v & 15)];
+}
+
+__global__ void k_cross_reduce(const double *part, int64_t nseg, int M1, int nb, int T, double *zeta)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= M1 * nb * nb) return;
+    const int m = t / (nb * nb), rem = t % (nb * nb), b1 = rem / nb, b2 = rem % nb;
+    const int r1 = b1, r2 = b2, i1 = nb + b1, i2 = nb + b2;
+    double rr = 0.0, ii = 0.0, ir = 0.0, ri = 0.0;
+    for (int64_t s = 0; s < nseg; ++s) {
+        const double *g = part + (size_t)(s * M1 + m) * (size_t)(T * T) * 256;
+        rr += cross_at(g, T, r1, r2);
+        ii += cross_at(g, T, i1, i2);
+        ir += cross_at(g, T, i1, r2);
+        ri += cross_at(g, T, r1, i2);
+    }
+    double *z = zeta + ((size_t)(m * nb + b1) * nb + b2) * 2;
+    z[0] += rr + ii;
+    z[1] += ir - ri;
+}
+
+size_t cross_partial_bytes(int64_t npiv, int m_max, int nbins)
+{
+    const int T = tiles_for(nbins);
+    const int64_t nseg = (npiv + kSeg - 1) / kSeg;
+    return (size_t)(nseg > 0 ? nseg : 1) * (size_t)(m_max + 1) * (size_t)(T * T) * 256 * sizeof(double);
+}
+
+z3_status launch_contract_cross(int64_t npiv, int m_max, int nbins, int prec, const void *A1, const void *A2,
+                                int64_t ldA, const double *piv_v, double *zeta, void *partials,
+                                size_t partial_bytes, hipStream_t s)
+{
+    if (npiv <= 0) return Z3_OK;
+    const int T = tiles_for(nbins);
+    const int64_t nseg = (npiv + kSeg - 1) / kSeg;
+    if (partial_bytes < cross_partial_bytes(npiv, m_max, nbins))
+        return fail(Z3_ERR_INVALID_ARG, "multi-field contraction: partial buffer too small");
+    if (nseg > 65535) return fail(Z3_ERR_OVERFLOW, "multi-field contraction: %lld pivot segments", (long long)nseg);
+    CrossArgs c;
+    c.A1 = A1; c.A2 = A2; c.ldA = ldA; c.npiv = npiv; c.v = piv_v; c.nb = nbins; c.T = T;
+    c.part = static_cast<double *>(partials);
+    dim3 grid((unsigned)(T * T), (unsigned)nseg, (unsigned)(m_max + 1));
+    if (prec == Z3_PREC_MIXED) hipLaunchKernelGGL(k_cross_tiles<true>, grid, dim3(64), 0, s, c);
+    else hipLaunchKernelGGL(k_cross_tiles<false>, grid, dim3(64), 0, s, c);
+    z3_status st = check_launch("k_cross_tiles");
+    if (st != Z3_OK) return st;
+    const int total = (m_max + 1) * nbins * nbins;
+    hipLaunchKernelGGL(k_cross_reduce, dim3((total + 127) / 128), dim3(128), 0, s,
+                       static_cast<const double *>(partials), nseg, m_max + 1, nbins, T, zeta);
+    return check_launch("k_cross_reduce");
+}
+
 // ---- sum of pivot weights (fixed order) ------------------------------------------------
 
 __global__ void k_sum_partials(const double *w, int64_t n, int64_t per_block, double *partial)

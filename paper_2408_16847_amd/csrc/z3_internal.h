@@ -159,6 +159,12 @@ z3_status launch_contract_staged(int64_t npiv, int m_max, int nbins, int prec, i
                                  const double *piv_v, size_t v_stride, double *zeta, size_t z_stride, void *partials,
                                  size_t partial_bytes, hipStream_t s);
 bool gram_lds_fits(int m_max, int nbins, int prec);
+// multi-field contraction: zeta[m][b1][b2] += sum_p v_p X1_m(b1; p) conj(X2_m(b2; p)),
+// X1 and X2 in the pivot-minor layout [m+1][2][nbins][ldA]
+z3_status launch_contract_cross(int64_t npiv, int m_max, int nbins, int prec, const void *A1, const void *A2,
+                                int64_t ldA, const double *piv_v, double *zeta, void *partials,
+                                size_t partial_bytes, hipStream_t s);
+size_t cross_partial_bytes(int64_t npiv, int m_max, int nbins);
 size_t contract_partial_bytes(int64_t npiv, int m_max, int nbins);
 z3_status launch_weight_sum(const double *w, int64_t n, double *out, hipStream_t s);
 z3_status launch_pivot_values(const double *w, const double *x, int64_t n, double *v, hipStream_t s);

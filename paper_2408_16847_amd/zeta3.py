@@ -176,6 +176,34 @@ def estimate(idx: Index, m_max: int, prec="fp64", p0: int = 0, p1: int | None = 
     return z[..., 0] + 1j * z[..., 1], int(pairs.item())
 
 
+def estimate_cross_raw(idx: Index, maps, m_max: int, prec="fp64", cyclic: bool = False, p0: int = 0,
+                       p1: int | None = None, zeta=None, pair_total=None, sum_w=None):
+    """Enqueue the multi-field estimator of attached maps (A, B, C) for pivots [p0, p1):
+    zeta += sum_p w_p x^A_p X^B(b1) conj X^C(b2) (summed over cyclic permutations if cyclic),
+    unnormalised; pair_total and sum_w as in estimate_raw.  No sync."""
+    p1 = idx.n if p1 is None else p1
+    a, b, c = (int(k) for k in maps)
+    if zeta is None:
+        zeta = torch.zeros((m_max + 1, idx.nbins, idx.nbins, 2), dtype=torch.float64, device="cuda")
+    _lib.call("z3_estimate_cross", idx.handle, a, b, c, 1 if cyclic else 0, m_max, PREC[prec], p0, p1,
+              _ptr(zeta), _ptr(pair_total), _stream())
+    if sum_w is not None:
+        _lib.call("z3_pivot_weight_sum", idx.handle, p0, p1, _ptr(sum_w), _stream())
+    return zeta
+
+
+def estimate_cross(idx: Index, maps, m_max: int, prec="fp64", cyclic: bool = False, p0: int = 0,
+                   p1: int | None = None):
+    """Normalised multi-field zeta_m as complex128 numpy [m+1, nb, nb], and the pair count."""
+    zeta = torch.zeros((m_max + 1, idx.nbins, idx.nbins, 2), dtype=torch.float64, device="cuda")
+    pairs = torch.zeros(1, dtype=torch.int64, device="cuda")
+    sw = torch.zeros(1, dtype=torch.float64, device="cuda")
+    estimate_cross_raw(idx, maps, m_max, prec, cyclic, p0, p1, zeta, pairs, sw)
+    _lib.call("z3_finalize", 1, m_max, idx.nbins, _ptr(zeta), _ptr(sw), _stream())
+    z = zeta.cpu().numpy()
+    return z[..., 0] + 1j * z[..., 1], int(pairs.item())
+
+
 def estimate_maps_raw(idx: Index, m_max: int, prec="fp64", p0: int = 0, p1: int | None = None, zeta=None,
                       pair_total=None, sum_w=None):
     """Enqueue the estimator for every attached map at once: zeta [nmaps, m+1, nb, nb, 2] +=."""

@@ -1,0 +1,102 @@
+"""GPU parity of the multi-field estimator (z3_estimate_cross).
+
+Three fields on one set of positions (attached maps A, B, C): the pivot carries A, the bin
+b1 field B and the bin b2 field C, optionally summed over the cyclic permutations (the
+remark after eq. ubEstimator).  Against the FP64 oracle (per-field C-oracle multipoles and
+the cross contraction, pinned by the multi-field triplet sum): pair counts exact, zeta_m
+within 1e-10 (FP64 path) and 1e-6 (mixed path) per-m max-normalised error.
+"""
+
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2408_16847_amd as z3
+from paper_2408_16847_amd import _lib
+from oracle import cpu
+from synth import CONFIGS, make_positions, make_values
+from tests import gpu_helpers as G
+from tests import pins
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cap3():
+    # three correlated lognormal fields on the cap20k positions (e.g. redshift bins of one sky)
+    cfg = CONFIGS["cap20k"]
+    xyz_t = make_positions(cfg)
+    x0, x1, x2 = (make_values(cfg, xyz_t, seed=s).numpy() for s in range(3))
+    fields = np.stack([x0, x0 + 0.5 * x1, x0 - 0.3 * x2])
+    return cfg, xyz_t.numpy(), fields
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("mixed", 1e-6)])
+@pytest.mark.parametrize("cyclic", [False, True])
+def test_cap20k_cross_fields(cap3, prec, tol, cyclic):
+    cfg, xyz, f = cap3
+    G.say("case: cap20k three fields", prec, "cyclic" if cyclic else "single term")
+    E = cfg.edges_chord2()
+    w = np.ones(xyz.shape[1])
+    idx = G.build(xyz, f, E)
+    z, pairs = z3.estimate_cross(idx, (0, 1, 2), cfg.m_max, prec=prec, cyclic=cyclic)
+    zo, po = cpu.estimate_cross(xyz, xyz, w, tuple(f), E, cfg.m_max, w, tuple(f), cyclic=cyclic)
+    assert pairs == po
+    e = G.err_m(z, zo)
+    G.say("err_m", prec, e)
+    assert e.max() <= tol, e
+
+
+def test_cross_of_one_field_is_the_estimator(cap3):
+    cfg, xyz, f = cap3
+    G.say("case: cross of one field")
+    E = cfg.edges_chord2()
+    idx = G.build(xyz, f, E)
+    z, pairs = z3.estimate(idx, cfg.m_max, map_index=1)
+    z1, p1 = z3.estimate_cross(idx, (1, 1, 1), cfg.m_max)
+    z3c, p3 = z3.estimate_cross(idx, (1, 1, 1), cfg.m_max, cyclic=True)
+    assert pairs == p1 == p3
+    assert G.err_m(z1, z).max() < 1e-12
+    assert G.err_m(z3c, 3.0 * z).max() < 1e-12
+    # exchanging the two neighbour fields conjugates and transposes
+    zbc, _ = z3.estimate_cross(idx, (0, 1, 2), cfg.m_max)
+    zcb, _ = z3.estimate_cross(idx, (0, 2, 1), cfg.m_max)
+    assert G.err_m(zcb, np.conj(np.swapaxes(zbc, 1, 2))).max() < 1e-12
+
+
+# FP64 only: on white-noise fields zeta is a sum of terms of random sign (condition number
+# ~ sqrt(pivots)), where the FP32 harmonics of the mixed path reach ~1e-6 on 3,000 points;
+# the mixed path is gated on the lognormal cap fields above.
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10)])
+def test_weighted_cross_fields_and_pivot_ranges(prec, tol):
+    G.say("case: weighted cap three fields", prec)
+    xyz, w, xa = pins.random_cap(3000, 4.0, 41)
+    rng = np.random.default_rng(42)
+    f = np.stack([xa, xa + rng.normal(size=3000), rng.normal(size=3000)])
+    E = pins.small_edges(6, lo=0.05, hi=1.5, log=True)
+    idx = G.build(xyz, f, E, w=w)
+    zo, po = cpu.estimate_cross(xyz, xyz, w, tuple(f), E, 5, w, tuple(f), cyclic=True)
+    zr = torch.zeros((6, 6, 6, 2), dtype=torch.float64, device="cuda")
+    sw = torch.zeros(1, dtype=torch.float64, device="cuda")
+    pt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    for p0, p1 in ((0, 333), (333, 2100), (2100, 3000)):
+        z3.estimate_cross_raw(idx, (0, 1, 2), 5, prec, True, p0, p1, zeta=zr, pair_total=pt, sum_w=sw)
+    torch.cuda.synchronize()
+    zc = zr.cpu().numpy() / sw.item()
+    assert int(pt.item()) == po
+    assert G.err_m(zc[..., 0] + 1j * zc[..., 1], zo).max() <= tol
+
+
+def test_cross_rejects_a_missing_map():
+    G.say("case: z3_estimate_cross map range")
+    xyz, E, x = pins.three_point_case()
+    idx = G.build(xyz, np.stack([x, x]), E)
+    zeta = torch.zeros((5, 3, 3, 2), dtype=torch.float64, device="cuda")
+    with pytest.raises(_lib.Zeta3Error) as ei:
+        _lib.call("z3_estimate_cross", idx.handle, 0, 1, 2, 0, 4, 0, 0, 3, ctypes.c_void_p(zeta.data_ptr()),
+                  ctypes.c_void_p(0), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert ei.value.status == 1
+    torch.cuda.synchronize()
+    assert torch.count_nonzero(zeta).item() == 0
