@@ -11,6 +11,7 @@ Prints one JSON line (progress goes to stderr).
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -122,6 +123,9 @@ def main():
     ap.add_argument("--prec", default="both", choices=["both", "fp64", "mixed"])
     ap.add_argument("--approx", action="store_true",
                     help="approximate search: neighbours from the Nside/2 averaged map, all pivots kept")
+    ap.add_argument("--nside", type=int, default=0,
+                    help="run the chosen HEALPix workload's recipe (field, bins, m) at this resolution instead")
+    ap.add_argument("--m-max", type=int, default=-1, help="override the workload's largest multipole")
     ap.add_argument("--cross", action="store_true",
                     help="multi-field estimator: three correlated fields on the positions, summed over the "
                          "cyclic permutations of (pivot; b1, b2) fields (one-map workloads)")
@@ -170,6 +174,12 @@ def main():
         return
 
     cfg = CONFIGS[args.config]
+    if args.nside > 0:
+        if cfg.kind != "healpix":
+            sys.exit("--nside needs a HEALPix workload")
+        cfg = dataclasses.replace(cfg, n_or_nside=args.nside, name=f"{cfg.name}@nside{args.nside}")
+    if args.m_max >= 0:
+        cfg = dataclasses.replace(cfg, m_max=args.m_max, name=f"{cfg.name}@m{args.m_max}")
     if (args.exclude_self or args.cross) and (args.approx or args.adjoint or cfg.nmaps > 1):
         print("--exclude-self and --cross apply to the one-map exact search only", file=sys.stderr)
         sys.exit(2)
