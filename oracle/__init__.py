@@ -35,6 +35,8 @@ Ym/Zm.binned, zetamEst2), with the readings listed in the design doc:
    multi-field form (remark after eq. ubEstimator): the pivot carries field A, X(b1) is
    taken from field B and X(b2) from field C; optionally summed over the cyclic
    permutations of (A, B, C);
+   pivots on a plane (positions [2, n], d2 = dx*dx + dy*dy, phi = atan2(dx, dy) from +y
+   towards +x) use the same steps 3-5;
 6. resum: zeta(b1, b2, phi) = sum_{m=-M}^{M} zeta_m exp(i m phi), zeta_{-m} = conj(zeta_m).
 
 Parity of every function here is pinned by tests that do not re-type its formulas

@@ -108,6 +108,43 @@ def zeta_cross_brute(piv, nbr, w, fields, edges, m_max, wp, pivot_fields, cyclic
     return acc / np.sum(wp), pairs
 
 
+def zeta_brute_planar(piv, nbr, w, x, edges, m_max, wp, xp):
+    """Triplet sum for pivots on a plane: positions [2, n]; the opening angle phi_j - phi_k
+    from the separation vectors, cos = d_j . d_k / |d_j||d_k|, sin = (d_j x d_k)_z / |d_j||d_k|
+    (angles measured from +y towards +x)."""
+    piv = np.asarray(piv, dtype=np.float64)
+    nbr = np.asarray(nbr, dtype=np.float64)
+    nb = len(edges) - 1
+    acc = np.zeros((m_max + 1, nb, nb), dtype=np.complex128)
+    pairs = 0
+    for p in range(piv.shape[1]):
+        dx = nbr[0] - piv[0, p]
+        dy = nbr[1] - piv[1, p]
+        b = _bins_by_loop(dx * dx + dy * dy, edges)
+        sel = b >= 0
+        if not sel.any():
+            continue
+        pairs += int(sel.sum())
+        bj = b[sel]
+        u, v = dx[sel], dy[sel]
+        nrm = np.hypot(u, v)
+        u, v = u / nrm, v / nrm
+        cosd = np.outer(u, u) + np.outer(v, v)
+        sind = np.outer(u, v) - np.outer(v, u)
+        dphi = np.arctan2(sind, cosd)
+        Wb = np.zeros(nb)
+        np.add.at(Wb, bj, w[sel])
+        g = w[sel] * x[sel] / Wb[bj]
+        gg = np.outer(g, g) * (wp[p] * xp[p])
+        key = (bj[:, None] * nb + bj[None, :]).ravel()
+        for m in range(m_max + 1):
+            ph = np.exp(-1j * m * dphi) * gg
+            re = np.bincount(key, weights=ph.real.ravel(), minlength=nb * nb)
+            im = np.bincount(key, weights=ph.imag.ravel(), minlength=nb * nb)
+            acc[m] += (re + 1j * im).reshape(nb, nb)
+    return acc / np.sum(wp), pairs
+
+
 def dirichlet_resum_brute(piv, nbr, w, x, edges, M, wp, xp, phi):
     """Triplet density smoothed by the Dirichlet kernel D_M(phi - (phi_j - phi_k)).
 

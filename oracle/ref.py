@@ -180,6 +180,52 @@ def estimate_cross(piv, nbr, w, fields, edges, m_max, wp, pivot_fields, cyclic=F
     return z / np.sum(wp), int(N.sum())
 
 
+def planar_bearing(dx, dy):
+    """Angle of a separation on the plane, from the +y axis towards +x."""
+    return np.arctan2(dx, dy)
+
+
+def multipoles_planar(piv, nbr, w, x, edges, m_max, block=128):
+    """Raw binned multipoles for pivots on a plane (the estimator is the same on any smooth
+    manifold, as the paper notes in its description of the code): positions [2, n] (x, y),
+    d2 = dx*dx + dy*dy rounded as written, the angle phi = atan2(dx, dy) measured from the +y
+    axis towards +x (the plane's "north" and "east").  Returns a, W, N as multipoles()."""
+    piv = np.asarray(piv, dtype=np.float64)
+    nbr = np.asarray(nbr, dtype=np.float64)
+    edges = np.asarray(edges, dtype=np.float64)
+    P, nb = piv.shape[1], len(edges) - 1
+    a = np.zeros((P, m_max + 1, nb), dtype=np.complex128)
+    W = np.zeros((P, nb))
+    N = np.zeros((P, nb), dtype=np.int64)
+    wx = w * x
+    for s in range(0, P, block):
+        e = min(P, s + block)
+        dx = nbr[0][None, :] - piv[0][s:e, None]
+        dy = nbr[1][None, :] - piv[1][s:e, None]
+        b = bin_index(dx * dx + dy * dy, edges)
+        pi, j = np.nonzero(b >= 0)
+        if pi.size == 0:
+            continue
+        bb = b[pi, j]
+        phi = planar_bearing(dx[pi, j], dy[pi, j])
+        key = pi * nb + bb
+        size = (e - s) * nb
+        W[s:e] = np.bincount(key, weights=w[j], minlength=size).reshape(e - s, nb)
+        N[s:e] = np.bincount(key, minlength=size).reshape(e - s, nb)
+        for m in range(m_max + 1):
+            re = np.bincount(key, weights=wx[j] * np.cos(m * phi), minlength=size)
+            im = np.bincount(key, weights=-wx[j] * np.sin(m * phi), minlength=size)
+            a[s:e, m] = (re + 1j * im).reshape(e - s, nb)
+    return a, W, N
+
+
+def estimate_planar(piv, nbr, w, x, edges, m_max, wp, xp):
+    """zeta_m(b1, b2) for pivots on a plane (multipoles_planar), normalised by sum_p w_p."""
+    a, W, N = multipoles_planar(piv, nbr, w, x, edges, m_max)
+    z = contract(normalise(a, W), wp * xp) / np.sum(wp)
+    return z, int(N.sum())
+
+
 def resum(zeta, phi):
     """zeta(b1, b2, phi) = sum_{m=-M}^{M} zeta_m exp(i m phi), zeta_{-m} = conj(zeta_m).
 

@@ -141,6 +141,48 @@ def check_cross_brute(n=220, seed=21, m_max=4, tol=1e-12, cyclic=False):
     assert err <= tol, err
 
 
+def random_square(n, side, seed):
+    """n points uniform in a square of the given side, weights in [0.5, 2], normal values."""
+    rng = np.random.default_rng(seed)
+    xy = rng.uniform(0.0, side, size=(2, n))
+    return xy, rng.uniform(0.5, 2.0, n), rng.normal(size=n)
+
+
+def planar_edges(nb=5, lo=0.2, hi=2.5, log=False):
+    """Squared-distance edges of nb bins between lo and hi (plane units)."""
+    r = np.geomspace(lo, hi, nb + 1) if log else np.linspace(lo, hi, nb + 1)
+    return r * r
+
+
+def check_brute_planar(n=250, seed=31, m_max=5, tol=1e-12, log=False):
+    xy, w, x = random_square(n, 6.0, seed)
+    E = planar_edges(6, log=log)
+    z, pairs = ref.estimate_planar(xy, xy, w, x, E, m_max, w, x)
+    zb, pb = brute.zeta_brute_planar(xy, xy, w, x, E, m_max, w, x)
+    assert pairs == pb, (pairs, pb)
+    err = rel_err(z, zb)
+    assert err <= tol, err
+
+
+def three_point_planar():
+    """P at the origin, A one unit along +y ("north"), B two units along +x ("east"):
+    the planar twin of three_point_case (|AB| = sqrt(5) beyond the last edge)."""
+    xy = np.array([[0.0, 0.0, 2.0], [0.0, 1.0, 0.0]])
+    E = np.array([0.9, 1.1, 1.9, 2.1]) ** 2
+    x = np.array([1.3, 0.7, -0.4])
+    return xy, E, x
+
+
+def check_three_point_planar(tol=1e-14):
+    xy, E, x = three_point_planar()
+    w = np.ones(3)
+    z, pairs = ref.estimate_planar(xy, xy, w, x, E, 4, w, x)
+    gold_pairs, gold = golden_three_point()
+    assert pairs == gold_pairs, pairs
+    err = np.abs(z - gold).max()
+    assert err <= tol, err
+
+
 def golden_three_point_no_self():
     """The hand-derived three-point values without the k = j terms: every non-empty bin
     of every pivot holds one point, so the diagonal entries vanish and the rest stays."""

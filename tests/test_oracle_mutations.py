@@ -3,7 +3,8 @@
 Each test swaps one oracle function for a plausibly wrong version and checks that a
 pin from tests/pins.py raises.  This shows the pins constrain every step: the bearing
 (sign and handedness), the exponent sign, the bin rule, the normaliser, the
-contraction's operand order, the pivot weight and the removal of the k = j terms and the operand order of the multi-field contraction.
+contraction's operand order, the pivot weight and the removal of the k = j terms, the operand order of the multi-field contraction and the
+planar bearing.
 """
 
 import numpy as np
@@ -138,3 +139,10 @@ def test_cross_pivot_field_swapped_fails_brute(monkeypatch):
     monkeypatch.setattr(ref, "estimate_cross", wrong)
     with pytest.raises(AssertionError):
         pins.check_cross_brute()
+
+
+def test_planar_bearing_from_the_x_axis_fails_three_point(monkeypatch):
+    # angle measured from +x counter-clockwise instead of from +y towards +x
+    monkeypatch.setattr(ref, "planar_bearing", lambda dx, dy: np.arctan2(dy, dx))
+    with pytest.raises(AssertionError):
+        pins.check_three_point_planar()

@@ -96,6 +96,31 @@ def test_cross_fields_special_cases():
     assert pins.rel_err(zcb, np.conj(np.swapaxes(zbc, 1, 2))) < 1e-13
 
 
+@pytest.mark.parametrize("seed,log", [(31, False), (33, True)])
+def test_planar_brute(seed, log):
+    pins.check_brute_planar(seed=seed, log=log)
+
+
+def test_planar_three_point_golden():
+    pins.check_three_point_planar()
+
+
+def test_planar_rotation_and_mirror():
+    # a rotation of the plane keeps zeta; a mirror keeps Re and flips Im (where the pair
+    # counts agree, i.e. no pair moved across a bin edge by rounding)
+    xy, w, x = pins.random_square(400, 6.0, 35)
+    E = pins.planar_edges(5)
+    z, p = ref.estimate_planar(xy, xy, w, x, E, 4, w, x)
+    a = 0.7
+    R = np.array([[math.cos(a), -math.sin(a)], [math.sin(a), math.cos(a)]])
+    zr, pr = ref.estimate_planar(R @ xy, R @ xy, w, x, E, 4, w, x)
+    mir = np.array([[-1.0], [1.0]]) * xy
+    zm, pm = ref.estimate_planar(mir, mir, w, x, E, 4, w, x)
+    assert p == pr == pm
+    assert pins.rel_err(zr, z) < 1e-10
+    assert pins.rel_err(zm, np.conj(z)) < 1e-12
+
+
 def test_no_self_pairs_three_point_and_c_oracle():
     pairs, gold = pins.golden_three_point_no_self()
     xyz, E, x = pins.three_point_case()
