@@ -180,6 +180,9 @@ def main():
         cfg = dataclasses.replace(cfg, n_or_nside=args.nside, name=f"{cfg.name}@nside{args.nside}")
     if args.m_max >= 0:
         cfg = dataclasses.replace(cfg, m_max=args.m_max, name=f"{cfg.name}@m{args.m_max}")
+    if cfg.kind == "plane" and (args.approx or args.adjoint or args.cross or args.graph):
+        print("the plane workload runs the one-map estimator only", file=sys.stderr)
+        sys.exit(2)
     if (args.exclude_self or args.cross) and (args.approx or args.adjoint or cfg.nmaps > 1):
         print("--exclude-self and --cross apply to the one-map exact search only", file=sys.stderr)
         sys.exit(2)
@@ -286,7 +289,7 @@ def main():
             idx.set_values(x3)
             z3.estimate_cross_raw(idx, (0, 1, 2), M, prec, True, zeta=zeta, pair_total=pairs, sum_w=sw)
         elif nbr is None:
-            idx = z3.Index(xyz, E)
+            idx = z3.Index(xyz, E, planar=cfg.kind == "plane")
             idx.set_values(x)
             z3.estimate_raw(idx, M, prec=prec, zeta=zeta, pair_total=pairs, sum_w=sw, self_pairs=self_pairs)
         else:
@@ -356,7 +359,8 @@ def main():
         "config": {"workload": cfg.name + ("+approx" if nbr else "") + ("+adjoint" if args.adjoint else "")
                    + ("+noself" if not self_pairs else "") + ("+cross3" if args.cross else ""),
                    "npoints": n, "nmaps": cfg.nmaps, "nbins": cfg.nbins, "m_max": M,
-                   "theta_arcmin": [cfg.theta_min * 10800 / np.pi, cfg.theta_max * 10800 / np.pi],
+                   **({"r_plane_units": [cfg.theta_min, cfg.theta_max]} if cfg.kind == "plane" else
+                      {"theta_arcmin": [cfg.theta_min * 10800 / np.pi, cfg.theta_max * 10800 / np.pi]}),
                    "log_bins": cfg.log_bins, "precision": main_prec, "pairs": r["pairs"]},
         "roofline": {"bound": rf_bound, "kernel": rf_kernel, "achieved": achieved,
                      "peak": rf_peak, "unit": "TFLOP/s", "frac": achieved / rf_peak if achieved else None,
@@ -386,7 +390,7 @@ def main():
         out["config"]["workload"] += "+graph"
     if args.save_zeta:
         np.savez(args.save_zeta, **{p: res[p]["zeta"] for p in res})
-    if args.cpu_sample != 0 and cfg.nmaps == 1 and not args.cross:
+    if args.cpu_sample != 0 and cfg.nmaps == 1 and not args.cross and cfg.kind != "plane":
         out["cpu_baseline"] = cpu_baseline(cfg, xyz, x, nbr, E, M, args.cpu_sample, z3, torch, self_pairs)
     print(json.dumps(out), flush=True)
 

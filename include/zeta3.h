@@ -150,6 +150,24 @@ z3_status z3_index_set_batch_shape(z3_index idx, int waves, int maps_per_wave);
 /* [host] The fixed or tuned shape for (m_max, prec); (0, 0) if not tuned yet. */
 z3_status z3_index_batch_shape(z3_index idx, int m_max, int prec, int *waves, int *maps_per_wave);
 
+/*
+ * Index of a catalogue on a plane (the estimator is the same for pivots on any smooth
+ * manifold; the paper's code offers the sphere and the plane, see its description of the
+ * cBalls code):
+ *   xy        [2][n] FP64 positions (x row, y row), any units, finite
+ *   w         [n] weights or NULL
+ *   edges_d2  [host] nbins+1 strictly increasing squared distances, 0 < E_0
+ *   cell_size strip height in the units of xy; <= 0 selects 1.4 x the mean spacing
+ * Pairs: d2 = dx*dx + dy*dy in FP64, E_b <= d2 < E_{b+1}; the angle of a separation is
+ * measured from the +y axis towards +x.  The index serves z3_index_set_values,
+ * z3_accumulate_multipoles, z3_estimate, z3_estimate_ex, z3_estimate_cross and
+ * z3_estimate_maps with one map; the many-map, external-pivot and adjoint entry points
+ * return Z3_ERR_UNSUPPORTED for it.  Synchronises on `stream`.
+ */
+z3_status z3_build_index_planar(int64_t n, const double *xy, const double *w, int nbins,
+                                const double *edges_d2, double cell_size, void *stream,
+                                z3_index *out);
+
 /* Release an index and its device memory (NULL is ignored).  Waits for its work. */
 void z3_index_free(z3_index idx);
 

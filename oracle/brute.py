@@ -108,7 +108,7 @@ def zeta_cross_brute(piv, nbr, w, fields, edges, m_max, wp, pivot_fields, cyclic
     return acc / np.sum(wp), pairs
 
 
-def zeta_brute_planar(piv, nbr, w, x, edges, m_max, wp, xp):
+def zeta_brute_planar(piv, nbr, w, x, edges, m_max, wp, xp, self_pairs=True):
     """Triplet sum for pivots on a plane: positions [2, n]; the opening angle phi_j - phi_k
     from the separation vectors, cos = d_j . d_k / |d_j||d_k|, sin = (d_j x d_k)_z / |d_j||d_k|
     (angles measured from +y towards +x)."""
@@ -136,6 +136,8 @@ def zeta_brute_planar(piv, nbr, w, x, edges, m_max, wp, xp):
         np.add.at(Wb, bj, w[sel])
         g = w[sel] * x[sel] / Wb[bj]
         gg = np.outer(g, g) * (wp[p] * xp[p])
+        if not self_pairs:
+            np.fill_diagonal(gg, 0.0)  # no triangle with k = j
         key = (bj[:, None] * nb + bj[None, :]).ravel()
         for m in range(m_max + 1):
             ph = np.exp(-1j * m * dphi) * gg

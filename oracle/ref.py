@@ -130,19 +130,21 @@ def self_pair_term(W, Q, vp):
     return np.where(W > 0, Q / (safe * safe), 0.0).T @ vp
 
 
-def estimate(piv, nbr, w, x, edges, m_max, wp, xp, self_pairs=True):
+def estimate(piv, nbr, w, x, edges, m_max, wp, xp, self_pairs=True, planar=False):
     """zeta_m(b1, b2) for the given pivot set, normalised by sum_p w_p; plus the pair total.
 
-    self_pairs=False removes the k = j terms from the diagonal b1 = b2 (self_pair_term).
+    self_pairs=False removes the k = j terms from the diagonal b1 = b2 (self_pair_term);
+    planar=True takes positions [2, n] on a plane (multipoles_planar).
     """
-    a, W, N = multipoles(piv, nbr, w, x, edges, m_max)
+    multipoles_ = multipoles_planar if planar else multipoles
+    a, W, N = multipoles_(piv, nbr, w, x, edges, m_max)
     X = normalise(a, W)
     z = contract(X, wp * xp)
     if not self_pairs:
         w = np.asarray(w, dtype=np.float64)
         x = np.asarray(x, dtype=np.float64)
         # Q_{p,b} = sum_{j in b} w_j (w_j x_j^2): the m = 0 sum of the field w x^2
-        q, _, _ = multipoles(piv, nbr, w, w * x * x, edges, 0)
+        q, _, _ = multipoles_(piv, nbr, w, w * x * x, edges, 0)
         d = self_pair_term(W, q[:, 0, :].real, wp * xp)
         nb = W.shape[1]
         z[:, np.arange(nb), np.arange(nb)] -= d[None, :]
@@ -159,7 +161,7 @@ def contract_cross(Xa, Xb, vp):
     return out
 
 
-def estimate_cross(piv, nbr, w, fields, edges, m_max, wp, pivot_fields, cyclic=False):
+def estimate_cross(piv, nbr, w, fields, edges, m_max, wp, pivot_fields, cyclic=False, planar=False):
     """Multi-field estimator (remark after eq. ubEstimator): the pivot carries field A, the
     bin b1 field B and the bin b2 field C,
 
@@ -171,7 +173,7 @@ def estimate_cross(piv, nbr, w, fields, edges, m_max, wp, pivot_fields, cyclic=F
     """
     X = []
     for xf in fields:
-        a, W, N = multipoles(piv, nbr, w, xf, edges, m_max)
+        a, W, N = (multipoles_planar if planar else multipoles)(piv, nbr, w, xf, edges, m_max)
         X.append(normalise(a, W))
     terms = [(0, 1, 2), (1, 2, 0), (2, 0, 1)] if cyclic else [(0, 1, 2)]
     z = 0

@@ -18,6 +18,7 @@ _D = ctypes.c_double
 # name -> (restype, argtypes); every symbol declared in include/zeta3.h
 SIGNATURES = {
     "z3_build_index": (_I, [_I64, _P, _P, _I, _P, _D, _P, ctypes.POINTER(_P)]),
+    "z3_build_index_planar": (_I, [_I64, _P, _P, _I, _P, _D, _P, ctypes.POINTER(_P)]),
     "z3_index_set_values": (_I, [_P, _I, _P, _P]),
     "z3_index_info": (_I, [_P, _P, _P, _P, _P, _P]),
     "z3_index_update_values": (_I, [_P, _P, _P]),

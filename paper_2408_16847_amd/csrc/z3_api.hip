@@ -189,6 +189,30 @@ Z3_API z3_status z3_build_index(int64_t n, const double *xyz, const double *w, i
     return build_index_impl(n, xyz, w, nbins, edges_chord2, cell_size, as_stream(stream), out);
 }
 
+Z3_API z3_status z3_build_index_planar(int64_t n, const double *xy, const double *w, int nbins,
+                                       const double *edges_d2, double cell_size, void *stream, z3_index *out)
+{
+    if (!out) return fail(Z3_ERR_INVALID_ARG, "z3_build_index_planar: out is NULL");
+    *out = nullptr;
+    if (n < 0) return fail(Z3_ERR_INVALID_ARG, "z3_build_index_planar: n < 0");
+    if (n >= ((int64_t)1 << 29)) return fail(Z3_ERR_OVERFLOW, "z3_build_index_planar: n >= 2^29");
+    if (n > 0 && !xy) return fail(Z3_ERR_INVALID_ARG, "z3_build_index_planar: xy is NULL");
+    if (nbins < 1 || nbins > Z3_MAX_NBINS)
+        return fail(Z3_ERR_INVALID_ARG, "z3_build_index_planar: nbins=%d outside 1..%d", nbins, Z3_MAX_NBINS);
+    if (!edges_d2) return fail(Z3_ERR_INVALID_ARG, "z3_build_index_planar: edges_d2 is NULL");
+    for (int b = 0; b <= nbins; ++b)
+        if (!std::isfinite(edges_d2[b]))
+            return fail(Z3_ERR_INVALID_ARG, "z3_build_index_planar: edge %d is not finite", b);
+    if (!(edges_d2[0] > 0.0))
+        return fail(Z3_ERR_INVALID_ARG, "z3_build_index_planar: E_0 must be > 0 (excludes self-pairs)");
+    for (int b = 0; b < nbins; ++b)
+        if (!(edges_d2[b + 1] > edges_d2[b]))
+            return fail(Z3_ERR_INVALID_ARG, "z3_build_index_planar: edges not strictly increasing at %d", b);
+    if (!std::isfinite(cell_size))
+        return fail(Z3_ERR_INVALID_ARG, "z3_build_index_planar: cell_size is not finite");
+    return build_index_impl(n, xy, w, nbins, edges_d2, cell_size, as_stream(stream), out, true);
+}
+
 Z3_API z3_status z3_index_set_values(z3_index idx, int nmaps, const double *x, void *stream)
 {
     if (!idx) return fail(Z3_ERR_INVALID_ARG, "z3_index_set_values: idx is NULL");
@@ -529,6 +553,8 @@ Z3_API z3_status z3_estimate_maps(z3_index idx, int m_max, int prec, int64_t p0,
     CallScope scope(idx, as_stream(stream));
     z3_status st = check_common("z3_estimate_maps", idx, 0, m_max, prec, p0, p1);
     if (st != Z3_OK) return st;
+    if (idx->planar && idx->nmaps > 1)
+        return fail(Z3_ERR_UNSUPPORTED, "z3_estimate_maps: the many-map kernels take sky catalogues only");
     if (!zeta) return fail(Z3_ERR_INVALID_ARG, "z3_estimate_maps: zeta is NULL");
     if (p1 == p0) return Z3_OK;
     hipStream_t s = as_stream(stream);
@@ -611,6 +637,7 @@ Z3_API z3_status z3_estimate_pivots(z3_index idx, int map, int64_t npiv, const d
 {
     CallScope scope(idx, as_stream(stream));
     if (!idx) return fail(Z3_ERR_INVALID_ARG, "z3_estimate_pivots: idx is NULL");
+    if (idx->planar) return fail(Z3_ERR_UNSUPPORTED, "z3_estimate_pivots: sky catalogues only");
     if (npiv < 0) return fail(Z3_ERR_INVALID_ARG, "z3_estimate_pivots: npiv < 0");
     if (npiv >= (int64_t)0x7fffffff) return fail(Z3_ERR_OVERFLOW, "z3_estimate_pivots: npiv >= 2^31 - 1");
     if (m_max < 0 || m_max > Z3_MAX_MMAX)
@@ -664,6 +691,7 @@ Z3_API z3_status z3_adjoint(z3_index idx, int map, int m_max, int64_t p0, int64_
 {
     CallScope scope(idx, as_stream(stream));
     z3_status st = check_common("z3_adjoint", idx, map, m_max, Z3_PREC_FP64, p0, p1);
+    if (st == Z3_OK && idx->planar) return fail(Z3_ERR_UNSUPPORTED, "z3_adjoint: sky catalogues only");
     if (st != Z3_OK) return st;
     if (!std::isfinite(scale)) return fail(Z3_ERR_INVALID_ARG, "z3_adjoint: scale is not finite");
     if (p1 == p0) return Z3_OK;
@@ -677,6 +705,7 @@ Z3_API z3_status z3_adjoint_maps(z3_index idx, int m_max, int64_t p0, int64_t p1
 {
     CallScope scope(idx, as_stream(stream));
     z3_status st = check_common("z3_adjoint_maps", idx, 0, m_max, Z3_PREC_FP64, p0, p1);
+    if (st == Z3_OK && idx->planar) return fail(Z3_ERR_UNSUPPORTED, "z3_adjoint_maps: sky catalogues only");
     if (st != Z3_OK) return st;
     if (!std::isfinite(scale)) return fail(Z3_ERR_INVALID_ARG, "z3_adjoint_maps: scale is not finite");
     if (p1 == p0) return Z3_OK;

@@ -179,6 +179,48 @@ __device__ __forceinline__ void band_window(const Band &bd, const int *cell_star
     cells_to_points(bd, cell_start, ca1, cb1, s1, l1);
 }
 
+// Window(s) of a strip for pivots on a plane: the strip's points have y - y0 in
+// [th_lo, th_hi] and cell coordinate (x - x0) sx; a point at distance in [R_in, R_out)
+// of the pivot (y - y0 = yrel, cell coordinate phd) has |dx| < sqrt(R_out^2 - dy_min^2)
+// and, when the strip lies within R_in in y, |dx| >= sqrt(R_in^2 - dy_max^2).  r2_out and
+// r2_in are the guarded squared radii; the cells entirely inside the inner gap are
+// skipped, which leaves up to two ranges.  Bounds in FP64, clamped to the strip.
+__device__ __forceinline__ void planar_window(const Band &bd, const int *cell_start, double yrel, double phd,
+                                              double sx, double r2_out, double r2_in, int &s0, int &l0, int &s1,
+                                              int &l1)
+{
+    s0 = l0 = s1 = l1 = 0;
+    const double dlo = bd.th_lo - yrel, dhi = bd.th_hi - yrel;
+    const double dymin = (dlo <= 0.0 && dhi >= 0.0) ? 0.0 : fmin(fabs(dlo), fabs(dhi));
+    const double dymax = fmax(fabs(dlo), fabs(dhi));
+    const double q_out = r2_out - dymin * dymin;
+    if (!(q_out > 0.0)) return;  // the strip lies entirely beyond R_out
+    const int C = bd.ncell;
+    const double cpr = (double)C / kTwoPi;  // as in the cell assignment
+    const double lim = (double)(C - 1);
+    const double dout = sqrt(q_out) * (1.0 + 1e-9) * sx + 1e-12;
+    const int clo = (int)fmin(fmax(floor((phd - dout) * cpr), 0.0), lim);
+    const int chi = (int)fmin(fmax(floor((phd + dout) * cpr), 0.0), lim);
+    int es = 0, ee = -1;
+    const double q_in = r2_in - dymax * dymax;
+    if (q_in > 0.0) {
+        const double din = sqrt(q_in) * (1.0 - 1e-9) * sx - 1e-12;
+        if (din > 0.0) {
+            // cells [es, ee] lie entirely inside (phd - din, phd + din)
+            es = (int)fmin(fmax(ceil((phd - din) * cpr), -1.0), lim + 1.0);
+            ee = (int)fmin(fmax(floor((phd + din) * cpr), 0.0), lim + 1.0) - 1;
+            es = max(es, clo);
+            ee = min(ee, chi);
+        }
+    }
+    if (es <= ee) {
+        cells_to_points(bd, cell_start, clo, es - 1, s0, l0);
+        cells_to_points(bd, cell_start, ee + 1, chi, s1, l1);
+    } else {
+        cells_to_points(bd, cell_start, clo, chi, s0, l0);
+    }
+}
+
 // Unit-length bearing (c, s) = (u1, u2) / |u| with FP64 accuracy: FP32 reciprocal
 // square root refined by one FP64 Newton step (relative error ~1e-14).  For every pair in
 // range |u|^2 >= E_0 (1 - E_nb / 4) > 0; the addend below only matters for |u| = 0.

@@ -125,6 +125,82 @@ __global__ void k_cell_of_point(int64_t n, const int *band, const double *phi, c
     atomicAdd(&cell_count[g], 1);
 }
 
+// ---- pivots on a plane -------------------------------------------------------------------
+// The plane reuses the sphere's grid: strips of y play the latitude bands and
+// (x - x0) * sx in [0, 2 pi) the longitude of the cells.
+
+// Per-block minima and maxima of x and y ([block][4]: min x, max x, min y, max y).
+__global__ void k_plane_range(const double *xyz, int64_t n, double *part)
+{
+    __shared__ double sh[4][256];
+    double v[4] = {INFINITY, -INFINITY, INFINITY, -INFINITY};
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double x = xyz[i], y = xyz[n + i];
+        v[0] = fmin(v[0], x); v[1] = fmax(v[1], x);
+        v[2] = fmin(v[2], y); v[3] = fmax(v[3], y);
+    }
+    for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] = v[k];
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            sh[0][threadIdx.x] = fmin(sh[0][threadIdx.x], sh[0][threadIdx.x + o]);
+            sh[1][threadIdx.x] = fmax(sh[1][threadIdx.x], sh[1][threadIdx.x + o]);
+            sh[2][threadIdx.x] = fmin(sh[2][threadIdx.x], sh[2][threadIdx.x + o]);
+            sh[3][threadIdx.x] = fmax(sh[3][threadIdx.x], sh[3][threadIdx.x + o]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) part[4 * blockIdx.x + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// [2][n] plane positions -> [3][n] with z = 0 (the records and the d2 test then see
+// dz = 0 exactly)
+__global__ void k_plane_xyz(const double *xy, int64_t n, double *xyz)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    xyz[i] = xy[i];
+    xyz[n + i] = xy[n + i];
+    xyz[2 * n + i] = 0.0;
+}
+
+// Strip of every point (y - y0 in place of the colatitude) and its cell coordinate.
+__global__ void k_band_of_point_plane(const double *xyz, int64_t n, double y0, double inv_h, double x0, double sx,
+                                      int nbands, int *band, double *phi_out, int *band_count,
+                                      double *band_th /* [nbands][2] */)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = i < n;
+    int k = -1;
+    double th = 0.0;
+    if (valid) {
+        th = xyz[n + i] - y0;  // >= 0: y0 is the smallest y
+        k = (int)(th * inv_h);
+        k = k < 0 ? 0 : (k >= nbands ? nbands - 1 : k);
+        band[i] = k;
+        phi_out[i] = (xyz[i] - x0) * sx;
+    }
+    const int lane = threadIdx.x & (kWave - 1);
+    uint64_t todo = __ballot(valid);
+    while (todo) {
+        const int leader = __ffsll((unsigned long long)todo) - 1;
+        const int kl = __shfl(k, leader, kWave);
+        const bool mine = valid && k == kl;
+        const uint64_t grp = __ballot(mine);
+        double lo = mine ? th : INFINITY, hi = mine ? th : 0.0;
+        for (int o = 32; o > 0; o >>= 1) {
+            lo = fmin(lo, __shfl_xor(lo, o, kWave));
+            hi = fmax(hi, __shfl_xor(hi, o, kWave));
+        }
+        if (lane == leader) {
+            atomicAdd(&band_count[kl], (int)__popcll(grp));
+            atomic_min_pos_double(&band_th[2 * kl], lo);
+            atomic_max_pos_double(&band_th[2 * kl + 1], hi);
+        }
+        todo &= ~grp;
+    }
+}
+
 __global__ void k_scatter(int64_t n, const int *cell, const int *cell_start, int *cell_fill, int *order)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -350,16 +426,77 @@ static z3_status dalloc(T **p, size_t count, const char *what)
 static inline unsigned grid_for(int64_t n) { return (unsigned)((n + 255) / 256 > 0 ? (n + 255) / 256 : 1); }
 
 z3_status build_index_impl(int64_t n, const double *xyz, const double *w, int nbins,
-                           const double *edges, double cell_size, hipStream_t s, z3_index *out)
+                           const double *edges, double cell_size, hipStream_t s, z3_index *out, bool planar)
 {
     z3_index idx = new (std::nothrow) z3_index_s();
     if (!idx) return fail(Z3_ERR_OUT_OF_MEMORY, "z3_build_index: host allocation failed");
     (void)hipGetDevice(&idx->device);
     idx->n = n;
     idx->nbins = nbins;
+    idx->planar = planar;
+    z3_status st = Z3_OK;
+    auto bail = [&](z3_status code) {
+        (void)hipStreamSynchronize(s);
+        free_ptrs(idx);
+        delete idx;
+        return code;
+    };
+    // plane: the [2][n] positions become [3][n] with z = 0 (freed on return; every path
+    // out of this function synchronises the stream first)
+    struct TmpBuf {
+        double *p = nullptr;
+        ~TmpBuf() { if (p) (void)hipFree(p); }
+    } xyz3;
+    if (planar && n > 0) {
+        if ((st = dalloc(&xyz3.p, 3 * (size_t)n, "alloc plane positions")) != Z3_OK) return bail(st);
+        hipLaunchKernelGGL(k_plane_xyz, dim3(grid_for(n)), dim3(256), 0, s, xyz, n, xyz3.p);
+        if ((st = check_launch("k_plane_xyz")) != Z3_OK) return bail(st);
+        xyz = xyz3.p;
+    }
+    // plane: bounding box of the points (x0 = min x, y0 = min y, extents lx, ly)
+    double lx = 0.0, ly = 0.0, scale = 0.0;
+    if (planar && n > 0) {
+        const int nblk = (int)std::min<int64_t>((n + 255) / 256, 1024);
+        double *d_part = nullptr;
+        if ((st = dalloc(&d_part, 4 * (size_t)nblk, "alloc plane range")) != Z3_OK) return bail(st);
+        hipLaunchKernelGGL(k_plane_range, dim3(nblk), dim3(256), 0, s, xyz, n, d_part);
+        st = check_launch("k_plane_range");
+        std::vector<double> part(4 * (size_t)nblk);
+        if (st == Z3_OK)
+            st = check_hip(hipMemcpyAsync(part.data(), d_part, part.size() * sizeof(double), hipMemcpyDeviceToHost, s),
+                           "copy plane range");
+        if (st == Z3_OK) st = check_hip(hipStreamSynchronize(s), "sync");
+        (void)hipFree(d_part);
+        if (st != Z3_OK) return bail(st);
+        double v[4] = {INFINITY, -INFINITY, INFINITY, -INFINITY};
+        for (int b = 0; b < nblk; ++b) {
+            v[0] = std::min(v[0], part[4 * b]); v[1] = std::max(v[1], part[4 * b + 1]);
+            v[2] = std::min(v[2], part[4 * b + 2]); v[3] = std::max(v[3], part[4 * b + 3]);
+        }
+        if (!(std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]) && std::isfinite(v[3])))
+            return bail(fail(Z3_ERR_INVALID_ARG, "z3_build_index_planar: positions are not finite"));
+        idx->plane_x0 = v[0];
+        idx->plane_y0 = v[2];
+        lx = v[1] - v[0];
+        ly = v[3] - v[2];
+        scale = std::max(std::max(std::fabs(v[0]), std::fabs(v[1])), std::max(std::fabs(v[2]), std::fabs(v[3])));
+        // cell coordinate (x - x0) sx stays below 2 pi
+        idx->plane_sx = kTwoPi / (lx * (1.0 + 1e-12) + 1e-300 + 1e-15 * scale);
+    }
     for (int b = 0; b <= nbins; ++b) {
         double e = edges[b];
         idx->edges.e[b] = e;
+        if (planar) {
+            // plane: rad_out is the enlarged radius, hav_out / hav_in the enlarged / reduced
+            // squared radii of the window search (membership is the exact d2 test); the
+            // absolute guard covers the rounding of coordinates of size `scale`
+            const double g = 1e-14 * scale, r = sqrt(e);
+            idx->edges.rad_out[b] = r * (1.0 + 1e-9) + g;
+            idx->edges.hav_out[b] = idx->edges.rad_out[b] * idx->edges.rad_out[b];
+            const double rin = std::max(0.0, r * (1.0 - 1e-9) - g);
+            idx->edges.hav_in[b] = rin * rin;
+            continue;
+        }
         // Rounding guards for the window search only (membership is decided by the exact
         // d2 test): the FP64 squared chord of two FP64 unit vectors differs from the
         // exact chord by far less than 1e-9 relative at the separations supported here.
@@ -368,13 +505,6 @@ z3_status build_index_impl(int64_t n, const double *xyz, const double *w, int nb
         double r = 2.0 * asin(std::min(1.0, sqrt(e) / 2.0));
         idx->edges.rad_out[b] = r * (1.0 + 1e-9) + 1e-12;
     }
-    z3_status st = Z3_OK;
-    auto bail = [&](z3_status code) {
-        (void)hipStreamSynchronize(s);
-        free_ptrs(idx);
-        delete idx;
-        return code;
-    };
     if ((st = dalloc(&idx->d_edges, 1, "alloc edges")) != Z3_OK) return bail(st);
     if ((st = check_hip(hipMemcpyAsync(idx->d_edges, &idx->edges, sizeof(EdgeTab), hipMemcpyHostToDevice, s),
                         "copy edges")) != Z3_OK)
@@ -384,7 +514,13 @@ z3_status build_index_impl(int64_t n, const double *xyz, const double *w, int nb
     double h = cell_size;
     double *d_range = nullptr;
     if ((st = dalloc(&d_range, 2, "alloc range")) != Z3_OK) return bail(st);
-    if (h <= 0.0) {
+    if (planar && h <= 0.0) {
+        // the same 1.4 x mean spacing as on the sphere
+        double area = lx * ly;
+        if (!(area > 0.0)) area = std::max(lx, ly) * std::max(lx, ly) / (double)std::max<int64_t>(n, 1);
+        if (!(area > 0.0)) area = 1.0;
+        h = Z3_BAND_HEIGHT_FACTOR * sqrt(area / (double)std::max<int64_t>(n, 1));
+    } else if (h <= 0.0) {
         double init[2] = {kPi, 0.0};
         st = check_hip(hipMemcpyAsync(d_range, init, sizeof(init), hipMemcpyHostToDevice, s), "copy range");
         if (st == Z3_OK && n > 0) {
@@ -407,10 +543,17 @@ z3_status build_index_impl(int64_t n, const double *xyz, const double *w, int nb
         h = Z3_BAND_HEIGHT_FACTOR * sqrt(area / (double)std::max<int64_t>(n, 1));
     }
     (void)hipFree(d_range);
-    h = std::min(h, kPi);
-    int nbands = (int)std::ceil(kPi / h);
-    if (nbands < 1) nbands = 1;
-    if (nbands > (1 << 26)) return bail(fail(Z3_ERR_INVALID_ARG, "z3_build_index: cell_size too small"));
+    int nbands = 1;
+    if (planar) {
+        const double nb_d = std::floor(ly / h) + 1.0;
+        if (!(nb_d <= (double)(1 << 26))) return bail(fail(Z3_ERR_INVALID_ARG, "z3_build_index_planar: cell_size too small"));
+        nbands = (int)nb_d;
+    } else {
+        h = std::min(h, kPi);
+        nbands = (int)std::ceil(kPi / h);
+        if (nbands < 1) nbands = 1;
+        if (nbands > (1 << 26)) return bail(fail(Z3_ERR_INVALID_ARG, "z3_build_index: cell_size too small"));
+    }
     idx->band_h = h;
     idx->nbands = nbands;
 
@@ -435,13 +578,17 @@ z3_status build_index_impl(int64_t n, const double *xyz, const double *w, int nb
     {
         // th_lo starts at +big, th_hi at 0
         std::vector<double> init(2 * (size_t)nbands);
-        for (int k = 0; k < nbands; ++k) { init[2 * k] = 4.0; init[2 * k + 1] = 0.0; }
+        for (int k = 0; k < nbands; ++k) { init[2 * k] = planar ? INFINITY : 4.0; init[2 * k + 1] = 0.0; }
         st = check_hip(hipMemcpyAsync(d_band_th, init.data(), init.size() * sizeof(double), hipMemcpyHostToDevice, s),
                        "copy band init");
         if (st == Z3_OK) st = check_hip(hipStreamSynchronize(s), "sync");
         if (st != Z3_OK) return bail2(st);
     }
-    if (n > 0) {
+    if (n > 0 && planar) {
+        hipLaunchKernelGGL(k_band_of_point_plane, dim3(grid_for(n)), dim3(256), 0, s, xyz, n, idx->plane_y0, 1.0 / h,
+                           idx->plane_x0, idx->plane_sx, nbands, d_band, d_phi, d_band_count, d_band_th);
+        if ((st = check_launch("k_band_of_point_plane")) != Z3_OK) return bail2(st);
+    } else if (n > 0) {
         hipLaunchKernelGGL(k_band_of_point, dim3(grid_for(n)), dim3(256), 0, s, xyz, n, 1.0 / h, nbands, d_band,
                            d_phi, d_band_count, d_band_th);
         if ((st = check_launch("k_band_of_point")) != Z3_OK) return bail2(st);

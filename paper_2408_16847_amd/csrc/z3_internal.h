@@ -61,6 +61,10 @@ struct z3_index_s {
     int *d_perm = nullptr;            // [n] original catalogue index
     int *d_band = nullptr;            // [n] band of each index-order point
     bool unit_w = true;               // all weights are 1 (W_{p,b} = N_{p,b})
+    // pivots on a plane: points (x, y, 0); bands are strips of y - plane_y0, and the
+    // longitude coordinate of the cells is (x - plane_x0) * plane_sx in [0, 2 pi)
+    bool planar = false;
+    double plane_x0 = 0.0, plane_y0 = 0.0, plane_sx = 0.0;
     // neighbour records in "doubled band" order: band k occupies [2 s_k, 2 s_k + 2 n_k)
     // and holds its n_k points twice, so every longitude window, wrapped or not, is one
     // contiguous range
@@ -115,7 +119,8 @@ z3_status check_launch(const char *what);
 
 // index kernels (z3_index.hip)
 z3_status build_index_impl(int64_t n, const double *xyz, const double *w, int nbins,
-                           const double *edges, double cell_size, hipStream_t s, z3_index *out);
+                           const double *edges, double cell_size, hipStream_t s, z3_index *out,
+                           bool planar = false);
 z3_status update_values_impl(z3_index idx, const double *x, hipStream_t s);
 z3_status set_values_impl(z3_index idx, int nmaps, const double *x, hipStream_t s);
 void free_index(z3_index idx);

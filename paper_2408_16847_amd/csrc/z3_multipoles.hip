@@ -23,6 +23,9 @@
 // polynomial families so that no trigonometric function is evaluated per pair.  Scaling
 // both recurrences by w_j x_j folds the field value in: two FMAs and two adds per m.
 //
+// Pivots on a plane (PLANAR): the same loop over a strip x cell grid of (x, y, 0) records;
+// the frame is fixed (angles from +y towards +x) and the windows are planar_window's.
+//
 // Optionally (SELF) the kernel also removes the k = j terms of the contraction's diagonal
 // (the overcount the paper points out in the kappa^3 multipole-signal subsection): per
 // (pivot, bin) it sums Q = sum_j (w_j x_j)^2 in FP64, forms v_p Q / W^2 (v_p Q for raw
@@ -59,6 +62,7 @@ struct MultArgs {
     uint64_t *pair_total;
     const double *pv;             // SELF: index-order pivot products w_p x_p
     double *self_part;            // SELF: [waves of the launch][nb] sums of v_p Q / W^2
+    double px0, py0, psx;         // PLANAR: plane origin and cell-coordinate scale
     int nblocks;
 };
 
@@ -74,7 +78,7 @@ constexpr int mult_waves_per_eu()
     return M <= 10 ? Z3_MULT_WAVES_PER_EU : (M <= 13 ? 3 : 2);
 }
 
-template <int M, bool MIXED, bool IDS, bool SELF>
+template <int M, bool MIXED, bool IDS, bool SELF, bool PLANAR>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(mult_waves_per_eu<M>())))
 void k_multipoles(MultArgs a)
 {
@@ -92,23 +96,33 @@ void k_multipoles(MultArgs a)
     const int64_t pp = valid ? p : a.p1 - 1;  // idle lanes shadow the last pivot
 
     const double xp = a.px[pp], yp = a.py[pp], zp = a.pz[pp];
-    const double sinth = sqrt(xp * xp + yp * yp);
-    const double th = atan2(sinth, zp);
-    double ph = atan2(yp, xp);
-    if (ph < 0.0) ph += kTwoPi;
-    double sh, ch;
-    sincos(0.5 * th, &sh, &ch);
-    const float inv_sp = sinth > 0.0 ? (float)(1.0 / sinth) : INFINITY;
-    const float phf = (float)ph;
-    // local north and east
-    double nx = -zp * xp, ny = -zp * yp, nz = 1.0 - zp * zp;
-    double nn = sqrt(nx * nx + ny * ny + nz * nz);
-    if (nn < 1e-12) {
-        nx = 1.0 - xp * xp; ny = -xp * yp; nz = -xp * zp;
-        nn = sqrt(nx * nx + ny * ny + nz * nz);
+    double th, sh = 0.0, ch = 0.0, phd = 0.0;
+    float inv_sp = 0.0f, phf = 0.0f;
+    double nx, ny, nz, ex, ey, ez;
+    if constexpr (PLANAR) {
+        // plane: strips of y, cells of x; angles from +y ("north") towards +x ("east")
+        th = yp - a.py0;
+        phd = (xp - a.px0) * a.psx;
+        nx = 0.0; ny = 1.0; nz = 0.0;
+        ex = 1.0; ey = 0.0; ez = 0.0;
+    } else {
+        const double sinth = sqrt(xp * xp + yp * yp);
+        th = atan2(sinth, zp);
+        double ph = atan2(yp, xp);
+        if (ph < 0.0) ph += kTwoPi;
+        sincos(0.5 * th, &sh, &ch);
+        inv_sp = sinth > 0.0 ? (float)(1.0 / sinth) : INFINITY;
+        phf = (float)ph;
+        // local north and east
+        nx = -zp * xp; ny = -zp * yp; nz = 1.0 - zp * zp;
+        double nn = sqrt(nx * nx + ny * ny + nz * nz);
+        if (nn < 1e-12) {
+            nx = 1.0 - xp * xp; ny = -xp * yp; nz = -xp * zp;
+            nn = sqrt(nx * nx + ny * ny + nz * nz);
+        }
+        nx /= nn; ny /= nn; nz /= nn;
+        ex = ny * zp - nz * yp; ey = nz * xp - nx * zp; ez = nx * yp - ny * xp;
     }
-    nx /= nn; ny /= nn; nz /= nn;
-    const double ex = ny * zp - nz * yp, ey = nz * xp - nx * zp, ez = nx * yp - ny * xp;
     // the mixed path's frame, rounded once
     const float nxf = (float)nx, nyf = (float)ny, nzf = (float)nz;
     const float exf = (float)ex, eyf = (float)ey, ezf = (float)ez;
@@ -140,7 +154,10 @@ void k_multipoles(MultArgs a)
             const Band bd = a.bands[k];
             if (bd.npts == 0) continue;
             int s0, l0, s1, l1;
-            band_window(bd, a.cell_start, th, sh, ch, inv_sp, phf, hav_out, hav_in, s0, l0, s1, l1);
+            if constexpr (PLANAR)
+                planar_window(bd, a.cell_start, th, phd, a.psx, hav_out, hav_in, s0, l0, s1, l1);
+            else
+                band_window(bd, a.cell_start, th, sh, ch, inv_sp, phf, hav_out, hav_in, s0, l0, s1, l1);
             const int base = 2 * bd.pt_start;
             // the band's doubled records (wave-uniform base), walked by byte offset
             const __amdgpu_buffer_rsrc_t rband = buffer_view(a.rec + base, (uint32_t)bd.npts * 64u);
@@ -534,19 +551,26 @@ z3_status launch_multipoles_maps(const z3_index_s *idx, int group, int m_max, in
     return st;
 }
 
-template <int M>
-static void launch_m(bool mixed, bool ids, bool self, const MultArgs &a, hipStream_t s)
+template <int M, bool PLANAR>
+static void launch_mp(bool mixed, bool ids, bool self, const MultArgs &a, hipStream_t s)
 {
     dim3 grid(a.nblocks), block(kBlock);
     if (mixed) {
-        if (ids) hipLaunchKernelGGL((k_multipoles<M, true, true, false>), grid, block, 0, s, a);
-        else if (self) hipLaunchKernelGGL((k_multipoles<M, true, false, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_multipoles<M, true, false, false>), grid, block, 0, s, a);
+        if (ids) hipLaunchKernelGGL((k_multipoles<M, true, true, false, PLANAR>), grid, block, 0, s, a);
+        else if (self) hipLaunchKernelGGL((k_multipoles<M, true, false, true, PLANAR>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_multipoles<M, true, false, false, PLANAR>), grid, block, 0, s, a);
     } else {
-        if (ids) hipLaunchKernelGGL((k_multipoles<M, false, true, false>), grid, block, 0, s, a);
-        else if (self) hipLaunchKernelGGL((k_multipoles<M, false, false, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_multipoles<M, false, false, false>), grid, block, 0, s, a);
+        if (ids) hipLaunchKernelGGL((k_multipoles<M, false, true, false, PLANAR>), grid, block, 0, s, a);
+        else if (self) hipLaunchKernelGGL((k_multipoles<M, false, false, true, PLANAR>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_multipoles<M, false, false, false, PLANAR>), grid, block, 0, s, a);
     }
+}
+
+template <int M>
+static void launch_m(bool planar, bool mixed, bool ids, bool self, const MultArgs &a, hipStream_t s)
+{
+    if (planar) launch_mp<M, true>(mixed, ids, self, a, s);
+    else launch_mp<M, false>(mixed, ids, self, a, s);
 }
 
 z3_status launch_multipoles(const z3_index_s *idx, Pivots piv, int map, int m_max, int prec, int norm,
@@ -574,12 +598,13 @@ z3_status launch_multipoles(const z3_index_s *idx, Pivots piv, int map, int m_ma
     a.A = A; a.ldA = ldA;
     a.W = W; a.counts = counts; a.idhash = idhash; a.pair_total = pair_total;
     a.pv = self_pv; a.self_part = self_part;
+    a.px0 = idx->plane_x0; a.py0 = idx->plane_y0; a.psx = idx->plane_sx;
     a.nblocks = (int)nblk;
     const bool mixed = prec == Z3_PREC_MIXED, ids = idhash != nullptr, self = self_part != nullptr;
     hipEvent_t ev0;
     profile_begin(s, &ev0);
     switch (m_max) {
-#define Z3_CASE(MM) case MM: launch_m<MM>(mixed, ids, self, a, s); break;
+#define Z3_CASE(MM) case MM: launch_m<MM>(idx->planar, mixed, ids, self, a, s); break;
         Z3_CASE(0) Z3_CASE(1) Z3_CASE(2) Z3_CASE(3) Z3_CASE(4) Z3_CASE(5) Z3_CASE(6) Z3_CASE(7)
         Z3_CASE(8) Z3_CASE(9) Z3_CASE(10) Z3_CASE(11) Z3_CASE(12) Z3_CASE(13) Z3_CASE(14)
         Z3_CASE(15) Z3_CASE(16)

@@ -36,19 +36,22 @@ def _dev(t, dtype=torch.float64):
 
 
 class Index:
-    """Sky-cell index of a catalogue (z3_build_index)."""
+    """Sky-cell index of a catalogue (z3_build_index); with planar=True, positions [2, n] on
+    a plane and squared-distance edges (z3_build_index_planar)."""
 
-    def __init__(self, xyz, edges_chord2, weights=None, cell_size: float = 0.0):
+    def __init__(self, xyz, edges_chord2, weights=None, cell_size: float = 0.0, planar: bool = False):
         xyz = _dev(xyz)
-        if xyz.dim() != 2 or xyz.shape[0] != 3:
-            raise ValueError("xyz must be [3, n]")
+        if xyz.dim() != 2 or xyz.shape[0] != (2 if planar else 3):
+            raise ValueError("positions must be [2, n] on a plane" if planar else "xyz must be [3, n]")
         self.n = int(xyz.shape[1])
+        self.planar = planar
         self.edges = np.ascontiguousarray(edges_chord2, dtype=np.float64)
         self.nbins = len(self.edges) - 1
         self._w = None if weights is None else _dev(weights)
         h = ctypes.c_void_p()
-        _lib.call("z3_build_index", self.n, _ptr(xyz), _ptr(self._w), self.nbins,
-                  self.edges.ctypes.data_as(ctypes.c_void_p), float(cell_size), _stream(), ctypes.byref(h))
+        _lib.call("z3_build_index_planar" if planar else "z3_build_index", self.n, _ptr(xyz), _ptr(self._w),
+                  self.nbins, self.edges.ctypes.data_as(ctypes.c_void_p), float(cell_size), _stream(),
+                  ctypes.byref(h))
         self._h = h
         self.nmaps = 0
         self._values = None

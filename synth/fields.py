@@ -31,6 +31,16 @@ def cap_points(n: int, radius_deg: float = 10.0, seed: int = 0, device="cpu") ->
     return torch.from_numpy(xyz).to(device)
 
 
+def plane_points(side: int, jitter: float = 0.25, seed: int = 0, device="cpu") -> torch.Tensor:
+    """side x side points on a plane, [2, n]: the unit grid (i, j) moved by a seeded uniform
+    offset in [-jitter, jitter] per coordinate (a pixelised flat map), row-major in j then i."""
+    rng = np.random.default_rng(3_000_000 + seed)
+    i, j = np.meshgrid(np.arange(side, dtype=np.float64), np.arange(side, dtype=np.float64), indexing="xy")
+    xy = np.stack([i.ravel(), j.ravel()])
+    xy += rng.uniform(-jitter, jitter, size=xy.shape)
+    return torch.from_numpy(xy).to(device)
+
+
 def field_params(nmodes: int, kappa_lo: float, kappa_hi: float, seed: int):
     rng = np.random.default_rng(seed)
     amp = rng.normal(0.0, 0.3, nmodes)

@@ -1,0 +1,161 @@
+"""GPU parity for pivots on a plane (z3_build_index_planar).
+
+The estimator is the same on any smooth manifold (the paper's description of its code):
+on a plane the pair test is d2 = dx^2 + dy^2 against squared-distance edges and the angle
+runs from +y towards +x.  Against the planar FP64 oracle (pinned by the planar triplet sum
+and the three-point golden values): pair counts and per-bin weights exact, multipoles
+within 1e-11, zeta_m within 1e-10 (FP64 path) and 1e-6 (mixed path, lognormal field).
+"""
+
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2408_16847_amd as z3
+from paper_2408_16847_amd import _lib
+from oracle import ref
+from synth import lognormal_field, plane_points
+from tests import gpu_helpers as G
+from tests import pins
+
+pytestmark = pytest.mark.gpu
+
+
+def build_plane(xy, x, edges, w=None, cell_size=0.0):
+    xy_d = torch.from_numpy(np.ascontiguousarray(xy)).cuda()
+    w_d = None if w is None else torch.from_numpy(np.ascontiguousarray(w, dtype=np.float64)).cuda()
+    idx = z3.Index(xy_d, edges, weights=w_d, cell_size=cell_size, planar=True)
+    idx.set_values(torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda())
+    torch.cuda.synchronize()
+    return idx
+
+
+@pytest.fixture(scope="module")
+def plane_map():
+    # a 90 x 90 jittered unit grid with a lognormal field, bins 0.8-12 units (log)
+    xy = plane_points(90, seed=4).numpy()
+    xyz = torch.from_numpy(np.concatenate([xy, np.zeros((1, xy.shape[1]))]))
+    x = lognormal_field(xyz, 64, 0.2, 2.0, 5).numpy()
+    E = np.geomspace(0.8, 12.0, 9) ** 2
+    return xy, x, E
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("mixed", 1e-6)])
+def test_three_point_on_the_plane(prec, tol):
+    G.say("case: planar three-point", prec)
+    xy, E, x = pins.three_point_planar()
+    idx = build_plane(xy, x, E)
+    z, pairs = z3.estimate(idx, 4, prec=prec)
+    gold_pairs, gold = pins.golden_three_point()
+    assert pairs == gold_pairs
+    assert np.abs(z - gold).max() < tol
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("mixed", 1e-6)])
+def test_plane_map_zeta(plane_map, prec, tol):
+    xy, x, E = plane_map
+    G.say("case: planar map", prec)
+    w = np.ones(xy.shape[1])
+    idx = build_plane(xy, x, E)
+    z, pairs = z3.estimate(idx, 8, prec=prec)
+    zo, po = ref.estimate_planar(xy, xy, w, x, E, 8, w, x)
+    assert pairs == po
+    e = G.err_m(z, zo)
+    G.say("err_m", prec, e)
+    assert e.max() <= tol, e
+    assert np.array_equal(z, np.conj(np.swapaxes(z, 1, 2)))
+
+
+def test_plane_per_pivot_multipoles_and_counts(plane_map):
+    xy, x, E = plane_map
+    G.say("case: planar per-pivot multipoles")
+    w = np.ones(xy.shape[1])
+    idx = build_plane(xy, x, E)
+    pm = G.perm(idx)
+    n = xy.shape[1]
+    for p0, p1 in ((0, 256), (3001, 3333), (n - 200, n)):
+        out = z3.accumulate(idx, 8, p0=p0, p1=p1, norm="none", want_w=True, want_counts=True)
+        torch.cuda.synchronize()
+        A = out["A"].cpu().numpy()  # [m+1, 2, nb, P]: (re, im) of a_{m,b}
+        a = np.transpose(A[:, 0] + 1j * A[:, 1], (2, 0, 1))
+        W = out["W"].cpu().numpy().T
+        N = out["counts"].cpu().numpy().T
+        sel = pm[p0:p1]
+        ao, Wo, No = ref.multipoles_planar(xy[:, sel], xy, w, x, E, 8)
+        assert np.array_equal(N, No)
+        assert np.array_equal(W, Wo)
+        scale = np.abs(ao).max(axis=1, keepdims=True) + 1e-300
+        assert (np.abs(a - ao) / scale).max() < 1e-11
+
+
+def test_plane_weighted_random_points_and_ranges():
+    G.say("case: planar weighted random points")
+    xy, w, x = pins.random_square(3000, 30.0, 51)
+    E = pins.planar_edges(6, lo=0.3, hi=4.0, log=True)
+    idx = build_plane(xy, x, E, w=w)
+    zo, po = ref.estimate_planar(xy, xy, w, x, E, 6, w, x)
+    z, pairs = z3.estimate(idx, 6)
+    assert pairs == po
+    assert G.err_m(z, zo).max() <= 1e-10
+    zr = torch.zeros((7, 6, 6, 2), dtype=torch.float64, device="cuda")
+    sw = torch.zeros(1, dtype=torch.float64, device="cuda")
+    pt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    for p0, p1 in ((0, 100), (100, 2222), (2222, 3000)):
+        z3.estimate_raw(idx, 6, "fp64", p0, p1, zeta=zr, pair_total=pt, sum_w=sw)
+    torch.cuda.synchronize()
+    zc = zr.cpu().numpy() / sw.item()
+    assert int(pt.item()) == po
+    assert G.err_m(zc[..., 0] + 1j * zc[..., 1], zo).max() <= 1e-10
+
+
+def test_plane_integer_grid_edge_ties():
+    # integer coordinates and integer squared edges: many pairs sit exactly on an edge
+    # (d2 exact in FP64), and each belongs to the bin that starts there
+    G.say("case: planar integer grid ties")
+    i, j = np.meshgrid(np.arange(40.0), np.arange(30.0), indexing="xy")
+    xy = np.stack([i.ravel(), j.ravel()])
+    x = np.random.default_rng(61).normal(size=xy.shape[1])
+    E = np.array([1.0, 2.0, 4.0, 5.0, 9.0, 10.0, 16.0])
+    idx = build_plane(xy, x, E, cell_size=1.0)
+    w = np.ones(xy.shape[1])
+    z, pairs = z3.estimate(idx, 4)
+    zo, po = ref.estimate_planar(xy, xy, w, x, E, 4, w, x)
+    assert pairs == po
+    assert G.err_m(z, zo).max() <= 1e-10
+
+
+def test_plane_sky_only_entry_points_rejected():
+    G.say("case: planar unsupported entry points")
+    xy, E, x = pins.three_point_planar()
+    idx = build_plane(xy, x, E)
+    G_ = torch.zeros((5, 3, 3, 2), dtype=torch.float64, device="cuda")
+    grad = torch.zeros(3, dtype=torch.float64, device="cuda")
+    with pytest.raises(_lib.Zeta3Error) as ei:
+        _lib.call("z3_adjoint", idx.handle, 0, 4, 0, 3, ctypes.c_void_p(G_.data_ptr()), 1.0,
+                  ctypes.c_void_p(grad.data_ptr()), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert ei.value.status == 4
+    torch.cuda.synchronize()
+    assert torch.count_nonzero(grad).item() == 0
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_plane_self_pairs_removed_and_three_fields(plane_map, prec):
+    xy, x, E = plane_map
+    G.say("case: planar self pairs and three fields", prec)
+    w = np.ones(xy.shape[1])
+    f = np.stack([x, x + 0.5 * np.roll(x, 7), x - 0.3 * np.roll(x, 13)])
+    idx = build_plane(xy, f, E)
+    zf, _ = ref.estimate(xy, xy, w, x, E, 6, w, x, planar=True)
+    z, pairs = z3.estimate(idx, 6, prec=prec, self_pairs=False)
+    zo, po = ref.estimate(xy, xy, w, x, E, 6, w, x, self_pairs=False, planar=True)
+    assert pairs == po
+    # FP64 against its own maximum; mixed against the with-self-terms scale (as on the sphere)
+    scale = zo if prec == "fp64" else zf
+    d = np.abs(z - zo).reshape(7, -1).max(1) / np.abs(scale).reshape(7, -1).max(1)
+    assert d.max() <= (1e-10 if prec == "fp64" else 1e-6), d
+    zc, pc = z3.estimate_cross(idx, (0, 1, 2), 6, prec=prec, cyclic=True)
+    zco, pco = ref.estimate_cross(xy, xy, w, tuple(f), E, 6, w, tuple(f), cyclic=True, planar=True)
+    assert pc == pco
+    assert G.err_m(zc, zco).max() <= (1e-10 if prec == "fp64" else 1e-6)

@@ -105,6 +105,24 @@ def test_planar_three_point_golden():
     pins.check_three_point_planar()
 
 
+def test_planar_self_pairs_and_fields_brute():
+    # the planar options follow the same pins as on the sphere: k != j and three fields
+    xy, w, x = pins.random_square(200, 6.0, 37)
+    y = np.random.default_rng(38).normal(size=200)
+    E = pins.planar_edges(5)
+    z, p = ref.estimate(xy, xy, w, x, E, 4, w, x, self_pairs=False, planar=True)
+    zs, _ = ref.estimate_planar(xy, xy, w, x, E, 4, w, x)
+    zb, pb = brute.zeta_brute_planar(xy, xy, w, x, E, 4, w, x)
+    assert p == pb and pins.rel_err(zs, zb) < 1e-12
+    zbn, _ = brute.zeta_brute_planar(xy, xy, w, x, E, 4, w, x, self_pairs=False)
+    assert pins.rel_err(z, zbn) < 1e-12
+    zc, _ = ref.estimate_cross(xy, xy, w, (x, x, x), E, 4, w, (x, x, x), planar=True)
+    assert pins.rel_err(zc, zs) < 1e-13
+    zc2, _ = ref.estimate_cross(xy, xy, w, (x, y, x), E, 4, w, (x, y, x), planar=True)
+    zc3, _ = ref.estimate_cross(xy, xy, w, (x, x, y), E, 4, w, (x, x, y), planar=True)
+    assert pins.rel_err(zc3, np.conj(np.swapaxes(zc2, 1, 2))) < 1e-13
+
+
 def test_planar_rotation_and_mirror():
     # a rotation of the plane keeps zeta; a mirror keeps Re and flips Im (where the pair
     # counts agree, i.e. no pair moved across a bin edge by rounding)
