@@ -225,8 +225,9 @@ z3_status z3_estimate_ex(z3_index idx, int map, int m_max, int prec, unsigned fl
  * or the sum of that term over the cyclic permutations (A;B,C) + (B;C,A) + (C;A,B)
  * (cyclic = 1).  Unnormalised like z3_estimate (divide by sum_p w_p, z3_finalize); the
  * result is not Hermitian unless B = C.  map_a, map_b, map_c in [0, nmaps); they may repeat.
- * The multipoles of each distinct field needed are computed once per pivot chunk (one
- * search pass per field, the chunk shrinks accordingly); pair_total += pairs counted once.
+ * The multipoles of each distinct field needed are computed once per pivot chunk: on the
+ * FP64 path of a sky index, fields within one group of 4 attached maps (maps 4g..4g+3) share
+ * one search pass; otherwise one search pass per field.  pair_total += pairs counted once.
  */
 z3_status z3_estimate_cross(z3_index idx, int map_a, int map_b, int map_c, int cyclic, int m_max,
                             int prec, int64_t p0, int64_t p1, double *zeta, uint64_t *pair_total,

@@ -517,7 +517,18 @@ Z3_API z3_status z3_estimate_cross(z3_index idx, int map_a, int map_b, int map_c
         if (k == nneed) need[nneed++] = f;
         slot_of[t] = k;
     }
-    int64_t chunk = chunk_pivots(idx, m_max, prec) / nneed;
+    // FP64 fields of one group of kMapGroup attached maps (sky catalogues): one pass of the
+    // register-tiled many-map kernel computes the group's multipoles with shared pair
+    // geometry (Nside 2048, three fields: 15.1 s against 18.0 s for three one-map passes).
+    // That kernel forms the harmonics in FP64, so the mixed path keeps one one-map pass
+    // per distinct field (12.7 s against 15.0 s)
+    const int grp = need[0] / kMapGroup;
+    bool grouped = prec == Z3_PREC_FP64 && !idx->planar && idx->ngroups > grp && nneed > 1;
+    for (int k = 0; k < nneed; ++k) grouped = grouped && need[k] / kMapGroup == grp;
+    if (grouped)
+        for (int t = 0; t < 3; ++t) slot_of[t] = fa[t] % kMapGroup;
+    const int nslots = grouped ? kMapGroup : nneed;
+    int64_t chunk = chunk_pivots(idx, m_max, prec) / nslots;
     chunk = (chunk / kBlock) * kBlock;
     if (chunk < 16 * kBlock) chunk = 16 * kBlock;
     if (chunk > p1 - p0) chunk = ((p1 - p0 + kBlock - 1) / kBlock) * kBlock;
@@ -525,11 +536,13 @@ Z3_API z3_status z3_estimate_cross(z3_index idx, int map_a, int map_b, int map_c
     const size_t slot_elems = (size_t)chunk * (size_t)(m_max + 1) * 2 * idx->nbins;
     const size_t pbytes = cross_partial_bytes(chunk, m_max, idx->nbins);
     void *wa = nullptr, *wp = nullptr;
-    if ((st = scratch_alloc(&wa, slot_elems * elem * nneed, s)) != Z3_OK) return st;
+    if ((st = scratch_alloc(&wa, slot_elems * elem * nslots, s)) != Z3_OK) return st;
     st = scratch_alloc(&wp, pbytes, s);
     for (int64_t c0 = p0; c0 < p1 && st == Z3_OK; c0 += chunk) {
         const int64_t c1 = c0 + chunk < p1 ? c0 + chunk : p1;
-        for (int k = 0; k < nneed && st == Z3_OK; ++k)
+        if (grouped)
+            st = launch_multipoles_maps(idx, grp, m_max, prec, c0, c1, wa, c1 - c0, slot_elems, nullptr, pair_total, s);
+        for (int k = 0; k < nneed && st == Z3_OK && !grouped; ++k)
             st = launch_multipoles(idx, Pivots{idx->d_x, idx->d_y, idx->d_z}, need[k], m_max, prec, Z3_NORM_BIN, c0,
                                    c1, static_cast<char *>(wa) + (size_t)k * slot_elems * elem, c1 - c0, nullptr,
                                    nullptr, nullptr, k == 0 ? pair_total : nullptr, s);

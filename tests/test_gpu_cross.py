@@ -100,3 +100,23 @@ def test_cross_rejects_a_missing_map():
     assert ei.value.status == 1
     torch.cuda.synchronize()
     assert torch.count_nonzero(zeta).item() == 0
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("mixed", 1e-6)])
+def test_cross_fields_in_different_map_groups(cap3, prec, tol):
+    # maps 0, 4 and 5 of six attached maps: not one group of four, so each field's
+    # multipoles come from its own one-map pass (maps 0, 1, 2 share one many-map pass)
+    cfg, xyz, f = cap3
+    G.say("case: cap20k fields in different map groups", prec)
+    E = cfg.edges_chord2()
+    w = np.ones(xyz.shape[1])
+    six = np.concatenate([f, f[::-1]])  # maps 3, 4, 5 = fields 2, 1, 0
+    idx = G.build(xyz, six, E)
+    z, pairs = z3.estimate_cross(idx, (0, 4, 5), cfg.m_max, prec=prec, cyclic=True)
+    fo = (f[0], f[1], f[0])
+    zo, po = cpu.estimate_cross(xyz, xyz, w, fo, E, cfg.m_max, w, fo, cyclic=True)
+    assert pairs == po
+    assert G.err_m(z, zo).max() <= tol
+    zg, pg = z3.estimate_cross(idx, (0, 1, 0), cfg.m_max, prec=prec, cyclic=True)
+    assert pg == pairs
+    assert G.err_m(zg, zo).max() <= tol
