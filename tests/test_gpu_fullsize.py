@@ -1,5 +1,6 @@
 """GPU parity at the full workload sizes the bench times (HEALPix Nside 2048 and 4096, the
-approximate Nside 4096 search, 64 maps at Nside 512), on sampled pivots the oracle computes
+approximate Nside 4096 search, 64 maps at Nside 512, Nside 2048 without the k = j terms,
+the flat plane3m map), on sampled pivots the oracle computes
 one by one: ragged pivot ranges
 at the north pole, across a band boundary near the equator (the 0 / 2 pi wrap of the
 longitude windows) and at the south pole.  Per-pivot pair counts, bin weights and neighbour
@@ -49,20 +50,26 @@ def _check_multipoles(idx, xyz_h, x_h, E, M, p0, p1, perm):
         assert err < tol, (prec, err)
 
 
-def _check_zeta(idx, xyz_h, x_h, E, M, ranges, perm):
+def _check_zeta(idx, xyz_h, x_h, E, M, ranges, perm, self_pairs=True):
     pm = np.concatenate([perm[p0:p1] for p0, p1 in ranges])
     w = np.ones(xyz_h.shape[1])
-    zo, po = cpu.estimate(xyz_h[:, pm], xyz_h, w, x_h, E, M, np.ones(len(pm)), x_h[pm])
+    zo, po = cpu.estimate(xyz_h[:, pm], xyz_h, w, x_h, E, M, np.ones(len(pm)), x_h[pm], self_pairs=self_pairs)
+    # without the k = j terms the mixed path is held to 1e-6 of the estimate's scale with
+    # them (the absolute error of X conj X does not shrink with the subtracted terms)
+    zs = zo if self_pairs else cpu.estimate(xyz_h[:, pm], xyz_h, w, x_h, E, M, np.ones(len(pm)), x_h[pm])[0]
     for prec, tol in (("fp64", 1e-10), ("mixed", 1e-6)):
         zeta = torch.zeros((M + 1, idx.nbins, idx.nbins, 2), dtype=torch.float64, device="cuda")
         pairs = torch.zeros(1, dtype=torch.int64, device="cuda")
         for p0, p1 in ranges:
-            z3.estimate_raw(idx, M, prec, p0, p1, zeta=zeta, pair_total=pairs)
+            z3.estimate_raw(idx, M, prec, p0, p1, zeta=zeta, pair_total=pairs, self_pairs=self_pairs)
         torch.cuda.synchronize()
         zg = zeta.cpu().numpy() / len(pm)
+        zg = zg[..., 0] + 1j * zg[..., 1]
         assert int(pairs.item()) == po
-        e = G.err_m(zg[..., 0] + 1j * zg[..., 1], zo).max()
-        G.say("  zeta", prec, len(pm), "pivots, err", e)
+        ref_scale = zo if prec == "fp64" else zs
+        d = np.abs(zg - zo).reshape(M + 1, -1).max(1) / np.abs(ref_scale).reshape(M + 1, -1).max(1)
+        e = G.err_m(zg, zo).max() if self_pairs else d.max()
+        G.say("  zeta", prec, "self pairs" if self_pairs else "no self pairs", len(pm), "pivots, err", e)
         assert e < tol, (prec, e)
 
 
@@ -82,6 +89,69 @@ def test_fullsize_healpix_sampled_pivots(name):
     for p0, p1 in ranges:
         _check_multipoles(idx, xyz_h, x_h, E, cfg.m_max, p0, p1, perm)
     _check_zeta(idx, xyz_h, x_h, E, cfg.m_max, ranges, perm)
+    if name == "nside2048":
+        _check_zeta(idx, xyz_h, x_h, E, cfg.m_max, ranges, perm, self_pairs=False)
+    idx.free()
+
+
+def test_fullsize_plane3m_sampled_pivots():
+    """The flat workload (1774 x 1774 jittered grid, 15 log bins 1-40 units, m <= 10):
+    ragged pivot ranges at the first strips, the middle and the last strips, against the
+    planar oracle over all 3.1e6 neighbours."""
+    from oracle import ref
+    cfg = CONFIGS["plane3m"]
+    G.say("case: full size plane3m")
+    xy = make_positions(cfg, device="cuda")
+    x = make_values(cfg, xy, seed=0)
+    E = cfg.edges_chord2()
+    idx = z3.Index(xy, E, planar=True)
+    idx.set_values(x)
+    perm = idx.perm().cpu().numpy()
+    xy_h, x_h = xy.cpu().numpy(), x.cpu().numpy()
+    n = len(perm)
+    ranges = [(0, 150), (n // 2 - 77, n // 2 + 123), (n - 170, n)]
+    w = np.ones(n)
+    M = cfg.m_max
+    rmax = np.sqrt(E[-1]) * (1 + 1e-6) + 1e-9
+
+    def near(piv_idx):
+        # neighbours inside the pivots' bounding box grown by the largest radius: every point
+        # outside it is farther than the last edge from every pivot, so the oracle's sums
+        # over this subset equal those over the whole map
+        lo = xy_h[:, piv_idx].min(1) - rmax
+        hi = xy_h[:, piv_idx].max(1) + rmax
+        return np.nonzero(np.all((xy_h >= lo[:, None]) & (xy_h <= hi[:, None]), axis=0))[0]
+
+    for p0, p1 in ranges:
+        sel = near(perm[p0:p1])
+        ao, Wo, No = ref.multipoles_planar(xy_h[:, perm[p0:p1]], xy_h[:, sel], w[sel], x_h[sel], E, M)
+        scale = np.abs(ao).max(axis=1, keepdims=True) + 1e-300
+        # mixed: 3e-5 rather than the sky's 1e-5: on a (jittered) grid many of the few pairs of
+        # an inner bin lie near phi = 0 or pi, where one pair's FP32 harmonics err by up to
+        # ~m^2 x 6e-8, and a bin of a few such pairs can partly cancel
+        for prec, tol in (("fp64", 1e-11), ("mixed", 3e-5)):
+            out = z3.accumulate(idx, M, p0, p1, prec=prec, norm="none", want_w=True, want_counts=True)
+            A = out["A"].double().cpu().numpy()
+            a = np.transpose(A[:, 0] + 1j * A[:, 1], (2, 0, 1))
+            assert np.array_equal(out["counts"].cpu().numpy().T, No), prec
+            assert np.array_equal(out["W"].cpu().numpy().T, Wo), prec
+            err = (np.abs(a - ao) / scale).max()
+            G.say("  plane multipoles", prec, p0, p1, "err", err)
+            assert err < tol, (prec, err)
+    pm = np.concatenate([perm[p0:p1] for p0, p1 in ranges])
+    sel = np.unique(np.concatenate([near(perm[p0:p1]) for p0, p1 in ranges]))
+    zo, po = ref.estimate_planar(xy_h[:, pm], xy_h[:, sel], w[sel], x_h[sel], E, M, np.ones(len(pm)), x_h[pm])
+    for prec, tol in (("fp64", 1e-10), ("mixed", 1e-6)):
+        zeta = torch.zeros((M + 1, idx.nbins, idx.nbins, 2), dtype=torch.float64, device="cuda")
+        pairs = torch.zeros(1, dtype=torch.int64, device="cuda")
+        for p0, p1 in ranges:
+            z3.estimate_raw(idx, M, prec, p0, p1, zeta=zeta, pair_total=pairs)
+        torch.cuda.synchronize()
+        zg = zeta.cpu().numpy() / len(pm)
+        assert int(pairs.item()) == po
+        e = G.err_m(zg[..., 0] + 1j * zg[..., 1], zo).max()
+        G.say("  plane zeta", prec, len(pm), "pivots, err", e)
+        assert e < tol, (prec, e)
     idx.free()
 
 
