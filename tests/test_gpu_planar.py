@@ -159,3 +159,30 @@ def test_plane_self_pairs_removed_and_three_fields(plane_map, prec):
     zco, pco = ref.estimate_cross(xy, xy, w, tuple(f), E, 6, w, tuple(f), cyclic=True, planar=True)
     assert pc == pco
     assert G.err_m(zc, zco).max() <= (1e-10 if prec == "fp64" else 1e-6)
+
+
+def test_plane_degenerate_catalogues():
+    G.say("case: planar degenerate catalogues")
+    E = np.array([0.5, 1.0, 4.0, 9.0])
+    rng = np.random.default_rng(71)
+    cases = {
+        "vertical line": np.stack([np.full(300, 2.5), np.sort(rng.uniform(0, 20, 300))]),
+        "horizontal line": np.stack([rng.uniform(-10, 10, 300), np.full(300, -3.0)]),
+        "one point": np.array([[1.0], [2.0]]),
+        "coincident points": np.full((2, 50), 7.0),
+        "far from the origin": rng.uniform(0, 8, (2, 400)) + 1e6,
+    }
+    for name, xy in cases.items():
+        x = rng.normal(size=xy.shape[1])
+        w = np.ones(xy.shape[1])
+        idx = build_plane(xy, x, E)
+        z, pairs = z3.estimate(idx, 3)
+        zo, po = ref.estimate_planar(xy, xy, w, x, E, 3, w, x)
+        assert pairs == po, name
+        assert G.err_m(z, zo).max() <= 1e-10, name
+        idx.free()
+    # an empty catalogue builds and estimates nothing
+    idx = z3.Index(torch.zeros((2, 0), dtype=torch.float64, device="cuda"), E, planar=True)
+    idx.set_values(torch.zeros((1, 0), dtype=torch.float64, device="cuda"))
+    z, pairs = z3.estimate(idx, 3)
+    assert pairs == 0 and not np.any(z)
