@@ -15,7 +15,9 @@ build.py        compiles oracle_cpu.c with gcc (-O2 -ffp-contract=off -fopenmp)
 
 What the oracle computes (paper: harmonic-decomposition section, eqs. Xmdef,
 zetaisohom, ubEstimator, eq_zeta_harmonic; binned estimator eqs. Xm.binned, zetamEst,
-Ym/Zm.binned, zetamEst2), with the readings listed in the design doc:
+Ym/Zm.binned, zetamEst2); where the paper is silent or inconsistent, the steps below
+state the reading taken (exponent sign exp(-i m phi), per-bin normaliser W_{p,b},
+half-open chord-squared bins, bearing from local north through east):
 
 1. pair geometry: delta = r_j - r_p, d2 = (dx*dx + dy*dy) + dz*dz in FP64, every
    operation rounded separately (no fused multiply-add);  pair kept iff

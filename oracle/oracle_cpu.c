@@ -6,7 +6,8 @@
  *
  * Computes exactly what oracle/ref.py computes (binned estimator of the paper's
  * "3PCF binned estimator" subsection: eqs. Xm.binned, Ym/Zm.binned, zetamEst,
- * zetamEst2, with the readings in the design doc), for catalogues too large for NumPy:
+ * zetamEst2, with the readings stated in oracle/__init__.py), for catalogues too
+ * large for NumPy:
  *
  *   d2 = (dx*dx + dy*dy) + dz*dz   (FP64, built with -ffp-contract=off: no FMA)
  *   pair kept iff E_0 <= d2 < E_nb, bin b: E_b <= d2 < E_{b+1}
