@@ -153,7 +153,7 @@ def main():
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the estimator's pivot sum would shard over GPUs with one "
-              "final all-reduce of zeta, which this build does not run; use --gpus 1", file=sys.stderr)
+              "final all-reduce of zeta, which this program does not run; use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -51,7 +51,7 @@ typedef enum {
     Z3_ERR_INVALID_ARG = 1,   /* bad sizes, NULL pointers, unsorted edges, ...         */
     Z3_ERR_OUT_OF_MEMORY = 2, /* device allocation failed                               */
     Z3_ERR_HIP = 3,           /* a HIP runtime call or a kernel failed                  */
-    Z3_ERR_UNSUPPORTED = 4,   /* valid request outside what this build implements       */
+    Z3_ERR_UNSUPPORTED = 4,   /* valid request outside what this library implements     */
     Z3_ERR_OVERFLOW = 5       /* catalogue or pair count beyond the supported range     */
 } z3_status;
 
