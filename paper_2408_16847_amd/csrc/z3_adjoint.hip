@@ -180,7 +180,21 @@ struct ScatterArgs {
     int nblocks;
     // map blockIdx.y: pv and grad advance by n_stride, rec by rec_stride, D by d_stride
     size_t n_stride, rec_stride, d_stride;
+    double px0, py0, psx;         // plane: origin and cell-coordinate scale
 };
+
+// Pivot on a plane: strip coordinate y - y0 in place of the colatitude, fixed frame
+// (angles from +y towards +x); the longitude fields are unused.
+__device__ __forceinline__ PivotFrame plane_frame(double xp, double yp, double zp, double y0)
+{
+    PivotFrame f;
+    f.xp = xp; f.yp = yp; f.zp = zp;
+    f.th = yp - y0;
+    f.sh = 0.0; f.ch = 0.0; f.inv_sp = 0.0f; f.phf = 0.0f;
+    f.nx = 0.0; f.ny = 1.0; f.nz = 0.0;
+    f.ex = 1.0; f.ey = 0.0; f.ez = 0.0;
+    return f;
+}
 
 // K maps per lane share each pair's geometry and harmonics; their D coefficients take
 // 2 (M + 1) K registers, so the occupancy target drops with K.
@@ -196,7 +210,7 @@ constexpr int adjoint_waves_per_eu()
 // maps.
 constexpr int kAggSlots = 1024;
 
-template <int M, int K>
+template <int M, int K, bool PLANAR = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(adjoint_waves_per_eu<M, K>())))
 void k_adjoint_scatter(ScatterArgs a)
 {
@@ -215,7 +229,9 @@ void k_adjoint_scatter(ScatterArgs a)
     const int64_t pp = valid ? p : a.p1 - 1;
     const size_t mp0 = (size_t)blockIdx.y * K;  // first map of this block
     a.rec += mp0 * a.rec_stride;  // positions (the same for every map)
-    const PivotFrame f = pivot_frame(a.px[pp], a.py[pp], a.pz[pp]);
+    const PivotFrame f = PLANAR ? plane_frame(a.px[pp], a.py[pp], a.pz[pp], a.py0)
+                                : pivot_frame(a.px[pp], a.py[pp], a.pz[pp]);
+    const double phd = PLANAR ? (a.px[pp] - a.px0) * a.psx : 0.0;
     double vp[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) vp[k] = valid ? a.scale * a.pv[(mp0 + k) * a.n_stride + pp] : 0.0;  // idle lanes add nothing
@@ -242,7 +258,10 @@ void k_adjoint_scatter(ScatterArgs a)
             const Band bd = a.bands[kb];
             if (bd.npts == 0) continue;
             int s0, l0, s1, l1;
-            band_window(bd, a.cell_start, f.th, f.sh, f.ch, f.inv_sp, f.phf, hav_out, hav_in, s0, l0, s1, l1);
+            if constexpr (PLANAR)
+                planar_window(bd, a.cell_start, f.th, phd, a.psx, hav_out, hav_in, s0, l0, s1, l1);
+            else
+                band_window(bd, a.cell_start, f.th, f.sh, f.ch, f.inv_sp, f.phf, hav_out, hav_in, s0, l0, s1, l1);
             const int base = 2 * bd.pt_start;
 #pragma unroll
             for (int seg = 0; seg < 2; ++seg) {
@@ -331,8 +350,12 @@ __global__ void k_grad_to_catalogue(int64_t n, const int *perm, const double *gs
 
 // Maps in pairs (geometry shared by two maps per lane), an odd last map alone.
 template <int M>
-static void launch_scatter_m(const ScatterArgs &a, int nm, hipStream_t s)
+static void launch_scatter_m(const ScatterArgs &a, int nm, bool planar, hipStream_t s)
 {
+    if (planar) {  // one map per lane, one grid row per map
+        hipLaunchKernelGGL((k_adjoint_scatter<M, 1, true>), dim3(a.nblocks, nm), dim3(kBlock), 0, s, a);
+        return;
+    }
     if (nm >= 4) hipLaunchKernelGGL((k_adjoint_scatter<M, 4>), dim3(a.nblocks, nm / 4), dim3(kBlock), 0, s, a);
     if (nm & 2) {
         ScatterArgs b = a;
@@ -405,8 +428,9 @@ static z3_status adjoint_chunk_maps(z3_index idx, int map, int nm, int m_max, in
     sa.n_stride = (size_t)idx->n;
     sa.rec_stride = (size_t)2 * idx->n;
     sa.d_stride = stride;
+    sa.px0 = idx->plane_x0; sa.py0 = idx->plane_y0; sa.psx = idx->plane_sx;
     switch (m_max) {
-#define Z3_CASE(MM) case MM: launch_scatter_m<MM>(sa, nm, s); break;
+#define Z3_CASE(MM) case MM: launch_scatter_m<MM>(sa, nm, idx->planar, s); break;
         Z3_CASE(0) Z3_CASE(1) Z3_CASE(2) Z3_CASE(3) Z3_CASE(4) Z3_CASE(5) Z3_CASE(6) Z3_CASE(7)
         Z3_CASE(8) Z3_CASE(9) Z3_CASE(10) Z3_CASE(11) Z3_CASE(12) Z3_CASE(13) Z3_CASE(14)
         Z3_CASE(15) Z3_CASE(16)

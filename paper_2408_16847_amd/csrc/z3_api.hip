@@ -704,7 +704,6 @@ Z3_API z3_status z3_adjoint(z3_index idx, int map, int m_max, int64_t p0, int64_
 {
     CallScope scope(idx, as_stream(stream));
     z3_status st = check_common("z3_adjoint", idx, map, m_max, Z3_PREC_FP64, p0, p1);
-    if (st == Z3_OK && idx->planar) return fail(Z3_ERR_UNSUPPORTED, "z3_adjoint: sky catalogues only");
     if (st != Z3_OK) return st;
     if (!std::isfinite(scale)) return fail(Z3_ERR_INVALID_ARG, "z3_adjoint: scale is not finite");
     if (p1 == p0) return Z3_OK;

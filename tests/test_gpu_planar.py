@@ -129,15 +129,41 @@ def test_plane_integer_grid_edge_ties():
 def test_plane_sky_only_entry_points_rejected():
     G.say("case: planar unsupported entry points")
     xy, E, x = pins.three_point_planar()
-    idx = build_plane(xy, x, E)
-    G_ = torch.zeros((5, 3, 3, 2), dtype=torch.float64, device="cuda")
-    grad = torch.zeros(3, dtype=torch.float64, device="cuda")
+    idx = build_plane(xy, np.stack([x, x]), E)
+    G_ = torch.zeros((2, 5, 3, 3, 2), dtype=torch.float64, device="cuda")
+    grad = torch.zeros((2, 3), dtype=torch.float64, device="cuda")
     with pytest.raises(_lib.Zeta3Error) as ei:
-        _lib.call("z3_adjoint", idx.handle, 0, 4, 0, 3, ctypes.c_void_p(G_.data_ptr()), 1.0,
+        _lib.call("z3_adjoint_maps", idx.handle, 4, 0, 3, ctypes.c_void_p(G_.data_ptr()), 1.0,
                   ctypes.c_void_p(grad.data_ptr()), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
     assert ei.value.status == 4
     torch.cuda.synchronize()
     assert torch.count_nonzero(grad).item() == 0
+
+
+def test_plane_adjoint_central_differences(plane_map):
+    # zeta is quadratic in each value, so a central difference of the FP64 forward is its
+    # derivative up to rounding, for any step
+    xy, x, E = plane_map
+    G.say("case: planar adjoint vs central differences")
+    M, nb = 6, len(E) - 1
+    rng = np.random.default_rng(81)
+    Gc = rng.normal(size=(M + 1, nb, nb)) + 1j * rng.normal(size=(M + 1, nb, nb))
+    Gt = torch.from_numpy(np.stack([Gc.real, Gc.imag], axis=-1)).cuda()
+    idx = build_plane(xy, x, E)
+    scale = 1.0 / xy.shape[1]
+    g = z3.adjoint(idx, Gt, scale, M).cpu().numpy()
+
+    def L(xx):
+        idx.set_values(torch.from_numpy(xx).cuda())
+        z, _ = z3.estimate(idx, M)
+        return float(np.sum(Gc.real * z.real + Gc.imag * z.imag))
+
+    for k in rng.choice(xy.shape[1], 6, replace=False):
+        h = 1.0
+        xp = x.copy(); xp[k] += h
+        xm = x.copy(); xm[k] -= h
+        fd = (L(xp) - L(xm)) / (2 * h)
+        assert abs(fd - g[k]) <= 1e-9 * max(np.abs(g).max(), 1e-300), (k, fd, g[k])
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
