@@ -126,6 +126,9 @@ def main():
     ap.add_argument("--nside", type=int, default=0,
                     help="run the chosen HEALPix workload's recipe (field, bins, m) at this resolution instead")
     ap.add_argument("--m-max", type=int, default=-1, help="override the workload's largest multipole")
+    ap.add_argument("--shard", default="",
+                    help="I/N: time one GPU's share of an N-GPU run, index-order pivots [I n/N, (I+1) n/N) "
+                         "against the whole neighbour catalogue (one-map exact search)")
     ap.add_argument("--cross", action="store_true",
                     help="multi-field estimator: three correlated fields on the positions, summed over the "
                          "cyclic permutations of (pivot; b1, b2) fields (one-map workloads)")
@@ -190,6 +193,12 @@ def main():
         print("--exclude-self and --cross are separate options", file=sys.stderr)
         sys.exit(2)
     self_pairs = not args.exclude_self
+    shard = None
+    if args.shard:
+        si, sn = (int(t) for t in args.shard.split("/"))
+        if not (0 <= si < sn) or args.approx or args.adjoint or args.cross or cfg.nmaps > 1:
+            sys.exit("--shard I/N needs 0 <= I < N and the one-map exact search")
+        shard = (si, sn)
     t0 = time.time()
     xyz = make_positions(cfg, device="cuda")
     if cfg.nmaps > 1:
@@ -291,7 +300,9 @@ def main():
         elif nbr is None:
             idx = z3.Index(xyz, E, planar=cfg.kind == "plane")
             idx.set_values(x)
-            z3.estimate_raw(idx, M, prec=prec, zeta=zeta, pair_total=pairs, sum_w=sw, self_pairs=self_pairs)
+            q0, q1 = (0, idx.n) if shard is None else (shard[0] * idx.n // shard[1], (shard[0] + 1) * idx.n // shard[1])
+            z3.estimate_raw(idx, M, prec=prec, p0=q0, p1=q1, zeta=zeta, pair_total=pairs, sum_w=sw,
+                            self_pairs=self_pairs)
         else:
             idx = z3.Index(nbr[0], E, weights=nbr[2])
             idx.set_values(nbr[1])
@@ -357,7 +368,8 @@ def main():
         "dtype": "f64" if main_prec == "fp64" else "f64 geometry + f32 multipoles/MFMA",
         "data": "synthetic",
         "config": {"workload": cfg.name + ("+approx" if nbr else "") + ("+adjoint" if args.adjoint else "")
-                   + ("+noself" if not self_pairs else "") + ("+cross3" if args.cross else ""),
+                   + ("+noself" if not self_pairs else "") + ("+cross3" if args.cross else "")
+                   + (f"+shard{shard[0]}of{shard[1]}" if shard else ""),
                    "npoints": n, "nmaps": cfg.nmaps, "nbins": cfg.nbins, "m_max": M,
                    **({"r_plane_units": [cfg.theta_min, cfg.theta_max]} if cfg.kind == "plane" else
                       {"theta_arcmin": [cfg.theta_min * 10800 / np.pi, cfg.theta_max * 10800 / np.pi]}),
@@ -365,7 +377,7 @@ def main():
         "roofline": {"bound": rf_bound, "kernel": rf_kernel, "achieved": achieved,
                      "peak": rf_peak, "unit": "TFLOP/s", "frac": achieved / rf_peak if achieved else None,
                      "traffic": measured_traffic(cfg.name, main_prec)
-                     if rf_kernel == "k_multipoles" and self_pairs and not args.cross else None,
+                     if rf_kernel == "k_multipoles" and self_pairs and not args.cross and shard is None else None,
                      "traffic_unit": "bytes per launch",
                      "avg_launch_ms": r["kernel_ms_total"] / r["kernel_launches"] if r["kernel_launches"] else None,
                      "launches_per_step": launches_per_step, "flops": rf_unit_note,
@@ -390,7 +402,7 @@ def main():
         out["config"]["workload"] += "+graph"
     if args.save_zeta:
         np.savez(args.save_zeta, **{p: res[p]["zeta"] for p in res})
-    if args.cpu_sample != 0 and cfg.nmaps == 1 and not args.cross and cfg.kind != "plane":
+    if args.cpu_sample != 0 and cfg.nmaps == 1 and not args.cross and cfg.kind != "plane" and shard is None:
         out["cpu_baseline"] = cpu_baseline(cfg, xyz, x, nbr, E, M, args.cpu_sample, z3, torch, self_pairs)
     print(json.dumps(out), flush=True)
 
