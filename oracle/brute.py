@@ -147,6 +147,47 @@ def zeta_brute_planar(piv, nbr, w, x, edges, m_max, wp, xp, self_pairs=True):
     return acc / np.sum(wp), pairs
 
 
+def zeta_cross_catalogues_brute(piv, wp, xp, nbr_b, w_b, x_b, nbr_c, w_c, x_c, edges, m_max):
+    """Triplet sum over distinct catalogues: pivot p (catalogue A), neighbour j of catalogue
+    B in bin a and neighbour k of catalogue C in bin b, each normalised by its own
+    catalogue's bin weight, with the opening angle from the tangent vectors at p."""
+    piv = np.asarray(piv, dtype=np.float64)
+    nb = len(edges) - 1
+    acc = np.zeros((m_max + 1, nb, nb), dtype=np.complex128)
+    pairs_b = pairs_c = 0
+
+    def side(r, nbr, w, x):
+        d = np.asarray(nbr, dtype=np.float64) - r[:, None]
+        d2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]
+        b = _bins_by_loop(d2, edges)
+        sel = b >= 0
+        t = d[:, sel] - np.outer(r, r @ d[:, sel])
+        t = t / np.linalg.norm(t, axis=0) if sel.any() else t
+        Wb = np.zeros(nb)
+        np.add.at(Wb, b[sel], w[sel])
+        return b[sel], t, w[sel] * x[sel] / np.where(Wb > 0, Wb, 1.0)[b[sel]], int(sel.sum())
+
+    for p in range(piv.shape[1]):
+        r = piv[:, p]
+        bj, tj, gj, nj = side(r, nbr_b, w_b, x_b)
+        bk, tk, gk, nk = side(r, nbr_c, w_c, x_c)
+        pairs_b += nj
+        pairs_c += nk
+        if nj == 0 or nk == 0:
+            continue
+        cosd = tj.T @ tk
+        sind = np.cross(tj.T[:, None, :], tk.T[None, :, :], axis=2) @ r
+        dphi = np.arctan2(sind, cosd)
+        gg = np.outer(gj, gk) * (wp[p] * xp[p])
+        key = (bj[:, None] * nb + bk[None, :]).ravel()
+        for m in range(m_max + 1):
+            ph = np.exp(-1j * m * dphi) * gg
+            re = np.bincount(key, weights=ph.real.ravel(), minlength=nb * nb)
+            im = np.bincount(key, weights=ph.imag.ravel(), minlength=nb * nb)
+            acc[m] += (re + 1j * im).reshape(nb, nb)
+    return acc / np.sum(wp), pairs_b, pairs_c
+
+
 def dirichlet_resum_brute(piv, nbr, w, x, edges, M, wp, xp, phi):
     """Triplet density smoothed by the Dirichlet kernel D_M(phi - (phi_j - phi_k)).
 

@@ -228,6 +228,17 @@ def estimate_planar(piv, nbr, w, x, edges, m_max, wp, xp):
     return z, int(N.sum())
 
 
+def estimate_cross_catalogues(piv, wp, xp, nbr_b, w_b, x_b, nbr_c, w_c, x_c, edges, m_max):
+    """One term of the multi-field estimator over distinct catalogues: pivots (piv, wp, xp)
+    carry field A; X^B(b1) is the bin average of catalogue B around each pivot, X^C(b2) that
+    of catalogue C:  (1/sum_p w_p) sum_p w_p x_p X^B_m(b1; p) conj(X^C_m(b2; p)).
+    Returns (zeta, pairs with B, pairs with C).  The cyclic sum rotates the roles."""
+    a_b, W_b, N_b = multipoles(piv, nbr_b, w_b, x_b, edges, m_max)
+    a_c, W_c, N_c = multipoles(piv, nbr_c, w_c, x_c, edges, m_max)
+    z = contract_cross(normalise(a_b, W_b), normalise(a_c, W_c), np.asarray(wp) * np.asarray(xp))
+    return z / np.sum(wp), int(N_b.sum()), int(N_c.sum())
+
+
 def resum(zeta, phi):
     """zeta(b1, b2, phi) = sum_{m=-M}^{M} zeta_m exp(i m phi), zeta_{-m} = conj(zeta_m).
 

@@ -183,6 +183,25 @@ def check_three_point_planar(tol=1e-14):
     assert err <= tol, err
 
 
+def three_catalogues(seed=91):
+    """Three different random catalogues on one 3-degree cap (weights, values)."""
+    out = []
+    for k, n in enumerate((180, 240, 210)):
+        xyz, w, x = random_cap(n, 3.0, seed + k)
+        out.append((xyz, w, x))
+    return out
+
+
+def check_cross_catalogues_brute(m_max=4, tol=1e-12):
+    (pa, wa, xa), (pb, wb, xb), (pc, wc, xc) = three_catalogues()
+    E = small_edges(5)
+    z, nb_, nc_ = ref.estimate_cross_catalogues(pa, wa, xa, pb, wb, xb, pc, wc, xc, E, m_max)
+    zb, pb_, pc_ = brute.zeta_cross_catalogues_brute(pa, wa, xa, pb, wb, xb, pc, wc, xc, E, m_max)
+    assert (nb_, nc_) == (pb_, pc_), ((nb_, nc_), (pb_, pc_))
+    err = rel_err(z, zb)
+    assert err <= tol, err
+
+
 def golden_three_point_no_self():
     """The hand-derived three-point values without the k = j terms: every non-empty bin
     of every pivot holds one point, so the diagonal entries vanish and the rest stays."""

@@ -146,3 +146,17 @@ def test_planar_bearing_from_the_x_axis_fails_three_point(monkeypatch):
     monkeypatch.setattr(ref, "planar_bearing", lambda dx, dy: np.arctan2(dy, dx))
     with pytest.raises(AssertionError):
         pins.check_three_point_planar()
+
+
+def test_cross_catalogues_shared_normaliser_fails_brute(monkeypatch):
+    # X^C normalised by catalogue B's bin weights instead of its own
+    orig = ref.estimate_cross_catalogues
+
+    def wrong(piv, wp, xp, nbr_b, w_b, x_b, nbr_c, w_c, x_c, edges, m_max):
+        a_b, W_b, N_b = ref.multipoles(piv, nbr_b, w_b, x_b, edges, m_max)
+        a_c, W_c, N_c = ref.multipoles(piv, nbr_c, w_c, x_c, edges, m_max)
+        z = ref.contract_cross(ref.normalise(a_b, W_b), ref.normalise(a_c, W_b), wp * xp)
+        return z / np.sum(wp), int(N_b.sum()), int(N_c.sum())
+    monkeypatch.setattr(ref, "estimate_cross_catalogues", wrong)
+    with pytest.raises(AssertionError):
+        pins.check_cross_catalogues_brute()

@@ -80,6 +80,20 @@ def test_cross_fields_brute(cyclic):
     pins.check_cross_brute(cyclic=cyclic)
 
 
+def test_cross_catalogues_brute():
+    pins.check_cross_catalogues_brute()
+
+
+def test_cross_catalogues_reduce_to_one_catalogue():
+    # all three roles on one catalogue: the single-catalogue estimator
+    xyz, w, x = pins.random_cap(250, 3.0, 97)
+    E = pins.small_edges(5)
+    z, p = ref.estimate(xyz, xyz, w, x, E, 4, w, x)
+    zc, pb, pc = ref.estimate_cross_catalogues(xyz, w, x, xyz, w, x, xyz, w, x, E, 4)
+    assert p == pb == pc
+    assert pins.rel_err(zc, z) < 1e-13
+
+
 def test_cross_fields_special_cases():
     # one field in all three roles: the single term is zeta, the cyclic sum 3 zeta; exchanging
     # the two neighbour fields conjugates and transposes
