@@ -235,6 +235,23 @@ z3_status z3_estimate_cross(z3_index idx, int map_a, int map_b, int map_c, int c
                             void *stream);
 
 /*
+ * One term of the multi-field estimator over distinct catalogues: pivots of catalogue A
+ * (external arrays, as for z3_estimate_pivots) against neighbour catalogue B (idx_b, map
+ * map_b) in bin b1 and neighbour catalogue C (idx_c, map_c) in bin b2:
+ *   zeta[m][b1][b2] += sum_p w_p x_p X^B_m(b1; p) conj(X^C_m(b2; p))
+ * each X the bin average of its own catalogue (eq. Xm.binned) around the pivot.  The two
+ * indexes need identical bin edges (Z3_ERR_INVALID_ARG otherwise); sky catalogues only.
+ *   piv_xyz [3][npiv] FP64 unit vectors, piv_w [npiv] or NULL, piv_x [npiv]
+ * pivots [p0, p1) are processed; pairs_b / pairs_c += the pairs with B / C (may be NULL);
+ * sum_w[0] += the pivots' weights (may be NULL).  The cyclic sum over (A;BC), (B;CA),
+ * (C;AB) is three calls with the roles rotated.  Unnormalised like z3_estimate.
+ */
+z3_status z3_estimate_cross_catalogues(z3_index idx_b, int map_b, z3_index idx_c, int map_c, int64_t npiv,
+                                       const double *piv_xyz, const double *piv_w, const double *piv_x,
+                                       int m_max, int prec, int64_t p0, int64_t p1, double *zeta,
+                                       uint64_t *pairs_b, uint64_t *pairs_c, double *sum_w, void *stream);
+
+/*
  * Fused estimator for ALL attached maps at once (many mock maps over one set of
  * positions, eqs. Xm.binned and zetamEst for each map): for every pair the bin test,
  * bearing and cos/sin(m phi) are computed once and applied to the values of all maps.

@@ -560,6 +560,79 @@ Z3_API z3_status z3_estimate_cross(z3_index idx, int map_a, int map_b, int map_c
     return st;
 }
 
+Z3_API z3_status z3_estimate_cross_catalogues(z3_index idx_b, int map_b, z3_index idx_c, int map_c, int64_t npiv,
+                                              const double *piv_xyz, const double *piv_w, const double *piv_x,
+                                              int m_max, int prec, int64_t p0, int64_t p1, double *zeta,
+                                              uint64_t *pairs_b, uint64_t *pairs_c, double *sum_w, void *stream)
+{
+    CallScope scope(idx_b, as_stream(stream));
+    if (!idx_b || !idx_c) return fail(Z3_ERR_INVALID_ARG, "z3_estimate_cross_catalogues: index is NULL");
+    if (idx_b->planar || idx_c->planar)
+        return fail(Z3_ERR_UNSUPPORTED, "z3_estimate_cross_catalogues: sky catalogues only");
+    if (npiv < 0 || npiv >= (int64_t)0x7fffffff)
+        return fail(Z3_ERR_INVALID_ARG, "z3_estimate_cross_catalogues: npiv=%lld", (long long)npiv);
+    if (m_max < 0 || m_max > Z3_MAX_MMAX)
+        return fail(Z3_ERR_INVALID_ARG, "z3_estimate_cross_catalogues: m_max=%d outside 0..%d", m_max, Z3_MAX_MMAX);
+    if (prec != Z3_PREC_FP64 && prec != Z3_PREC_MIXED)
+        return fail(Z3_ERR_INVALID_ARG, "z3_estimate_cross_catalogues: unknown precision %d", prec);
+    if (p0 < 0 || p1 < p0 || p1 > npiv)
+        return fail(Z3_ERR_INVALID_ARG, "z3_estimate_cross_catalogues: pivot range [%lld, %lld) outside [0, %lld]",
+                    (long long)p0, (long long)p1, (long long)npiv);
+    if (!zeta) return fail(Z3_ERR_INVALID_ARG, "z3_estimate_cross_catalogues: zeta is NULL");
+    if (p1 > p0 && (!piv_xyz || !piv_x)) return fail(Z3_ERR_INVALID_ARG, "z3_estimate_cross_catalogues: NULL pivots");
+    const z3_index_s *ix[2] = {idx_b, idx_c};
+    const int mp[2] = {map_b, map_c};
+    for (int k = 0; k < 2; ++k) {
+        if (ix[k]->n > 0 && (ix[k]->nmaps < 1 || !ix[k]->d_v))
+            return fail(Z3_ERR_INVALID_ARG, "z3_estimate_cross_catalogues: no values attached to index %d", k);
+        if (ix[k]->n > 0 && (mp[k] < 0 || mp[k] >= ix[k]->nmaps))
+            return fail(Z3_ERR_INVALID_ARG, "z3_estimate_cross_catalogues: map %d outside 0..%d", mp[k],
+                        ix[k]->nmaps - 1);
+    }
+    if (idx_b->nbins != idx_c->nbins)
+        return fail(Z3_ERR_INVALID_ARG, "z3_estimate_cross_catalogues: the indexes have different bins");
+    for (int b = 0; b <= idx_b->nbins; ++b)
+        if (idx_b->edges.e[b] != idx_c->edges.e[b])
+            return fail(Z3_ERR_INVALID_ARG, "z3_estimate_cross_catalogues: the indexes have different bin edges");
+    if (p1 == p0) return Z3_OK;
+    hipStream_t s = as_stream(stream);
+    z3_status st = Z3_OK;
+    if (sum_w) {
+        st = piv_w ? launch_weight_sum(piv_w + p0, p1 - p0, sum_w, s) : launch_add_scalar(sum_w, (double)(p1 - p0), s);
+        if (st != Z3_OK) return st;
+    }
+    if (idx_b->n == 0 || idx_c->n == 0) return Z3_OK;  // an empty neighbour catalogue: every X is 0
+    const int nb = idx_b->nbins;
+    int64_t chunk = chunk_pivots(idx_b, m_max, prec) / 2;
+    chunk = (chunk / kBlock) * kBlock;
+    if (chunk < 16 * kBlock) chunk = 16 * kBlock;
+    if (chunk > p1 - p0) chunk = ((p1 - p0 + kBlock - 1) / kBlock) * kBlock;
+    const size_t elem = prec == Z3_PREC_FP64 ? 8 : 4;
+    const size_t slot_bytes = (size_t)chunk * (size_t)(m_max + 1) * 2 * nb * elem;
+    const size_t pbytes = cross_partial_bytes(chunk, m_max, nb);
+    void *wa = nullptr, *wp = nullptr, *wv = nullptr;
+    if ((st = scratch_alloc(&wa, 2 * slot_bytes, s)) != Z3_OK) return st;
+    if ((st = scratch_alloc(&wp, pbytes, s)) == Z3_OK) st = scratch_alloc(&wv, (size_t)chunk * sizeof(double), s);
+    const Pivots piv{piv_xyz, piv_xyz + npiv, piv_xyz + 2 * npiv};
+    for (int64_t c0 = p0; c0 < p1 && st == Z3_OK; c0 += chunk) {
+        const int64_t c1 = c0 + chunk < p1 ? c0 + chunk : p1;
+        st = launch_pivot_values(piv_w ? piv_w + c0 : nullptr, piv_x + c0, c1 - c0, static_cast<double *>(wv), s);
+        if (st == Z3_OK)
+            st = launch_multipoles(idx_b, piv, map_b, m_max, prec, Z3_NORM_BIN, c0, c1, wa, c1 - c0, nullptr, nullptr,
+                                   nullptr, pairs_b, s);
+        if (st == Z3_OK)
+            st = launch_multipoles(idx_c, piv, map_c, m_max, prec, Z3_NORM_BIN, c0, c1,
+                                   static_cast<char *>(wa) + slot_bytes, c1 - c0, nullptr, nullptr, nullptr, pairs_c, s);
+        if (st == Z3_OK)
+            st = launch_contract_cross(c1 - c0, m_max, nb, prec, wa, static_cast<char *>(wa) + slot_bytes, c1 - c0,
+                                       static_cast<const double *>(wv), zeta, wp, pbytes, s);
+    }
+    scratch_free(wv, s);
+    scratch_free(wp, s);
+    scratch_free(wa, s);
+    return st;
+}
+
 Z3_API z3_status z3_estimate_maps(z3_index idx, int m_max, int prec, int64_t p0, int64_t p1, double *zeta,
                                   uint64_t *pair_total, void *stream)
 {

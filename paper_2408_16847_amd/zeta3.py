@@ -246,6 +246,26 @@ def estimate_pivots_raw(idx: Index, piv_xyz, piv_x, piv_w=None, m_max: int = 0, 
     return zeta
 
 
+def estimate_cross_catalogues(idx_b: Index, idx_c: Index, piv_xyz, piv_x, piv_w=None, m_max: int = 0,
+                              prec="fp64", map_b: int = 0, map_c: int = 0, zeta=None, sum_w=None):
+    """One term of the multi-field estimator over distinct catalogues: external pivots (field
+    A) against neighbour catalogues B (bin b1) and C (bin b2), z3_estimate_cross_catalogues.
+    Returns (zeta [m+1, nb, nb, 2] CUDA, unnormalised, +=; pairs with B; pairs with C);
+    sum_w (a 1-element CUDA tensor) += the pivots' weights if given."""
+    piv_xyz = _dev(piv_xyz)
+    piv_x = _dev(piv_x)
+    piv_w = None if piv_w is None else _dev(piv_w)
+    P = int(piv_xyz.shape[1])
+    if zeta is None:
+        zeta = torch.zeros((m_max + 1, idx_b.nbins, idx_b.nbins, 2), dtype=torch.float64, device="cuda")
+    pb = torch.zeros(1, dtype=torch.int64, device="cuda")
+    pc = torch.zeros(1, dtype=torch.int64, device="cuda")
+    _lib.call("z3_estimate_cross_catalogues", idx_b.handle, map_b, idx_c.handle, map_c, P, _ptr(piv_xyz),
+              _ptr(piv_w), _ptr(piv_x), m_max, PREC[prec], 0, P, _ptr(zeta), _ptr(pb), _ptr(pc), _ptr(sum_w),
+              _stream())
+    return zeta, int(pb.item()), int(pc.item())
+
+
 def estimate_pivots(idx: Index, piv_xyz, piv_x, piv_w=None, m_max: int = 0, prec="fp64", p0: int = 0,
                     p1: int | None = None, map_index: int = 0):
     """Normalised zeta_m (complex128 numpy) and the pair count for external pivots."""

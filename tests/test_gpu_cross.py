@@ -120,3 +120,60 @@ def test_cross_fields_in_different_map_groups(cap3, prec, tol):
     zg, pg = z3.estimate_cross(idx, (0, 1, 0), cfg.m_max, prec=prec, cyclic=True)
     assert pg == pairs
     assert G.err_m(zg, zo).max() <= tol
+
+
+def _catalogues():
+    # three different point sets on one 4-degree cap, each with its own weights and a
+    # lognormal field (galaxy samples of different surveys, say)
+    from synth import lognormal_field
+    out = []
+    for k, n in enumerate((2500, 3200, 2800)):
+        xyz, w, _ = pins.random_cap(n, 4.0, 301 + k)
+        x = lognormal_field(torch.from_numpy(xyz), 64, 20.0, 200.0, 11 + k).numpy()
+        out.append((xyz, w, x))
+    return out
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("mixed", 1e-6)])
+def test_cross_distinct_catalogues(prec, tol):
+    from oracle import ref
+    G.say("case: three distinct catalogues", prec)
+    cats = _catalogues()
+    E = pins.small_edges(6, lo=0.05, hi=1.2, log=True)
+    idxs = [G.build(xyz, x, E, w=w) for xyz, w, x in cats]
+    total = 0
+    total_o = 0
+    for a, b, c in ((0, 1, 2), (1, 2, 0), (2, 0, 1)):
+        pa, wa, xa = cats[a]
+        sw = torch.zeros(1, dtype=torch.float64, device="cuda")
+        zt, pb, pc = z3.estimate_cross_catalogues(idxs[b], idxs[c], torch.from_numpy(pa).cuda(),
+                                                  torch.from_numpy(xa).cuda(), torch.from_numpy(wa).cuda(), 5,
+                                                  prec=prec, sum_w=sw)
+        torch.cuda.synchronize()
+        zg = zt.cpu().numpy() / sw.item()
+        zg = zg[..., 0] + 1j * zg[..., 1]
+        zo, pbo, pco = ref.estimate_cross_catalogues(pa, wa, xa, *cats[b], *cats[c], E, 5)
+        assert (pb, pc) == (pbo, pco)
+        assert G.err_m(zg, zo).max() <= tol
+        total = total + zg
+        total_o = total_o + zo
+    assert G.err_m(total, total_o).max() <= tol
+
+
+def test_cross_catalogues_one_catalogue_and_bad_bins():
+    G.say("case: distinct-catalogue entry, one catalogue, mismatched bins")
+    xyz, w, x = _catalogues()[0]
+    E = pins.small_edges(6, lo=0.05, hi=1.2, log=True)
+    idx = G.build(xyz, x, E, w=w)
+    z, pairs = z3.estimate(idx, 5)
+    sw = torch.zeros(1, dtype=torch.float64, device="cuda")
+    zt, pb, pc = z3.estimate_cross_catalogues(idx, idx, torch.from_numpy(xyz).cuda(), torch.from_numpy(x).cuda(),
+                                              torch.from_numpy(w).cuda(), 5, sum_w=sw)
+    torch.cuda.synchronize()
+    zg = zt.cpu().numpy() / sw.item()
+    assert pb == pc == pairs
+    assert G.err_m(zg[..., 0] + 1j * zg[..., 1], z).max() < 1e-12
+    idx2 = G.build(xyz, x, pins.small_edges(6, lo=0.05, hi=1.3, log=True), w=w)
+    with pytest.raises(_lib.Zeta3Error) as ei:
+        z3.estimate_cross_catalogues(idx, idx2, torch.from_numpy(xyz).cuda(), torch.from_numpy(x).cuda(), None, 5)
+    assert ei.value.status == 1
