@@ -257,7 +257,8 @@ z3_status z3_estimate_cross_catalogues(z3_index idx_b, int map_b, z3_index idx_c
  * bearing and cos/sin(m phi) are computed once and applied to the values of all maps.
  * zeta [nmaps][m_max+1][nbins][nbins][2] += (unnormalised, one block per map, in map
  * order); pair_total += the number of pairs (counted once, not per map), or NULL.
- * Up to 4 maps: register-tiled kernel, FP64 multipole sums.  More maps: the per-pair
+ * Up to 4 maps: one-map passes for 2 maps (FP64) or up to 3 (mixed), otherwise the
+ * register-tiled kernel, FP64 multipole sums.  More maps: the per-pair
  * harmonics of a group of 64 x (waves per block) candidates form the B operand of MFMA
  * products with the maps' values (block shape: see z3_index_set_batch_shape); FP64 path
  * in FP64 MFMA, mixed path in FP32 MFMA with the FP32 sums added into FP64 every 128

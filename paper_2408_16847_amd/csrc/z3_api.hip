@@ -523,7 +523,8 @@ Z3_API z3_status z3_estimate_cross(z3_index idx, int map_a, int map_b, int map_c
     // That kernel forms the harmonics in FP64, so the mixed path keeps one one-map pass
     // per distinct field (12.7 s against 15.0 s)
     const int grp = need[0] / kMapGroup;
-    bool grouped = prec == Z3_PREC_FP64 && !idx->planar && idx->ngroups > grp && nneed > 1;
+    // (two FP64 fields: two one-map passes beat the four-map kernel, as in z3_estimate_maps)
+    bool grouped = prec == Z3_PREC_FP64 && !idx->planar && idx->ngroups > grp && nneed > 2;
     for (int k = 0; k < nneed; ++k) grouped = grouped && need[k] / kMapGroup == grp;
     if (grouped)
         for (int t = 0; t < 3; ++t) slot_of[t] = fa[t] % kMapGroup;
@@ -648,6 +649,14 @@ Z3_API z3_status z3_estimate_maps(z3_index idx, int m_max, int prec, int64_t p0,
     const size_t elem = prec == Z3_PREC_FP64 ? 8 : 4;
     const size_t per_map_piv = (size_t)(m_max + 1) * 2 * idx->nbins * elem;
     const size_t zstride = (size_t)(m_max + 1) * idx->nbins * idx->nbins * 2;
+    // A group of four maps costs the register-tiled kernel the same however many of them are
+    // real, about 3.2-3.4 one-map passes on the mixed path and 2.5 in FP64 (Nside 512 and
+    // 2048, m_max = 10): fewer maps than that run as one-map passes, pairs counted once
+    if (idx->nmaps <= (prec == Z3_PREC_MIXED ? 3 : 2)) {
+        for (int k = 0; k < idx->nmaps && st == Z3_OK; ++k)
+            st = z3_estimate(idx, k, m_max, prec, p0, p1, zeta + k * zstride, k == 0 ? pair_total : nullptr, stream);
+        return st;
+    }
     if (idx->nmaps > kMapGroup) {
         // MFMA many-map kernel: all maps of a pivot chunk in one launch, then one
         // contraction launch for all maps

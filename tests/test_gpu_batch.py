@@ -97,11 +97,12 @@ def test_batch_autotune_picks_a_shape(weighted_cap64):
     idx.free()
 
 
-@pytest.mark.parametrize("nmaps", [3, 20])
+@pytest.mark.parametrize("nmaps", [2, 3, 4, 20])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_many_maps_match_one_map_kernel(nmaps, prec):
     """HEALPix Nside 64 (full sky: poles, wrap-around, full bands), maps against the FP64
-    one-map kernel; 3 maps run the register-tiled kernel, 20 the MFMA kernel."""
+    one-map kernel; 2 maps (and 3 on the mixed path) run one-map passes, 3-4 maps the
+    register-tiled kernel, 20 the MFMA kernel."""
     G.say("case: many maps vs one-map kernel", nmaps, prec)
     xyz_t = ring_centres(64)
     cfg = CONFIGS["nside512"]

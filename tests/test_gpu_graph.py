@@ -35,7 +35,7 @@ def _eager(idx, x, M, prec, t):
     return zeta.cpu().numpy(), grad.cpu().numpy()
 
 
-@pytest.mark.parametrize("nmaps,prec", [(6, "mixed"), (6, "fp64"), (1, "mixed")])
+@pytest.mark.parametrize("nmaps,prec", [(6, "mixed"), (6, "fp64"), (3, "mixed"), (1, "mixed")])
 def test_graph_replays_match_eager(nmaps, prec):
     G.say("case: graph step", nmaps, prec)
     xyz, w, _ = pins.random_cap(3000, 5.0, 31)
