@@ -160,10 +160,10 @@ z3_status z3_index_batch_shape(z3_index idx, int m_max, int prec, int *waves, in
  *   cell_size strip height in the units of xy; <= 0 selects 1.4 x the mean spacing
  * Pairs: d2 = dx*dx + dy*dy in FP64, E_b <= d2 < E_{b+1}; the angle of a separation is
  * measured from the +y axis towards +x.  The index serves z3_index_set_values,
- * z3_accumulate_multipoles, z3_estimate, z3_estimate_ex, z3_estimate_cross, z3_adjoint
- * and z3_estimate_maps with one map; the many-map (z3_estimate_maps with more than one
- * map, z3_adjoint_maps) and external-pivot entry points return Z3_ERR_UNSUPPORTED for it.
- * Synchronises on `stream`.
+ * z3_accumulate_multipoles, z3_estimate, z3_estimate_ex, z3_estimate_cross, z3_adjoint,
+ * z3_estimate_maps and z3_adjoint_maps (one-map passes per map); the external-pivot entry
+ * points (z3_estimate_pivots, z3_estimate_cross_catalogues) return Z3_ERR_UNSUPPORTED for
+ * it.  Synchronises on `stream`.
  */
 z3_status z3_build_index_planar(int64_t n, const double *xy, const double *w, int nbins,
                                 const double *edges_d2, double cell_size, void *stream,

@@ -640,8 +640,6 @@ Z3_API z3_status z3_estimate_maps(z3_index idx, int m_max, int prec, int64_t p0,
     CallScope scope(idx, as_stream(stream));
     z3_status st = check_common("z3_estimate_maps", idx, 0, m_max, prec, p0, p1);
     if (st != Z3_OK) return st;
-    if (idx->planar && idx->nmaps > 1)
-        return fail(Z3_ERR_UNSUPPORTED, "z3_estimate_maps: the many-map kernels take sky catalogues only");
     if (!zeta) return fail(Z3_ERR_INVALID_ARG, "z3_estimate_maps: zeta is NULL");
     if (p1 == p0) return Z3_OK;
     hipStream_t s = as_stream(stream);
@@ -651,8 +649,9 @@ Z3_API z3_status z3_estimate_maps(z3_index idx, int m_max, int prec, int64_t p0,
     const size_t zstride = (size_t)(m_max + 1) * idx->nbins * idx->nbins * 2;
     // A group of four maps costs the register-tiled kernel the same however many of them are
     // real, about 3.2-3.4 one-map passes on the mixed path and 2.5 in FP64 (Nside 512 and
-    // 2048, m_max = 10): fewer maps than that run as one-map passes, pairs counted once
-    if (idx->nmaps <= (prec == Z3_PREC_MIXED ? 3 : 2)) {
+    // 2048, m_max = 10): fewer maps than that run as one-map passes, pairs counted once.  On
+    // a plane (the many-map kernels take sky catalogues) every map runs a one-map pass.
+    if (idx->nmaps <= (prec == Z3_PREC_MIXED ? 3 : 2) || idx->planar) {
         for (int k = 0; k < idx->nmaps && st == Z3_OK; ++k)
             st = z3_estimate(idx, k, m_max, prec, p0, p1, zeta + k * zstride, k == 0 ? pair_total : nullptr, stream);
         return st;
@@ -799,12 +798,18 @@ Z3_API z3_status z3_adjoint_maps(z3_index idx, int m_max, int64_t p0, int64_t p1
 {
     CallScope scope(idx, as_stream(stream));
     z3_status st = check_common("z3_adjoint_maps", idx, 0, m_max, Z3_PREC_FP64, p0, p1);
-    if (st == Z3_OK && idx->planar) return fail(Z3_ERR_UNSUPPORTED, "z3_adjoint_maps: sky catalogues only");
     if (st != Z3_OK) return st;
     if (!std::isfinite(scale)) return fail(Z3_ERR_INVALID_ARG, "z3_adjoint_maps: scale is not finite");
     if (p1 == p0) return Z3_OK;
     if (!G || !grad_x) return fail(Z3_ERR_INVALID_ARG, "z3_adjoint_maps: G or grad_x is NULL");
     if (idx->nmaps == 1) return z3_adjoint(idx, 0, m_max, p0, p1, G, scale, grad_x, stream);
+    if (idx->planar) {
+        // plane: the many-map recompute kernels take sky catalogues, so one adjoint per map
+        const size_t gstride = (size_t)(m_max + 1) * idx->nbins * idx->nbins * 2;
+        for (int k = 0; k < idx->nmaps && st == Z3_OK; ++k)
+            st = z3_adjoint(idx, k, m_max, p0, p1, G + k * gstride, scale, grad_x + (size_t)k * idx->n, stream);
+        return st;
+    }
     return adjoint_maps_impl(idx, m_max, p0, p1, G, scale, grad_x, as_stream(stream),
                              chunk_pivots(idx, m_max, Z3_PREC_FP64));
 }

@@ -129,15 +129,37 @@ def test_plane_integer_grid_edge_ties():
 def test_plane_sky_only_entry_points_rejected():
     G.say("case: planar unsupported entry points")
     xy, E, x = pins.three_point_planar()
-    idx = build_plane(xy, np.stack([x, x]), E)
-    G_ = torch.zeros((2, 5, 3, 3, 2), dtype=torch.float64, device="cuda")
-    grad = torch.zeros((2, 3), dtype=torch.float64, device="cuda")
+    idx = build_plane(xy, x, E)
+    zeta = torch.zeros((5, 3, 3, 2), dtype=torch.float64, device="cuda")
+    piv = torch.zeros((3, 1), dtype=torch.float64, device="cuda")
+    piv[0, 0] = 1.0
     with pytest.raises(_lib.Zeta3Error) as ei:
-        _lib.call("z3_adjoint_maps", idx.handle, 4, 0, 3, ctypes.c_void_p(G_.data_ptr()), 1.0,
-                  ctypes.c_void_p(grad.data_ptr()), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+        z3.estimate_pivots_raw(idx, piv, torch.ones(1, dtype=torch.float64, device="cuda"), None, 4, zeta=zeta)
     assert ei.value.status == 4
     torch.cuda.synchronize()
-    assert torch.count_nonzero(grad).item() == 0
+    assert torch.count_nonzero(zeta).item() == 0
+
+
+@pytest.mark.parametrize("nmaps,prec", [(2, "fp64"), (3, "mixed"), (5, "fp64")])
+def test_plane_several_maps_forward_and_adjoint(plane_map, nmaps, prec):
+    xy, x, E = plane_map
+    G.say("case: planar maps", nmaps, prec)
+    xs = np.stack([np.roll(x, 11 * k) for k in range(nmaps)])
+    idx = build_plane(xy, xs, E)
+    zs, pairs = z3.estimate_maps(idx, 5, prec=prec)
+    tol = 1e-12 if prec == "fp64" else 1e-6
+    for k in range(nmaps):
+        z1, p1 = z3.estimate(idx, 5, prec="fp64", map_index=k)
+        assert p1 == pairs
+        assert G.err_m(zs[k], z1).max() < tol
+    rng = np.random.default_rng(83)
+    Gc = rng.normal(size=(nmaps, 6, len(E) - 1, len(E) - 1, 2))
+    Gt = torch.from_numpy(Gc).cuda()
+    scale = 1.0 / xy.shape[1]
+    ga = z3.adjoint_maps(idx, Gt, scale, 5).cpu().numpy()
+    for k in (0, nmaps - 1):
+        g1 = z3.adjoint(idx, Gt[k].contiguous(), scale, 5, map_index=k).cpu().numpy()
+        assert np.abs(ga[k] - g1).max() <= 1e-12 * np.abs(g1).max()
 
 
 def test_plane_adjoint_central_differences(plane_map):
