@@ -161,9 +161,9 @@ z3_status z3_index_batch_shape(z3_index idx, int m_max, int prec, int *waves, in
  * Pairs: d2 = dx*dx + dy*dy in FP64, E_b <= d2 < E_{b+1}; the angle of a separation is
  * measured from the +y axis towards +x.  The index serves z3_index_set_values,
  * z3_accumulate_multipoles, z3_estimate, z3_estimate_ex, z3_estimate_cross, z3_adjoint,
- * z3_estimate_maps and z3_adjoint_maps (one-map passes per map); the external-pivot entry
- * points (z3_estimate_pivots, z3_estimate_cross_catalogues) return Z3_ERR_UNSUPPORTED for
- * it.  Synchronises on `stream`.
+ * z3_estimate_maps and z3_adjoint_maps (one-map passes per map), z3_estimate_pivots and
+ * z3_estimate_cross_catalogues, whose pivot positions are then [2][npiv] (x row, y row).
+ * Synchronises on `stream`.
  */
 z3_status z3_build_index_planar(int64_t n, const double *xy, const double *w, int nbins,
                                 const double *edges_d2, double cell_size, void *stream,
@@ -240,8 +240,9 @@ z3_status z3_estimate_cross(z3_index idx, int map_a, int map_b, int map_c, int c
  * map_b) in bin b1 and neighbour catalogue C (idx_c, map_c) in bin b2:
  *   zeta[m][b1][b2] += sum_p w_p x_p X^B_m(b1; p) conj(X^C_m(b2; p))
  * each X the bin average of its own catalogue (eq. Xm.binned) around the pivot.  The two
- * indexes need identical bin edges (Z3_ERR_INVALID_ARG otherwise); sky catalogues only.
- *   piv_xyz [3][npiv] FP64 unit vectors, piv_w [npiv] or NULL, piv_x [npiv]
+ * indexes need identical bin edges and the same geometry (Z3_ERR_INVALID_ARG otherwise).
+ *   piv_xyz [3][npiv] FP64 unit vectors ([2][npiv] plane positions for planar indexes),
+ *   piv_w [npiv] or NULL, piv_x [npiv]
  * pivots [p0, p1) are processed; pairs_b / pairs_c += the pairs with B / C (may be NULL);
  * sum_w[0] += the pivots' weights (may be NULL).  The cyclic sum over (A;BC), (B;CA),
  * (C;AB) is three calls with the roles rotated.  Unnormalised like z3_estimate.
@@ -274,8 +275,9 @@ z3_status z3_estimate_maps(z3_index idx, int m_max, int prec, int64_t p0, int64_
  * Fused estimator for an external pivot catalogue against the index's neighbours (the
  * pivot field of the cross-correlation remark in the harmonic-decomposition section;
  * also the approximate search, whose neighbour catalogue is a coarsened map):
- *   piv_xyz  [3][npiv] FP64 unit vectors in the caller's order (a spatially coherent
- *            order, such as HEALPix RING, keeps neighbouring pivots in one wave)
+ *   piv_xyz  [3][npiv] FP64 unit vectors ([2][npiv] positions for a planar index) in the
+ *            caller's order (a spatially coherent order, such as HEALPix RING, keeps
+ *            neighbouring pivots in one wave)
  *   piv_w    [npiv] pivot weights, or NULL for all 1
  *   piv_x    [npiv] pivot values
  * Pivots [p0, p1) are processed; zeta += sum_p w_p x_p X(b1) conj X(b2) (unnormalised),

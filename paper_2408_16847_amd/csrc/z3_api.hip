@@ -568,8 +568,8 @@ Z3_API z3_status z3_estimate_cross_catalogues(z3_index idx_b, int map_b, z3_inde
 {
     CallScope scope(idx_b, as_stream(stream));
     if (!idx_b || !idx_c) return fail(Z3_ERR_INVALID_ARG, "z3_estimate_cross_catalogues: index is NULL");
-    if (idx_b->planar || idx_c->planar)
-        return fail(Z3_ERR_UNSUPPORTED, "z3_estimate_cross_catalogues: sky catalogues only");
+    if (idx_b->planar != idx_c->planar)
+        return fail(Z3_ERR_INVALID_ARG, "z3_estimate_cross_catalogues: one index on a plane, one on the sky");
     if (npiv < 0 || npiv >= (int64_t)0x7fffffff)
         return fail(Z3_ERR_INVALID_ARG, "z3_estimate_cross_catalogues: npiv=%lld", (long long)npiv);
     if (m_max < 0 || m_max > Z3_MAX_MMAX)
@@ -611,10 +611,14 @@ Z3_API z3_status z3_estimate_cross_catalogues(z3_index idx_b, int map_b, z3_inde
     const size_t elem = prec == Z3_PREC_FP64 ? 8 : 4;
     const size_t slot_bytes = (size_t)chunk * (size_t)(m_max + 1) * 2 * nb * elem;
     const size_t pbytes = cross_partial_bytes(chunk, m_max, nb);
-    void *wa = nullptr, *wp = nullptr, *wv = nullptr;
+    void *wa = nullptr, *wp = nullptr, *wv = nullptr, *wz = nullptr;
     if ((st = scratch_alloc(&wa, 2 * slot_bytes, s)) != Z3_OK) return st;
     if ((st = scratch_alloc(&wp, pbytes, s)) == Z3_OK) st = scratch_alloc(&wv, (size_t)chunk * sizeof(double), s);
-    const Pivots piv{piv_xyz, piv_xyz + npiv, piv_xyz + 2 * npiv};
+    // plane: pivots are [2][npiv] (x, y); a zero row stands for z
+    if (st == Z3_OK && idx_b->planar) st = scratch_alloc(&wz, (size_t)npiv * sizeof(double), s);
+    if (st == Z3_OK && idx_b->planar) st = launch_fill(static_cast<double *>(wz), npiv, 0.0, s);
+    const Pivots piv{piv_xyz, piv_xyz + npiv,
+                     idx_b->planar ? static_cast<const double *>(wz) : piv_xyz + 2 * npiv};
     for (int64_t c0 = p0; c0 < p1 && st == Z3_OK; c0 += chunk) {
         const int64_t c1 = c0 + chunk < p1 ? c0 + chunk : p1;
         st = launch_pivot_values(piv_w ? piv_w + c0 : nullptr, piv_x + c0, c1 - c0, static_cast<double *>(wv), s);
@@ -628,6 +632,7 @@ Z3_API z3_status z3_estimate_cross_catalogues(z3_index idx_b, int map_b, z3_inde
             st = launch_contract_cross(c1 - c0, m_max, nb, prec, wa, static_cast<char *>(wa) + slot_bytes, c1 - c0,
                                        static_cast<const double *>(wv), zeta, wp, pbytes, s);
     }
+    scratch_free(wz, s);
     scratch_free(wv, s);
     scratch_free(wp, s);
     scratch_free(wa, s);
@@ -731,7 +736,6 @@ Z3_API z3_status z3_estimate_pivots(z3_index idx, int map, int64_t npiv, const d
 {
     CallScope scope(idx, as_stream(stream));
     if (!idx) return fail(Z3_ERR_INVALID_ARG, "z3_estimate_pivots: idx is NULL");
-    if (idx->planar) return fail(Z3_ERR_UNSUPPORTED, "z3_estimate_pivots: sky catalogues only");
     if (npiv < 0) return fail(Z3_ERR_INVALID_ARG, "z3_estimate_pivots: npiv < 0");
     if (npiv >= (int64_t)0x7fffffff) return fail(Z3_ERR_OVERFLOW, "z3_estimate_pivots: npiv >= 2^31 - 1");
     if (m_max < 0 || m_max > Z3_MAX_MMAX)
@@ -760,10 +764,14 @@ Z3_API z3_status z3_estimate_pivots(z3_index idx, int map, int64_t npiv, const d
     size_t elem = prec == Z3_PREC_FP64 ? 8 : 4;
     size_t abytes = (size_t)chunk * (size_t)(m_max + 1) * 2 * idx->nbins * elem;
     size_t pbytes = contract_partial_bytes(chunk, m_max, idx->nbins);
-    void *wa = nullptr, *wp = nullptr, *wv = nullptr;
+    void *wa = nullptr, *wp = nullptr, *wv = nullptr, *wz = nullptr;
     if ((st = scratch_alloc(&wa, abytes, s)) != Z3_OK) return st;
     if ((st = scratch_alloc(&wp, pbytes, s)) == Z3_OK) st = scratch_alloc(&wv, (size_t)chunk * sizeof(double), s);
-    const Pivots piv{piv_xyz, piv_xyz + npiv, piv_xyz + 2 * npiv};
+    // plane: pivots are [2][npiv] (x, y); a zero row stands for z
+    if (st == Z3_OK && idx->planar) st = scratch_alloc(&wz, (size_t)npiv * sizeof(double), s);
+    if (st == Z3_OK && idx->planar) st = launch_fill(static_cast<double *>(wz), npiv, 0.0, s);
+    const Pivots piv{piv_xyz, piv_xyz + npiv,
+                     idx->planar ? static_cast<const double *>(wz) : piv_xyz + 2 * npiv};
     for (int64_t c0 = p0; c0 < p1 && st == Z3_OK; c0 += chunk) {
         int64_t c1 = c0 + chunk < p1 ? c0 + chunk : p1;
         st = launch_pivot_values(piv_w ? piv_w + c0 : nullptr, piv_x + c0, c1 - c0, static_cast<double *>(wv), s);
@@ -774,6 +782,7 @@ Z3_API z3_status z3_estimate_pivots(z3_index idx, int map, int64_t npiv, const d
             st = launch_contract(c1 - c0, m_max, idx->nbins, prec, wa, c1 - c0, static_cast<const double *>(wv),
                                  zeta, wp, pbytes, s);
     }
+    scratch_free(wz, s);
     scratch_free(wv, s);
     scratch_free(wp, s);
     scratch_free(wa, s);

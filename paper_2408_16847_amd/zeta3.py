@@ -237,6 +237,7 @@ def estimate_pivots_raw(idx: Index, piv_xyz, piv_x, piv_w=None, m_max: int = 0, 
     piv_xyz = _dev(piv_xyz)
     piv_x = _dev(piv_x)
     piv_w = None if piv_w is None else _dev(piv_w)
+    _check_pivot_rows(idx, piv_xyz)
     P = int(piv_xyz.shape[1])
     p1 = P if p1 is None else p1
     if zeta is None:
@@ -244,6 +245,14 @@ def estimate_pivots_raw(idx: Index, piv_xyz, piv_x, piv_w=None, m_max: int = 0, 
     _lib.call("z3_estimate_pivots", idx.handle, map_index, P, _ptr(piv_xyz), _ptr(piv_w), _ptr(piv_x), m_max,
               PREC[prec], p0, p1, _ptr(zeta), _ptr(pair_total), _ptr(sum_w), _stream())
     return zeta
+
+
+def _check_pivot_rows(idx: Index, piv_xyz):
+    rows = 2 if getattr(idx, "planar", False) else 3
+    if piv_xyz.dim() != 2 or piv_xyz.shape[0] != rows:
+        raise ValueError(f"pivot positions must be [{rows}, P] for this index")
+    if piv_xyz.shape[1] > 0 and piv_xyz.stride(0) != piv_xyz.shape[1]:
+        raise ValueError("pivot positions must be contiguous rows")
 
 
 def estimate_cross_catalogues(idx_b: Index, idx_c: Index, piv_xyz, piv_x, piv_w=None, m_max: int = 0,
@@ -255,6 +264,7 @@ def estimate_cross_catalogues(idx_b: Index, idx_c: Index, piv_xyz, piv_x, piv_w=
     piv_xyz = _dev(piv_xyz)
     piv_x = _dev(piv_x)
     piv_w = None if piv_w is None else _dev(piv_w)
+    _check_pivot_rows(idx_b, piv_xyz)
     P = int(piv_xyz.shape[1])
     if zeta is None:
         zeta = torch.zeros((m_max + 1, idx_b.nbins, idx_b.nbins, 2), dtype=torch.float64, device="cuda")
