@@ -235,7 +235,9 @@ void k_multipoles(MultArgs a)
                     double4 rn = load_record(rband, off < oend ? off : 0u);
                     for (; off < oend; off += 32u) {
                         const double4 r = rn;
-                        rn = load_record(rband, off + 32u < oend ? off + 32u : off);
+                        // past the window this reads a record of the band (or, past the band,
+                        // zeros from the buffer's range check) that is never used
+                        rn = load_record(rband, off + 32u);
                         const double dx = r.x - xp, dy = r.y - yp, dz = r.z - zp;
                         const double d2 = (dx * dx + dy * dy) + dz * dz;
                         if (d2 >= elo && d2 < ehi) {
