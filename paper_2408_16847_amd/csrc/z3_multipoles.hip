@@ -229,15 +229,13 @@ void k_multipoles(MultArgs a)
                     }
                 }
                 if constexpr (MIXED) {
-                    // one candidate per step; the next record is requested before this one
-                    // is processed, so that its latency (an L2 or HBM miss now and then)
-                    // overlaps this candidate's work
-                    double4 rn = load_record(rband, off < oend ? off : 0u);
-                    for (; off < oend; off += 32u) {
-                        const double4 r = rn;
-                        // past the window this reads a record of the band (or, past the band,
-                        // zeros from the buffer's range check) that is never used
-                        rn = load_record(rband, off + 32u);
+                    // one candidate at a time, its record requested one candidate ahead so
+                    // that the latency (an L2 or HBM miss now and then) overlaps the previous
+                    // candidate's work; two candidates per trip with two record registers
+                    // in turn, so that the record requested ahead needs no copy.  Past the
+                    // window a request reads a record of the band that is never used (or,
+                    // past the band, zeros from the buffer's range check).
+                    auto cand = [&](const double4 &r, uint32_t o) __attribute__((always_inline)) {
                         const double dx = r.x - xp, dy = r.y - yp, dz = r.z - zp;
                         const double d2 = (dx * dx + dy * dy) + dz * dz;
                         if (d2 >= elo && d2 < ehi) {
@@ -246,7 +244,7 @@ void k_multipoles(MultArgs a)
                                 // record index from the byte offset, as an opaque shift so
                                 // that the compiler keeps no second induction variable
                                 uint32_t jo;
-                                asm("v_lshrrev_b32 %0, 5, %1" : "=v"(jo) : "v"(off));
+                                asm("v_lshrrev_b32 %0, 5, %1" : "=v"(jo) : "v"(o));
                                 const int j = base + (int)jo;
                                 if (!unit_w) Wb += a.wdbl[j];
                                 if constexpr (IDS) hsum += mix64((uint64_t)a.permdbl[j]);
@@ -280,6 +278,14 @@ void k_multipoles(MultArgs a)
                                 }
                             }
                         }
+                    };
+                    double4 ra = load_record(rband, off < oend ? off : 0u);
+                    for (; off < oend; off += 64u) {
+                        const double4 rb = load_record(rband, off + 32u);
+                        cand(ra, off);
+                        if (off + 32u >= oend) break;
+                        ra = load_record(rband, off + 64u);
+                        cand(rb, off + 32u);
                     }
                 }
             }
