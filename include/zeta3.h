@@ -57,8 +57,10 @@ typedef enum {
 
 enum {
     Z3_PREC_FP64 = 0,  /* all arithmetic in FP64                                         */
-    Z3_PREC_MIXED = 1  /* FP64 separations and bin decisions, FP32 bearing/recurrence
-                          with FP64 per-bin sums, FP32 MFMA contraction with FP64 sums */
+    Z3_PREC_MIXED = 1  /* multipoles formed in FP64 (separations, bins, bearing,
+                          harmonics, sums) and stored in FP32; split-FP32 MFMA contraction
+                          with FP64 sums; many-map kernel: FP64 harmonics rounded once,
+                          FP32 MFMA products added into FP64 */
 };
 
 enum {
@@ -82,7 +84,8 @@ enum {
  * binned estimator; it replaces the paper's tree search with a latitude-band x
  * longitude-cell grid, points sorted by cell).
  *   n              number of points, 0 <= n < 2^29 (Z3_ERR_OVERFLOW above)
- *   xyz            [3][n] FP64 unit vectors (x row, y row, z row)
+ *   xyz            [3][n] FP64 unit vectors (x row, y row, z row); | |r|^2 - 1 | above
+ *                  1e-10 for any point, or a non-finite coordinate, is Z3_ERR_INVALID_ARG
  *   w              [n] FP64 weights w_i (eq. of the discrete field), or NULL for all 1
  *   nbins          1 .. Z3_MAX_NBINS
  *   edges_chord2   [host] nbins+1 strictly increasing chord-squared edges, 0 < E_0,
@@ -122,9 +125,10 @@ z3_status z3_index_update_values(z3_index idx, const double *x, void *stream);
  * far) bytes, kept until z3_index_free; [host] reserved (may be NULL) receives the size.
  * Run each call once eagerly with the arguments it will be captured with, then prepare,
  * then capture.  A captured call whose needs exceed the reservation fails with
- * Z3_ERR_INVALID_ARG (and the capture is then unusable).  Synchronises the device; growing
- * the workspace frees the previous one, which invalidates graphs captured before.  Graphs
- * captured on one index share the workspace: their replays must not overlap in time.
+ * Z3_ERR_INVALID_ARG (and the capture is then unusable).  Synchronises the device.  Growing
+ * the reservation allocates a new workspace for later captures and keeps the previous one
+ * (graphs captured before still point at it) until z3_index_free.  Graphs captured on one
+ * index may share a workspace: their replays must not overlap in time.
  * z3_contract and z3_build_index / z3_index_set_values cannot be captured.
  */
 z3_status z3_index_prepare_capture(z3_index idx, size_t min_bytes, size_t *reserved);
@@ -241,7 +245,8 @@ z3_status z3_estimate_cross(z3_index idx, int map_a, int map_b, int map_c, int c
  *   zeta[m][b1][b2] += sum_p w_p x_p X^B_m(b1; p) conj(X^C_m(b2; p))
  * each X the bin average of its own catalogue (eq. Xm.binned) around the pivot.  The two
  * indexes need identical bin edges and the same geometry (Z3_ERR_INVALID_ARG otherwise).
- *   piv_xyz [3][npiv] FP64 unit vectors ([2][npiv] plane positions for planar indexes),
+ *   piv_xyz [3][npiv] FP64 positions ([2][npiv] plane positions for planar indexes), of
+ *           any length (see z3_estimate_pivots),
  *   piv_w [npiv] or NULL, piv_x [npiv]
  * pivots [p0, p1) are processed; pairs_b / pairs_c += the pairs with B / C (may be NULL);
  * sum_w[0] += the pivots' weights (may be NULL).  The cyclic sum over (A;BC), (B;CA),
@@ -258,7 +263,7 @@ z3_status z3_estimate_cross_catalogues(z3_index idx_b, int map_b, z3_index idx_c
  * bearing and cos/sin(m phi) are computed once and applied to the values of all maps.
  * zeta [nmaps][m_max+1][nbins][nbins][2] += (unnormalised, one block per map, in map
  * order); pair_total += the number of pairs (counted once, not per map), or NULL.
- * Up to 4 maps: one-map passes for 2 maps (FP64) or up to 3 (mixed), otherwise the
+ * Up to 4 maps: one-map passes for 1 or 2 maps, otherwise the
  * register-tiled kernel, FP64 multipole sums.  More maps: the per-pair
  * harmonics of a group of 64 x (waves per block) candidates form the B operand of MFMA
  * products with the maps' values (block shape: see z3_index_set_batch_shape); FP64 path
@@ -275,9 +280,11 @@ z3_status z3_estimate_maps(z3_index idx, int m_max, int prec, int64_t p0, int64_
  * Fused estimator for an external pivot catalogue against the index's neighbours (the
  * pivot field of the cross-correlation remark in the harmonic-decomposition section;
  * also the approximate search, whose neighbour catalogue is a coarsened map):
- *   piv_xyz  [3][npiv] FP64 unit vectors ([2][npiv] positions for a planar index) in the
+ *   piv_xyz  [3][npiv] FP64 positions ([2][npiv] positions for a planar index) in the
  *            caller's order (a spatially coherent order, such as HEALPix RING, keeps
- *            neighbouring pivots in one wave)
+ *            neighbouring pivots in one wave).  Normally unit vectors; a pivot of another
+ *            length keeps the chord test on the raw vectors (its windows are rescaled),
+ *            so pair lists match a direct evaluation of d2 on the same vectors
  *   piv_w    [npiv] pivot weights, or NULL for all 1
  *   piv_x    [npiv] pivot values
  * Pivots [p0, p1) are processed; zeta += sum_p w_p x_p X(b1) conj X(b2) (unnormalised),

@@ -240,10 +240,11 @@ Z3_API z3_status z3_index_prepare_capture(z3_index idx, size_t min_bytes, size_t
         z3_status st = check_hip(hipSetDevice(idx->device), "hipSetDevice");
         if (st == Z3_OK) st = check_hip(hipDeviceSynchronize(), "hipDeviceSynchronize");
         if (st != Z3_OK) return st;
-        if (idx->cap_ws) (void)hipFree(idx->cap_ws);
-        idx->cap_ws = nullptr;
-        idx->cap_bytes = 0;
-        if ((st = check_hip(hipMalloc(&idx->cap_ws, want), "hipMalloc (capture workspace)")) != Z3_OK) return st;
+        void *ws = nullptr;
+        if ((st = check_hip(hipMalloc(&ws, want), "hipMalloc (capture workspace)")) != Z3_OK) return st;
+        // graphs captured against the previous workspace still point at it: keep it
+        if (idx->cap_ws) idx->cap_retired.push_back(idx->cap_ws);
+        idx->cap_ws = ws;
         idx->cap_bytes = want;
     }
     if (reserved) *reserved = idx->cap_bytes;
@@ -517,14 +518,13 @@ Z3_API z3_status z3_estimate_cross(z3_index idx, int map_a, int map_b, int map_c
         if (k == nneed) need[nneed++] = f;
         slot_of[t] = k;
     }
-    // FP64 fields of one group of kMapGroup attached maps (sky catalogues): one pass of the
-    // register-tiled many-map kernel computes the group's multipoles with shared pair
-    // geometry (Nside 2048, three fields: 15.1 s against 18.0 s for three one-map passes).
-    // That kernel forms the harmonics in FP64, so the mixed path keeps one one-map pass
-    // per distinct field (12.7 s against 15.0 s)
+    // Three distinct fields of one group of kMapGroup attached maps (sky catalogues): one
+    // pass of the register-tiled many-map kernel computes the group's multipoles with shared
+    // pair geometry (Nside 2048, FP64: 15.1 s against 18.0 s for three one-map passes).  Both
+    // precisions form the harmonics in FP64, so the choice is the same for both; two fields
+    // run two one-map passes, as in z3_estimate_maps.
     const int grp = need[0] / kMapGroup;
-    // (two FP64 fields: two one-map passes beat the four-map kernel, as in z3_estimate_maps)
-    bool grouped = prec == Z3_PREC_FP64 && !idx->planar && idx->ngroups > grp && nneed > 2;
+    bool grouped = !idx->planar && idx->ngroups > grp && nneed > 2;
     for (int k = 0; k < nneed; ++k) grouped = grouped && need[k] / kMapGroup == grp;
     if (grouped)
         for (int t = 0; t < 3; ++t) slot_of[t] = fa[t] % kMapGroup;
@@ -653,10 +653,10 @@ Z3_API z3_status z3_estimate_maps(z3_index idx, int m_max, int prec, int64_t p0,
     const size_t per_map_piv = (size_t)(m_max + 1) * 2 * idx->nbins * elem;
     const size_t zstride = (size_t)(m_max + 1) * idx->nbins * idx->nbins * 2;
     // A group of four maps costs the register-tiled kernel the same however many of them are
-    // real, about 3.2-3.4 one-map passes on the mixed path and 2.5 in FP64 (Nside 512 and
-    // 2048, m_max = 10): fewer maps than that run as one-map passes, pairs counted once.  On
+    // real, about 2.5 one-map passes (Nside 512 and 2048, m_max = 10; both precisions form
+    // the harmonics in FP64): one or two maps run as one-map passes, pairs counted once.  On
     // a plane (the many-map kernels take sky catalogues) every map runs a one-map pass.
-    if (idx->nmaps <= (prec == Z3_PREC_MIXED ? 3 : 2) || idx->planar) {
+    if (idx->nmaps <= 2 || idx->planar) {
         for (int k = 0; k < idx->nmaps && st == Z3_OK; ++k)
             st = z3_estimate(idx, k, m_max, prec, p0, p1, zeta + k * zstride, k == 0 ? pair_total : nullptr, stream);
         return st;

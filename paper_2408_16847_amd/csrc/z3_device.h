@@ -19,6 +19,15 @@ __device__ __forceinline__ int wave_max(int v)
     return v;
 }
 
+// A wave-uniform double moved to scalar registers (the value of the first active lane).
+__device__ __forceinline__ double uniform_f64(double v)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+    return __builtin_bit_cast(double, (uint64_t)hi << 32 | lo);
+}
+
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v)
 {
     unsigned lo = (unsigned)v, hi = (unsigned)(v >> 32);

@@ -112,6 +112,21 @@ __global__ void k_band_of_point(const double *xyz, int64_t n, double inv_h, int 
     }
 }
 
+// Largest deviation | |r|^2 - 1 | of the positions from unit length (non-finite -> +inf),
+// reduced per wave, then one atomic per wave.
+__global__ void k_norm_dev(const double *xyz, int64_t n, double *out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double dev = 0.0;
+    if (i < n) {
+        const double x = xyz[i], y = xyz[n + i], z = xyz[2 * n + i];
+        dev = fabs((x * x + y * y + z * z) - 1.0);
+        if (!(dev <= 1e300)) dev = INFINITY;
+    }
+    for (int o = 32; o > 0; o >>= 1) dev = fmax(dev, __shfl_xor(dev, o, kWave));
+    if ((threadIdx.x & (kWave - 1)) == 0 && dev > 0.0) atomic_max_pos_double(out, dev);
+}
+
 __global__ void k_cell_of_point(int64_t n, const int *band, const double *phi, const Band *bands,
                                 int *cell, int *cell_count)
 {
@@ -406,6 +421,8 @@ static void free_ptrs(z3_index idx)
                   idx->d_vgrp, idx->d_vmat64, idx->d_vmat32, idx->cap_ws};
     for (void *p : ps)
         if (p) (void)hipFree(p);
+    for (void *p : idx->cap_retired) (void)hipFree(p);
+    idx->cap_retired.clear();
 }
 
 void free_index(z3_index idx)
@@ -593,13 +610,33 @@ z3_status build_index_impl(int64_t n, const double *xyz, const double *w, int nb
                            d_phi, d_band_count, d_band_th);
         if ((st = check_launch("k_band_of_point")) != Z3_OK) return bail2(st);
     }
+    // sky positions must be unit vectors: the windows are angular while membership is the
+    // chord test on the raw vectors, and the windows' guards (1e-9 relative) cover a
+    // deviation | |r|^2 - 1 | of up to kMaxNormDev only
+    double *d_dev = nullptr;
+    if (!planar) {
+        if ((st = dalloc(&d_dev, 1, "alloc norm deviation")) != Z3_OK) return bail2(st);
+        st = check_hip(hipMemsetAsync(d_dev, 0, sizeof(double), s), "clear norm deviation");
+        if (st == Z3_OK && n > 0) {
+            hipLaunchKernelGGL(k_norm_dev, dim3(grid_for(n)), dim3(256), 0, s, xyz, n, d_dev);
+            st = check_launch("k_norm_dev");
+        }
+        if (st != Z3_OK) { (void)hipStreamSynchronize(s); (void)hipFree(d_dev); return bail2(st); }
+    }
     std::vector<int> bcount(nbands);
     std::vector<double> bth(2 * (size_t)nbands);
+    double dev = 0.0;
     st = check_hip(hipMemcpyAsync(bcount.data(), d_band_count, nbands * sizeof(int), hipMemcpyDeviceToHost, s), "copy");
     if (st == Z3_OK)
         st = check_hip(hipMemcpyAsync(bth.data(), d_band_th, bth.size() * sizeof(double), hipMemcpyDeviceToHost, s), "copy");
+    if (st == Z3_OK && d_dev) st = check_hip(hipMemcpyAsync(&dev, d_dev, sizeof(double), hipMemcpyDeviceToHost, s), "copy");
     if (st == Z3_OK) st = check_hip(hipStreamSynchronize(s), "sync");
+    if (d_dev) (void)hipFree(d_dev);
     if (st != Z3_OK) return bail2(st);
+    if (!(dev <= kMaxNormDev))
+        return bail2(fail(Z3_ERR_INVALID_ARG,
+                          "z3_build_index: positions are not unit vectors (max | |r|^2 - 1 | = %g, limit %g)", dev,
+                          kMaxNormDev));
 
     // the multipole kernel addresses a band's doubled records (64 B per point) with 32-bit
     // byte offsets

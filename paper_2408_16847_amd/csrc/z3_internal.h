@@ -1,6 +1,8 @@
 // Internal declarations of libzeta3 (not part of the ABI).
 #pragma once
 
+#include <vector>
+
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <stddef.h>
@@ -18,6 +20,10 @@ constexpr int kBlock = 256;      // threads per block of the multipole kernel (4
 constexpr int kCellsPerPoint = Z3_CELLS_PER_POINT;  // longitude cells per point of a band (tuning)
 constexpr int kMapGroup = 4;       // maps carried per lane by the many-map kernel
 constexpr int kWave = 64;
+// Largest | |r|^2 - 1 | accepted for catalogue positions on the sphere (z3_build_index)
+constexpr double kMaxNormDev = 1e-10;
+// Pivots whose length differs from 1 by more than this get windows rescaled to their length
+constexpr double kPivotNormTol = 4e-11;
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kTwoPi = 6.28318530717958647692;
 
@@ -85,6 +91,9 @@ struct z3_index_s {
     // take their chunk buffers from here instead of allocating
     void *cap_ws = nullptr;
     size_t cap_bytes = 0;
+    // earlier, smaller capture workspaces: graphs captured before a reservation grew still
+    // point at them, so they are kept (not freed) until z3_index_free
+    std::vector<void *> cap_retired;
     size_t ws_peak = 0;               // largest scratch total of one eager call on this index
 };
 

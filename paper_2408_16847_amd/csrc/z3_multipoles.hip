@@ -31,11 +31,14 @@
 // (pivot, bin) it sums Q = sum_j (w_j x_j)^2 in FP64, forms v_p Q / W^2 (v_p Q for raw
 // sums), adds that over the wave in a fixed order and writes one value per (wave, bin).
 //
-// Precision: the FP64 path normalises the bearing with an FP32-seeded reciprocal square
-// root refined by one FP64 Newton step and runs everything in FP64.  The mixed path keeps
-// the separations and bin decisions in FP64, forms the bearing in FP32 (the separation
-// rounded once, an FP32 frame, hardware reciprocal square root), runs the recurrences in
-// FP32 and adds the FP32 sums of each band window into FP64 bin sums.
+// Precision: both paths form the separation, the exact squared chord, the bearing (an
+// FP32-seeded reciprocal square root refined by one FP64 Newton step) and the harmonics in
+// FP64 and add them into FP64 bin sums; the mixed path stores the normalised multipoles in
+// FP32 for its split-FP32 MFMA contraction.  An FP32 bearing or FP32 recurrences would carry
+// an angle error of ~1e-7 per pair, which the m-th harmonic multiplies by m: ~1e-6 at
+// m = 10 on fields whose 3PCF is a sum of terms of random sign.  On this hardware the FP32
+// vector instructions (packed forms excluded) issue at the FP64 rate, so the FP64 harmonics
+// cost the same instructions and are exact to ~1e-15.
 #include "z3_internal.h"
 #include "z3_device.h"
 
@@ -78,7 +81,7 @@ constexpr int mult_waves_per_eu()
     return M <= 10 ? Z3_MULT_WAVES_PER_EU : (M <= 13 ? 3 : 2);
 }
 
-template <int M, bool MIXED, bool IDS, bool SELF, bool PLANAR>
+template <int M, bool F32OUT, bool IDS, bool SELF, bool PLANAR>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(mult_waves_per_eu<M>())))
 void k_multipoles(MultArgs a)
 {
@@ -123,9 +126,25 @@ void k_multipoles(MultArgs a)
         nx /= nn; ny /= nn; nz /= nn;
         ex = ny * zp - nz * yp; ey = nz * xp - nx * zp; ez = nx * yp - ny * xp;
     }
-    // the mixed path's frame, rounded once
-    const float nxf = (float)nx, nyf = (float)ny, nzf = (float)nz;
-    const float exf = (float)ex, eyf = (float)ey, ezf = (float)ez;
+
+    // External pivots need not be unit vectors (the index's points are, to within the
+    // windows' guards).  For a pivot of length rho = 1 + d and a unit neighbour at angle t,
+    // the chord test reads d2 = d^2 + rho 4 hav(t), so the pair lies in [E_lo, E_hi) iff
+    // hav(t) lies in [(E_lo - d^2) / 4 rho, (E_hi - d^2) / 4 rho): the wave's windows then
+    // use the envelope of those bounds over its lanes (wave-uniform, per bin).
+    double dmin = 0.0, dmax = 0.0;
+    if constexpr (!PLANAR) {
+        const double dp = sqrt(xp * xp + yp * yp + zp * zp) - 1.0;
+        dmin = dp; dmax = dp;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            dmin = fmin(dmin, __shfl_xor(dmin, o, kWave));
+            dmax = fmax(dmax, __shfl_xor(dmax, o, kWave));
+        }
+        dmin = uniform_f64(dmin);
+        dmax = uniform_f64(dmax);
+    }
+    const bool rescale = __builtin_amdgcn_readfirstlane((int)!(dmin >= -kPivotNormTol && dmax <= kPivotNormTol));
 
     const int64_t col = p - a.p0;
     const int nb = a.nb;
@@ -134,8 +153,16 @@ void k_multipoles(MultArgs a)
 
     for (int bin = 0; bin < nb; ++bin) {
         const double elo = a.edges->e[bin], ehi = a.edges->e[bin + 1];
-        const double hav_out = a.edges->hav_out[bin + 1], hav_in = a.edges->hav_in[bin];
-        const double rad = a.edges->rad_out[bin + 1];
+        double hav_out = a.edges->hav_out[bin + 1], hav_in = a.edges->hav_in[bin];
+        double rad = a.edges->rad_out[bin + 1];
+        if (rescale) {
+            const double dsq = fmax(dmin * dmin, dmax * dmax);
+            hav_out = 1.0 + fmin(dmin, 0.0) > 1e-3 ? fmin(hav_out / (1.0 + dmin) * (1.0 + 1e-15), 1.0 + 2e-9)
+                                                   : 1.0 + 2e-9;
+            hav_in = (hav_in - 0.25 * dsq) / (1.0 + fmax(dmax, 0.0)) * (1.0 - 1e-15) - 1e-300;
+            rad = 2.0 * asin(fmin(1.0, sqrt(hav_out))) * (1.0 + 1e-9) + 1e-12;
+            if (!(hav_in <= hav_out)) hav_in = -1.0;  // non-finite pivots: no inner exclusion
+        }
         int klo = (int)floor((th - rad) * a.inv_h);
         int khi = (int)floor((th + rad) * a.inv_h);
         klo = max(klo, 0);
@@ -161,17 +188,12 @@ void k_multipoles(MultArgs a)
             const int base = 2 * bd.pt_start;
             // the band's doubled records (wave-uniform base), walked by byte offset
             const __amdgpu_buffer_rsrc_t rband = buffer_view(a.rec + base, (uint32_t)bd.npts * 64u);
-            float Yf[M + 1], Zf[M + 1];
-            if constexpr (MIXED) {
-#pragma unroll
-                for (int m = 0; m <= M; ++m) { Yf[m] = 0.0f; Zf[m] = 0.0f; }
-            }
 #pragma unroll
             for (int seg = 0; seg < 2; ++seg) {
                 uint32_t off = (uint32_t)(seg == 0 ? s0 : s1) * 32u;
                 const uint32_t oend = off + (uint32_t)(seg == 0 ? l0 : l1) * 32u;
-                if constexpr (!MIXED) {
-                    // FP64: two candidates per step, both carried through the bearing and the
+                {
+                    // two candidates per step, both carried through the bearing and the
                     // recurrences (a rejected or missing one with weight 0), so that two
                     // independent FP64 dependency chains interleave
                     for (; off < oend; off += 64u) {
@@ -228,74 +250,6 @@ void k_multipoles(MultArgs a)
                         }
                     }
                 }
-                if constexpr (MIXED) {
-                    // one candidate at a time, its record requested one candidate ahead so
-                    // that the latency (an L2 or HBM miss now and then) overlaps the previous
-                    // candidate's work; two candidates per trip with two record registers
-                    // in turn, so that the record requested ahead needs no copy.  Past the
-                    // window a request reads a record of the band that is never used (or,
-                    // past the band, zeros from the buffer's range check).
-                    auto cand = [&](const double4 &r, uint32_t o) __attribute__((always_inline)) {
-                        const double dx = r.x - xp, dy = r.y - yp, dz = r.z - zp;
-                        const double d2 = (dx * dx + dy * dy) + dz * dz;
-                        if (d2 >= elo && d2 < ehi) {
-                            cnt += 1;
-                            if (IDS || !unit_w) {  // wave-uniform
-                                // record index from the byte offset, as an opaque shift so
-                                // that the compiler keeps no second induction variable
-                                uint32_t jo;
-                                asm("v_lshrrev_b32 %0, 5, %1" : "=v"(jo) : "v"(o));
-                                const int j = base + (int)jo;
-                                if (!unit_w) Wb += a.wdbl[j];
-                                if constexpr (IDS) hsum += mix64((uint64_t)a.permdbl[j]);
-                            }
-                            if constexpr (SELF) Qb = fma(r.w, r.w, Qb);
-                            // the bearing in FP32: the separation rounded once, the tangent
-                            // components against the FP32 frame, then the hardware reciprocal
-                            // square root (the FP32 harmonics that follow carry errors of the
-                            // same order; the FP32 frame also frees six registers)
-                            const float dxf = (float)dx, dyf = (float)dy, dzf = (float)dz;
-                            const float v = (float)r.w;
-                            const float u1f = fmaf(dxf, nxf, fmaf(dyf, nyf, dzf * nzf));
-                            const float u2f = fmaf(dxf, exf, fmaf(dyf, eyf, dzf * ezf));
-                            // + 1e-30: q > 0 for coincident points, below the rounding otherwise
-                            const float rq = __builtin_amdgcn_rsqf(fmaf(u1f, u1f, fmaf(u2f, u2f, 1e-30f)));
-                            const float cf = u1f * rq, sf = u2f * rq;
-                            Yf[0] += v;
-                            if constexpr (M >= 1) {
-                                const float tc = cf + cf;
-                                float t2 = v, t1 = v * cf, s2 = 0.0f, s1 = v * sf;
-                                Yf[1] += t1;
-                                Zf[1] += s1;
-#pragma unroll
-                                for (int m = 2; m <= M; ++m) {
-                                    const float tm = fmaf(tc, t1, -t2);
-                                    const float sm = fmaf(tc, s1, -s2);
-                                    Yf[m] += tm;
-                                    Zf[m] += sm;
-                                    t2 = t1; t1 = tm;
-                                    s2 = s1; s1 = sm;
-                                }
-                            }
-                        }
-                    };
-                    double4 ra = load_record(rband, off < oend ? off : 0u);
-                    for (; off < oend; off += 64u) {
-                        const double4 rb = load_record(rband, off + 32u);
-                        cand(ra, off);
-                        if (off + 32u >= oend) break;
-                        ra = load_record(rband, off + 64u);
-                        cand(rb, off + 32u);
-                    }
-                }
-            }
-            if constexpr (MIXED) {
-                // per-window FP32 partial sums go into the bin's FP64 sums
-#pragma unroll
-                for (int m = 0; m <= M; ++m) {
-                    Y[m] += (double)Yf[m];
-                    Z[m] += (double)Zf[m];
-                }
             }
         }
 
@@ -313,7 +267,7 @@ void k_multipoles(MultArgs a)
                     const double im = m == 0 ? 0.0 : -Z[m] * inv;
                     const size_t ore = ((size_t)(2 * m) * nb + bin) * (size_t)a.ldA + col;
                     const size_t oim = ((size_t)(2 * m + 1) * nb + bin) * (size_t)a.ldA + col;
-                    if constexpr (MIXED) {
+                    if constexpr (F32OUT) {
                         static_cast<float *>(a.A)[ore] = (float)re;
                         static_cast<float *>(a.A)[oim] = (float)im;
                     } else {
@@ -559,11 +513,12 @@ z3_status launch_multipoles_maps(const z3_index_s *idx, int group, int m_max, in
     return st;
 }
 
+// The mixed path differs only in the output: FP32 multipoles for its split-FP32 contraction.
 template <int M, bool PLANAR>
-static void launch_mp(bool mixed, bool ids, bool self, const MultArgs &a, hipStream_t s)
+static void launch_mp(bool f32out, bool ids, bool self, const MultArgs &a, hipStream_t s)
 {
     dim3 grid(a.nblocks), block(kBlock);
-    if (mixed) {
+    if (f32out) {
         if (ids) hipLaunchKernelGGL((k_multipoles<M, true, true, false, PLANAR>), grid, block, 0, s, a);
         else if (self) hipLaunchKernelGGL((k_multipoles<M, true, false, true, PLANAR>), grid, block, 0, s, a);
         else hipLaunchKernelGGL((k_multipoles<M, true, false, false, PLANAR>), grid, block, 0, s, a);

@@ -331,12 +331,13 @@ class GraphStep:
         nm, n, nb = idx.nmaps, idx.n, idx.nbins
         self.x = torch.zeros((nm, n), dtype=torch.float64, device="cuda")
         self.target = _dev(target).reshape(nm, m_max + 1, nb, nb, 2).clone()
-        self.zeta_raw = torch.zeros((nm, m_max + 1, nb, nb, 2), dtype=torch.float64, device="cuda")
-        self.zeta = torch.zeros_like(self.zeta_raw)
+        self.zeta = torch.zeros((nm, m_max + 1, nb, nb, 2), dtype=torch.float64, device="cuda")
         self.grad = torch.zeros((nm, n), dtype=torch.float64, device="cuda")
-        sw = torch.zeros(1, dtype=torch.float64, device="cuda")
-        _lib.call("z3_pivot_weight_sum", idx.handle, 0, n, _ptr(sw), _stream())
-        s = float(sw.item())
+        # the pivots' weight sum (positions and weights are fixed): read by z3_finalize on the
+        # device inside the graph; the adjoint takes its reciprocal as a host scalar
+        self.sum_w = torch.zeros(1, dtype=torch.float64, device="cuda")
+        _lib.call("z3_pivot_weight_sum", idx.handle, 0, n, _ptr(self.sum_w), _stream())
+        s = float(self.sum_w.item())
         self.scale = 1.0 / s if s != 0.0 else 0.0
         self.stream = stream if stream is not None else torch.cuda.Stream()
         self.stream.wait_stream(torch.cuda.current_stream())
@@ -354,10 +355,11 @@ class GraphStep:
 
     def _body(self):
         self.idx.update_values(self.x)
-        self.zeta_raw.zero_()
+        self.zeta.zero_()
         _lib.call("z3_estimate_maps", self.idx.handle, self.m_max, PREC[self.prec], 0, self.idx.n,
-                  _ptr(self.zeta_raw), _ptr(None), _stream())
-        torch.mul(self.zeta_raw, self.scale, out=self.zeta)
+                  _ptr(self.zeta), _ptr(None), _stream())
+        _lib.call("z3_finalize", self.idx.nmaps, self.m_max, self.idx.nbins, _ptr(self.zeta), _ptr(self.sum_w),
+                  _stream())
         g = 2.0 * (self.zeta - self.target)  # dL/dzeta
         self.grad.zero_()
         _lib.call("z3_adjoint_maps", self.idx.handle, self.m_max, 0, self.idx.n, _ptr(g), float(self.scale),
@@ -386,19 +388,22 @@ class Zeta3Fn(torch.autograd.Function):
             zeta = estimate_maps_raw(idx, m_max, prec, sum_w=sw)
         else:
             zeta = estimate_raw(idx, m_max, prec, sum_w=sw)
-        scale = 1.0 / float(sw.item()) if float(sw.item()) != 0.0 else 0.0
-        ctx.idx, ctx.m_max, ctx.scale, ctx.shape = idx, m_max, scale, x.shape
-        return zeta * scale
+        # eq. zetamEst's 1/sum_p w_p, on the device
+        _lib.call("z3_finalize", idx.nmaps, m_max, idx.nbins, _ptr(zeta), _ptr(sw), _stream())
+        ctx.idx, ctx.m_max, ctx.sum_w, ctx.shape = idx, m_max, sw, x.shape
+        return zeta
 
     @staticmethod
     def backward(ctx, g):
         idx = ctx.idx
         g = g.contiguous()
+        s = float(ctx.sum_w.item())
+        scale = 1.0 / s if s != 0.0 else 0.0
         if len(ctx.shape) == 2:
             grad = torch.zeros(ctx.shape, dtype=torch.float64, device="cuda")
-            adjoint_maps(idx, g, ctx.scale, ctx.m_max, grad=grad)
+            adjoint_maps(idx, g, scale, ctx.m_max, grad=grad)
         else:
-            grad = adjoint(idx, g, ctx.scale, ctx.m_max)
+            grad = adjoint(idx, g, scale, ctx.m_max)
         return grad, None, None, None
 
 

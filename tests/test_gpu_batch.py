@@ -42,12 +42,11 @@ def weighted_cap64():
     return xyz, w, xs, E
 
 
-# White-noise maps (zero mean, no correlation) make zeta a sum of terms of random sign:
-# its condition number sum |t| / |sum t| ~ sqrt(pivots) ~ 55 here, which the mixed path's
-# FP32 multipoles (~1e-7 per term) turn into ~5e-6 relative error; they are used on the
-# FP64 path only.  The lognormal maps are the estimator's workload.
+# Lognormal maps (the estimator's workload) and white-noise maps (zero mean, no correlation:
+# zeta is a sum of terms of random sign, condition number sum |t| / |sum t| ~ sqrt(pivots)
+# ~ 55 here), both precisions.
 @pytest.mark.parametrize("field,prec,tol", [("lognormal", "fp64", 1e-10), ("lognormal", "mixed", 1e-6),
-                                            ("white", "fp64", 1e-10)])
+                                            ("white", "fp64", 1e-10), ("white", "mixed", 1e-6)])
 def test_batch_tiles_identical_and_match_oracle(weighted_cap64, field, prec, tol):
     G.say("case: batch tiles", field, prec)
     xyz, w, xs, E = weighted_cap64
@@ -72,8 +71,10 @@ def test_batch_tiles_identical_and_match_oracle(weighted_cap64, field, prec, tol
         assert po == ref[1]
         e = G.err_m(z[s, ..., 0] + 1j * z[s, ..., 1], zo)
         z1, _ = z3.estimate(idx, M, prec=prec, map_index=s)
-        G.say("map", s, "err", e.max(), "one-map kernel err", G.err_m(z1, zo).max())
+        e1 = G.err_m(z1, zo)
+        G.say("map", s, "err", e.max(), "one-map kernel err", e1.max())
         assert e.max() < tol, (s, e)
+        assert e1.max() < tol, (s, e1)
     idx.free()
 
 

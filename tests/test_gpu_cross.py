@@ -66,10 +66,9 @@ def test_cross_of_one_field_is_the_estimator(cap3):
     assert G.err_m(zcb, np.conj(np.swapaxes(zbc, 1, 2))).max() < 1e-12
 
 
-# FP64 only: on white-noise fields zeta is a sum of terms of random sign (condition number
-# ~ sqrt(pivots)), where the FP32 harmonics of the mixed path reach ~1e-6 on 3,000 points;
-# the mixed path is gated on the lognormal cap fields above.
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10)])
+# weighted fields, two of them white noise (zeta a sum of terms of random sign, condition
+# number ~ sqrt(pivots)), both precisions
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("mixed", 1e-6)])
 def test_weighted_cross_fields_and_pivot_ranges(prec, tol):
     G.say("case: weighted cap three fields", prec)
     xyz, w, xa = pins.random_cap(3000, 4.0, 41)

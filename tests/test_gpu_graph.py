@@ -1,5 +1,7 @@
 """Forward + adjoint captured in one HIP graph (GraphStep): every replay, with new field
-values and eager work between replays, against the same computation run eagerly."""
+values and eager work between replays, against the same computation run eagerly.  The
+binding's normalised zeta (GraphStep, Zeta3Fn) is the library's z3_estimate(_maps)
+followed by z3_finalize on the device, bit for bit."""
 
 import numpy as np
 import pytest
@@ -18,14 +20,21 @@ def _maps(xyz, nmaps, seed0):
     return torch.stack([make_values(CONFIGS["cap20k"], xyz_t, seed=seed0 + s) for s in range(nmaps)])
 
 
+def _finalized(idx, M, prec):
+    """z3_estimate_maps (z3_estimate for one map), then z3_finalize with the pivot weight sum."""
+    zeta = z3.estimate_maps_raw(idx, M, prec)
+    sw = torch.zeros(1, dtype=torch.float64, device="cuda")
+    z3._lib.call("z3_pivot_weight_sum", idx.handle, 0, idx.n, z3.zeta3._ptr(sw), z3.zeta3._stream())
+    z3._lib.call("z3_finalize", idx.nmaps, M, idx.nbins, z3.zeta3._ptr(zeta), z3.zeta3._ptr(sw),
+                 z3.zeta3._stream())
+    return zeta, float(sw.item())
+
+
 def _eager(idx, x, M, prec, t):
     """zeta (normalised) and dL/dx for L = sum (zeta - t)^2, by the eager calls."""
     idx.set_values(x.cuda())
-    zr = z3.estimate_maps_raw(idx, M, prec)
-    sw = torch.zeros(1, dtype=torch.float64, device="cuda")
-    z3._lib.call("z3_pivot_weight_sum", idx.handle, 0, idx.n, z3.zeta3._ptr(sw), z3.zeta3._stream())
-    scale = 1.0 / float(sw.item())
-    zeta = zr * scale
+    zeta, s = _finalized(idx, M, prec)
+    scale = 1.0 / s
     g = (2.0 * (zeta - t)).contiguous()
     if idx.nmaps > 1:
         grad = z3.adjoint_maps(idx, g, scale, M)
@@ -33,6 +42,24 @@ def _eager(idx, x, M, prec, t):
         grad = z3.adjoint(idx, g[0], scale, M).unsqueeze(0)
     torch.cuda.synchronize()
     return zeta.cpu().numpy(), grad.cpu().numpy()
+
+
+@pytest.mark.parametrize("nmaps,prec", [(1, "fp64"), (1, "mixed"), (5, "mixed")])
+def test_autograd_forward_is_estimate_then_finalize(nmaps, prec):
+    G.say("case: Zeta3Fn forward vs z3_estimate + z3_finalize", nmaps, prec)
+    xyz, w, _ = pins.random_cap(2000, 4.0, 17)
+    E = pins.small_edges(4, lo=0.1, hi=1.5, log=True)
+    M = 5
+    x = _maps(xyz, nmaps, 300)
+    xs = x[0] if nmaps == 1 else x
+    idx = G.build(xyz, xs.numpy(), E, w=w)
+    zf = z3.Zeta3Fn.apply(xs.cuda(), idx, M, prec)
+    ze, _ = _finalized(idx, M, prec)
+    torch.cuda.synchronize()
+    zf = zf.cpu().numpy().reshape(ze.shape)
+    assert np.array_equal(zf, ze.cpu().numpy())
+    assert np.abs(zf).max() > 0
+    idx.free()
 
 
 @pytest.mark.parametrize("nmaps,prec", [(6, "mixed"), (6, "fp64"), (3, "mixed"), (1, "mixed")])

@@ -231,6 +231,36 @@ def test_external_pivots_subset_and_cross_catalogue(cap):
     assert G.err_m(z, zo).max() < 1e-10
 
 
+def test_position_lengths(cap):
+    """Index positions must be unit vectors to 1e-10 (Z3_ERR_INVALID_ARG otherwise); external
+    pivots may have any length near 1: their windows follow the chord test on the raw
+    vectors, so pair lists equal those of the brute-force NumPy oracle on the same vectors."""
+    from oracle import ref
+    cfg, xyz, x = cap
+    G.say("case: position lengths")
+    E = cfg.edges_chord2()
+    bad = xyz.copy()
+    bad[:, 17] *= 1.0 + 1e-9
+    with pytest.raises(z3.zeta3._lib.Zeta3Error) as ei:
+        G.build(bad, x, E)
+    assert ei.value.status == 1
+    idx = G.build(xyz, x, E)
+    rng = np.random.default_rng(5)
+    sel = np.arange(2000, 4000)
+    scale = 1.0 + rng.choice([0.0, 3e-11, -2e-9, 1e-7, -1e-6, 2e-3], size=len(sel))
+    pv = np.ascontiguousarray(xyz[:, sel] * scale)
+    w = np.ones(xyz.shape[1])
+    zo, po = ref.estimate(pv, xyz, w, x, E, cfg.m_max, w[sel], x[sel])
+    for prec, tol in (("fp64", 1e-10), ("mixed", 1e-6)):
+        z, pairs = z3.estimate_pivots(idx, torch.from_numpy(pv).cuda(), torch.from_numpy(x[sel]).cuda(),
+                                      m_max=cfg.m_max, prec=prec)
+        assert pairs == po, (prec, pairs, po)
+        e = G.err_m(z, zo)
+        G.say("err_m", prec, e.max())
+        assert e.max() < tol
+    idx.free()
+
+
 def test_approximate_search_degraded_neighbours():
     """Full-resolution pivots against the Nside/2 averaged map (weights = 4 children)."""
     from synth import degrade_ring
