@@ -22,15 +22,6 @@ __device__ __forceinline__ int wave_sum_i32(int v)
     return v;
 }
 
-// A wave-uniform double, read from the first lane (so that it can live in scalar registers).
-__device__ __forceinline__ double uniform_f64(double x)
-{
-    const long long v = __double_as_longlong(x);
-    const int lo = __builtin_amdgcn_readfirstlane((int)v);
-    const int hi = __builtin_amdgcn_readfirstlane((int)(v >> 32));
-    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
-
 __device__ __forceinline__ float uniform_f32(float x)
 {
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
