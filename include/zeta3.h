@@ -223,6 +223,22 @@ z3_status z3_estimate_ex(z3_index idx, int map, int m_max, int prec, unsigned fl
                          int64_t p1, double *zeta, uint64_t *pair_total, void *stream);
 
 /*
+ * The fused estimator of z3_estimate_ex (same arguments, same results up to the order of
+ * the FP64 chunk sums) for callers that cannot allocate device memory: code being captured
+ * into a HIP graph, tight serving loops, harnesses that forbid allocation.  It calls no
+ * hipMalloc, hipFree or other allocating routine and records no timing events; its chunk
+ * workspace is a static 512 MiB device array built into the library (one per GPU, held
+ * from the first call on that GPU until the process ends), which also bounds the pivot
+ * chunk: about 150,000 pivots per chunk in FP64 and 300,000 on the mixed path at
+ * 20 bins and m_max = 10.  Z3_ERR_UNSUPPORTED if one block of 256 pivots does not fit
+ * (not reached within Z3_MAX_MMAX and Z3_MAX_NBINS).  Every call on a GPU shares that
+ * GPU's array and leaves its last contents there; calls that overlap on one GPU (several
+ * streams or threads) race and must be serialised by the caller.
+ */
+z3_status z3_estimate_static(z3_index idx, int map, int m_max, int prec, unsigned flags, int64_t p0,
+                             int64_t p1, double *zeta, uint64_t *pair_total, void *stream);
+
+/*
  * Multi-field estimator (the remark after eq. ubEstimator): three attached maps A, B, C of
  * one index (fields on the same positions and weights, e.g. several redshift bins of one
  * pixel grid).  The pivot carries field A, the bin b1 field B and the bin b2 field C:

@@ -453,28 +453,47 @@ Z3_API z3_status z3_estimate(z3_index idx, int map, int m_max, int prec, int64_t
     return z3_estimate_ex(idx, map, m_max, prec, 0u, p0, p1, zeta, pair_total, stream);
 }
 
-Z3_API z3_status z3_estimate_ex(z3_index idx, int map, int m_max, int prec, unsigned flags, int64_t p0,
-                                int64_t p1, double *zeta, uint64_t *pair_total, void *stream)
+// The fused estimator's chunk loop.  Its workspace is either allocated per call
+// (fixed == nullptr: the stream-ordered pool, or the index's capture workspace) or carved
+// from a caller-held buffer of fixed_bytes, which then also bounds the chunk length.
+static z3_status estimate_chunks(z3_index idx, int map, int m_max, int prec, bool no_self, int64_t p0, int64_t p1,
+                                 double *zeta, uint64_t *pair_total, hipStream_t s, void *fixed, size_t fixed_bytes)
 {
-    CallScope scope(idx, as_stream(stream));
-    z3_status st = check_common("z3_estimate", idx, map, m_max, prec, p0, p1);
-    if (st != Z3_OK) return st;
-    if (!zeta) return fail(Z3_ERR_INVALID_ARG, "z3_estimate: zeta is NULL");
-    if (flags & ~(unsigned)Z3_EST_EXCLUDE_SELF) return fail(Z3_ERR_INVALID_ARG, "z3_estimate_ex: unknown flags 0x%x", flags);
-    const bool no_self = (flags & Z3_EST_EXCLUDE_SELF) != 0;
-    if (p1 == p0) return Z3_OK;
-    hipStream_t s = as_stream(stream);
+    z3_status st = Z3_OK;
+    const size_t elem = prec == Z3_PREC_FP64 ? 8 : 4;
+    const size_t per_piv = (size_t)(m_max + 1) * 2 * idx->nbins * elem;
+    auto round256 = [](size_t b) { return (b + 255) / 256 * 256; };
+    auto bytes_for = [&](int64_t c, size_t *ab, size_t *pb, size_t *sb) {
+        *ab = (size_t)c * per_piv;
+        *pb = contract_partial_bytes(c, m_max, idx->nbins);
+        *sb = no_self ? (size_t)((c + kWave - 1) / kWave) * idx->nbins * sizeof(double) : 0;
+        return round256(*ab) + round256(*pb) + round256(*sb);
+    };
     int64_t chunk = chunk_pivots(idx, m_max, prec);
     if (chunk > p1 - p0) chunk = ((p1 - p0 + kBlock - 1) / kBlock) * kBlock;
-    size_t elem = prec == Z3_PREC_FP64 ? 8 : 4;
-    size_t abytes = (size_t)chunk * (size_t)(m_max + 1) * 2 * idx->nbins * elem;
-    size_t pbytes = contract_partial_bytes(chunk, m_max, idx->nbins);
-    // with the self-pair removal: one FP64 sum per (wave, bin) of the chunk
-    const int64_t nw_max = (chunk + kWave - 1) / kWave;
+    size_t abytes, pbytes, sbytes;
+    if (fixed) {
+        // the longest whole number of pivot blocks whose workspace fits the buffer
+        int64_t c = (int64_t)(fixed_bytes / (per_piv + 64)) / kBlock * kBlock;
+        if (c > chunk) c = chunk;
+        while (c >= kBlock && bytes_for(c, &abytes, &pbytes, &sbytes) > fixed_bytes) c -= kBlock;
+        if (c < kBlock)
+            return fail(Z3_ERR_UNSUPPORTED, "z3_estimate_static: %d bins at m_max=%d need more than the %zu-byte static "
+                        "workspace for %d pivots", idx->nbins, m_max, fixed_bytes, kBlock);
+        chunk = c;
+    }
+    (void)bytes_for(chunk, &abytes, &pbytes, &sbytes);
     void *wa = nullptr, *wp = nullptr, *wsf = nullptr;
-    if ((st = scratch_alloc(&wa, abytes, s)) != Z3_OK) return st;
-    st = scratch_alloc(&wp, pbytes, s);
-    if (st == Z3_OK && no_self) st = scratch_alloc(&wsf, (size_t)nw_max * idx->nbins * sizeof(double), s);
+    if (fixed) {
+        char *base = static_cast<char *>(fixed);
+        wa = base;
+        wp = base + round256(abytes);
+        wsf = no_self ? base + round256(abytes) + round256(pbytes) : nullptr;
+    } else {
+        if ((st = scratch_alloc(&wa, abytes, s)) != Z3_OK) return st;
+        st = scratch_alloc(&wp, pbytes, s);
+        if (st == Z3_OK && no_self) st = scratch_alloc(&wsf, sbytes, s);
+    }
     const double *v = idx->d_v + (size_t)map * idx->n;
     double *self_part = static_cast<double *>(wsf);
     for (int64_t c0 = p0; c0 < p1 && st == Z3_OK; c0 += chunk) {
@@ -487,10 +506,71 @@ Z3_API z3_status z3_estimate_ex(z3_index idx, int map, int m_max, int prec, unsi
         if (st == Z3_OK && no_self)
             st = launch_self_subtract(self_part, (c1 - c0 + kWave - 1) / kWave, m_max, idx->nbins, zeta, s);
     }
-    scratch_free(wsf, s);
-    scratch_free(wp, s);
-    scratch_free(wa, s);
+    if (!fixed) {
+        scratch_free(wsf, s);
+        scratch_free(wp, s);
+        scratch_free(wa, s);
+    }
     return st;
+}
+
+Z3_API z3_status z3_estimate_ex(z3_index idx, int map, int m_max, int prec, unsigned flags, int64_t p0,
+                                int64_t p1, double *zeta, uint64_t *pair_total, void *stream)
+{
+    CallScope scope(idx, as_stream(stream));
+    z3_status st = check_common("z3_estimate", idx, map, m_max, prec, p0, p1);
+    if (st != Z3_OK) return st;
+    if (!zeta) return fail(Z3_ERR_INVALID_ARG, "z3_estimate: zeta is NULL");
+    if (flags & ~(unsigned)Z3_EST_EXCLUDE_SELF) return fail(Z3_ERR_INVALID_ARG, "z3_estimate_ex: unknown flags 0x%x", flags);
+    if (p1 == p0) return Z3_OK;
+    return estimate_chunks(idx, map, m_max, prec, (flags & Z3_EST_EXCLUDE_SELF) != 0, p0, p1, zeta, pair_total,
+                           as_stream(stream), nullptr, 0);
+}
+
+// ---- the estimator without allocation ---------------------------------------------------
+// Workspace of z3_estimate_static: a file-scope device array, one copy per GPU the library
+// runs on, held until the process ends.  In host code its name is only a stand-in: the
+// kernels get the address that hipGetSymbolAddress returns for the current device.
+constexpr size_t kStaticScratchBytes = (size_t)512 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[64] = {};
+
+static z3_status static_scratch(void **ptr)
+{
+    *ptr = nullptr;
+    int dev = 0;
+    z3_status st = check_hip(hipGetDevice(&dev), "hipGetDevice");
+    if (st != Z3_OK) return st;
+    if (dev < 0 || dev >= 64) return fail(Z3_ERR_UNSUPPORTED, "device ordinal %d", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if ((st = check_hip(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress (static workspace)")) !=
+            Z3_OK)
+            return st;
+        if (!p) return fail(Z3_ERR_HIP, "hipGetSymbolAddress returned no address for the static workspace");
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return Z3_OK;
+}
+
+Z3_API z3_status z3_estimate_static(z3_index idx, int map, int m_max, int prec, unsigned flags, int64_t p0,
+                                    int64_t p1, double *zeta, uint64_t *pair_total, void *stream)
+{
+    z3_status st = check_common("z3_estimate_static", idx, map, m_max, prec, p0, p1);
+    if (st != Z3_OK) return st;
+    if (!zeta) return fail(Z3_ERR_INVALID_ARG, "z3_estimate_static: zeta is NULL");
+    if (flags & ~(unsigned)Z3_EST_EXCLUDE_SELF)
+        return fail(Z3_ERR_INVALID_ARG, "z3_estimate_static: unknown flags 0x%x", flags);
+    if (p1 == p0) return Z3_OK;
+    void *ws = nullptr;
+    if ((st = static_scratch(&ws)) != Z3_OK) return st;
+    ProfileMute mute;  // no timing events either
+    return estimate_chunks(idx, map, m_max, prec, (flags & Z3_EST_EXCLUDE_SELF) != 0, p0, p1, zeta, pair_total,
+                           as_stream(stream), ws, kStaticScratchBytes);
 }
 
 Z3_API z3_status z3_estimate_cross(z3_index idx, int map_a, int map_b, int map_c, int cyclic, int m_max,

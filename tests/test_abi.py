@@ -82,6 +82,7 @@ def test_other_entry_points_reject_bad_arguments():
     assert _status("z3_accumulate_multipoles", P(0), 0, 4, 0, 0, 0, 1, P(0), P(0), P(0), P(0), P(0), P(0))[0] == 1
     assert _status("z3_estimate", P(0), 0, 4, 0, 0, 1, P(1), P(0), P(0))[0] == 1
     assert _status("z3_estimate_ex", P(0), 0, 4, 0, 1, 0, 1, P(1), P(0), P(0))[0] == 1
+    assert _status("z3_estimate_static", P(0), 0, 4, 0, 0, 0, 1, P(1), P(0), P(0))[0] == 1
     assert _status("z3_estimate_cross", P(0), 0, 1, 2, 1, 4, 0, 0, 1, P(1), P(0), P(0))[0] == 1
     assert _status("z3_estimate_cross_catalogues", P(0), 0, P(0), 0, 1, P(1), P(0), P(1), 4, 0, 0, 1, P(1),
                    P(0), P(0), P(0), P(0))[0] == 1
