@@ -193,61 +193,56 @@ void k_multipoles(MultArgs a)
                 uint32_t off = (uint32_t)(seg == 0 ? s0 : s1) * 32u;
                 const uint32_t oend = off + (uint32_t)(seg == 0 ? l0 : l1) * 32u;
                 {
-                    // two candidates per step, both carried through the bearing and the
-                    // recurrences (a rejected or missing one with weight 0), so that two
-                    // independent FP64 dependency chains interleave
-                    for (; off < oend; off += 64u) {
-                        const bool two = off + 32u < oend;
-                        const double4 r0 = load_record(rband, off);
-                        const double4 r1 = load_record(rband, two ? off + 32u : off);
-                        const double dx0 = r0.x - xp, dy0 = r0.y - yp, dz0 = r0.z - zp;
-                        const double dx1 = r1.x - xp, dy1 = r1.y - yp, dz1 = r1.z - zp;
-                        const double d20 = (dx0 * dx0 + dy0 * dy0) + dz0 * dz0;
-                        const double d21 = (dx1 * dx1 + dy1 * dy1) + dz1 * dz1;
-                        const bool in0 = d20 >= elo && d20 < ehi;
-                        const bool in1 = two && d21 >= elo && d21 < ehi;
-                        if (in0 || in1) {
-                            cnt += (in0 ? 1 : 0) + (in1 ? 1 : 0);
+                    // one candidate at a time, its record requested one candidate ahead so
+                    // that an L2 or HBM miss overlaps the previous candidate's work; two
+                    // candidates per trip with two record registers in turn, so the record
+                    // requested ahead needs no copy.  Past the window a request reads a
+                    // record of the band that is never used (or, past the band, zeros from
+                    // the buffer's range check).
+                    auto cand = [&](const double4 &r, uint32_t o) __attribute__((always_inline)) {
+                        const double dx = r.x - xp, dy = r.y - yp, dz = r.z - zp;
+                        const double d2 = (dx * dx + dy * dy) + dz * dz;
+                        if (d2 >= elo && d2 < ehi) {
+                            cnt += 1;
                             if (IDS || !unit_w) {  // wave-uniform
+                                // record index from the byte offset, as an opaque shift so
+                                // that the compiler keeps no second induction variable
                                 uint32_t jo;
-                                asm("v_lshrrev_b32 %0, 5, %1" : "=v"(jo) : "v"(off));
+                                asm("v_lshrrev_b32 %0, 5, %1" : "=v"(jo) : "v"(o));
                                 const int j = base + (int)jo;
-                                if (in0) {
-                                    if (!unit_w) Wb += a.wdbl[j];
-                                    if constexpr (IDS) hsum += mix64((uint64_t)a.permdbl[j]);
-                                }
-                                if (in1) {
-                                    if (!unit_w) Wb += a.wdbl[j + 1];
-                                    if constexpr (IDS) hsum += mix64((uint64_t)a.permdbl[j + 1]);
-                                }
+                                if (!unit_w) Wb += a.wdbl[j];
+                                if constexpr (IDS) hsum += mix64((uint64_t)a.permdbl[j]);
                             }
-                            const double u10 = fma(dx0, nx, fma(dy0, ny, dz0 * nz));
-                            const double u20 = fma(dx0, ex, fma(dy0, ey, dz0 * ez));
-                            const double u11 = fma(dx1, nx, fma(dy1, ny, dz1 * nz));
-                            const double u21 = fma(dx1, ex, fma(dy1, ey, dz1 * ez));
-                            double c0, sn0, c1, sn1;
-                            unit_bearing(u10, u20, c0, sn0);
-                            unit_bearing(u11, u21, c1, sn1);
-                            const double v0 = in0 ? r0.w : 0.0, v1 = in1 ? r1.w : 0.0;
-                            if constexpr (SELF) Qb = fma(v1, v1, fma(v0, v0, Qb));
-                            Y[0] += v0 + v1;
+                            const double v = r.w;
+                            if constexpr (SELF) Qb = fma(v, v, Qb);
+                            const double u1 = fma(dx, nx, fma(dy, ny, dz * nz));
+                            const double u2 = fma(dx, ex, fma(dy, ey, dz * ez));
+                            double c, sn;
+                            unit_bearing(u1, u2, c, sn);
+                            Y[0] += v;
                             if constexpr (M >= 1) {
-                                const double tc0 = c0 + c0, tc1 = c1 + c1;
-                                double p2 = v0, p1 = v0 * c0, q2 = 0.0, q1 = v0 * sn0;
-                                double g2 = v1, g1 = v1 * c1, h2 = 0.0, h1 = v1 * sn1;
-                                Y[1] += p1 + g1;
-                                Z[1] += q1 + h1;
+                                const double tc = c + c;
+                                double t2 = v, t1 = v * c, s2 = 0.0, s1 = v * sn;
+                                Y[1] += t1;
+                                Z[1] += s1;
 #pragma unroll
                                 for (int m = 2; m <= M; ++m) {
-                                    const double pm = fma(tc0, p1, -p2), qm = fma(tc0, q1, -q2);
-                                    const double gm = fma(tc1, g1, -g2), hm = fma(tc1, h1, -h2);
-                                    Y[m] += pm + gm;
-                                    Z[m] += qm + hm;
-                                    p2 = p1; p1 = pm; q2 = q1; q1 = qm;
-                                    g2 = g1; g1 = gm; h2 = h1; h1 = hm;
+                                    const double tm = fma(tc, t1, -t2), sm = fma(tc, s1, -s2);
+                                    Y[m] += tm;
+                                    Z[m] += sm;
+                                    t2 = t1; t1 = tm;
+                                    s2 = s1; s1 = sm;
                                 }
                             }
                         }
+                    };
+                    double4 ra = load_record(rband, off < oend ? off : 0u);
+                    for (; off < oend; off += 64u) {
+                        const double4 rb = load_record(rband, off + 32u);
+                        cand(ra, off);
+                        if (off + 32u >= oend) break;
+                        ra = load_record(rband, off + 64u);
+                        cand(rb, off + 32u);
                     }
                 }
             }
