@@ -27,6 +27,8 @@ def _load():
         lib.zo_zeta.argtypes = [I64, P, P, P, P, P, I64, P, P, P, P, P, ctypes.c_int, P, ctypes.c_int,
                                 P, P, ctypes.c_int]
         lib.zo_zeta.restype = ctypes.c_int
+        lib.zo_setup_seconds.argtypes = [I64, P, P, P, P, P, ctypes.c_int, P, ctypes.c_int]
+        lib.zo_setup_seconds.restype = ctypes.c_double
         _lib = lib
     return _lib
 
@@ -99,6 +101,21 @@ def estimate(piv, nbr, w, x, edges, m_max, wp, xp, nthreads=0, self_pairs=True):
         d = ref.self_pair_term(W, q[:, 0, :].real, np.asarray(pv, np.float64))
         z[:, np.arange(nb), np.arange(nb)] -= d[None, :] / np.sum(wp)
     return z, int(pairs[0])
+
+
+def setup_seconds(nbr, w, x, edges, m_max):
+    """Seconds the C oracle spends building its neighbour grid (part of every estimate call)."""
+    lib = _load()
+    nbr = _c(nbr)
+    w = _c(w)
+    v = _c(np.asarray(w, np.float64) * np.asarray(x, np.float64))
+    edges = _c(edges)
+    nx, ny, nz = _c(nbr[0]), _c(nbr[1]), _c(nbr[2])
+    t = lib.zo_setup_seconds(nbr.shape[1], _ptr(nx), _ptr(ny), _ptr(nz), _ptr(w), _ptr(v), len(edges) - 1,
+                             _ptr(edges), m_max)
+    if t < 0:
+        raise RuntimeError("zo_setup_seconds failed")
+    return t
 
 
 def estimate_cross(piv, nbr, w, fields, edges, m_max, wp, pivot_fields, cyclic=False, nthreads=0):

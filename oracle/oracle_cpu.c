@@ -202,6 +202,20 @@ int zo_multipoles(int64_t n, const double *x, const double *y, const double *z,
 }
 
 /*
+ * Wall time of the oracle's catalogue set-up alone (the cube grid over all n neighbours,
+ * which zo_zeta and zo_multipoles build on every call), in seconds; -1 on failure.
+ */
+double zo_setup_seconds(int64_t n, const double *x, const double *y, const double *z,
+                        const double *w, const double *v, int nb, const double *edges, int m_max)
+{
+    const double t0 = omp_get_wtime();
+    catalogue c;
+    if (catalogue_init(&c, n, x, y, z, w, v, nb, edges, m_max)) return -1.0;
+    grid_free(&c.cg);
+    return omp_get_wtime() - t0;
+}
+
+/*
  * zeta over the given pivots: zeta[m][b1][b2][2] = (1/sum w_p) sum_p v_p X(b1) conj X(b2)
  * (pivot values vp = w_p x_p, pivot weights pw).  Pivots are processed in blocks of
  * 1024; each block's partial sum is added in block order, so the result does not
