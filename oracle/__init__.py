@@ -9,6 +9,8 @@ Contents
 --------
 ref.py          plain NumPy estimator (direct trigonometry), for catalogues up to ~1e5 points
 brute.py        brute-force triplet sum that needs no reference direction (tiny inputs)
+hist.py         angular-histogram + Fourier-sum estimator (the histogram picture of the
+                complexity discussion; each pair at its angular bin's centre)
 oracle_cpu.c    plain C + OpenMP FP64 estimator with its own cube-grid search (large inputs)
 cpu.py          ctypes wrapper of the compiled oracle_cpu.c
 build.py        compiles oracle_cpu.c with gcc (-O2 -ffp-contract=off -fopenmp)

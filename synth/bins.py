@@ -40,3 +40,19 @@ def chord2_edges(theta: np.ndarray) -> np.ndarray:
 
 def arcmin(x: float) -> float:
     return math.radians(x / 60.0)
+
+
+def phi_boundaries(n_phi: int) -> np.ndarray:
+    """Boundary directions of n_phi equal angular bins around a pivot: row k is
+    (cos(2 pi k / n_phi), sin(2 pi k / n_phi)) in FP64 ([n_phi, 2]).
+
+    Angular bin k holds the bearings [2 pi k / n_phi, 2 pi (k + 1) / n_phi), bearings
+    measured from local north towards east.  Every implementation receives this table
+    and decides bin membership by sign tests against these very numbers, as the radial
+    bins are decided against the chord-squared table.
+    """
+    if n_phi < 4:
+        raise ValueError("need n_phi >= 4")
+    k = np.arange(n_phi, dtype=np.float64)
+    t = 2.0 * np.pi * k / n_phi
+    return np.ascontiguousarray(np.stack([np.cos(t), np.sin(t)], axis=1))

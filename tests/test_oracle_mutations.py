@@ -160,3 +160,39 @@ def test_cross_catalogues_shared_normaliser_fails_brute(monkeypatch):
     monkeypatch.setattr(ref, "estimate_cross_catalogues", wrong)
     with pytest.raises(AssertionError):
         pins.check_cross_catalogues_brute()
+
+
+# ---- angular-histogram estimator (oracle/hist.py) ------------------------------------------
+
+from oracle import hist  # noqa: E402
+from tests import test_oracle_hist as H  # noqa: E402
+
+
+def test_hist_bin_start_phase_fails_ring_closed_form(monkeypatch):
+    def start(Hh, m_max):
+        F = np.fft.fft(Hh, axis=-1)
+        return F[..., :m_max + 1]  # every pair at its bin's start, no half-bin phase
+    monkeypatch.setattr(hist, "fourier_over_bins", start)
+    with pytest.raises(AssertionError):
+        H.test_ring_closed_form(8, 5, 3)
+
+
+def test_hist_conjugated_transform_fails_three_point(monkeypatch):
+    orig = hist.fourier_over_bins
+    monkeypatch.setattr(hist, "fourier_over_bins", lambda Hh, m: np.conj(orig(Hh, m)))
+    with pytest.raises(AssertionError):
+        H.test_three_point_golden(8)
+
+
+def test_hist_mirrored_boundaries_fail_bearing_bins(monkeypatch):
+    orig = hist.angular_bin
+    monkeypatch.setattr(hist, "angular_bin", lambda u1, u2, b: orig(u1, u2, b * np.array([1.0, -1.0])))
+    with pytest.raises(AssertionError):
+        H.test_bins_match_direct_bearing(16)
+
+
+def test_hist_flipped_east_fails_bearing_bins(monkeypatch):
+    orig = hist.frame_unnormalised
+    monkeypatch.setattr(hist, "frame_unnormalised", lambda piv: (orig(piv)[0], -orig(piv)[1]))
+    with pytest.raises(AssertionError):
+        H.test_bins_match_direct_bearing(16)
