@@ -147,6 +147,9 @@ def main():
                     help="with --adjoint: check the gradient at this many random (map, pixel) entries against "
                          "central differences of the FP64 forward (after the timed steps)")
     ap.add_argument("--cpu-sample", type=int, default=-1, help="oracle pivots (-1: automatic, 0: skip)")
+    ap.add_argument("--hist", type=int, default=0, metavar="N_PHI",
+                    help="angular-histogram estimator with N_PHI angular bins (one-map exact search on the "
+                         "sky; --m-max up to N_PHI/2 - 1)")
     ap.add_argument("--with-4096", default="auto", choices=["auto", "on", "off"],
                     help="after the timed steps, one step of the Nside 4096 map (exact and approximate search, "
                          "both precisions) as a nested record; auto: with the default Nside 2048 run")
@@ -191,6 +194,10 @@ def main():
         cfg = dataclasses.replace(cfg, m_max=args.m_max, name=f"{cfg.name}@m{args.m_max}")
     if cfg.kind == "plane" and (args.approx or args.adjoint or args.cross or args.graph):
         print("the plane workload runs the one-map estimator only", file=sys.stderr)
+        sys.exit(2)
+    if args.hist and (cfg.kind != "healpix" and cfg.kind != "cap" or args.approx or args.adjoint or args.cross
+                      or args.exclude_self or args.graph or cfg.nmaps > 1):
+        print("--hist runs the one-map exact search on a sky workload", file=sys.stderr)
         sys.exit(2)
     if (args.exclude_self or args.cross) and (args.approx or args.adjoint or cfg.nmaps > 1):
         print("--exclude-self and --cross apply to the one-map exact search only", file=sys.stderr)
@@ -303,6 +310,12 @@ def main():
             idx = z3.Index(xyz, E)
             idx.set_values(x3)
             z3.estimate_cross_raw(idx, (0, 1, 2), M, prec, True, zeta=zeta, pair_total=pairs, sum_w=sw)
+        elif args.hist:
+            from synth import phi_boundaries
+            idx = z3.Index(xyz, E)
+            idx.set_values(x)
+            idx.set_phi_bins(phi_boundaries(args.hist))
+            z3.estimate_hist_raw(idx, M, prec=prec, zeta=zeta, pair_total=pairs, sum_w=sw)
         elif nbr is None:
             idx = z3.Index(xyz, E, planar=cfg.kind == "plane")
             idx.set_values(x)
@@ -355,6 +368,12 @@ def main():
         rf_kernel, rf_bound, rf_peak = "k_multipoles_batch", "mfma", PEAK_MFMA_TFLOPS[main_prec]
         rf_flops = 2.0 * (2 * M + 1) * r["pairs"] * cfg.nmaps
         rf_unit_note = "2 (2 m_max + 1) flop per (pair, map)"
+    elif args.hist:
+        # per pair: separation 3, chord 5 + 2 tests, tangent components 10, sign tests 6,
+        # histogram add 1 = 27 flop; per (pivot, bin, angular bin, m): 4 flop of the transform
+        rf_kernel, rf_bound, rf_peak = "k_multipoles_hist", "alu", PEAK_VALU_TFLOPS["fp64"]
+        rf_flops = 27.0 * r["pairs"] + 4.0 * n * cfg.nbins * args.hist * (M + 1)
+        rf_unit_note = "27 flop per pair + 4 flop per (pivot, radial bin, angular bin, m)"
     else:
         rf_kernel, rf_bound, rf_peak = "k_multipoles", "alu", PEAK_VALU_TFLOPS[main_prec]
         rf_flops = FLOPS_PER_UPDATE * updates
@@ -374,6 +393,7 @@ def main():
         "dtype": "f64" if main_prec == "fp64" else "f64 multipoles, f32 storage + split-f32 MFMA",
         "data": "synthetic",
         "config": {"workload": cfg.name + ("+approx" if nbr else "") + ("+adjoint" if args.adjoint else "")
+                   + (f"+hist{args.hist}" if args.hist else "")
                    + ("+noself" if not self_pairs else "") + ("+cross3" if args.cross else "")
                    + (f"+shard{shard[0]}of{shard[1]}" if shard else ""),
                    "npoints": n, "nmaps": cfg.nmaps, "nbins": cfg.nbins, "m_max": M,
@@ -409,10 +429,11 @@ def main():
         out["config"]["workload"] += "+graph"
     if args.save_zeta:
         np.savez(args.save_zeta, **{p: res[p]["zeta"] for p in res})
-    if args.cpu_sample != 0 and cfg.nmaps == 1 and not args.cross and cfg.kind != "plane" and shard is None:
+    if args.cpu_sample != 0 and cfg.nmaps == 1 and not args.cross and cfg.kind != "plane" and shard is None \
+            and not args.hist:
         out["cpu_baseline"] = cpu_baseline(cfg, xyz, x, nbr, E, M, args.cpu_sample, z3, torch, self_pairs)
     plain = (args.config == "nside2048" and args.nside == 0 and args.m_max < 0 and not (
-        args.approx or args.adjoint or args.cross or args.exclude_self or shard or args.graph))
+        args.approx or args.adjoint or args.cross or args.exclude_self or shard or args.graph or args.hist))
     if args.with_4096 == "on" or (args.with_4096 == "auto" and plain and args.prec == "both"):
         del xyz, x
         torch.cuda.empty_cache()

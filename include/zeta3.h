@@ -78,6 +78,9 @@ enum {
 /* Largest supported multipole and bin count. */
 #define Z3_MAX_MMAX 16
 #define Z3_MAX_NBINS 64
+/* Angular-histogram estimator: bins per circle and largest multipole (m_max < n_phi / 2). */
+#define Z3_MAX_NPHI 256
+#define Z3_MAX_MMAX_HIST 127
 
 /*
  * Build the sky-cell index of a catalogue of n points (the neighbour search of the
@@ -237,6 +240,48 @@ z3_status z3_estimate_ex(z3_index idx, int map, int m_max, int prec, unsigned fl
  */
 z3_status z3_estimate_static(z3_index idx, int map, int m_max, int prec, unsigned flags, int64_t p0,
                              int64_t p1, double *zeta, uint64_t *pair_total, void *stream);
+
+/*
+ * Angular bins of the histogram estimator (the complexity discussion of the "3PCF binned
+ * estimator" subsection: histograms around each pivot in radial and n_phi angular bins,
+ * then a Fourier transform over the angular bins).  bounds [host] [n_phi][2] FP64 holds the
+ * boundary directions (cos, sin)(2 pi k / n_phi), k = 0..n_phi-1 (angular bin k covers the
+ * bearings [2 pi k, 2 pi (k+1)) / n_phi, measured from local north towards east); every
+ * row must lie within 1e-15 of those values (Z3_ERR_INVALID_ARG otherwise), 4 <= n_phi <=
+ * Z3_MAX_NPHI.  The pair's bin is decided by sign tests against exactly these numbers:
+ * bin k iff c_k u2 - s_k u1 >= 0 and c_{k+1} u2 - s_{k+1} u1 < 0, with (u1, u2) the
+ * separation's components on the unnormalised local north N = (-z x, -z y, 1 - z z)
+ * (N = (1 - x x, -x y, -x z) where (N.N) < 1e-24) and east E = N x r_p, every product and
+ * sum rounded on its own and summed as (x + y) + z.  Sky indexes only (Z3_ERR_UNSUPPORTED
+ * on a plane).  Allocates and copies synchronously; replaces earlier bins of the index.
+ */
+z3_status z3_index_set_phi_bins(z3_index idx, int n_phi, const double *bounds);
+
+/*
+ * Per-pivot multipoles of the histogram estimator for pivots [p0, p1) in index order:
+ *   H_{p,b,k} = sum of w_j x_j over the pairs of radial bin b and angular bin k,
+ *   a_{m,b}(p) = sum_k H_{p,b,k} exp(-i m (k + 1/2) dphi)   (each pair at its bin centre),
+ * then X = a / W_{p,b} (Z3_NORM_BIN) as in z3_accumulate_multipoles, for
+ * 0 <= m_max < n_phi / 2 (and <= Z3_MAX_MMAX_HIST).  Outputs as z3_accumulate_multipoles
+ * (A [m_max+1][2][nbins][P] FP64 or FP32 per prec, W, counts; each may be NULL), plus
+ *   counts_phi [nbins][n_phi][P] int32 pairs per (pivot, radial bin, angular bin), or NULL
+ * (needs 816 n_phi bytes of LDS per block, 560 n_phi without counts_phi; Z3_ERR_UNSUPPORTED
+ * beyond the device's limit).  Sums are FP64 on both precisions.
+ */
+z3_status z3_accumulate_histogram(z3_index idx, int map, int m_max, int prec, int norm, int64_t p0,
+                                  int64_t p1, void *A, double *W, int64_t *counts, int *counts_phi,
+                                  uint64_t *pair_total, void *stream);
+
+/*
+ * Fused histogram estimator for pivots [p0, p1): the multipoles of z3_accumulate_histogram
+ * per pivot chunk, contracted as in z3_estimate (eq. zetamEst); zeta [m_max+1][nbins][nbins][2]
+ * += (unnormalised), pair_total += pairs (may be NULL).  Both precisions keep the chunk's
+ * multipoles in FP64 and contract them in FP64 (identical results): the pair walk and the
+ * transform, FP64 on both, are the whole cost, and FP32 storage would reach ~1e-6 relative
+ * error on noise-dominated high multipoles.
+ */
+z3_status z3_estimate_histogram(z3_index idx, int map, int m_max, int prec, int64_t p0, int64_t p1,
+                                double *zeta, uint64_t *pair_total, void *stream);
 
 /*
  * Multi-field estimator (the remark after eq. ubEstimator): three attached maps A, B, C of

@@ -32,6 +32,9 @@ SIGNATURES = {
     "z3_estimate": (_I, [_P, _I, _I, _I, _I64, _I64, _P, _P, _P]),
     "z3_estimate_ex": (_I, [_P, _I, _I, _I, ctypes.c_uint, _I64, _I64, _P, _P, _P]),
     "z3_estimate_static": (_I, [_P, _I, _I, _I, ctypes.c_uint, _I64, _I64, _P, _P, _P]),
+    "z3_index_set_phi_bins": (_I, [_P, _I, _P]),
+    "z3_accumulate_histogram": (_I, [_P, _I, _I, _I, _I, _I64, _I64, _P, _P, _P, _P, _P, _P]),
+    "z3_estimate_histogram": (_I, [_P, _I, _I, _I, _I64, _I64, _P, _P, _P]),
     "z3_estimate_cross": (_I, [_P, _I, _I, _I, _I, _I, _I, _I64, _I64, _P, _P, _P]),
     "z3_estimate_cross_catalogues": (_I, [_P, _I, _P, _I, _I64, _P, _P, _P, _I, _I, _I64, _I64, _P, _P, _P, _P,
                                           _P]),

@@ -322,7 +322,7 @@ Z3_API z3_status z3_contract(int64_t npiv, int m_max, int nbins, int prec, const
 {
     CallScope scope(nullptr, as_stream(stream));
     if (npiv < 0) return fail(Z3_ERR_INVALID_ARG, "z3_contract: npiv < 0");
-    if (m_max < 0 || m_max > Z3_MAX_MMAX) return fail(Z3_ERR_INVALID_ARG, "z3_contract: bad m_max");
+    if (m_max < 0 || m_max > Z3_MAX_MMAX_HIST) return fail(Z3_ERR_INVALID_ARG, "z3_contract: bad m_max");
     if (nbins < 1 || nbins > Z3_MAX_NBINS) return fail(Z3_ERR_INVALID_ARG, "z3_contract: bad nbins");
     if (prec != Z3_PREC_FP64 && prec != Z3_PREC_MIXED)
         return fail(Z3_ERR_INVALID_ARG, "z3_contract: unknown precision %d", prec);
@@ -525,6 +525,110 @@ Z3_API z3_status z3_estimate_ex(z3_index idx, int map, int m_max, int prec, unsi
     if (p1 == p0) return Z3_OK;
     return estimate_chunks(idx, map, m_max, prec, (flags & Z3_EST_EXCLUDE_SELF) != 0, p0, p1, zeta, pair_total,
                            as_stream(stream), nullptr, 0);
+}
+
+// ---- angular-histogram estimator ---------------------------------------------------------
+
+Z3_API z3_status z3_index_set_phi_bins(z3_index idx, int n_phi, const double *bounds)
+{
+    if (!idx) return fail(Z3_ERR_INVALID_ARG, "z3_index_set_phi_bins: idx is NULL");
+    if (idx->planar) return fail(Z3_ERR_UNSUPPORTED, "z3_index_set_phi_bins: sky indexes only");
+    if (n_phi < 4 || n_phi > Z3_MAX_NPHI)
+        return fail(Z3_ERR_INVALID_ARG, "z3_index_set_phi_bins: n_phi=%d outside 4..%d", n_phi, Z3_MAX_NPHI);
+    if (!bounds) return fail(Z3_ERR_INVALID_ARG, "z3_index_set_phi_bins: bounds is NULL");
+    // the bin centres (k + 1/2) 2 pi / n_phi of the transform assume equal bins from north
+    for (int k = 0; k < n_phi; ++k) {
+        const double t = kTwoPi * k / n_phi;
+        const double c = bounds[2 * k], sn = bounds[2 * k + 1];
+        if (!(std::fabs(c - std::cos(t)) <= 1e-15 && std::fabs(sn - std::sin(t)) <= 1e-15))
+            return fail(Z3_ERR_INVALID_ARG,
+                        "z3_index_set_phi_bins: row %d is not (cos, sin)(2 pi %d / %d) to 1e-15", k, k, n_phi);
+    }
+    std::vector<double> tab(4 * (size_t)n_phi);
+    for (int j = 0; j < 2 * n_phi; ++j) {
+        tab[2 * j] = std::cos(kPi * j / n_phi);
+        tab[2 * j + 1] = std::sin(kPi * j / n_phi);
+    }
+    z3_status st = check_hip(hipSetDevice(idx->device), "hipSetDevice");
+    if (st != Z3_OK) return st;
+    double2 *db = nullptr, *dt = nullptr;
+    st = check_hip(hipMalloc((void **)&db, (size_t)n_phi * sizeof(double2)), "hipMalloc (angular bins)");
+    if (st == Z3_OK) st = check_hip(hipMalloc((void **)&dt, 2 * (size_t)n_phi * sizeof(double2)), "hipMalloc (phases)");
+    if (st == Z3_OK)
+        st = check_hip(hipMemcpy(db, bounds, (size_t)n_phi * sizeof(double2), hipMemcpyHostToDevice), "copy bins");
+    if (st == Z3_OK)
+        st = check_hip(hipMemcpy(dt, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice), "copy phases");
+    if (st == Z3_OK) st = check_hip(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    if (st != Z3_OK) {
+        if (db) (void)hipFree(db);
+        if (dt) (void)hipFree(dt);
+        return st;
+    }
+    if (idx->d_phi_bounds) (void)hipFree(idx->d_phi_bounds);
+    if (idx->d_phi_tab) (void)hipFree(idx->d_phi_tab);
+    idx->d_phi_bounds = db;
+    idx->d_phi_tab = dt;
+    idx->n_phi = n_phi;
+    return Z3_OK;
+}
+
+static z3_status check_hist(const char *fn, const z3_index_s *idx, int map, int m_max, int prec, int64_t p0,
+                            int64_t p1)
+{
+    if (!idx) return fail(Z3_ERR_INVALID_ARG, "%s: idx is NULL", fn);
+    if (idx->n_phi < 4) return fail(Z3_ERR_INVALID_ARG, "%s: no angular bins (z3_index_set_phi_bins)", fn);
+    if (m_max < 0 || m_max > Z3_MAX_MMAX_HIST || 2 * m_max >= idx->n_phi)
+        return fail(Z3_ERR_INVALID_ARG, "%s: m_max=%d outside 0..min(%d, n_phi/2 - 1) (n_phi=%d)", fn, m_max,
+                    Z3_MAX_MMAX_HIST, idx->n_phi);
+    // the remaining checks are those of the direct estimator (with any m_max <= Z3_MAX_MMAX)
+    return check_common(fn, idx, map, 0, prec, p0, p1);
+}
+
+Z3_API z3_status z3_accumulate_histogram(z3_index idx, int map, int m_max, int prec, int norm, int64_t p0,
+                                         int64_t p1, void *A, double *W, int64_t *counts, int *counts_phi,
+                                         uint64_t *pair_total, void *stream)
+{
+    z3_status st = check_hist("z3_accumulate_histogram", idx, map, m_max, prec, p0, p1);
+    if (st != Z3_OK) return st;
+    if (norm != Z3_NORM_BIN && norm != Z3_NORM_NONE)
+        return fail(Z3_ERR_INVALID_ARG, "z3_accumulate_histogram: unknown norm %d", norm);
+    if (p1 == p0) return Z3_OK;
+    return launch_multipoles_hist(idx, map, m_max, prec, norm, p0, p1, A, p1 - p0, W, counts, counts_phi,
+                                  pair_total, as_stream(stream));
+}
+
+Z3_API z3_status z3_estimate_histogram(z3_index idx, int map, int m_max, int prec, int64_t p0, int64_t p1,
+                                       double *zeta, uint64_t *pair_total, void *stream)
+{
+    CallScope scope(idx, as_stream(stream));
+    z3_status st = check_hist("z3_estimate_histogram", idx, map, m_max, prec, p0, p1);
+    if (st != Z3_OK) return st;
+    if (!zeta) return fail(Z3_ERR_INVALID_ARG, "z3_estimate_histogram: zeta is NULL");
+    if (p1 == p0) return Z3_OK;
+    hipStream_t s = as_stream(stream);
+    // Both precisions store the chunk's multipoles in FP64 and contract them in FP64: the
+    // estimator's cost is the FP64 pair walk and transform, so FP32 storage would save
+    // nothing measurable, and on fields whose zeta_m is a sum of terms of random sign it
+    // would cost ~1e-6 at the higher multipoles this estimator is for.
+    const int sprec = Z3_PREC_FP64;
+    int64_t chunk = chunk_pivots(idx, m_max, sprec);
+    if (chunk > p1 - p0) chunk = ((p1 - p0 + kBlock - 1) / kBlock) * kBlock;
+    const size_t abytes = (size_t)chunk * (size_t)(m_max + 1) * 2 * idx->nbins * sizeof(double);
+    const size_t pbytes = contract_partial_bytes(chunk, m_max, idx->nbins);
+    void *wa = nullptr, *wp = nullptr;
+    if ((st = scratch_alloc(&wa, abytes, s)) != Z3_OK) return st;
+    st = scratch_alloc(&wp, pbytes, s);
+    const double *v = idx->d_v + (size_t)map * idx->n;
+    for (int64_t c0 = p0; c0 < p1 && st == Z3_OK; c0 += chunk) {
+        const int64_t c1 = c0 + chunk < p1 ? c0 + chunk : p1;
+        st = launch_multipoles_hist(idx, map, m_max, sprec, Z3_NORM_BIN, c0, c1, wa, c1 - c0, nullptr, nullptr,
+                                    nullptr, pair_total, s);
+        if (st == Z3_OK)
+            st = launch_contract(c1 - c0, m_max, idx->nbins, sprec, wa, c1 - c0, v + c0, zeta, wp, pbytes, s);
+    }
+    scratch_free(wp, s);
+    scratch_free(wa, s);
+    return st;
 }
 
 // ---- the estimator without allocation ---------------------------------------------------
@@ -916,7 +1020,7 @@ Z3_API z3_status z3_pivot_weight_sum(z3_index idx, int64_t p0, int64_t p1, doubl
 Z3_API z3_status z3_finalize(int nmaps, int m_max, int nbins, double *zeta, const double *sum_w,
                              void *stream)
 {
-    if (nmaps < 1 || m_max < 0 || m_max > Z3_MAX_MMAX || nbins < 1 || nbins > Z3_MAX_NBINS)
+    if (nmaps < 1 || m_max < 0 || m_max > Z3_MAX_MMAX_HIST || nbins < 1 || nbins > Z3_MAX_NBINS)
         return fail(Z3_ERR_INVALID_ARG, "z3_finalize: bad sizes");
     if (!zeta || !sum_w) return fail(Z3_ERR_INVALID_ARG, "z3_finalize: NULL pointer");
     return launch_finalize(nmaps, m_max, nbins, zeta, sum_w, as_stream(stream));
@@ -925,7 +1029,7 @@ Z3_API z3_status z3_finalize(int nmaps, int m_max, int nbins, double *zeta, cons
 Z3_API z3_status z3_resum(int m_max, int nbins, const double *zeta, int nphi, const double *phi,
                           double *out, void *stream)
 {
-    if (m_max < 0 || m_max > Z3_MAX_MMAX || nbins < 1 || nbins > Z3_MAX_NBINS || nphi < 0)
+    if (m_max < 0 || m_max > Z3_MAX_MMAX_HIST || nbins < 1 || nbins > Z3_MAX_NBINS || nphi < 0)
         return fail(Z3_ERR_INVALID_ARG, "z3_resum: bad sizes");
     if (nphi == 0) return Z3_OK;
     if (!zeta || !phi || !out) return fail(Z3_ERR_INVALID_ARG, "z3_resum: NULL pointer");

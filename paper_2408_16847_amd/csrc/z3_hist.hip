@@ -1,0 +1,347 @@
+// Angular-histogram multipoles: the picture the complexity discussion of the "3PCF binned
+// estimator" subsection draws of the method -- histograms around each pivot in radial and
+// n_phi angular bins, then a Fourier transform over the angular bins -- as an estimator.
+//
+// Every pair of radial bin b whose bearing lies in angular bin k = [k dphi, (k+1) dphi)
+// (dphi = 2 pi / n_phi, bearings from local north towards east) adds w_j x_j to H_{b,k}; the
+// multipoles take each pair at its bin centre:
+//     a_{m,b} = sum_k H_{b,k} exp(-i m (k + 1/2) dphi),   m <= m_max < n_phi / 2,
+// so the per-pair cost no longer grows with m_max (the direct kernel's does, by 4 FP64
+// operations per multipole), and m_max is no longer bounded by the direct kernel's registers.
+//
+// The angular bin is decided exactly, against the caller's FP64 boundary table
+// D_k = (cos k dphi, sin k dphi): bin k iff  c_k u2 - s_k u1 >= 0  and
+// c_{k+1} u2 - s_{k+1} u1 < 0, where u1, u2 are the separation's components on the
+// unnormalised local north N = (-z x, -z y, 1 - z^2) (x-axis fallback at the poles) and east
+// E = N x r_p, each dot product summed as (x + y) + z with every operation rounded on its own
+// (this file is compiled with -ffp-contract=off).  An FP32 arctangent, accurate to 2e-5 rad,
+// decides every bearing farther than 5e-5 rad from a boundary; the others take the sign
+// tests, which confirm the estimate or move it to the neighbouring bin.
+//
+// Work decomposition: one wave per block, one lane per pivot (64 consecutive index-order
+// pivots), the same band windows, records and one-ahead record requests as k_multipoles.
+// Each lane owns one column of an LDS histogram [n_phi][64] (consecutive lanes in
+// consecutive words: no bank conflicts whatever the bins), cleared per radial bin; a run of
+// pairs in one angular bin is summed in registers first.  After the
+// bin's windows each lane sums its column against the bin-centre phases
+// exp(-i pi j / n_phi), j = m (2k + 1) mod 2 n_phi, read from an LDS table at a wave-uniform
+// address (one broadcast read per phase), kHistMC multipoles at a time.  Sums stay in FP64 on both precision
+// paths; the mixed path stores the multipoles in FP32.
+#include "z3_internal.h"
+#include "z3_device.h"
+
+namespace z3 {
+
+struct HistArgs {
+    const double *px, *py, *pz;   // index-order positions (the pivots)
+    const double4 *rec;           // doubled-band records {x, y, z, w x} of the map
+    const double *wdbl;           // doubled-band weights, or null when all weights are 1
+    const int *cell_start;
+    const Band *bands;
+    int nbands;
+    double inv_h;
+    const EdgeTab *edges;
+    int nb;
+    int64_t p0, p1;
+    int n_phi;
+    float phi_scale;              // n_phi / (2 pi)
+    float phi_guard;              // 5e-5 rad in units of angular bins
+    const double2 *bounds;        // [n_phi] boundary directions (cos, sin) of the angular bins
+    const double2 *tab;           // [2 n_phi] (cos, sin)(pi j / n_phi)
+    int m_max;
+    int norm;
+    void *A;                      // [m_max+1][2][nb][ldA] FP64 or FP32, or null
+    int64_t ldA;
+    double *W;
+    int64_t *counts;              // [nb][ldA] pairs per (pivot, bin), or null
+    int *counts_phi;              // [nb][n_phi][ldA] pairs per (pivot, bin, angular bin), or null
+    uint64_t *pair_total;
+    int nblocks;
+};
+
+constexpr int kHistMC = 16;  // multipoles per pass of the transform
+
+__device__ __forceinline__ bool left_of(const double2 *D, int k, double u1, double u2)
+{
+    const double2 d = D[k];
+    const double a = d.x * u2;
+    const double b = d.y * u1;
+    return a - b >= 0.0;
+}
+
+__device__ __forceinline__ int angular_bin(const double2 *D, int n, float scale, float guard, double u1,
+                                           double u2)
+{
+    // bearing from an FP32 arctangent: octant reduction and the odd polynomial of
+    // Abramowitz & Stegun 4.4.49 on [0, 1] (error <= 1e-5 rad); with the FP32 rounding of
+    // u1, u2, of the reciprocal and of the octant arithmetic the estimate is within 2e-5 rad
+    // of the bearing.  A bearing farther than `guard` (5e-5 rad, in bins) from the nearest
+    // boundary is in the estimated bin by the exact rule too; nearer ones take the sign tests.
+    const float f1 = (float)u1, f2 = (float)u2;
+    const float ax = fabsf(f1), ay = fabsf(f2);
+    const float mn = fminf(ax, ay), mx = fmaxf(ax, ay);
+    const float t = mx > 0.0f ? mn * __builtin_amdgcn_rcpf(mx) : 0.0f;
+    const float t2 = t * t;
+    const float at = t * fmaf(t2, fmaf(t2, fmaf(t2, fmaf(t2, 0.0208351f, -0.0851330f), 0.1801410f), -0.3302995f),
+                              0.9998660f);
+    float ph = ay > ax ? 1.57079633f - at : at;
+    ph = f1 < 0.0f ? 3.14159265f - ph : ph;
+    ph = f2 < 0.0f ? 6.28318531f - ph : ph;
+    const float q = ph * scale;
+    int k = (int)q;
+    k = min(max(k, 0), n - 1);
+    const float fr = q - (float)k;
+    if (fr > guard && fr < 1.0f - guard) return k;
+    int k1 = k + 1 == n ? 0 : k + 1;
+    bool lk = left_of(D, k, u1, u2), lk1 = left_of(D, k1, u1, u2);
+    // the signs "left of boundary k" form one circular run, so the bin (the run's end) is
+    // reached by stepping towards it; at most n steps
+    for (int it = 0; it < n && !(lk && !lk1); ++it) {
+        if (!lk) {
+            k1 = k;
+            k = k == 0 ? n - 1 : k - 1;
+            lk1 = lk;
+            lk = left_of(D, k, u1, u2);
+        } else {
+            k = k1;
+            k1 = k1 + 1 == n ? 0 : k1 + 1;
+            lk = lk1;
+            lk1 = left_of(D, k1, u1, u2);
+        }
+    }
+    return k;
+}
+
+template <bool F32OUT, bool CNT>
+__global__ __launch_bounds__(kWave) void k_multipoles_hist(HistArgs a)
+{
+    extern __shared__ double smem[];
+    const int n = a.n_phi;
+    double *H = smem;                                                  // [n][64]
+    double2 *D = reinterpret_cast<double2 *>(H + (size_t)n * kWave);   // [n]
+    double2 *T = D + n;                                                // [2n]
+    int *C = reinterpret_cast<int *>(T + 2 * n);                       // [n][64] (CNT)
+    const int lane = threadIdx.x;
+    for (int k = lane; k < n; k += kWave) D[k] = a.bounds[k];
+    for (int j = lane; j < 2 * n; j += kWave) T[j] = a.tab[j];
+    __syncthreads();
+
+    const int lb = xcd_block(blockIdx.x, a.nblocks);
+    const int64_t p = a.p0 + (int64_t)lb * kWave + lane;
+    const bool valid = p < a.p1;
+    const int64_t pp = valid ? p : a.p1 - 1;  // idle lanes shadow the last pivot
+    const double xp = a.px[pp], yp = a.py[pp], zp = a.pz[pp];
+    const double sinth = sqrt(xp * xp + yp * yp);
+    const double th = atan2(sinth, zp);
+    double ph = atan2(yp, xp);
+    if (ph < 0.0) ph += kTwoPi;
+    double sh, ch;
+    sincos(0.5 * th, &sh, &ch);
+    const float inv_sp = sinth > 0.0 ? (float)(1.0 / sinth) : INFINITY;
+    const float phf = (float)ph;
+    // unnormalised local north and east of the bin decision
+    double nx = -zp * xp, ny = -zp * yp, nz = 1.0 - zp * zp;
+    const double nn = (nx * nx + ny * ny) + nz * nz;
+    if (nn < 1e-24) {
+        nx = 1.0 - xp * xp;
+        ny = -xp * yp;
+        nz = -xp * zp;
+    }
+    const double ex = ny * zp - nz * yp, ey = nz * xp - nx * zp, ez = nx * yp - ny * xp;
+
+    const int64_t col = p - a.p0;
+    const int nb = a.nb;
+    const bool unit_w = a.wdbl == nullptr;
+    uint64_t my_pairs = 0;
+
+    for (int bin = 0; bin < nb; ++bin) {
+        for (int k = 0; k < n; ++k) {
+            H[k * kWave + lane] = 0.0;
+            if constexpr (CNT) C[k * kWave + lane] = 0;
+        }
+        const double elo = a.edges->e[bin], ehi = a.edges->e[bin + 1];
+        const double hav_out = a.edges->hav_out[bin + 1], hav_in = a.edges->hav_in[bin];
+        int klo, khi;
+        band_range(th, a.edges->rad_out[bin + 1], a.inv_h, a.nbands, klo, khi);
+        double Wb = 0.0;
+        int cnt = 0;
+        // run of consecutive pairs in one angular bin, summed in registers and added to the
+        // LDS column when the bin changes (neighbouring candidates of a window mostly share
+        // a bin, so most pairs skip the LDS read-modify-write)
+        int krun = 0, crun = 0;
+        double vrun = 0.0;
+        for (int kb = klo; kb <= khi; ++kb) {
+            const Band bd = a.bands[kb];
+            if (bd.npts == 0) continue;
+            int s0, l0, s1, l1;
+            band_window(bd, a.cell_start, th, sh, ch, inv_sp, phf, hav_out, hav_in, s0, l0, s1, l1);
+            const int base = 2 * bd.pt_start;
+            const __amdgpu_buffer_rsrc_t rband = buffer_view(a.rec + base, (uint32_t)bd.npts * 64u);
+            auto cand = [&](const double4 &r, uint32_t o) __attribute__((always_inline)) {
+                const double dx = r.x - xp, dy = r.y - yp, dz = r.z - zp;
+                const double d2 = (dx * dx + dy * dy) + dz * dz;
+                if (d2 >= elo && d2 < ehi) {
+                    cnt += 1;
+                    if (!unit_w) Wb += a.wdbl[base + (int)(o >> 5)];
+                    const double u1 = (dx * nx + dy * ny) + dz * nz;
+                    const double u2 = (dx * ex + dy * ey) + dz * ez;
+                    const int k = angular_bin(D, n, a.phi_scale, a.phi_guard, u1, u2);
+                    if (k != krun) {
+                        H[krun * kWave + lane] += vrun;
+                        if constexpr (CNT) C[krun * kWave + lane] += crun;
+                        krun = k;
+                        vrun = 0.0;
+                        crun = 0;
+                    }
+                    vrun += r.w;
+                    crun += 1;
+                }
+            };
+#pragma unroll
+            for (int seg = 0; seg < 2; ++seg) {
+                uint32_t off = (uint32_t)(seg == 0 ? s0 : s1) * 32u;
+                const uint32_t oend = off + (uint32_t)(seg == 0 ? l0 : l1) * 32u;
+                // record requested one candidate ahead, two record registers in turn; past
+                // the window a request reads an unused record of the band (or zeros past it)
+                double4 ra = load_record(rband, off < oend ? off : 0u);
+                for (; off < oend; off += 64u) {
+                    const double4 rb = load_record(rband, off + 32u);
+                    cand(ra, off);
+                    if (off + 32u >= oend) break;
+                    ra = load_record(rband, off + 64u);
+                    cand(rb, off + 32u);
+                }
+            }
+        }
+
+        H[krun * kWave + lane] += vrun;
+        if constexpr (CNT) C[krun * kWave + lane] += crun;
+        if (valid) {
+            my_pairs += (uint64_t)cnt;
+            if (unit_w) Wb = (double)cnt;
+        }
+        double inv = 1.0;
+        if (a.norm == Z3_NORM_BIN) inv = Wb > 0.0 ? 1.0 / Wb : 0.0;
+        // Fourier sum over the angular bins at their centres
+        if (a.A) {
+            const int n2 = 2 * n;
+            for (int m0 = 0; m0 <= a.m_max; m0 += kHistMC) {
+                double Y[kHistMC], Z[kHistMC];
+#pragma unroll
+                for (int i = 0; i < kHistMC; ++i) { Y[i] = 0.0; Z[i] = 0.0; }
+                for (int k = 0; k < n; ++k) {
+                    const double h = H[k * kWave + lane];
+                    const int step = 2 * k + 1;
+                    int j = (m0 * step) % n2;
+#pragma unroll
+                    for (int i = 0; i < kHistMC; ++i) {
+                        const double2 w = T[j];  // wave-uniform address: one broadcast read
+                        Y[i] = fma(h, w.x, Y[i]);
+                        Z[i] = fma(h, w.y, Z[i]);
+                        j += step;
+                        j = j >= n2 ? j - n2 : j;
+                    }
+                }
+                if (valid) {
+#pragma unroll
+                    for (int i = 0; i < kHistMC; ++i) {
+                        const int m = m0 + i;
+                        if (m > a.m_max) break;
+                        const double re = Y[i] * inv;
+                        const double im = m == 0 ? 0.0 : -Z[i] * inv;
+                        const size_t ore = ((size_t)(2 * m) * nb + bin) * (size_t)a.ldA + col;
+                        const size_t oim = ((size_t)(2 * m + 1) * nb + bin) * (size_t)a.ldA + col;
+                        if constexpr (F32OUT) {
+                            static_cast<float *>(a.A)[ore] = (float)re;
+                            static_cast<float *>(a.A)[oim] = (float)im;
+                        } else {
+                            static_cast<double *>(a.A)[ore] = re;
+                            static_cast<double *>(a.A)[oim] = im;
+                        }
+                    }
+                }
+            }
+        }
+        if (valid) {
+            const size_t ob = (size_t)bin * (size_t)a.ldA + col;
+            if (a.W) a.W[ob] = Wb;
+            if (a.counts) a.counts[ob] = cnt;
+            if constexpr (CNT) {
+                for (int k = 0; k < n; ++k)
+                    a.counts_phi[((size_t)bin * n + k) * (size_t)a.ldA + col] = C[k * kWave + lane];
+            }
+        }
+    }
+
+    if (a.pair_total) {
+        const uint64_t tot = wave_sum_u64(valid ? my_pairs : 0);
+        if (lane == 0 && tot) atomicAdd((unsigned long long *)a.pair_total, (unsigned long long)tot);
+    }
+}
+
+size_t hist_lds_bytes(int n_phi, bool counts)
+{
+    return (size_t)n_phi * kWave * sizeof(double) + 3 * (size_t)n_phi * sizeof(double2) +
+           (counts ? (size_t)n_phi * kWave * sizeof(int) : 0);
+}
+
+z3_status launch_multipoles_hist(const z3_index_s *idx, int map, int m_max, int prec, int norm, int64_t p0,
+                                 int64_t p1, void *A, int64_t ldA, double *W, int64_t *counts, int *counts_phi,
+                                 uint64_t *pair_total, hipStream_t s)
+{
+    if (idx->n_phi < 4 || !idx->d_phi_bounds || !idx->d_phi_tab)
+        return fail(Z3_ERR_INVALID_ARG, "angular bins not set on this index (z3_index_set_phi_bins)");
+    if (m_max < 0 || 2 * m_max >= idx->n_phi)
+        return fail(Z3_ERR_INVALID_ARG, "m_max=%d needs m_max < n_phi / 2 = %d / 2", m_max, idx->n_phi);
+    const int64_t nblk = (p1 - p0 + kWave - 1) / kWave;
+    if (nblk > 0x7fffffff) return fail(Z3_ERR_OVERFLOW, "too many pivot blocks");
+    if (nblk == 0) return Z3_OK;
+    const bool cnt = counts_phi != nullptr;
+    const size_t lds = hist_lds_bytes(idx->n_phi, cnt);
+    int dev = 0, lds_max = 0;
+    z3_status st = check_hip(hipGetDevice(&dev), "hipGetDevice");
+    if (st == Z3_OK)
+        st = check_hip(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev),
+                       "hipDeviceGetAttribute");
+    if (st != Z3_OK) return st;
+    if (lds > (size_t)lds_max)
+        return fail(Z3_ERR_UNSUPPORTED, "n_phi=%d needs %zu bytes of LDS per block%s, the device offers %d",
+                    idx->n_phi, lds, cnt ? " with per-cell counts" : "", lds_max);
+    HistArgs a;
+    a.px = idx->d_x; a.py = idx->d_y; a.pz = idx->d_z;
+    a.rec = idx->d_rec + (size_t)map * 2 * idx->n;
+    a.wdbl = idx->unit_w ? nullptr : idx->d_wdbl;
+    a.cell_start = idx->d_cell_start;
+    a.bands = idx->d_bands;
+    a.nbands = idx->nbands;
+    a.inv_h = 1.0 / idx->band_h;
+    a.edges = idx->d_edges;
+    a.nb = idx->nbins;
+    a.p0 = p0; a.p1 = p1;
+    a.n_phi = idx->n_phi;
+    a.phi_scale = (float)((double)idx->n_phi / kTwoPi);
+    a.phi_guard = (float)(5e-5 * (double)idx->n_phi / kTwoPi);
+    a.bounds = idx->d_phi_bounds;
+    a.tab = idx->d_phi_tab;
+    a.m_max = m_max;
+    a.norm = norm;
+    a.A = A; a.ldA = ldA;
+    a.W = W; a.counts = counts; a.counts_phi = counts_phi; a.pair_total = pair_total;
+    a.nblocks = (int)nblk;
+    const bool f32 = prec == Z3_PREC_MIXED;
+    hipEvent_t ev0;
+    profile_begin(s, &ev0);
+    const dim3 grid((unsigned)nblk), block(kWave);
+    if (f32) {
+        if (cnt) hipLaunchKernelGGL((k_multipoles_hist<true, true>), grid, block, lds, s, a);
+        else hipLaunchKernelGGL((k_multipoles_hist<true, false>), grid, block, lds, s, a);
+    } else {
+        if (cnt) hipLaunchKernelGGL((k_multipoles_hist<false, true>), grid, block, lds, s, a);
+        else hipLaunchKernelGGL((k_multipoles_hist<false, false>), grid, block, lds, s, a);
+    }
+    st = check_launch("k_multipoles_hist");
+    profile_end(s, ev0);
+    return st;
+}
+
+}  // namespace z3

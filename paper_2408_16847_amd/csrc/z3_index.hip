@@ -418,7 +418,7 @@ static void free_ptrs(z3_index idx)
 {
     void *ps[] = {idx->d_edges, idx->d_bands, idx->d_cell_start, idx->d_x, idx->d_y, idx->d_z,
                   idx->d_w, idx->d_perm, idx->d_band, idx->d_wdbl, idx->d_permdbl, idx->d_v, idx->d_rec,
-                  idx->d_vgrp, idx->d_vmat64, idx->d_vmat32, idx->cap_ws};
+                  idx->d_vgrp, idx->d_vmat64, idx->d_vmat32, idx->cap_ws, idx->d_phi_bounds, idx->d_phi_tab};
     for (void *p : ps)
         if (p) (void)hipFree(p);
     for (void *p : idx->cap_retired) (void)hipFree(p);

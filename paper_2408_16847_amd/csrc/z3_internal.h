@@ -94,6 +94,10 @@ struct z3_index_s {
     // earlier, smaller capture workspaces: graphs captured before a reservation grew still
     // point at them, so they are kept (not freed) until z3_index_free
     std::vector<void *> cap_retired;
+    // angular bins of the histogram estimator (z3_index_set_phi_bins)
+    int n_phi = 0;
+    double2 *d_phi_bounds = nullptr;  // [n_phi] boundary directions (cos, sin) of the bins
+    double2 *d_phi_tab = nullptr;     // [2 n_phi] (cos, sin)(pi j / n_phi): bin-centre phases
     size_t ws_peak = 0;               // largest scratch total of one eager call on this index
 };
 
@@ -144,6 +148,12 @@ z3_status launch_multipoles(const z3_index_s *idx, Pivots piv, int map, int m_ma
                             int64_t *counts, uint64_t *idhash, uint64_t *pair_total,
                             hipStream_t s, const double *self_pv = nullptr,
                             double *self_part = nullptr);
+
+// angular-histogram multipoles (z3_hist.hip); counts_phi [nb][n_phi][ldA] or null
+z3_status launch_multipoles_hist(const z3_index_s *idx, int map, int m_max, int prec, int norm, int64_t p0,
+                                 int64_t p1, void *A, int64_t ldA, double *W, int64_t *counts, int *counts_phi,
+                                 uint64_t *pair_total, hipStream_t s);
+size_t hist_lds_bytes(int n_phi, bool counts);
 
 int batch_ldv(int nmaps);
 int batch_num_shapes();

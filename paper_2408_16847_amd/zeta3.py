@@ -54,6 +54,7 @@ class Index:
                   ctypes.byref(h))
         self._h = h
         self.nmaps = 0
+        self.n_phi = 0
         self._values = None
 
     @property
@@ -80,6 +81,16 @@ class Index:
         if x.numel() != self.nmaps * self.n:
             raise ValueError("values must be [nmaps, n] with the attached nmaps")
         _lib.call("z3_index_update_values", self._h, _ptr(x), _stream())
+        return self
+
+    def set_phi_bins(self, bounds):
+        """Angular bins of the histogram estimator: bounds [n_phi, 2] FP64 boundary
+        directions (cos, sin)(2 pi k / n_phi), k = 0..n_phi-1 (z3_index_set_phi_bins)."""
+        b = np.ascontiguousarray(bounds, dtype=np.float64)
+        if b.ndim != 2 or b.shape[1] != 2:
+            raise ValueError("bounds must be [n_phi, 2]")
+        _lib.call("z3_index_set_phi_bins", self._h, int(b.shape[0]), b.ctypes.data_as(ctypes.c_void_p))
+        self.n_phi = int(b.shape[0])
         return self
 
     def info(self):
@@ -138,6 +149,47 @@ def accumulate(idx: Index, m_max: int, p0: int = 0, p1: int | None = None, prec=
               _ptr(A), _ptr(W), _ptr(C), _ptr(H), _ptr(pair_total), _stream())
     out["A"], out["W"], out["counts"], out["idhash"] = A, W, C, H
     return out
+
+
+def accumulate_hist(idx: Index, m_max: int, p0: int = 0, p1: int | None = None, prec="fp64", norm="bin",
+                    map_index: int = 0, want_a=True, want_w=False, want_counts=False, want_counts_phi=False,
+                    pair_total=None):
+    """Per-pivot multipoles of the angular-histogram estimator (z3_accumulate_histogram):
+    A [m_max+1, 2, nb, P], W [nb, P], counts [nb, P], counts_phi [nb, n_phi, P] (int32)."""
+    p1 = idx.n if p1 is None else p1
+    P = p1 - p0
+    adt = torch.float64 if prec == "fp64" else torch.float32
+    A = torch.empty((m_max + 1, 2, idx.nbins, P), dtype=adt, device="cuda") if want_a else None
+    W = torch.empty((idx.nbins, P), dtype=torch.float64, device="cuda") if want_w else None
+    C = torch.empty((idx.nbins, P), dtype=torch.int64, device="cuda") if want_counts else None
+    K = torch.empty((idx.nbins, idx.n_phi, P), dtype=torch.int32, device="cuda") if want_counts_phi else None
+    _lib.call("z3_accumulate_histogram", idx.handle, map_index, m_max, PREC[prec], NORM[norm], p0, p1, _ptr(A),
+              _ptr(W), _ptr(C), _ptr(K), _ptr(pair_total), _stream())
+    return {"A": A, "W": W, "counts": C, "counts_phi": K}
+
+
+def estimate_hist_raw(idx: Index, m_max: int, prec="fp64", p0: int = 0, p1: int | None = None,
+                      map_index: int = 0, zeta=None, pair_total=None, sum_w=None):
+    """Enqueue the fused histogram estimator for pivots [p0, p1): zeta += (unnormalised)."""
+    p1 = idx.n if p1 is None else p1
+    if zeta is None:
+        zeta = torch.zeros((m_max + 1, idx.nbins, idx.nbins, 2), dtype=torch.float64, device="cuda")
+    _lib.call("z3_estimate_histogram", idx.handle, map_index, m_max, PREC[prec], p0, p1, _ptr(zeta),
+              _ptr(pair_total), _stream())
+    if sum_w is not None:
+        _lib.call("z3_pivot_weight_sum", idx.handle, p0, p1, _ptr(sum_w), _stream())
+    return zeta
+
+
+def estimate_hist(idx: Index, m_max: int, prec="fp64", p0: int = 0, p1: int | None = None, map_index: int = 0):
+    """Normalised zeta_m of the histogram estimator (complex128 numpy [m+1, nb, nb]) and the pair count."""
+    zeta = torch.zeros((m_max + 1, idx.nbins, idx.nbins, 2), dtype=torch.float64, device="cuda")
+    pairs = torch.zeros(1, dtype=torch.int64, device="cuda")
+    sw = torch.zeros(1, dtype=torch.float64, device="cuda")
+    estimate_hist_raw(idx, m_max, prec, p0, p1, map_index, zeta, pairs, sw)
+    _lib.call("z3_finalize", 1, m_max, idx.nbins, _ptr(zeta), _ptr(sw), _stream())
+    z = zeta.cpu().numpy()
+    return z[..., 0] + 1j * z[..., 1], int(pairs.item())
 
 
 def contract(A, piv_v, m_max: int, nbins: int, prec="fp64", zeta=None):

@@ -83,6 +83,9 @@ def test_other_entry_points_reject_bad_arguments():
     assert _status("z3_estimate", P(0), 0, 4, 0, 0, 1, P(1), P(0), P(0))[0] == 1
     assert _status("z3_estimate_ex", P(0), 0, 4, 0, 1, 0, 1, P(1), P(0), P(0))[0] == 1
     assert _status("z3_estimate_static", P(0), 0, 4, 0, 0, 0, 1, P(1), P(0), P(0))[0] == 1
+    assert _status("z3_index_set_phi_bins", P(0), 16, P(1))[0] == 1
+    assert _status("z3_accumulate_histogram", P(0), 0, 4, 0, 0, 0, 1, P(0), P(0), P(0), P(0), P(0), P(0))[0] == 1
+    assert _status("z3_estimate_histogram", P(0), 0, 4, 0, 0, 1, P(1), P(0), P(0))[0] == 1
     assert _status("z3_estimate_cross", P(0), 0, 1, 2, 1, 4, 0, 0, 1, P(1), P(0), P(0))[0] == 1
     assert _status("z3_estimate_cross_catalogues", P(0), 0, P(0), 0, 1, P(1), P(0), P(1), 4, 0, 0, 1, P(1),
                    P(0), P(0), P(0), P(0))[0] == 1
@@ -93,10 +96,12 @@ def test_other_entry_points_reject_bad_arguments():
     bad = np.array([0.0, 4.0])
     assert _status("z3_build_index_planar", 1, P(1), P(0), 1, bad.ctypes.data_as(P), 0.0, P(0),
                    ctypes.byref(out))[0] == 1
-    assert _status("z3_contract", 10, 17, 4, 0, P(1), P(1), P(1), P(0))[0] == 1
+    assert _status("z3_contract", 10, 128, 4, 0, P(1), P(1), P(1), P(0))[0] == 1
     assert _status("z3_contract", 10, 4, 4, 7, P(1), P(1), P(1), P(0))[0] == 1
     assert _status("z3_contract", 10, 4, 4, 0, P(1), P(1), P(0), P(0))[0] == 1
     assert _status("z3_resum", 4, 65, P(1), 3, P(1), P(1), P(0))[0] == 1
+    assert _status("z3_resum", 128, 4, P(1), 3, P(1), P(1), P(0))[0] == 1
+    assert _status("z3_finalize", 1, 128, 4, P(1), P(1), P(0))[0] == 1
     assert _status("z3_finalize", 0, 4, 4, P(1), P(1), P(0))[0] == 1
     assert _status("z3_index_info", P(0), P(0), P(0), P(0), P(0), P(0))[0] == 1
     # index-based calls with a NULL index
