@@ -11,6 +11,8 @@ ref.py          plain NumPy estimator (direct trigonometry), for catalogues up t
 brute.py        brute-force triplet sum that needs no reference direction (tiny inputs)
 hist.py         angular-histogram + Fourier-sum estimator (the histogram picture of the
                 complexity discussion; each pair at its angular bin's centre)
+fftlog.py       FFTLog chain of the modelling appendix (c_m, Gamma-ratio Hankel factors,
+                A_{s1 s2} quadrature, I = U A V^T) for the functions A_0, A_1, A_2
 oracle_cpu.c    plain C + OpenMP FP64 estimator with its own cube-grid search (large inputs)
 cpu.py          ctypes wrapper of the compiled oracle_cpu.c
 build.py        compiles oracle_cpu.c with gcc (-O2 -ffp-contract=off -fopenmp)

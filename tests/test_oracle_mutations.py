@@ -196,3 +196,35 @@ def test_hist_flipped_east_fails_bearing_bins(monkeypatch):
     monkeypatch.setattr(hist, "frame_unnormalised", lambda piv: (orig(piv)[0], -orig(piv)[1]))
     with pytest.raises(AssertionError):
         H.test_bins_match_direct_bearing(16)
+
+
+# ---- FFTLog chain (oracle/fftlog.py) --------------------------------------------------------
+
+from oracle import fftlog  # noqa: E402
+from tests import test_oracle_fftlog as FL  # noqa: E402
+
+
+def test_fftlog_phases_without_n_minus_1_over_n_fail(monkeypatch):
+    orig = fftlog.coefficients
+
+    def wrong(Pk, kmin, kmax, nu):
+        c, eta = orig(Pk, kmin, kmax, nu)
+        N = len(Pk)
+        return c * (kmin ** (-1j * eta)) * kmin ** (1j * eta * N / (N - 1)), eta * N / (N - 1)
+    monkeypatch.setattr(fftlog, "coefficients", wrong)
+    with pytest.raises(AssertionError):
+        FL.test_hankel_factor_closed_forms(0, 0, -1.3)
+
+
+def test_fftlog_gamma_factor_without_pi_fails(monkeypatch):
+    orig = fftlog.gamma_factor
+    monkeypatch.setattr(fftlog, "gamma_factor", lambda a, n, mt: orig(a, n, mt) * np.pi)
+    with pytest.raises(AssertionError):
+        FL.test_hankel_factor_closed_forms(1, 1, -2.5)
+
+
+def test_fftlog_quadrature_measure_fails(monkeypatch):
+    orig = fftlog.a_matrix
+    monkeypatch.setattr(fftlog, "a_matrix", lambda chi, Fc, a1, a2: orig(chi, np.asarray(Fc) / chi, a1, a2))
+    with pytest.raises(AssertionError):
+        FL.test_a_matrix_closed_form()
