@@ -150,6 +150,9 @@ def main():
     ap.add_argument("--hist", type=int, default=0, metavar="N_PHI",
                     help="angular-histogram estimator with N_PHI angular bins (one-map exact search on the "
                          "sky; --m-max up to N_PHI/2 - 1)")
+    ap.add_argument("--fftlog", type=int, default=0, metavar="NMODELS",
+                    help="FFTLog modelling workload instead of the estimator: A_0, A_1, A_2 of NMODELS "
+                         "line-of-sight kernels (N = 256, k in [1e-6, 100], 512 chi points, 64 angles)")
     ap.add_argument("--with-4096", default="auto", choices=["auto", "on", "off"],
                     help="after the timed steps, one step of the Nside 4096 map (exact and approximate search, "
                          "both precisions) as a nested record; auto: with the default Nside 2048 run")
@@ -183,6 +186,10 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8}))
+        return
+
+    if args.fftlog > 0:
+        fftlog_bench(args, z3, torch)
         return
 
     cfg = CONFIGS[args.config]
@@ -584,6 +591,91 @@ def fd_check(cfg, xyz, E, M, last, k, z3, torch):
             "max_abs_grad": float(np.abs(fd).max()), "seconds": time.perf_counter() - t0,
             "note": "relative to the largest sampled gradient; FP64 forward differences, exact for the "
                     "quadratic dependence of zeta on one value"}
+
+
+FFTLOG_SETTINGS = dict(N=256, k_min=1e-6, k_max=100.0, nchi=512, chi_min=1e-4, chi_max=60.0, ntheta=64,
+                       theta_min=0.002, theta_max=0.2)
+FFTLOG_NU = (-0.3, -1.3, -1.3, -0.3)  # biases of the (0,0), (1,1), (1,-1), (2,0) factors
+
+
+def fftlog_bench(args, z3, torch):
+    """A_0, A_1, A_2 of a batch of line-of-sight kernels through z3_fftlog_a_functions.  The
+    dominant kernel is the chi-quadrature product A_b = X1^T diag(d_b) X2 (three per model):
+    8 (N + 1)^2 nchi flop per product and model (complex FP64 multiply-adds)."""
+    from synth import fftlog_inputs
+    S = FFTLOG_SETTINGS
+    nm = args.fftlog
+    Pk, F, theta, _, _ = fftlog_inputs(N=S["N"], k_min=S["k_min"], k_max=S["k_max"], nchi=S["nchi"],
+                                       chi_min=S["chi_min"], chi_max=S["chi_max"], nmodels=nm, ntheta=S["ntheta"],
+                                       theta_min=S["theta_min"], theta_max=S["theta_max"], seed=11)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    Pk_d, F_d, th_d = dev(Pk), dev(F), dev(theta)
+    ws = torch.empty(z3.fftlog_workspace_size(S["N"], S["nchi"], S["ntheta"], nm), dtype=torch.uint8, device="cuda")
+    out = torch.empty((nm, 3, S["ntheta"], S["ntheta"]), dtype=torch.float64, device="cuda")
+
+    def run():
+        z3.fftlog_a_functions(Pk_d, S["k_min"], S["k_max"], FFTLOG_NU, F_d, S["chi_min"], S["chi_max"], th_d,
+                              workspace=ws, out=out)
+
+    for _ in range(args.warmup):
+        run()
+    torch.cuda.synchronize()
+    z3.profile_read(reset=True)
+    z3.profile_enable(True)
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        run()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / args.steps
+    launches, kms = z3.profile_read(reset=True)
+    z3.profile_enable(False)
+    ns = S["N"] + 1
+    flops_launch = 8.0 * ns * ns * S["nchi"] * nm
+    kern_s = kms / max(launches, 1) / 1e3
+    achieved = flops_launch / kern_s / 1e12 if kern_s > 0 else None
+    total_flops = nm * 3 * 8.0 * (ns * ns * S["nchi"] + S["ntheta"] * ns * ns + S["ntheta"] ** 2 * ns)
+    log(f"[bench] fftlog: {nm} models in {dt * 1e3:.2f} ms/step; k_cgemm<true> {kms / max(launches, 1):.3f} ms "
+        f"x {launches / args.steps:.0f} per step ({achieved:.1f} TFLOP/s)")
+    # oracle on a bounded sample of the models, and GPU parity on the same models
+    from oracle import fftlog
+    from synth import log_grid
+    chi = log_grid(S["chi_min"], S["chi_max"], S["nchi"])
+    got = out.cpu().numpy()
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    ns_cpu, t_cpu, err = 0, 0.0, 0.0
+    while ns_cpu < nm and t_cpu < 10.0:
+        t0 = time.perf_counter()
+        ref = fftlog.a_functions(Pk, S["k_min"], S["k_max"], chi, F[ns_cpu], theta, *FFTLOG_NU).real
+        t_cpu += time.perf_counter() - t0
+        err = max(err, float(np.abs(got[ns_cpu] - ref).max() / np.abs(ref).max()))
+        ns_cpu += 1
+    log(f"[bench] fftlog oracle: {ns_cpu} models in {t_cpu:.2f}s, GPU max-normalised error {err:.2e}")
+    rec = {
+        "metric": "FFTLog A-function sets/s (A_0, A_1, A_2 on a 64 x 64 angle grid)",
+        "value": nm / dt,
+        "unit": "models/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"fftlog N={S['N']} k=[1e-6,100] nchi={S['nchi']} ntheta={S['ntheta']} "
+                               f"models={nm}", "nu": list(FFTLOG_NU), **S, "nmodels": nm,
+                   "total_flops_per_step": total_flops},
+        "roofline": {"bound": "mfma", "kernel": "k_cgemm<true>", "achieved": achieved,
+                     "peak": PEAK_MFMA_TFLOPS["fp64"], "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_MFMA_TFLOPS["fp64"] if achieved else None, "traffic": None,
+                     "avg_launch_ms": kms / max(launches, 1), "launches_per_step": launches / args.steps,
+                     "flops": "8 (N+1)^2 nchi flop per chi-quadrature product and model"},
+        "cpu_baseline": {"value": ns_cpu / t_cpu, "unit": "models/s", "cores": threads, "kind": "oracle",
+                         "sample": f"the first {ns_cpu} models, one oracle call each (NumPy, BLAS threads)",
+                         "seconds": t_cpu, "gpu_max_err_on_sample": err},
+    }
+    print(json.dumps(rec), flush=True)
 
 
 def cpu_baseline(cfg, xyz, x, nbr, E, M, nsample, z3, torch, self_pairs=True):

@@ -38,6 +38,7 @@
 #ifndef ZETA3_H
 #define ZETA3_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -393,6 +394,48 @@ z3_status z3_finalize(int nmaps, int m_max, int nbins, double *zeta, const doubl
 z3_status z3_resum(int m_max, int nbins, const double *zeta, int nphi, const double *phi,
                    double *out, void *stream);
 
+/*
+ * FFTLog evaluation of the line-of-sight integrals of the modelling appendix ("FFTLog for
+ * the line-of-sight integral"): the building blocks A_0, A_1, A_2 of the pre-cyclic model
+ * 3PCF (eq. zetapc) for a batch of models that share the linear power spectrum and the
+ * angle grid, each with its own line-of-sight kernel F(chi) = q_A q_B q_C D_+^4.
+ *
+ *   c_s     (eqs. pklfft, pklfft_eta, cm): N samples P(k_l), k_l = k_min (k_max/k_min)^{l/(N-1)},
+ *           s = -N/2..N/2, eta_s = ((N-1)/N) 2 pi s / ln(k_max/k_min), end weights 1/2
+ *   a_s     = 1 + nu + i eta_s, one bias nu per factor (n, mt):
+ *           nu[0] (0,0), nu[1] (1,1), nu[2] (1,-1), nu[3] (2,0)
+ *   g(a_s)  = 2^{mt+a_s-1} Gamma((1+mt+a_s+n)/2) / (pi Gamma((1-a_s-mt+n)/2))  (the Gamma-ratio
+ *           form of the k integral)
+ *   A_{s1 s2} = int dchi F(chi) chi^{-a_s1 - a_s2 - 2}: trapezoid rule in ln chi on the nchi
+ *           points chi_j = chi_min (chi_max/chi_min)^{j/(nchi-1)}
+ *   I^{(n1,mt1)}_{(n2,mt2)}(theta_i, theta_j) = sum_{s1,s2} c_s1 g1(a_s1) theta_i^{-(1+a_s1+mt1)}
+ *           A_{s1 s2} c_s2 g2(a_s2) theta_j^{-(1+a_s2+mt2)}
+ *   out[b][0] = A_0 = Re I^{(0,0)}_{(0,0)}, out[b][1] = A_1 = Re (I^{(1,1)}_{(1,-1)} + its
+ *           transpose), out[b][2] = A_2 = Re I^{(2,0)}_{(2,0)}      (each [ntheta][ntheta])
+ *
+ *   N        even, 4 <= N <= Z3_MAX_FFTLOG_N;  Pk [N] FP64 samples of P_L on the k_l grid
+ *   nu       [host] 4 biases, |nu| <= 50; a bias that puts a pole of either Gamma function
+ *            on eta = 0 is Z3_ERR_INVALID_ARG
+ *   F        [nmodels][nchi] FP64 kernel samples on the chi_j grid, nchi >= 2
+ *   theta    [ntheta] FP64 angles in radians, > 0 (not checked: a non-positive angle gives
+ *            non-finite outputs), 1 <= ntheta <= Z3_MAX_FFTLOG_THETA
+ *   out      [nmodels][3][ntheta][ntheta] FP64, overwritten (not accumulated)
+ *   workspace, workspace_bytes: device scratch of the caller, 256-byte aligned; NULL makes the library take it
+ *            from its stream-ordered pool (at most 1 GiB; the call cannot then be captured
+ *            into a graph).  z3_fftlog_workspace_size gives the bytes for a number of models
+ *            per pass; a smaller workspace processes fewer models per pass (Z3_ERR_INVALID_ARG
+ *            if it holds none).
+ * The three products A = X1^T diag(d) X2, U1 A and (U1 A) U2^T run on FP64 matrix cores;
+ * everything is FP64.
+ */
+#define Z3_MAX_FFTLOG_N 4096
+#define Z3_MAX_FFTLOG_THETA 4096
+z3_status z3_fftlog_workspace_size(int N, int nchi, int ntheta, int models_per_pass, size_t *bytes);
+z3_status z3_fftlog_a_functions(int N, const double *Pk, double k_min, double k_max, const double *nu,
+                                int nchi, double chi_min, double chi_max, int nmodels, const double *F,
+                                int ntheta, const double *theta, double *out, void *workspace,
+                                size_t workspace_bytes, void *stream);
+
 /* Wait for the stream and report any asynchronous error. */
 z3_status z3_sync(void *stream);
 
@@ -401,8 +444,9 @@ const char *z3_last_error(void);
 
 /*
  * Kernel timing for measurement: when enabled, the library brackets every launch of
- * its forward multipole kernels (one-map, register-tiled many-map and MFMA many-map)
- * with HIP events on the launch stream.  Launches made inside the adjoint calls and
+ * its forward multipole kernels (one-map, register-tiled many-map, MFMA many-map and
+ * angular-histogram) and of the chi-quadrature product of z3_fftlog_a_functions with HIP
+ * events on the launch stream.  Launches made inside the adjoint calls and
  * calls on a stream that is being captured into a graph are not timed.  z3_profile_read
  * waits for those events and returns the number of launches and their summed duration.
  */

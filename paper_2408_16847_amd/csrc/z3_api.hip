@@ -1036,6 +1036,72 @@ Z3_API z3_status z3_resum(int m_max, int nbins, const double *zeta, int nphi, co
     return launch_resum(m_max, nbins, zeta, nphi, phi, out, as_stream(stream));
 }
 
+// Gamma-function poles of the k integral: at eta = 0 the arguments (1 + mt + a + n) / 2 and
+// (1 - a - mt + n) / 2 are real; a non-positive integer there has no finite log Gamma.
+static bool fftlog_pole(int n, int mt, double nu)
+{
+    const double a = 1.0 + nu;
+    const double x[2] = {0.5 * (1.0 + mt + a + n), 0.5 * (1.0 - a - mt + n)};
+    for (double v : x)
+        if (v < 0.5 && std::fabs(v - std::nearbyint(v)) < 1e-9) return true;
+    return false;
+}
+
+Z3_API z3_status z3_fftlog_workspace_size(int N, int nchi, int ntheta, int models_per_pass, size_t *bytes)
+{
+    if (!bytes) return fail(Z3_ERR_INVALID_ARG, "z3_fftlog_workspace_size: bytes is NULL");
+    if (N < 4 || N > Z3_MAX_FFTLOG_N || N % 2 || nchi < 2 || ntheta < 1 || ntheta > Z3_MAX_FFTLOG_THETA ||
+        models_per_pass < 1)
+        return fail(Z3_ERR_INVALID_ARG, "z3_fftlog_workspace_size: bad sizes");
+    *bytes = fftlog_workspace_bytes(N, nchi, ntheta, models_per_pass);
+    return Z3_OK;
+}
+
+Z3_API z3_status z3_fftlog_a_functions(int N, const double *Pk, double k_min, double k_max, const double *nu,
+                                       int nchi, double chi_min, double chi_max, int nmodels, const double *F,
+                                       int ntheta, const double *theta, double *out, void *workspace,
+                                       size_t workspace_bytes, void *stream)
+{
+    if (N < 4 || N > Z3_MAX_FFTLOG_N || N % 2 || nchi < 2 || ntheta < 1 || ntheta > Z3_MAX_FFTLOG_THETA ||
+        nmodels < 0)
+        return fail(Z3_ERR_INVALID_ARG, "z3_fftlog_a_functions: bad sizes");
+    if (!nu) return fail(Z3_ERR_INVALID_ARG, "z3_fftlog_a_functions: nu is NULL");
+    if (!(k_min > 0.0) || !(k_max > k_min) || !std::isfinite(k_max) || !(chi_min > 0.0) || !(chi_max > chi_min) ||
+        !std::isfinite(chi_max))
+        return fail(Z3_ERR_INVALID_ARG, "z3_fftlog_a_functions: need 0 < k_min < k_max and 0 < chi_min < chi_max");
+    const int ns[4] = {0, 1, 1, 2}, mts[4] = {0, 1, -1, 0};
+    for (int f = 0; f < 4; ++f) {
+        if (!std::isfinite(nu[f]) || std::fabs(nu[f]) > 50.0)
+            return fail(Z3_ERR_INVALID_ARG, "z3_fftlog_a_functions: nu[%d] = %g outside [-50, 50]", f, nu[f]);
+        if (fftlog_pole(ns[f], mts[f], nu[f]))
+            return fail(Z3_ERR_INVALID_ARG, "z3_fftlog_a_functions: nu[%d] = %g puts a Gamma pole on eta = 0", f,
+                        nu[f]);
+    }
+    if (nmodels == 0) return Z3_OK;
+    if (!Pk || !F || !theta || !out) return fail(Z3_ERR_INVALID_ARG, "z3_fftlog_a_functions: NULL pointer");
+    const hipStream_t s = as_stream(stream);
+    int chunk = nmodels < 65535 ? nmodels : 65535;  // one grid z index per model of a pass
+    if (workspace) {
+        if (reinterpret_cast<uintptr_t>(workspace) % 256)
+            return fail(Z3_ERR_INVALID_ARG, "z3_fftlog_a_functions: workspace not 256-byte aligned");
+        while (chunk > 1 && fftlog_workspace_bytes(N, nchi, ntheta, chunk) > workspace_bytes) chunk = (chunk + 1) / 2;
+        if (fftlog_workspace_bytes(N, nchi, ntheta, chunk) > workspace_bytes)
+            return fail(Z3_ERR_INVALID_ARG, "z3_fftlog_a_functions: workspace of %zu bytes holds no model (%zu needed)",
+                        workspace_bytes, fftlog_workspace_bytes(N, nchi, ntheta, 1));
+        return fftlog_impl(N, Pk, k_min, k_max, nu, nchi, chi_min, chi_max, nmodels, F, ntheta, theta, out,
+                           workspace, chunk, s);
+    }
+    CallScope scope(nullptr, s);
+    const size_t kMaxAuto = (size_t)1 << 30;
+    while (chunk > 1 && fftlog_workspace_bytes(N, nchi, ntheta, chunk) > kMaxAuto) chunk = (chunk + 1) / 2;
+    void *ws = nullptr;
+    z3_status st = scratch_alloc(&ws, fftlog_workspace_bytes(N, nchi, ntheta, chunk), s);
+    if (st != Z3_OK) return st;
+    st = fftlog_impl(N, Pk, k_min, k_max, nu, nchi, chi_min, chi_max, nmodels, F, ntheta, theta, out, ws, chunk, s);
+    scratch_free(ws, s);
+    return st;
+}
+
 Z3_API z3_status z3_sync(void *stream)
 {
     z3_status st = check_hip(hipStreamSynchronize(as_stream(stream)), "hipStreamSynchronize");

@@ -195,6 +195,12 @@ z3_status launch_pivot_values(const double *w, const double *x, int64_t n, doubl
 z3_status launch_add_scalar(double *out, double value, hipStream_t s);
 z3_status launch_fill(double *p, int64_t n, double value, hipStream_t s);
 // zeta[m][b][b] re -= sum over the nw rows of part [nw][nbins] (column b), for m <= m_max
+// FFTLog line-of-sight integrals (z3_fftlog.hip): workspace bytes for `chunk` models per
+// pass, and the evaluation itself (nu [4] host; every array a device pointer)
+size_t fftlog_workspace_bytes(int N, int nchi, int T, int chunk);
+z3_status fftlog_impl(int N, const double *Pk, double k_min, double k_max, const double *nu, int nchi, double chi_min,
+                      double chi_max, int nmodels, const double *F, int T, const double *theta, double *out,
+                      void *ws, int chunk, hipStream_t s);
 z3_status launch_self_subtract(const double *part, int64_t nw, int m_max, int nbins, double *zeta,
                                hipStream_t s);
 

@@ -472,6 +472,41 @@ def resum(zeta, phi):
     return out
 
 
+FFTLOG_FACTORS = ((0, 0), (1, 1), (1, -1), (2, 0))  # (n, mt) of the four biases, in order
+
+
+def fftlog_workspace_size(N: int, nchi: int, ntheta: int, models_per_pass: int) -> int:
+    """Device bytes z3_fftlog_a_functions needs to process models_per_pass models at once."""
+    b = ctypes.c_size_t()
+    _lib.call("z3_fftlog_workspace_size", int(N), int(nchi), int(ntheta), int(models_per_pass), ctypes.byref(b))
+    return b.value
+
+
+def fftlog_a_functions(Pk, k_min: float, k_max: float, nu, F, chi_min: float, chi_max: float, theta,
+                       workspace=None, out=None):
+    """A_0, A_1, A_2 of the modelling appendix for a batch of line-of-sight kernels
+    (z3_fftlog_a_functions): Pk [N] on the log-spaced k grid, F [nmodels, nchi] on the
+    log-spaced chi grid, theta [T] radians, nu the four biases of FFTLOG_FACTORS.
+    Returns a float64 CUDA tensor [nmodels, 3, T, T]."""
+    Pk = _dev(Pk)
+    F = _dev(F)
+    theta = _dev(theta)
+    if F.dim() == 1:
+        F = F[None]
+    nmodels, nchi = int(F.shape[0]), int(F.shape[1])
+    T = int(theta.numel())
+    nu = np.ascontiguousarray(np.asarray(nu, dtype=np.float64).reshape(4))
+    if out is None:
+        out = torch.empty((nmodels, 3, T, T), dtype=torch.float64, device="cuda")
+    elif tuple(out.shape) != (nmodels, 3, T, T) or out.dtype != torch.float64 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float64 tensor [nmodels, 3, T, T]")
+    ws_bytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
+    _lib.call("z3_fftlog_a_functions", int(Pk.numel()), _ptr(Pk), float(k_min), float(k_max),
+              nu.ctypes.data_as(ctypes.c_void_p), nchi, float(chi_min), float(chi_max), nmodels, _ptr(F), T,
+              _ptr(theta), _ptr(out), _ptr(workspace), ctypes.c_size_t(ws_bytes), _stream())
+    return out
+
+
 def profile_enable(on=True):
     _lib.call("z3_profile_enable", int(bool(on)))
 
