@@ -600,8 +600,9 @@ FFTLOG_NU = (-0.3, -1.3, -1.3, -0.3)  # biases of the (0,0), (1,1), (1,-1), (2,0
 
 def fftlog_bench(args, z3, torch):
     """A_0, A_1, A_2 of a batch of line-of-sight kernels through z3_fftlog_a_functions.  The
-    dominant kernel is the chi-quadrature product A_b = X1^T diag(d_b) X2 (three per model):
-    8 (N + 1)^2 nchi flop per product and model (complex FP64 multiply-adds)."""
+    dominant kernel is the product of the angle factor's s1 >= 0 half with the Hankel matrix of
+    the chi integrals (three launches per pass, one per function): 8 ntheta (N + 1) (N/2 + 1)
+    flop per launch and model (complex FP64 multiply-adds)."""
     from synth import fftlog_inputs
     S = FFTLOG_SETTINGS
     nm = args.fftlog
@@ -630,11 +631,12 @@ def fftlog_bench(args, z3, torch):
     launches, kms = z3.profile_read(reset=True)
     z3.profile_enable(False)
     ns = S["N"] + 1
-    flops_launch = 8.0 * ns * ns * S["nchi"] * nm
+    flops_launch = 8.0 * S["ntheta"] * ns * (S["N"] // 2 + 1) * nm
     kern_s = kms / max(launches, 1) / 1e3
     achieved = flops_launch / kern_s / 1e12 if kern_s > 0 else None
-    total_flops = nm * 3 * 8.0 * (ns * ns * S["nchi"] + S["ntheta"] * ns * ns + S["ntheta"] ** 2 * ns)
-    log(f"[bench] fftlog: {nm} models in {dt * 1e3:.2f} ms/step; k_cgemm<true> {kms / max(launches, 1):.3f} ms "
+    total_flops = nm * 3 * (4.0 * ns * S["nchi"] + 8.0 * S["ntheta"] * ns * (S["N"] // 2 + 1)
+                            + 4.0 * S["ntheta"] ** 2 * ns)
+    log(f"[bench] fftlog: {nm} models in {dt * 1e3:.2f} ms/step; k_cgemm<2> {kms / max(launches, 1):.3f} ms "
         f"x {launches / args.steps:.0f} per step ({achieved:.1f} TFLOP/s)")
     # oracle on a bounded sample of the models, and GPU parity on the same models
     from oracle import fftlog
@@ -666,11 +668,11 @@ def fftlog_bench(args, z3, torch):
         "config": {"workload": f"fftlog N={S['N']} k=[1e-6,100] nchi={S['nchi']} ntheta={S['ntheta']} "
                                f"models={nm}", "nu": list(FFTLOG_NU), **S, "nmodels": nm,
                    "total_flops_per_step": total_flops},
-        "roofline": {"bound": "mfma", "kernel": "k_cgemm<true>", "achieved": achieved,
+        "roofline": {"bound": "mfma", "kernel": "k_cgemm<2>", "achieved": achieved,
                      "peak": PEAK_MFMA_TFLOPS["fp64"], "unit": "TFLOP/s",
                      "frac": achieved / PEAK_MFMA_TFLOPS["fp64"] if achieved else None, "traffic": None,
                      "avg_launch_ms": kms / max(launches, 1), "launches_per_step": launches / args.steps,
-                     "flops": "8 (N+1)^2 nchi flop per chi-quadrature product and model"},
+                     "flops": "8 ntheta (N+1) (N/2+1) flop per product (omega U1) H and model"},
         "cpu_baseline": {"value": ns_cpu / t_cpu, "unit": "models/s", "cores": threads, "kind": "oracle",
                          "sample": f"the first {ns_cpu} models, one oracle call each (NumPy, BLAS threads)",
                          "seconds": t_cpu, "gpu_max_err_on_sample": err},

@@ -425,8 +425,12 @@ z3_status z3_resum(int m_max, int nbins, const double *zeta, int nphi, const dou
  *            into a graph).  z3_fftlog_workspace_size gives the bytes for a number of models
  *            per pass; a smaller workspace processes fewer models per pass (Z3_ERR_INVALID_ARG
  *            if it holds none).
- * The three products A = X1^T diag(d) X2, U1 A and (U1 A) U2^T run on FP64 matrix cores;
- * everything is FP64.
+ * Since eta_s is linear in s, A_{s1 s2} depends on s1 + s2 only: the library forms its
+ * 2N + 1 distinct entries h(s1 + s2) (one product over chi for all models) and never the
+ * (N+1)^2 matrix; since P is real, the terms (s1, s2) and (-s1, -s2) are conjugate and only
+ * s1 >= 0 is summed (I = Re of twice that half, the s1 = 0 column once).  The products run on
+ * FP64 matrix cores.  Everything is FP64; the results equal the dense-matrix evaluation up to
+ * rounding (P and F must be real: they are FP64 arrays).
  */
 #define Z3_MAX_FFTLOG_N 4096
 #define Z3_MAX_FFTLOG_THETA 4096
