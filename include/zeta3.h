@@ -440,6 +440,16 @@ z3_status z3_fftlog_a_functions(int N, const double *Pk, double k_min, double k_
                                 int ntheta, const double *theta, double *out, void *workspace,
                                 size_t workspace_bytes, void *stream);
 
+/*
+ * Largest single device allocation the library may make, in bytes (default: no limit; the
+ * environment variable Z3_DEVICE_ALLOC_LIMIT_MB, read when the library is loaded, sets the
+ * initial value).  A call that would need a larger buffer fails with Z3_ERR_OUT_OF_MEMORY
+ * before it touches the device, exactly as when the device allocation itself fails: no
+ * output written, no index created.  For callers that share a GPU, and for testing the
+ * out-of-memory paths.  Applies to every thread and device; SIZE_MAX lifts it.
+ */
+z3_status z3_set_device_alloc_limit(size_t max_bytes);
+
 /* Wait for the stream and report any asynchronous error. */
 z3_status z3_sync(void *stream);
 

@@ -47,6 +47,7 @@ SIGNATURES = {
     "z3_resum": (_I, [_I, _I, _P, _I, _P, _P, _P]),
     "z3_fftlog_workspace_size": (_I, [_I, _I, _I, _I, _P]),
     "z3_fftlog_a_functions": (_I, [_I, _P, _D, _D, _P, _I, _D, _D, _I, _P, _I, _P, _P, _P, ctypes.c_size_t, _P]),
+    "z3_set_device_alloc_limit": (_I, [ctypes.c_size_t]),
     "z3_sync": (_I, [_P]),
     "z3_status_string": (ctypes.c_char_p, [_I]),
     "z3_last_error": (ctypes.c_char_p, []),

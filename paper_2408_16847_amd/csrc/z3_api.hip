@@ -3,6 +3,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
+#include <atomic>
 #include <mutex>
 #include <vector>
 
@@ -32,6 +33,29 @@ z3_status check_hip(hipError_t e, const char *what)
 }
 
 z3_status check_launch(const char *what) { return check_hip(hipGetLastError(), what); }
+
+// Largest single device allocation the library makes (z3_set_device_alloc_limit; initial
+// value from Z3_DEVICE_ALLOC_LIMIT_MB, else unlimited).  Checked before any device call, so a
+// request above it fails with Z3_ERR_OUT_OF_MEMORY exactly as a failed allocation does.
+static size_t initial_alloc_limit()
+{
+    if (const char *e = getenv("Z3_DEVICE_ALLOC_LIMIT_MB")) {
+        char *end = nullptr;
+        const double mb = strtod(e, &end);
+        if (end != e && mb >= 0.0 && mb < 1e12) return (size_t)(mb * 1048576.0);
+    }
+    return SIZE_MAX;
+}
+static std::atomic<size_t> g_alloc_limit{initial_alloc_limit()};
+
+z3_status alloc_allowed(size_t bytes, const char *what)
+{
+    const size_t lim = g_alloc_limit.load(std::memory_order_relaxed);
+    if (bytes > lim)
+        return fail(Z3_ERR_OUT_OF_MEMORY, "%s: %zu bytes exceed the device allocation limit of %zu bytes", what, bytes,
+                    lim);
+    return Z3_OK;
+}
 
 // One private memory pool per device, never trimmed: the fused estimator allocates its
 // chunk workspace stream-ordered on every call, and the pool hands the same memory back
@@ -96,9 +120,10 @@ z3_status scratch_alloc(void **p, size_t bytes, hipStream_t s)
         sc->used += aligned;
         return Z3_OK;
     }
-    hipMemPool_t pool;
-    z3_status st = pool_for_current_device(&pool);
+    z3_status st = alloc_allowed(aligned, "scratch workspace");
     if (st != Z3_OK) return st;
+    hipMemPool_t pool;
+    if ((st = pool_for_current_device(&pool)) != Z3_OK) return st;
     st = check_hip(hipMallocFromPoolAsync(p, aligned, pool, s), "hipMallocFromPoolAsync");
     if (st == Z3_OK && sc) sc->used += aligned;
     return st;
@@ -237,7 +262,9 @@ Z3_API z3_status z3_index_prepare_capture(z3_index idx, size_t min_bytes, size_t
     if (!idx) return fail(Z3_ERR_INVALID_ARG, "z3_index_prepare_capture: idx is NULL");
     const size_t want = idx->ws_peak > min_bytes ? idx->ws_peak : min_bytes;
     if (want > idx->cap_bytes) {
-        z3_status st = check_hip(hipSetDevice(idx->device), "hipSetDevice");
+        z3_status st = alloc_allowed(want, "z3_index_prepare_capture");
+        if (st != Z3_OK) return st;
+        st = check_hip(hipSetDevice(idx->device), "hipSetDevice");
         if (st == Z3_OK) st = check_hip(hipDeviceSynchronize(), "hipDeviceSynchronize");
         if (st != Z3_OK) return st;
         void *ws = nullptr;
@@ -549,7 +576,8 @@ Z3_API z3_status z3_index_set_phi_bins(z3_index idx, int n_phi, const double *bo
         tab[2 * j] = std::cos(kPi * j / n_phi);
         tab[2 * j + 1] = std::sin(kPi * j / n_phi);
     }
-    z3_status st = check_hip(hipSetDevice(idx->device), "hipSetDevice");
+    z3_status st = alloc_allowed(2 * (size_t)n_phi * sizeof(double2), "z3_index_set_phi_bins");
+    if (st == Z3_OK) st = check_hip(hipSetDevice(idx->device), "hipSetDevice");
     if (st != Z3_OK) return st;
     double2 *db = nullptr, *dt = nullptr;
     st = check_hip(hipMalloc((void **)&db, (size_t)n_phi * sizeof(double2)), "hipMalloc (angular bins)");
@@ -1100,6 +1128,12 @@ Z3_API z3_status z3_fftlog_a_functions(int N, const double *Pk, double k_min, do
     st = fftlog_impl(N, Pk, k_min, k_max, nu, nchi, chi_min, chi_max, nmodels, F, ntheta, theta, out, ws, chunk, s);
     scratch_free(ws, s);
     return st;
+}
+
+Z3_API z3_status z3_set_device_alloc_limit(size_t max_bytes)
+{
+    g_alloc_limit.store(max_bytes, std::memory_order_relaxed);
+    return Z3_OK;
 }
 
 Z3_API z3_status z3_sync(void *stream)

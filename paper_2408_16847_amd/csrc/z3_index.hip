@@ -396,21 +396,26 @@ static z3_status exclusive_scan(const int *in, int64_t n, int *out, hipStream_t 
 {
     int64_t tiles = (n + kScanTile - 1) / kScanTile;
     if (tiles < 1) tiles = 1;
-    int *sums = nullptr;
-    z3_status st = check_hip(hipMallocAsync((void **)&sums, (size_t)(tiles + 1) * sizeof(int), s), "scan alloc");
+    const size_t bytes = (size_t)(tiles + 1) * sizeof(int);
+    // both partial-sum buffers are released (stream-ordered) on every path out
+    struct Tmp {
+        int *p = nullptr;
+        hipStream_t s;
+        ~Tmp() { if (p) (void)hipFreeAsync(p, s); }
+    } sums{nullptr, s}, offs{nullptr, s};
+    z3_status st = alloc_allowed(bytes, "scan alloc");
+    if (st == Z3_OK) st = check_hip(hipMallocAsync((void **)&sums.p, bytes, s), "scan alloc");
     if (st != Z3_OK) return st;
-    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)tiles), dim3(kScanThreads), 0, s, in, n, out, sums);
+    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)tiles), dim3(kScanThreads), 0, s, in, n, out, sums.p);
     if ((st = check_launch("k_scan_tiles")) != Z3_OK) return st;
     if (tiles > 1) {
-        int *offs = nullptr;
-        st = check_hip(hipMallocAsync((void **)&offs, (size_t)(tiles + 1) * sizeof(int), s), "scan alloc");
+        st = alloc_allowed(bytes, "scan alloc");
+        if (st == Z3_OK) st = check_hip(hipMallocAsync((void **)&offs.p, bytes, s), "scan alloc");
         if (st != Z3_OK) return st;
-        if ((st = exclusive_scan(sums, tiles, offs, s)) != Z3_OK) return st;
-        hipLaunchKernelGGL(k_scan_add, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, out, n, offs);
+        if ((st = exclusive_scan(sums.p, tiles, offs.p, s)) != Z3_OK) return st;
+        hipLaunchKernelGGL(k_scan_add, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, out, n, offs.p);
         if ((st = check_launch("k_scan_add")) != Z3_OK) return st;
-        (void)hipFreeAsync(offs, s);
     }
-    (void)hipFreeAsync(sums, s);
     return Z3_OK;
 }
 
@@ -437,7 +442,10 @@ template <class T>
 static z3_status dalloc(T **p, size_t count, const char *what)
 {
     *p = nullptr;
-    return check_hip(hipMalloc((void **)p, (count ? count : 1) * sizeof(T)), what);
+    const size_t bytes = (count ? count : 1) * sizeof(T);
+    const z3_status st = alloc_allowed(bytes, what);
+    if (st != Z3_OK) return st;
+    return check_hip(hipMalloc((void **)p, bytes), what);
 }
 
 static inline unsigned grid_for(int64_t n) { return (unsigned)((n + 255) / 256 > 0 ? (n + 255) / 256 : 1); }

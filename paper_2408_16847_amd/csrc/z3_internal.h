@@ -129,6 +129,8 @@ struct ProfileMute {
 z3_status fail(z3_status s, const char *fmt, ...);
 z3_status check_hip(hipError_t e, const char *what);
 z3_status check_launch(const char *what);
+// Z3_ERR_OUT_OF_MEMORY if `bytes` exceed the device allocation limit (z3_set_device_alloc_limit)
+z3_status alloc_allowed(size_t bytes, const char *what);
 
 // index kernels (z3_index.hip)
 z3_status build_index_impl(int64_t n, const double *xyz, const double *w, int nbins,
