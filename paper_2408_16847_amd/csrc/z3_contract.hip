@@ -443,74 +443,155 @@ z3_status launch_contract(int64_t npiv, int m_max, int nbins, int prec, const vo
 // For the pivot field's values v_p and two neighbour fields with multipoles U1 and U2 (same
 // pivots, same bins):  G = sum_p v_p U1_p U2_p^T, a full 2nb x 2nb matrix (no symmetry), and
 //     Re zeta_m(b1, b2) = G(r1, r2) + G(i1, i2),   Im zeta_m(b1, b2) = G(i1, r2) - G(r1, i2),
-// i.e. sum_p v_p X1(b1) conj(X2(b2)).  One wave per (16 x 16 tile, pivot segment, m), MFMA
-// as in k_gram_tiles (split FP32 operand on the mixed path), fixed-order FP64 sums.
+// i.e. sum_p v_p X1(b1) conj(X2(b2)).  One block of kGramWaves waves per (pivot segment, m):
+// tiles of kGramKP pivots of both fields' 2nb rows of that m are staged in LDS as
+// [pivot][row], 16 consecutive pivots of a row on 16 consecutive lanes (one contiguous run
+// of the pivot-minor layout), and the waves run the T x T tile pairs out of LDS, so every
+// multipole is read from memory once per launch.  MFMA as in the one-field contraction
+// (split FP32 operand on the mixed path), fixed-order FP64 sums.
 
 struct CrossArgs {
     const void *A1, *A2;  // [m+1][2][nb][ldA] multipoles of the b1 field and of the b2 field
     int64_t ldA;
     int64_t npiv;
     const double *v;      // pivot products w_p x_p of the pivot field
-    int nb, T;
+    int nb, T, M1;
+    int ldr;              // LDS row length: the least >= 2 nb that is 17 mod 32 (conflict-free
+                          // staging writes, 16 pivots of a row 17 banks apart; operand reads
+                          // of the four pivot groups nearly so)
     double *part;         // [seg][m][T * T][256]
 };
 
-template <bool F32>
-__global__ __launch_bounds__(64) void k_cross_tiles(CrossArgs c)
-{
-    const int tp = blockIdx.x, seg = blockIdx.y, m = blockIdx.z;
-    const int I = tp / c.T, J = tp % c.T;
-    const int lane = threadIdx.x;
-    const int row = lane & 15, kq = lane >> 4;
-    const int ui = I * 16 + row, uj = J * 16 + row;
-    const int two_nb = 2 * c.nb;
-    const bool vi = ui < two_nb, vj = uj < two_nb;
-    const size_t oi = vi ? ((size_t)2 * m * c.nb + ui) * (size_t)c.ldA : 0;
-    const size_t oj = vj ? ((size_t)2 * m * c.nb + uj) * (size_t)c.ldA : 0;
-    const int64_t pbeg = (int64_t)seg * kSeg;
-    const int64_t pend = min(c.npiv, pbeg + kSeg);
-    double *out = c.part + ((size_t)(seg * gridDim.z + m) * (size_t)(c.T * c.T) + tp) * 256;
+constexpr int kCrossKP = 32;  // pivots per LDS tile of the multi-field contraction (8 MFMA k-steps)
 
-    if constexpr (!F32) {
-        const double *A1 = static_cast<const double *>(c.A1), *A2 = static_cast<const double *>(c.A2);
-        v4d acc = {0.0, 0.0, 0.0, 0.0};
-        for (int64_t s = pbeg; s < pend; s += 16) {
+// NW waves per block, UPW tile pairs per wave, tile pairs blockIdx.y NW UPW onwards; each
+// thread stages up to ROWS rows of both fields per tile (2 nb <= 16 T <= ROWS x 2 NW for
+// every shape launched).
+template <bool F32, int NW, int UPW, int ROWS>
+__global__ __launch_bounds__(NW * 64) void k_cross_lds(CrossArgs c)
+{
+    typedef typename std::conditional<F32, float, double>::type E;
+    constexpr int kThreads = NW * 64, kRows = ROWS;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int ldr = c.ldr;
+    E *t1 = reinterpret_cast<E *>(smem);                          // [kCrossKP][ldr]
+    E *t2 = t1 + kCrossKP * ldr;                                  // [kCrossKP][ldr]
+    double *vt = reinterpret_cast<double *>(t2 + kCrossKP * ldr);  // [kCrossKP]
+    const int64_t seg = blockIdx.x / c.M1;
+    const int m = (int)(blockIdx.x - seg * c.M1);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int row = lane & 15, kq = lane >> 4;
+    const int two_nb = 2 * c.nb, T = c.T;
+    const E *src1 = static_cast<const E *>(c.A1) + (size_t)2 * m * c.nb * c.ldA;
+    const E *src2 = static_cast<const E *>(c.A2) + (size_t)2 * m * c.nb * c.ldA;
+
+    int ua[UPW], ub[UPW];
+    v4d acc[UPW];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int64_t p = s + 4 * kq + q;
-                const bool in = p < pend;
-                const double vp = in ? c.v[p] : 0.0;
-                const double ai = (vi && in) ? A1[oi + p] : 0.0;
-                const double bj = (vj && in) ? A2[oj + p] : 0.0;
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ai * vp, bj, acc, 0, 0, 0);
-            }
+    for (int j = 0; j < UPW; ++j) {
+        const int tp = (int)blockIdx.y * NW * UPW + wave + NW * j;
+        acc[j] = v4d{0.0, 0.0, 0.0, 0.0};
+        ua[j] = ub[j] = -1;
+        if (tp < T * T) {
+            ua[j] = (tp / T) * 16 + row;
+            ub[j] = (tp % T) * 16 + row;
         }
-#pragma unroll
-        for (int k = 0; k < 4; ++k) out[(4 * k + kq) * 16 + row] = acc[k];
-    } else {
-        const float *A1 = static_cast<const float *>(c.A1), *A2 = static_cast<const float *>(c.A2);
-        v4d acc = {0.0, 0.0, 0.0, 0.0};
-        for (int64_t s = pbeg; s < pend; s += 16) {
-            v4f part = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int64_t p = s + 4 * kq + q;
-                const bool in = p < pend;
-                const double vp = in ? c.v[p] : 0.0;
-                const float ui = (vi && in) ? A1[oi + p] : 0.0f;
-                const float bj = (vj && in) ? A2[oj + p] : 0.0f;
-                const double a = (double)ui * vp;
-                const float ahi = (float)a;
-                const float alo = (float)(a - (double)ahi);
-                part = __builtin_amdgcn_mfma_f32_16x16x4f32(ahi, bj, part, 0, 0, 0);
-                part = __builtin_amdgcn_mfma_f32_16x16x4f32(alo, bj, part, 0, 0, 0);
-            }
-#pragma unroll
-            for (int k = 0; k < 4; ++k) acc[k] += (double)part[k];
-        }
-#pragma unroll
-        for (int k = 0; k < 4; ++k) out[(4 * kq + k) * 16 + row] = acc[k];
     }
+    const int64_t pbeg = seg * kSeg;
+    const int64_t pend = min(c.npiv, pbeg + kSeg);
+    // staging: thread -> (row u, pivot k), kCrossKP pivots of a row on consecutive lanes (one
+    // contiguous run of the pivot-minor layout); the next tile's global loads are issued
+    // before the current tile's MFMAs
+    const int k = tid % kCrossKP, u0 = tid / kCrossKP, ustep = kThreads / kCrossKP;
+    E a[kRows], b[kRows];
+    auto fetch = [&](int64_t q0) {
+        const bool kin = q0 + k < pend;
+#pragma unroll
+        for (int i = 0; i < kRows; ++i) {
+            const int uu = u0 + i * ustep;
+            const bool in = uu < two_nb && kin;
+            a[i] = in ? src1[(size_t)uu * c.ldA + q0 + k] : E(0);
+            b[i] = in ? src2[(size_t)uu * c.ldA + q0 + k] : E(0);
+        }
+    };
+    fetch(pbeg);
+    for (int64_t p0 = pbeg; p0 < pend; p0 += kCrossKP) {
+        const int np = (int)min((int64_t)kCrossKP, pend - p0);
+        __syncthreads();  // the previous tile is consumed
+#pragma unroll
+        for (int i = 0; i < kRows; ++i) {
+            const int uu = u0 + i * ustep;
+            if (uu < two_nb) {
+                t1[k * ldr + uu] = a[i];
+                t2[k * ldr + uu] = b[i];
+            }
+        }
+        if (tid < kCrossKP) vt[tid] = tid < np ? c.v[p0 + tid] : 0.0;
+        __syncthreads();
+        if (p0 + kCrossKP < pend) fetch(p0 + kCrossKP);
+#pragma unroll
+        for (int h = 0; h < kCrossKP / 16; ++h) {
+            double vk[4];
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) vk[ks] = vt[16 * h + 4 * ks + kq];
+#pragma unroll
+            for (int j = 0; j < UPW; ++j) {
+                if (ua[j] < 0) continue;  // wave-uniform
+                if constexpr (F32) {
+                    // FP32 products over 16 pivots, then into the FP64 sum; the scaled operand
+                    // v_p U1 is formed in FP64 and carried as FP32 hi + lo
+                    v4f part = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                    for (int ks = 0; ks < 4; ++ks) {
+                        const int base = (16 * h + 4 * ks + kq) * ldr;
+                        const float x1 = ua[j] < two_nb ? t1[base + ua[j]] : 0.0f;
+                        const float x2 = ub[j] < two_nb ? t2[base + ub[j]] : 0.0f;
+                        const double av = (double)x1 * vk[ks];
+                        const float ahi = (float)av;
+                        const float alo = (float)(av - (double)ahi);
+                        part = __builtin_amdgcn_mfma_f32_16x16x4f32(ahi, x2, part, 0, 0, 0);
+                        part = __builtin_amdgcn_mfma_f32_16x16x4f32(alo, x2, part, 0, 0, 0);
+                    }
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) acc[j][q] += (double)part[q];
+                } else {
+#pragma unroll
+                    for (int ks = 0; ks < 4; ++ks) {
+                        const int base = (16 * h + 4 * ks + kq) * ldr;
+                        const double x1 = ua[j] < two_nb ? t1[base + ua[j]] : 0.0;
+                        const double x2 = ub[j] < two_nb ? t2[base + ub[j]] : 0.0;
+                        acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1 * vk[ks], x2, acc[j], 0, 0, 0);
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < UPW; ++j) {
+        if (ua[j] < 0) continue;
+        const int tp = (int)blockIdx.y * NW * UPW + wave + NW * j;
+        double *out = c.part + ((size_t)(seg * c.M1 + m) * (size_t)(T * T) + tp) * 256;
+        // f64 16x16x4 result: register q of lane l is D[4q + l/16][l % 16];
+        // f32 16x16x4 result: register q of lane l is D[4 (l/16) + q][l % 16]
+#pragma unroll
+        for (int q = 0; q < 4; ++q) out[(F32 ? 4 * kq + q : 4 * q + kq) * 16 + row] = acc[j][q];
+    }
+}
+
+template <bool F32, int NW, int UPW, int ROWS>
+static void launch_cross_lds(dim3 grid, size_t lds, const CrossArgs &c, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_cross_lds<F32, NW, UPW, ROWS>), grid, dim3(NW * 64), lds, s, c);
+}
+
+template <bool F32>
+static void launch_cross_shape(int T, dim3 grid, size_t lds, const CrossArgs &c, hipStream_t s)
+{
+    // one tile pair per wave: T^2 waves up to T = 4; beyond, groups of 16 pairs in blocks of
+    // their own (grid.y), each staging the whole tile
+    if (T <= 2) launch_cross_lds<F32, 4, 1, 4>(grid, lds, c, s);
+    else if (T == 3) launch_cross_lds<F32, 9, 1, 3>(grid, lds, c, s);
+    else launch_cross_lds<F32, 16, 1, 4>(dim3(grid.x, (unsigned)((T * T + 15) / 16)), lds, c, s);
 }
 
 __device__ __forceinline__ double cross_at(const double *seg_m, int T, int u, int v)
@@ -553,14 +634,26 @@ z3_status launch_contract_cross(int64_t npiv, int m_max, int nbins, int prec, co
     const int64_t nseg = (npiv + kSeg - 1) / kSeg;
     if (partial_bytes < cross_partial_bytes(npiv, m_max, nbins))
         return fail(Z3_ERR_INVALID_ARG, "multi-field contraction: partial buffer too small");
-    if (nseg > 65535) return fail(Z3_ERR_OVERFLOW, "multi-field contraction: %lld pivot segments", (long long)nseg);
+    if (nseg * (m_max + 1) > (int64_t)(UINT32_MAX / 1024))
+        return fail(Z3_ERR_OVERFLOW, "multi-field contraction: %lld pivot segments", (long long)nseg);
     CrossArgs c;
-    c.A1 = A1; c.A2 = A2; c.ldA = ldA; c.npiv = npiv; c.v = piv_v; c.nb = nbins; c.T = T;
+    c.A1 = A1; c.A2 = A2; c.ldA = ldA; c.npiv = npiv; c.v = piv_v; c.nb = nbins; c.T = T; c.M1 = m_max + 1;
+    c.ldr = 2 * nbins + ((17 - 2 * nbins) % 32 + 32) % 32;
     c.part = static_cast<double *>(partials);
-    dim3 grid((unsigned)(T * T), (unsigned)nseg, (unsigned)(m_max + 1));
-    if (prec == Z3_PREC_MIXED) hipLaunchKernelGGL(k_cross_tiles<true>, grid, dim3(64), 0, s, c);
-    else hipLaunchKernelGGL(k_cross_tiles<false>, grid, dim3(64), 0, s, c);
-    z3_status st = check_launch("k_cross_tiles");
+    const bool f32 = prec == Z3_PREC_MIXED;
+    const size_t lds = 2 * (size_t)kCrossKP * c.ldr * (f32 ? 4 : 8) + kCrossKP * sizeof(double);
+    int dev = 0, lds_max = 0;
+    z3_status st0 = check_hip(hipGetDevice(&dev), "hipGetDevice");
+    if (st0 == Z3_OK)
+        st0 = check_hip(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), "LDS size");
+    if (st0 != Z3_OK) return st0;
+    if (lds > (size_t)lds_max)
+        return fail(Z3_ERR_UNSUPPORTED, "multi-field contraction of %d bins needs %zu bytes of LDS per block (%d)", nbins,
+                    lds, lds_max);
+    const dim3 grid((unsigned)(nseg * (m_max + 1)));
+    if (f32) launch_cross_shape<true>(T, grid, lds, c, s);
+    else launch_cross_shape<false>(T, grid, lds, c, s);
+    z3_status st = check_launch("k_cross_lds");
     if (st != Z3_OK) return st;
     const int total = (m_max + 1) * nbins * nbins;
     hipLaunchKernelGGL(k_cross_reduce, dim3((total + 127) / 128), dim3(128), 0, s,

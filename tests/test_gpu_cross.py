@@ -88,6 +88,25 @@ def test_weighted_cross_fields_and_pivot_ranges(prec, tol):
     assert G.err_m(zc[..., 0] + 1j * zc[..., 1], zo).max() <= tol
 
 
+# many bins: the contraction's wider tile shapes (2 nb = 60, 80, 128 rows: 4 x 4 tile pairs
+# in one block, 5 x 5 and 8 x 8 in groups of 16 pairs per block)
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("mixed", 1e-6)])
+@pytest.mark.parametrize("nbins", [30, 40, 64])
+def test_cross_fields_many_bins(prec, tol, nbins):
+    G.say("case: three fields,", nbins, "bins", prec)
+    xyz, w, xa = pins.random_cap(2500, 5.0, 43)
+    rng = np.random.default_rng(44)
+    f = np.stack([xa, xa + 0.5 * rng.normal(size=2500), xa - 0.3 * rng.normal(size=2500)])
+    E = pins.small_edges(nbins, lo=0.05, hi=2.0, log=True)
+    idx = G.build(xyz, f, E, w=w)
+    z, pairs = z3.estimate_cross(idx, (0, 1, 2), 4, prec=prec, cyclic=True)
+    zo, po = cpu.estimate_cross(xyz, xyz, w, tuple(f), E, 4, w, tuple(f), cyclic=True)
+    assert pairs == po
+    e = G.err_m(z, zo)
+    G.say("err_m", prec, e)
+    assert e.max() <= tol, e
+
+
 def test_cross_rejects_a_missing_map():
     G.say("case: z3_estimate_cross map range")
     xyz, E, x = pins.three_point_case()
