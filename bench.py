@@ -452,34 +452,41 @@ def entry_errors(test, ref):
     """Error of the mixed path against FP64 per (m, b1, b2) and component: |test - ref| / |ref|,
     with entries where |ref| < 1e-3 max_m |ref| flagged as cancellation-limited (their
     relative error measures the rounding of a near-zero sum, not the path); per m the largest
-    relative error over the well-conditioned entries, and the worst entries overall."""
+    relative error over the well-conditioned entries, and the worst entries overall.  Several
+    maps ([map][m][b1][b2]): every map's entries, per m the worst map."""
+    if ref.ndim == 3:
+        test, ref = test[None], ref[None]
     rows = []
-    per_m = []
+    per_m = [None] * ref.shape[1]
     ncanc = 0
-    for m in range(ref.shape[0]):
-        r = np.stack([ref[m].real, ref[m].imag], -1)
-        t = np.stack([test[m].real, test[m].imag], -1)
-        scale = np.abs(r).max()
-        d = np.abs(t - r)
-        canc = np.abs(r) < 1e-3 * scale
-        if m == 0:
-            canc[..., 1] = True  # Im zeta_0 is 0 by construction
-        b1, b2 = np.meshgrid(np.arange(r.shape[0]), np.arange(r.shape[1]), indexing="ij")
-        for c in (0, 1):
-            cm = canc[..., c]
-            ncanc += int(cm.sum())
-            rel = np.where(cm, np.nan, d[..., c] / np.where(cm, 1.0, np.abs(r[..., c])))
-            for i, j in zip(b1[~cm], b2[~cm]):
-                rows.append((float(rel[i, j]), m, int(i), int(j), "re" if c == 0 else "im"))
-        good = ~canc
-        per_m.append(float((d[good] / np.abs(r[good])).max()) if good.any() else None)
+    for k in range(ref.shape[0]):
+        for m in range(ref.shape[1]):
+            r = np.stack([ref[k, m].real, ref[k, m].imag], -1)
+            t = np.stack([test[k, m].real, test[k, m].imag], -1)
+            scale = np.abs(r).max()
+            d = np.abs(t - r)
+            canc = np.abs(r) < 1e-3 * scale
+            if m == 0:
+                canc[..., 1] = True  # Im zeta_0 is 0 by construction
+            b1, b2 = np.meshgrid(np.arange(r.shape[0]), np.arange(r.shape[1]), indexing="ij")
+            for c in (0, 1):
+                cm = canc[..., c]
+                ncanc += int(cm.sum())
+                rel = np.where(cm, np.nan, d[..., c] / np.where(cm, 1.0, np.abs(r[..., c])))
+                for i, j in zip(b1[~cm], b2[~cm]):
+                    rows.append((float(rel[i, j]), k, m, int(i), int(j), "re" if c == 0 else "im"))
+            good = ~canc
+            if good.any():
+                e = float((d[good] / np.abs(r[good])).max())
+                per_m[m] = e if per_m[m] is None else max(per_m[m], e)
     rel_all = np.array([q[0] for q in rows])
     worst = sorted(rows, reverse=True)[:5]
     return {"entries": int(ref.size * 2), "cancellation_limited": ncanc,
             "rule": "cancellation-limited: |zeta64| < 1e-3 of the largest |zeta64| of that m (and Im zeta_0)",
             "max_rel_err": float(rel_all.max()), "median_rel_err": float(np.median(rel_all)),
             "p99_rel_err": float(np.percentile(rel_all, 99)), "max_rel_err_per_m": per_m,
-            "worst": [{"rel_err": q[0], "m": q[1], "b1": q[2], "b2": q[3], "part": q[4]} for q in worst]}
+            "worst": [{"rel_err": q[0], **({"map": q[1]} if ref.shape[0] > 1 else {}), "m": q[2], "b1": q[3],
+                       "b2": q[4], "part": q[5]} for q in worst]}
 
 
 def nside4096_record(z3, torch):

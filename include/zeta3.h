@@ -24,7 +24,7 @@
  *  - Array arguments are DEVICE pointers owned by the caller unless marked [host].
  *  - "stream" is a hipStream_t passed as void* (NULL = the legacy default stream).
  *    Every call only enqueues work on that stream and returns; the exceptions are
- *    z3_build_index (synchronises once on the stream to size its tables) and z3_sync.
+ *    z3_build_index (synchronises on the stream to size its tables) and z3_sync.
  *  - Every function returns a z3_status and never throws.  On Z3_ERR_INVALID_ARG no
  *    output has been written.  The text of the last error of the calling thread is
  *    returned by z3_last_error().  Asynchronous device faults surface as Z3_ERR_HIP
@@ -97,7 +97,8 @@ enum {
  *   cell_size      band height in radians; <= 0 selects 0.6 * sqrt(A / n) where A is
  *                  the area of the catalogue's colatitude range
  *   out            receives the index; free it with z3_index_free
- * Synchronises once on `stream`.  The input arrays may be freed after it returns.
+ * Synchronises on `stream` (to size its tables, and before it returns).  The input arrays
+ * may be freed after it returns.
  */
 z3_status z3_build_index(int64_t n, const double *xyz, const double *w, int nbins,
                          const double *edges_chord2, double cell_size, void *stream,

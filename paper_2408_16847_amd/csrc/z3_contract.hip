@@ -4,11 +4,12 @@
 //     G = sum_p v_p U_p U_p^T                       (2nb x 2nb real Gram matrix)
 //     Re zeta_m(b1, b2) = G(r1, r2) + G(i1, i2),   Im zeta_m(b1, b2) = G(i1, r2) - G(r1, i2)
 // (r = b, i = nb + b), which is sum_p v_p X(b1) conj(X(b2)) written in real arithmetic.
-// The Gram matrix is a dense contraction over pivots: one wave64 computes one 16x16 tile
-// of G over a segment of pivots with v_mfma_f64_16x16x4f64 (FP64 path) or
-// v_mfma_f32_16x16x4f32 (mixed path: FP32 multipoles U; the scaled operand v_p U_i is
-// formed in FP64 and split into FP32 hi + lo parts, two MFMAs per step; FP32 sums over
-// 16 pivots are added into FP64 segment sums).
+// The Gram matrix is a dense contraction over pivots, formed in 16 x 16 tiles over segments
+// of pivots with v_mfma_f64_16x16x4f64 (FP64 path) or v_mfma_f32_16x16x4f32 (mixed path: FP32
+// multipoles U; the scaled operand v_p U_i is formed in FP64 and split into FP32 hi + lo
+// parts, two MFMAs per step; FP32 sums over 16 pivots are added into FP64 segment sums),
+// from tiles of pivots staged in LDS (k_pair_lds for the pivot-minor layout of the one-map
+// kernels, k_gram_lds for the many-map kernel's pivot-major staging).
 // Only tiles on or above the diagonal are formed; entries below are read from their
 // mirror, so zeta(b2, b1) is exactly conj(zeta(b1, b2)) and Im zeta(b, b) is exactly 0.
 // Segment partials are summed in FP64 in segment order (deterministic).
@@ -31,86 +32,6 @@ size_t contract_partial_bytes(int64_t npiv, int m_max, int nbins)
     const int T = tiles_for(nbins);
     const int64_t nseg = (npiv + kSeg - 1) / kSeg;
     return (size_t)(nseg > 0 ? nseg : 1) * (size_t)(m_max + 1) * (size_t)(T * (T + 1) / 2) * 256 * sizeof(double);
-}
-
-struct ContractArgs {
-    const void *A;
-    int64_t ldA;
-    int64_t npiv;
-    const double *v;
-    int nb, T, ntp;
-    int M1;              // m_max + 1; blockIdx.z = map * M1 + m
-    size_t a_stride;     // elements between the maps' multipoles
-    size_t v_stride;     // elements between the maps' pivot values
-    double *part;        // [seg][map][m][tile pair][256]
-};
-
-template <bool F32>
-__global__ __launch_bounds__(64) void k_gram_tiles(ContractArgs c)
-{
-    const int tp = blockIdx.x, seg = blockIdx.y, m = blockIdx.z % c.M1;
-    const size_t map = blockIdx.z / c.M1;
-    c.v += map * c.v_stride;
-    int I = 0, r = tp;
-    while (r >= c.T - I) { r -= c.T - I; ++I; }
-    const int J = I + r;
-    const int lane = threadIdx.x;
-    const int row = lane & 15, kq = lane >> 4;
-    const int ui = I * 16 + row, uj = J * 16 + row;
-    const int two_nb = 2 * c.nb;
-    const bool vi = ui < two_nb, vj = uj < two_nb;
-    // U index u = comp * nb + b lives at A[(2m + comp) * nb + b][p] = A[2 m nb + u][p]
-    const size_t oi = vi ? ((size_t)2 * m * c.nb + ui) * (size_t)c.ldA : 0;
-    const size_t oj = vj ? ((size_t)2 * m * c.nb + uj) * (size_t)c.ldA : 0;
-    const int64_t pbeg = (int64_t)seg * kSeg;
-    const int64_t pend = min(c.npiv, pbeg + kSeg);
-
-    if constexpr (!F32) {
-        const double *A = static_cast<const double *>(c.A) + map * c.a_stride;
-        v4d acc = {0.0, 0.0, 0.0, 0.0};
-        for (int64_t s = pbeg; s < pend; s += 16) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int64_t p = s + 4 * kq + q;
-                const bool in = p < pend;
-                const double vp = in ? c.v[p] : 0.0;
-                const double ai = (vi && in) ? A[oi + p] : 0.0;
-                const double bj = (vj && in) ? A[oj + p] : 0.0;
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ai * vp, bj, acc, 0, 0, 0);
-            }
-        }
-        // v_mfma_f64_16x16x4f64 result layout: register k of lane l holds D[4k + l/16][l % 16]
-        double *out = c.part + ((size_t)(seg * gridDim.z + blockIdx.z) * c.ntp + tp) * 256;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) out[(4 * k + kq) * 16 + row] = acc[k];
-    } else {
-        const float *A = static_cast<const float *>(c.A) + map * c.a_stride;
-        v4d acc = {0.0, 0.0, 0.0, 0.0};
-        for (int64_t s = pbeg; s < pend; s += 16) {
-            // FP32 products and sums over 16 pivots, then into the FP64 segment sum
-            v4f part = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int64_t p = s + 4 * kq + q;
-                const bool in = p < pend;
-                const double vp = in ? c.v[p] : 0.0;
-                const float ui = (vi && in) ? A[oi + p] : 0.0f;
-                const float bj = (vj && in) ? A[oj + p] : 0.0f;
-                // split-precision operand: v_p U_i formed in FP64, carried as hi + lo
-                const double a = (double)ui * vp;
-                const float ahi = (float)a;
-                const float alo = (float)(a - (double)ahi);
-                part = __builtin_amdgcn_mfma_f32_16x16x4f32(ahi, bj, part, 0, 0, 0);
-                part = __builtin_amdgcn_mfma_f32_16x16x4f32(alo, bj, part, 0, 0, 0);
-            }
-#pragma unroll
-            for (int k = 0; k < 4; ++k) acc[k] += (double)part[k];
-        }
-        // v_mfma_f32_16x16x4f32 result layout: register k of lane l holds D[4 (l/16) + k][l % 16]
-        double *out = c.part + ((size_t)(seg * gridDim.z + blockIdx.z) * c.ntp + tp) * 256;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) out[(4 * kq + k) * 16 + row] = (double)acc[k];
-    }
 }
 
 // G(u, v) of one segment, read from the tile holding min/max of (u, v).
@@ -144,13 +65,210 @@ __global__ void k_gram_reduce(const double *part, int64_t nseg, int nmaps, int M
     z[1] += ir - ri;
 }
 
-// ---- LDS-staged contraction -------------------------------------------------------------
-// One block of kGramWaves waves per (pivot segment, map).  Tiles of kGramKP pivots are
-// staged in LDS as [pivot][bin][row] (row = 2 m + comp) from either multipole layout (the
-// many-map kernel's pivot-major staging, or the pivot-minor [row][bin][pivot] layout), with
-// the layout's contiguous dimension on consecutive lanes.  Every wave then runs its
-// (m, tile pair) units over the tile out of LDS, so each multipole is fetched once per block
-// rather than once per tile pair, and the pivot-major staging needs no transpose.
+// ---- LDS-staged pair contraction over pivot-minor multipoles --------------------------------
+// G = sum_p v_p U1_p U2_p^T per (map, m): with U1 = U2 the Gram matrix of one field (only the
+// tile pairs on or above the diagonal), else the full product of two fields (the multi-field
+// estimator: Re zeta_m(b1, b2) = G(r1, r2) + G(i1, i2), Im zeta_m(b1, b2) = G(i1, r2) -
+// G(r1, i2), i.e. sum_p v_p X1(b1) conj(X2(b2))).  One block per (pivot segment, map, m):
+// tiles of kCrossKP pivots of the fields' 2nb rows of that m are staged in LDS as
+// [pivot][row], consecutive pivots of a row on consecutive lanes (one contiguous run of the
+// pivot-minor layout), and the waves run the 16 x 16 tile pairs out of LDS, so every
+// multipole is read from memory once per launch; the next tile's loads are in flight
+// during the current tile's MFMAs.  MFMA as in the pivot-major contraction below (split FP32
+// operand on the mixed path), fixed-order FP64 sums.
+
+struct PairArgs {
+    const void *A1, *A2;  // [map][m+1][2][nb][ldA] multipoles of the b1 and b2 fields (Gram: A1 only)
+    int64_t ldA;
+    int64_t npiv;
+    const double *v;      // pivot products w_p x_p of the pivot field
+    size_t a_stride;      // elements between the maps' multipoles (Gram of several maps)
+    size_t v_stride;      // elements between the maps' pivot products
+    int nb, T, M1, nmaps;
+    int npairs;           // tile pairs per (map, m): T^2, or T (T + 1) / 2 for a Gram matrix
+    int ldr;              // LDS row length: the least >= 2 nb that is 17 mod 32 (conflict-free
+                          // staging writes, 16 pivots of a row 17 banks apart; operand reads
+                          // of the four pivot groups nearly so)
+    double *part;         // [seg][map][m][npairs][256]
+};
+
+constexpr int kCrossKP = 32;  // pivots per LDS tile of the multi-field contraction (8 MFMA k-steps)
+
+// NW waves per block, UPW tile pairs per wave, tile pairs blockIdx.y NW UPW onwards; each
+// thread stages up to ROWS rows of both fields per tile (2 nb <= 16 T <= ROWS x 2 NW for
+// every shape launched).  SYM: a Gram matrix of one field (A2 = A1; only the tile pairs on
+// or above the diagonal, the others are their mirror).
+template <bool F32, int NW, int UPW, int ROWS, bool SYM>
+__global__ __launch_bounds__(NW * 64) void k_pair_lds(PairArgs c)
+{
+    typedef typename std::conditional<F32, float, double>::type E;
+    constexpr int kThreads = NW * 64, kRows = ROWS;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int ldr = c.ldr;
+    E *t1 = reinterpret_cast<E *>(smem);                          // [kCrossKP][ldr]
+    E *t2 = SYM ? t1 : t1 + kCrossKP * ldr;                       // [kCrossKP][ldr]
+    double *vt = reinterpret_cast<double *>(t1 + 2 * kCrossKP * ldr);  // [kCrossKP]
+    const int64_t unit = blockIdx.x;  // (segment, map, m)
+    const int m = (int)(unit % c.M1);
+    const int map = (int)((unit / c.M1) % c.nmaps);
+    const int64_t seg = unit / ((int64_t)c.M1 * c.nmaps);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int row = lane & 15, kq = lane >> 4;
+    const int two_nb = 2 * c.nb, T = c.T;
+    const size_t mo = (size_t)map * c.a_stride + (size_t)2 * m * c.nb * c.ldA;
+    const E *src1 = static_cast<const E *>(c.A1) + mo;
+    const E *src2 = static_cast<const E *>(SYM ? c.A1 : c.A2) + mo;
+    const double *v = c.v + (size_t)map * c.v_stride;
+
+    int ua[UPW], ub[UPW];
+    v4d acc[UPW];
+#pragma unroll
+    for (int j = 0; j < UPW; ++j) {
+        const int tp = (int)blockIdx.y * NW * UPW + wave + NW * j;
+        acc[j] = v4d{0.0, 0.0, 0.0, 0.0};
+        ua[j] = ub[j] = -1;
+        if (tp < c.npairs) {
+            int I = tp / T, J = tp % T;
+            if constexpr (SYM) {
+                int r = tp;
+                I = 0;
+                while (r >= T - I) { r -= T - I; ++I; }
+                J = I + r;
+            }
+            ua[j] = I * 16 + row;
+            ub[j] = J * 16 + row;
+        }
+    }
+    const int64_t pbeg = seg * kSeg;
+    const int64_t pend = min(c.npiv, pbeg + kSeg);
+    // staging: thread -> (row u, pivot k), kCrossKP pivots of a row on consecutive lanes (one
+    // contiguous run of the pivot-minor layout); the next tile's global loads are issued
+    // before the current tile's MFMAs
+    const int k = tid % kCrossKP, u0 = tid / kCrossKP, ustep = kThreads / kCrossKP;
+    E a[kRows], b[kRows];
+    auto fetch = [&](int64_t q0) {
+        const bool kin = q0 + k < pend;
+#pragma unroll
+        for (int i = 0; i < kRows; ++i) {
+            const int uu = u0 + i * ustep;
+            const bool in = uu < two_nb && kin;
+            a[i] = in ? src1[(size_t)uu * c.ldA + q0 + k] : E(0);
+            if constexpr (!SYM) b[i] = in ? src2[(size_t)uu * c.ldA + q0 + k] : E(0);
+        }
+    };
+    fetch(pbeg);
+    for (int64_t p0 = pbeg; p0 < pend; p0 += kCrossKP) {
+        const int np = (int)min((int64_t)kCrossKP, pend - p0);
+        __syncthreads();  // the previous tile is consumed
+#pragma unroll
+        for (int i = 0; i < kRows; ++i) {
+            const int uu = u0 + i * ustep;
+            if (uu < two_nb) {
+                t1[k * ldr + uu] = a[i];
+                if constexpr (!SYM) t2[k * ldr + uu] = b[i];
+            }
+        }
+        if (tid < kCrossKP) vt[tid] = tid < np ? v[p0 + tid] : 0.0;
+        __syncthreads();
+        if (p0 + kCrossKP < pend) fetch(p0 + kCrossKP);
+#pragma unroll
+        for (int h = 0; h < kCrossKP / 16; ++h) {
+            double vk[4];
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) vk[ks] = vt[16 * h + 4 * ks + kq];
+#pragma unroll
+            for (int j = 0; j < UPW; ++j) {
+                if (ua[j] < 0) continue;  // wave-uniform
+                if constexpr (F32) {
+                    // FP32 products over 16 pivots, then into the FP64 sum; the scaled operand
+                    // v_p U1 is formed in FP64 and carried as FP32 hi + lo
+                    v4f part = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                    for (int ks = 0; ks < 4; ++ks) {
+                        const int base = (16 * h + 4 * ks + kq) * ldr;
+                        const float x1 = ua[j] < two_nb ? t1[base + ua[j]] : 0.0f;
+                        const float x2 = ub[j] < two_nb ? t2[base + ub[j]] : 0.0f;
+                        const double av = (double)x1 * vk[ks];
+                        const float ahi = (float)av;
+                        const float alo = (float)(av - (double)ahi);
+                        part = __builtin_amdgcn_mfma_f32_16x16x4f32(ahi, x2, part, 0, 0, 0);
+                        part = __builtin_amdgcn_mfma_f32_16x16x4f32(alo, x2, part, 0, 0, 0);
+                    }
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) acc[j][q] += (double)part[q];
+                } else {
+#pragma unroll
+                    for (int ks = 0; ks < 4; ++ks) {
+                        const int base = (16 * h + 4 * ks + kq) * ldr;
+                        const double x1 = ua[j] < two_nb ? t1[base + ua[j]] : 0.0;
+                        const double x2 = ub[j] < two_nb ? t2[base + ub[j]] : 0.0;
+                        acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1 * vk[ks], x2, acc[j], 0, 0, 0);
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < UPW; ++j) {
+        if (ua[j] < 0) continue;
+        const int tp = (int)blockIdx.y * NW * UPW + wave + NW * j;
+        double *out = c.part + ((size_t)unit * (size_t)c.npairs + tp) * 256;
+        // f64 16x16x4 result: register q of lane l is D[4q + l/16][l % 16];
+        // f32 16x16x4 result: register q of lane l is D[4 (l/16) + q][l % 16]
+#pragma unroll
+        for (int q = 0; q < 4; ++q) out[(F32 ? 4 * kq + q : 4 * q + kq) * 16 + row] = acc[j][q];
+    }
+}
+
+template <bool F32, int NW, int UPW, int ROWS, bool SYM>
+static void launch_pair_lds(dim3 grid, size_t lds, const PairArgs &c, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_pair_lds<F32, NW, UPW, ROWS, SYM>), grid, dim3(NW * 64), lds, s, c);
+}
+
+template <bool F32, bool SYM>
+static void launch_pair_shape(dim3 grid, size_t lds, const PairArgs &c, hipStream_t s)
+{
+    // one tile pair per wave, as many waves as pairs up to T = 4 (6 or 9 waves at T = 3: 9
+    // stage the 48 rows three per thread); beyond, groups of 16 pairs in blocks of their own
+    // (grid.y), each staging the whole tile
+    const int T = c.T;
+    if (T <= 2) launch_pair_lds<F32, 4, 1, 4, SYM>(grid, lds, c, s);
+    else if (T == 3 && SYM) launch_pair_lds<F32, 6, 1, 4, SYM>(grid, lds, c, s);
+    else if (T == 3) launch_pair_lds<F32, 9, 1, 3, SYM>(grid, lds, c, s);
+    else if (T == 4 && SYM) launch_pair_lds<F32, 10, 1, 4, SYM>(grid, lds, c, s);
+    else launch_pair_lds<F32, 16, 1, 4, SYM>(dim3(grid.x, (unsigned)((c.npairs + 15) / 16)), lds, c, s);
+}
+
+// LDS-staged pair contraction over pivot-minor multipoles: one block per (segment, map, m)
+static z3_status launch_pair(const PairArgs &c0, bool f32, bool sym, int64_t nseg, hipStream_t s)
+{
+    PairArgs c = c0;
+    c.ldr = 2 * c.nb + ((17 - 2 * c.nb) % 32 + 32) % 32;
+    const size_t lds = 2 * (size_t)kCrossKP * c.ldr * (f32 ? 4 : 8) + kCrossKP * sizeof(double);
+    int dev = 0, lds_max = 0;
+    z3_status st = check_hip(hipGetDevice(&dev), "hipGetDevice");
+    if (st == Z3_OK)
+        st = check_hip(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), "LDS size");
+    if (st != Z3_OK) return st;
+    if (lds > (size_t)lds_max)
+        return fail(Z3_ERR_UNSUPPORTED, "contraction of %d bins needs %zu bytes of LDS per block (%d)", c.nb, lds,
+                    lds_max);
+    const int64_t nblk = nseg * c.nmaps * c.M1;
+    if (nblk > (int64_t)(UINT32_MAX / 1024))
+        return fail(Z3_ERR_OVERFLOW, "contraction of %lld pivot segments x %d maps", (long long)nseg, c.nmaps);
+    const dim3 grid((unsigned)nblk);
+    if (f32) sym ? launch_pair_shape<true, true>(grid, lds, c, s) : launch_pair_shape<true, false>(grid, lds, c, s);
+    else sym ? launch_pair_shape<false, true>(grid, lds, c, s) : launch_pair_shape<false, false>(grid, lds, c, s);
+    return check_launch("k_pair_lds");
+}
+
+// ---- LDS-staged contraction of the pivot-major staging ------------------------------------
+// One block of kGramWaves waves per (pivot segment, map).  Tiles of kGramKP pivots of the
+// many-map kernel's pivot-major staging (one contiguous run of R = 2 (m_max + 1) rows per
+// pivot and bin) are staged in LDS as [pivot][bin][row], runs on consecutive lanes.  Every
+// wave then runs its (m, tile pair) units over the tile out of LDS, so each multipole is
+// fetched once per block and the staging needs no transpose.
 constexpr int kGramWaves = 8;
 constexpr int kGramThreads = kGramWaves * 64;
 constexpr int kGramKP = 16;                      // pivots per LDS tile (4 MFMA k-steps)
@@ -196,7 +314,7 @@ struct GramArgs {
     double *part;        // [seg][map][m][tile pair][256]
 };
 
-template <bool F32, bool PM, int UPW>
+template <bool F32, int UPW>
 __global__ __launch_bounds__(kGramThreads) void k_gram_lds(GramArgs g)
 {
     typedef typename std::conditional<F32, float, double>::type T;
@@ -244,61 +362,32 @@ __global__ __launch_bounds__(kGramThreads) void k_gram_lds(GramArgs g)
         // Each thread walks its elements (inner index b by `step`, wrapping into the outer
         // index) with incremental addresses, and issues the global loads of 8 elements
         // before it writes any of them to LDS, so their latencies overlap.
-        if constexpr (PM) {
-            // runs of R rows per (pivot, bin), contiguous in memory: lanes along the run
-            const int step = kGramThreads >> g.lpr_shift;
-            const int r = tid & ((1 << g.lpr_shift) - 1);
-            const int kb0 = tid >> g.lpr_shift;
-            int k = kb0 / nb, b = kb0 - k * nb;
-            const T *ptr = src + (size_t)(p0 + k) * g.src.sp + (size_t)b * g.src.sb + r;
-            int li = kb0 * R + r;
-            const int64_t d_in = (int64_t)step * g.src.sb, d_wrap = g.src.sp - (int64_t)nb * g.src.sb;
-            while (k < kGramKP) {
-                T val[8];
-                int at[8];
+        // runs of R rows per (pivot, bin), contiguous in memory: lanes along the run
+        const int step = kGramThreads >> g.lpr_shift;
+        const int r = tid & ((1 << g.lpr_shift) - 1);
+        const int kb0 = tid >> g.lpr_shift;
+        int k = kb0 / nb, b = kb0 - k * nb;
+        const T *ptr = src + (size_t)(p0 + k) * g.src.sp + (size_t)b * g.src.sb + r;
+        int li = kb0 * R + r;
+        const int64_t d_in = (int64_t)step * g.src.sb, d_wrap = g.src.sp - (int64_t)nb * g.src.sb;
+        while (k < kGramKP) {
+            T val[8];
+            int at[8];
 #pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    at[i] = -1;
-                    if (k < kGramKP) {
-                        if (r < R) at[i] = li;
-                        val[i] = (k < np && r < R) ? *ptr : T(0);
-                        b += step;
-                        ptr += d_in;
-                        li += step * R;
-                        while (b >= nb) { b -= nb; ++k; ptr += d_wrap; }
-                    }
+            for (int i = 0; i < 8; ++i) {
+                at[i] = -1;
+                if (k < kGramKP) {
+                    if (r < R) at[i] = li;
+                    val[i] = (k < np && r < R) ? *ptr : T(0);
+                    b += step;
+                    ptr += d_in;
+                    li += step * R;
+                    while (b >= nb) { b -= nb; ++k; ptr += d_wrap; }
                 }
-#pragma unroll
-                for (int i = 0; i < 8; ++i)
-                    if (at[i] >= 0) tile[at[i]] = val[i];
             }
-        } else {
-            // runs of kGramKP pivots per (row, bin): lanes along the pivots
-            const int k = tid & (kGramKP - 1), step = kGramThreads / kGramKP;
-            const int rb0 = tid / kGramKP;
-            int r = rb0 / nb, b = rb0 - r * nb;
-            const T *ptr = src + (size_t)(p0 + k) * g.src.sp + (size_t)b * g.src.sb + (size_t)r * g.src.sr;
-            int li = (k * nb + b) * R + r;
-            const int64_t d_in = (int64_t)step * g.src.sb, d_wrap = g.src.sr - (int64_t)nb * g.src.sb;
-            while (r < R) {
-                T val[8];
-                int at[8];
 #pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    at[i] = -1;
-                    if (r < R) {
-                        at[i] = li;
-                        val[i] = k < np ? *ptr : T(0);
-                        b += step;
-                        ptr += d_in;
-                        li += step * R;
-                        while (b >= nb) { b -= nb; ++r; ptr += d_wrap; li += 1 - nb * R; }
-                    }
-                }
-#pragma unroll
-                for (int i = 0; i < 8; ++i)
-                    if (at[i] >= 0) tile[at[i]] = val[i];
-            }
+            for (int i = 0; i < 8; ++i)
+                if (at[i] >= 0) tile[at[i]] = val[i];
         }
         if (tid < kGramKP) vt[tid] = tid < np ? v[p0 + tid] : 0.0;
         __syncthreads();
@@ -348,11 +437,11 @@ __global__ __launch_bounds__(kGramThreads) void k_gram_lds(GramArgs g)
     }
 }
 
-template <bool F32, bool PM>
+template <bool F32>
 static void launch_gram_lds(int upw, dim3 grid, size_t lds, const GramArgs &g, hipStream_t s)
 {
-    if (upw == 5) hipLaunchKernelGGL((k_gram_lds<F32, PM, 5>), grid, dim3(kGramThreads), lds, s, g);
-    else hipLaunchKernelGGL((k_gram_lds<F32, PM, 9>), grid, dim3(kGramThreads), lds, s, g);
+    if (upw == 5) hipLaunchKernelGGL((k_gram_lds<F32, 5>), grid, dim3(kGramThreads), lds, s, g);
+    else hipLaunchKernelGGL((k_gram_lds<F32, 9>), grid, dim3(kGramThreads), lds, s, g);
 }
 
 static z3_status contract_src(int64_t npiv, int m_max, int nbins, int prec, int nmaps, const GramSrc &src, bool pm,
@@ -368,7 +457,9 @@ static z3_status contract_src(int64_t npiv, int m_max, int nbins, int prec, int 
     if ((int64_t)nmaps * (m_max + 1) > 65535) return fail(Z3_ERR_OVERFLOW, "too many maps for one contraction");
     const bool f32 = prec == Z3_PREC_MIXED;
     z3_status st;
-    if (gram_lds_fits(m_max, nbins, prec)) {
+    if (pm) {
+        if (!gram_lds_fits(m_max, nbins, prec))
+            return fail(Z3_ERR_UNSUPPORTED, "pivot-major contraction for m_max=%d, %d bins", m_max, nbins);
         // one block per (segment, map): the dispatch stays below 2^32 work-items
         if (nseg * nmaps > (int64_t)(UINT32_MAX / kGramThreads))
             return fail(Z3_ERR_OVERFLOW, "contraction of %lld pivots x %d maps in one launch", (long long)npiv, nmaps);
@@ -390,21 +481,24 @@ static z3_status contract_src(int64_t npiv, int m_max, int nbins, int prec, int 
         const int upw = gram_upw(g.nunits);
         const dim3 grid((unsigned)(nseg * nmaps));
         const size_t lds = g.tile_bytes + kGramKP * sizeof(double);
-        if (f32) pm ? launch_gram_lds<true, true>(upw, grid, lds, g, s) : launch_gram_lds<true, false>(upw, grid, lds, g, s);
-        else pm ? launch_gram_lds<false, true>(upw, grid, lds, g, s) : launch_gram_lds<false, false>(upw, grid, lds, g, s);
+        if (f32) launch_gram_lds<true>(upw, grid, lds, g, s);
+        else launch_gram_lds<false>(upw, grid, lds, g, s);
         st = check_launch("k_gram_lds");
     } else {
-        if (pm) return fail(Z3_ERR_UNSUPPORTED, "pivot-major contraction for m_max=%d, %d bins", m_max, nbins);
-        ContractArgs c;
-        c.A = src.base; c.ldA = src.sb; c.npiv = npiv; c.v = piv_v; c.nb = nbins; c.T = T; c.ntp = ntp;
-        c.M1 = m_max + 1;
+        PairArgs c = {};
+        c.A1 = src.base;
+        c.ldA = src.sb;
+        c.npiv = npiv;
+        c.v = piv_v;
         c.a_stride = src.map_stride;
         c.v_stride = v_stride;
+        c.nb = nbins;
+        c.T = T;
+        c.M1 = m_max + 1;
+        c.nmaps = nmaps;
+        c.npairs = ntp;
         c.part = static_cast<double *>(partials);
-        dim3 grid(ntp, (unsigned)nseg, (unsigned)(nmaps * (m_max + 1)));
-        if (f32) hipLaunchKernelGGL(k_gram_tiles<true>, grid, dim3(64), 0, s, c);
-        else hipLaunchKernelGGL(k_gram_tiles<false>, grid, dim3(64), 0, s, c);
-        st = check_launch("k_gram_tiles");
+        st = launch_pair(c, f32, true, nseg, s);
     }
     if (st != Z3_OK) return st;
     const int total = nmaps * (m_max + 1) * nbins * nbins;
@@ -437,161 +531,6 @@ z3_status launch_contract(int64_t npiv, int m_max, int nbins, int prec, const vo
                           hipStream_t s)
 {
     return launch_contract_maps(npiv, m_max, nbins, prec, 1, A, ldA, 0, piv_v, 0, zeta, 0, partials, partial_bytes, s);
-}
-
-// ---- multi-field contraction ------------------------------------------------------------
-// For the pivot field's values v_p and two neighbour fields with multipoles U1 and U2 (same
-// pivots, same bins):  G = sum_p v_p U1_p U2_p^T, a full 2nb x 2nb matrix (no symmetry), and
-//     Re zeta_m(b1, b2) = G(r1, r2) + G(i1, i2),   Im zeta_m(b1, b2) = G(i1, r2) - G(r1, i2),
-// i.e. sum_p v_p X1(b1) conj(X2(b2)).  One block of kGramWaves waves per (pivot segment, m):
-// tiles of kGramKP pivots of both fields' 2nb rows of that m are staged in LDS as
-// [pivot][row], 16 consecutive pivots of a row on 16 consecutive lanes (one contiguous run
-// of the pivot-minor layout), and the waves run the T x T tile pairs out of LDS, so every
-// multipole is read from memory once per launch.  MFMA as in the one-field contraction
-// (split FP32 operand on the mixed path), fixed-order FP64 sums.
-
-struct CrossArgs {
-    const void *A1, *A2;  // [m+1][2][nb][ldA] multipoles of the b1 field and of the b2 field
-    int64_t ldA;
-    int64_t npiv;
-    const double *v;      // pivot products w_p x_p of the pivot field
-    int nb, T, M1;
-    int ldr;              // LDS row length: the least >= 2 nb that is 17 mod 32 (conflict-free
-                          // staging writes, 16 pivots of a row 17 banks apart; operand reads
-                          // of the four pivot groups nearly so)
-    double *part;         // [seg][m][T * T][256]
-};
-
-constexpr int kCrossKP = 32;  // pivots per LDS tile of the multi-field contraction (8 MFMA k-steps)
-
-// NW waves per block, UPW tile pairs per wave, tile pairs blockIdx.y NW UPW onwards; each
-// thread stages up to ROWS rows of both fields per tile (2 nb <= 16 T <= ROWS x 2 NW for
-// every shape launched).
-template <bool F32, int NW, int UPW, int ROWS>
-__global__ __launch_bounds__(NW * 64) void k_cross_lds(CrossArgs c)
-{
-    typedef typename std::conditional<F32, float, double>::type E;
-    constexpr int kThreads = NW * 64, kRows = ROWS;
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int ldr = c.ldr;
-    E *t1 = reinterpret_cast<E *>(smem);                          // [kCrossKP][ldr]
-    E *t2 = t1 + kCrossKP * ldr;                                  // [kCrossKP][ldr]
-    double *vt = reinterpret_cast<double *>(t2 + kCrossKP * ldr);  // [kCrossKP]
-    const int64_t seg = blockIdx.x / c.M1;
-    const int m = (int)(blockIdx.x - seg * c.M1);
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int row = lane & 15, kq = lane >> 4;
-    const int two_nb = 2 * c.nb, T = c.T;
-    const E *src1 = static_cast<const E *>(c.A1) + (size_t)2 * m * c.nb * c.ldA;
-    const E *src2 = static_cast<const E *>(c.A2) + (size_t)2 * m * c.nb * c.ldA;
-
-    int ua[UPW], ub[UPW];
-    v4d acc[UPW];
-#pragma unroll
-    for (int j = 0; j < UPW; ++j) {
-        const int tp = (int)blockIdx.y * NW * UPW + wave + NW * j;
-        acc[j] = v4d{0.0, 0.0, 0.0, 0.0};
-        ua[j] = ub[j] = -1;
-        if (tp < T * T) {
-            ua[j] = (tp / T) * 16 + row;
-            ub[j] = (tp % T) * 16 + row;
-        }
-    }
-    const int64_t pbeg = seg * kSeg;
-    const int64_t pend = min(c.npiv, pbeg + kSeg);
-    // staging: thread -> (row u, pivot k), kCrossKP pivots of a row on consecutive lanes (one
-    // contiguous run of the pivot-minor layout); the next tile's global loads are issued
-    // before the current tile's MFMAs
-    const int k = tid % kCrossKP, u0 = tid / kCrossKP, ustep = kThreads / kCrossKP;
-    E a[kRows], b[kRows];
-    auto fetch = [&](int64_t q0) {
-        const bool kin = q0 + k < pend;
-#pragma unroll
-        for (int i = 0; i < kRows; ++i) {
-            const int uu = u0 + i * ustep;
-            const bool in = uu < two_nb && kin;
-            a[i] = in ? src1[(size_t)uu * c.ldA + q0 + k] : E(0);
-            b[i] = in ? src2[(size_t)uu * c.ldA + q0 + k] : E(0);
-        }
-    };
-    fetch(pbeg);
-    for (int64_t p0 = pbeg; p0 < pend; p0 += kCrossKP) {
-        const int np = (int)min((int64_t)kCrossKP, pend - p0);
-        __syncthreads();  // the previous tile is consumed
-#pragma unroll
-        for (int i = 0; i < kRows; ++i) {
-            const int uu = u0 + i * ustep;
-            if (uu < two_nb) {
-                t1[k * ldr + uu] = a[i];
-                t2[k * ldr + uu] = b[i];
-            }
-        }
-        if (tid < kCrossKP) vt[tid] = tid < np ? c.v[p0 + tid] : 0.0;
-        __syncthreads();
-        if (p0 + kCrossKP < pend) fetch(p0 + kCrossKP);
-#pragma unroll
-        for (int h = 0; h < kCrossKP / 16; ++h) {
-            double vk[4];
-#pragma unroll
-            for (int ks = 0; ks < 4; ++ks) vk[ks] = vt[16 * h + 4 * ks + kq];
-#pragma unroll
-            for (int j = 0; j < UPW; ++j) {
-                if (ua[j] < 0) continue;  // wave-uniform
-                if constexpr (F32) {
-                    // FP32 products over 16 pivots, then into the FP64 sum; the scaled operand
-                    // v_p U1 is formed in FP64 and carried as FP32 hi + lo
-                    v4f part = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-                    for (int ks = 0; ks < 4; ++ks) {
-                        const int base = (16 * h + 4 * ks + kq) * ldr;
-                        const float x1 = ua[j] < two_nb ? t1[base + ua[j]] : 0.0f;
-                        const float x2 = ub[j] < two_nb ? t2[base + ub[j]] : 0.0f;
-                        const double av = (double)x1 * vk[ks];
-                        const float ahi = (float)av;
-                        const float alo = (float)(av - (double)ahi);
-                        part = __builtin_amdgcn_mfma_f32_16x16x4f32(ahi, x2, part, 0, 0, 0);
-                        part = __builtin_amdgcn_mfma_f32_16x16x4f32(alo, x2, part, 0, 0, 0);
-                    }
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) acc[j][q] += (double)part[q];
-                } else {
-#pragma unroll
-                    for (int ks = 0; ks < 4; ++ks) {
-                        const int base = (16 * h + 4 * ks + kq) * ldr;
-                        const double x1 = ua[j] < two_nb ? t1[base + ua[j]] : 0.0;
-                        const double x2 = ub[j] < two_nb ? t2[base + ub[j]] : 0.0;
-                        acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1 * vk[ks], x2, acc[j], 0, 0, 0);
-                    }
-                }
-            }
-        }
-    }
-#pragma unroll
-    for (int j = 0; j < UPW; ++j) {
-        if (ua[j] < 0) continue;
-        const int tp = (int)blockIdx.y * NW * UPW + wave + NW * j;
-        double *out = c.part + ((size_t)(seg * c.M1 + m) * (size_t)(T * T) + tp) * 256;
-        // f64 16x16x4 result: register q of lane l is D[4q + l/16][l % 16];
-        // f32 16x16x4 result: register q of lane l is D[4 (l/16) + q][l % 16]
-#pragma unroll
-        for (int q = 0; q < 4; ++q) out[(F32 ? 4 * kq + q : 4 * q + kq) * 16 + row] = acc[j][q];
-    }
-}
-
-template <bool F32, int NW, int UPW, int ROWS>
-static void launch_cross_lds(dim3 grid, size_t lds, const CrossArgs &c, hipStream_t s)
-{
-    hipLaunchKernelGGL((k_cross_lds<F32, NW, UPW, ROWS>), grid, dim3(NW * 64), lds, s, c);
-}
-
-template <bool F32>
-static void launch_cross_shape(int T, dim3 grid, size_t lds, const CrossArgs &c, hipStream_t s)
-{
-    // one tile pair per wave: T^2 waves up to T = 4; beyond, groups of 16 pairs in blocks of
-    // their own (grid.y), each staging the whole tile
-    if (T <= 2) launch_cross_lds<F32, 4, 1, 4>(grid, lds, c, s);
-    else if (T == 3) launch_cross_lds<F32, 9, 1, 3>(grid, lds, c, s);
-    else launch_cross_lds<F32, 16, 1, 4>(dim3(grid.x, (unsigned)((T * T + 15) / 16)), lds, c, s);
 }
 
 __device__ __forceinline__ double cross_at(const double *seg_m, int T, int u, int v)
@@ -634,26 +573,19 @@ z3_status launch_contract_cross(int64_t npiv, int m_max, int nbins, int prec, co
     const int64_t nseg = (npiv + kSeg - 1) / kSeg;
     if (partial_bytes < cross_partial_bytes(npiv, m_max, nbins))
         return fail(Z3_ERR_INVALID_ARG, "multi-field contraction: partial buffer too small");
-    if (nseg * (m_max + 1) > (int64_t)(UINT32_MAX / 1024))
-        return fail(Z3_ERR_OVERFLOW, "multi-field contraction: %lld pivot segments", (long long)nseg);
-    CrossArgs c;
-    c.A1 = A1; c.A2 = A2; c.ldA = ldA; c.npiv = npiv; c.v = piv_v; c.nb = nbins; c.T = T; c.M1 = m_max + 1;
-    c.ldr = 2 * nbins + ((17 - 2 * nbins) % 32 + 32) % 32;
+    PairArgs c = {};
+    c.A1 = A1;
+    c.A2 = A2;
+    c.ldA = ldA;
+    c.npiv = npiv;
+    c.v = piv_v;
+    c.nb = nbins;
+    c.T = T;
+    c.M1 = m_max + 1;
+    c.nmaps = 1;
+    c.npairs = T * T;
     c.part = static_cast<double *>(partials);
-    const bool f32 = prec == Z3_PREC_MIXED;
-    const size_t lds = 2 * (size_t)kCrossKP * c.ldr * (f32 ? 4 : 8) + kCrossKP * sizeof(double);
-    int dev = 0, lds_max = 0;
-    z3_status st0 = check_hip(hipGetDevice(&dev), "hipGetDevice");
-    if (st0 == Z3_OK)
-        st0 = check_hip(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), "LDS size");
-    if (st0 != Z3_OK) return st0;
-    if (lds > (size_t)lds_max)
-        return fail(Z3_ERR_UNSUPPORTED, "multi-field contraction of %d bins needs %zu bytes of LDS per block (%d)", nbins,
-                    lds, lds_max);
-    const dim3 grid((unsigned)(nseg * (m_max + 1)));
-    if (f32) launch_cross_shape<true>(T, grid, lds, c, s);
-    else launch_cross_shape<false>(T, grid, lds, c, s);
-    z3_status st = check_launch("k_cross_lds");
+    z3_status st = launch_pair(c, prec == Z3_PREC_MIXED, false, nseg, s);
     if (st != Z3_OK) return st;
     const int total = (m_max + 1) * nbins * nbins;
     hipLaunchKernelGGL(k_cross_reduce, dim3((total + 127) / 128), dim3(128), 0, s,

@@ -48,30 +48,51 @@ __device__ __forceinline__ double longitude(double x, double y)
 
 // ---- kernels ---------------------------------------------------------------------------
 
-__global__ void k_theta_range(const double *xyz, int64_t n, double *range /* [2]: min, max */)
+// Colatitude range of the positions and their largest deviation | |r|^2 - 1 | from unit
+// length (non-finite -> +inf), one pass over the coordinates: a grid-stride extremum per
+// thread, a block reduction, one atomic per block and quantity.
+__global__ __launch_bounds__(256) void k_sky_range(const double *xyz, int64_t n, double *range /* [3] */)
 {
-    __shared__ double smin[256], smax[256];
-    double lo = 4.0, hi = 0.0;
+    __shared__ double smin[256], smax[256], sdev[256];
+    double lo = 4.0, hi = 0.0, dev = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        double th = colatitude(xyz[i], xyz[n + i], xyz[2 * n + i]);
+        const double x = xyz[i], y = xyz[n + i], z = xyz[2 * n + i];
+        const double th = colatitude(x, y, z);
         lo = fmin(lo, th);
         hi = fmax(hi, th);
+        double d = fabs((x * x + y * y + z * z) - 1.0);
+        if (!(d <= 1e300)) d = INFINITY;
+        dev = fmax(dev, d);
     }
     smin[threadIdx.x] = lo;
     smax[threadIdx.x] = hi;
+    sdev[threadIdx.x] = dev;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
         if ((int)threadIdx.x < o) {
             smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + o]);
             smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + o]);
+            sdev[threadIdx.x] = fmax(sdev[threadIdx.x], sdev[threadIdx.x + o]);
         }
         __syncthreads();
     }
     if (threadIdx.x == 0) {
         atomic_min_pos_double(&range[0], smin[0]);
         atomic_max_pos_double(&range[1], smax[0]);
+        if (sdev[0] > 0.0) atomic_max_pos_double(&range[2], sdev[0]);
     }
 }
+
+// colatitude ranges of the bands start empty: [lo0, 0]
+__global__ void k_init_band_th(double *band_th, int nbands, double lo0)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nbands) return;
+    band_th[2 * k] = lo0;
+    band_th[2 * k + 1] = 0.0;
+}
+
+__global__ void k_set_int(int *p, int v) { *p = v; }
 
 // Band of every point, with per-band counts and colatitude ranges.  Consecutive points
 // usually share a band, so the lanes of a wave combine their updates per distinct band
@@ -110,21 +131,6 @@ __global__ void k_band_of_point(const double *xyz, int64_t n, double inv_h, int 
         }
         todo &= ~grp;
     }
-}
-
-// Largest deviation | |r|^2 - 1 | of the positions from unit length (non-finite -> +inf),
-// reduced per wave, then one atomic per wave.
-__global__ void k_norm_dev(const double *xyz, int64_t n, double *out)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double dev = 0.0;
-    if (i < n) {
-        const double x = xyz[i], y = xyz[n + i], z = xyz[2 * n + i];
-        dev = fabs((x * x + y * y + z * z) - 1.0);
-        if (!(dev <= 1e300)) dev = INFINITY;
-    }
-    for (int o = 32; o > 0; o >>= 1) dev = fmax(dev, __shfl_xor(dev, o, kWave));
-    if ((threadIdx.x & (kWave - 1)) == 0 && dev > 0.0) atomic_max_pos_double(out, dev);
 }
 
 __global__ void k_cell_of_point(int64_t n, const int *band, const double *phi, const Band *bands,
@@ -535,37 +541,47 @@ z3_status build_index_impl(int64_t n, const double *xyz, const double *w, int nb
                         "copy edges")) != Z3_OK)
         return bail(st);
 
-    // ---- band height -------------------------------------------------------------------
+    // ---- band height; sky positions: colatitude range and unit-length check --------------
+    // Sky positions must be unit vectors: the windows are angular while membership is the
+    // chord test on the raw vectors, and the windows' guards (1e-9 relative) cover a
+    // deviation | |r|^2 - 1 | of up to kMaxNormDev only.
     double h = cell_size;
     double *d_range = nullptr;
-    if ((st = dalloc(&d_range, 2, "alloc range")) != Z3_OK) return bail(st);
+    if ((st = dalloc(&d_range, 3, "alloc range")) != Z3_OK) return bail(st);
     if (planar && h <= 0.0) {
         // the same 1.4 x mean spacing as on the sphere
         double area = lx * ly;
         if (!(area > 0.0)) area = std::max(lx, ly) * std::max(lx, ly) / (double)std::max<int64_t>(n, 1);
         if (!(area > 0.0)) area = 1.0;
         h = Z3_BAND_HEIGHT_FACTOR * sqrt(area / (double)std::max<int64_t>(n, 1));
-    } else if (h <= 0.0) {
-        double init[2] = {kPi, 0.0};
-        st = check_hip(hipMemcpyAsync(d_range, init, sizeof(init), hipMemcpyHostToDevice, s), "copy range");
+    } else if (!planar) {
+        double rg[3] = {kPi, 0.0, 0.0};
+        st = check_hip(hipMemcpyAsync(d_range, rg, sizeof(rg), hipMemcpyHostToDevice, s), "copy range");
         if (st == Z3_OK && n > 0) {
             unsigned g = grid_for(n) < 2048u ? grid_for(n) : 2048u;
-            hipLaunchKernelGGL(k_theta_range, dim3(g), dim3(256), 0, s, xyz, n, d_range);
-            st = check_launch("k_theta_range");
+            hipLaunchKernelGGL(k_sky_range, dim3(g), dim3(256), 0, s, xyz, n, d_range);
+            st = check_launch("k_sky_range");
         }
-        double rg[2] = {0.0, kPi};
         if (st == Z3_OK) st = check_hip(hipMemcpyAsync(rg, d_range, sizeof(rg), hipMemcpyDeviceToHost, s), "copy range");
         if (st == Z3_OK) st = check_hip(hipStreamSynchronize(s), "sync");
         if (st != Z3_OK) { (void)hipFree(d_range); return bail(st); }
-        double area = 2.0 * kPi * (cos(std::min(rg[0], rg[1])) - cos(std::max(rg[0], rg[1])));
-        if (!(area > 0.0)) area = 1e-12;
-        // 1.4 x the mean point spacing: about two HEALPix rings per band (ring spacing
-        // 2 / (3 Nside) rad at low latitudes, mean spacing ~1.023 / Nside).  Each band
-        // costs every pivot one longitude window per bin, whose set-up (window bounds,
-        // cell lookups, the mixed path's flush into FP64) outweighs the few candidates
-        // that a taller band adds at the window ends; measured on HEALPix maps at Nside
-        // 512 and 2048 against 0.6 (one ring per band) to 2.6, 1.3-1.8 is best.
-        h = Z3_BAND_HEIGHT_FACTOR * sqrt(area / (double)std::max<int64_t>(n, 1));
+        if (!(rg[2] <= kMaxNormDev)) {
+            (void)hipFree(d_range);
+            return bail(fail(Z3_ERR_INVALID_ARG,
+                             "z3_build_index: positions are not unit vectors (max | |r|^2 - 1 | = %g, limit %g)", rg[2],
+                             kMaxNormDev));
+        }
+        if (h <= 0.0) {
+            double area = 2.0 * kPi * (cos(std::min(rg[0], rg[1])) - cos(std::max(rg[0], rg[1])));
+            if (!(area > 0.0)) area = 1e-12;
+            // 1.4 x the mean point spacing: about two HEALPix rings per band (ring spacing
+            // 2 / (3 Nside) rad at low latitudes, mean spacing ~1.023 / Nside).  Each band
+            // costs every pivot one longitude window per bin, whose set-up (window bounds,
+            // cell lookups, the mixed path's flush into FP64) outweighs the few candidates
+            // that a taller band adds at the window ends; measured on HEALPix maps at Nside
+            // 512 and 2048 against 0.6 (one ring per band) to 2.6, 1.3-1.8 is best.
+            h = Z3_BAND_HEIGHT_FACTOR * sqrt(area / (double)std::max<int64_t>(n, 1));
+        }
     }
     (void)hipFree(d_range);
     int nbands = 1;
@@ -600,15 +616,10 @@ z3_status build_index_impl(int64_t n, const double *xyz, const double *w, int nb
     if ((st = dalloc(&d_band_count, nbands, "alloc band count")) != Z3_OK) return bail2(st);
     if ((st = dalloc(&d_band_th, 2 * (size_t)nbands, "alloc band theta")) != Z3_OK) return bail2(st);
     hipLaunchKernelGGL(k_fill_int, dim3(grid_for(nbands)), dim3(256), 0, s, d_band_count, (int64_t)nbands, 0);
-    {
-        // th_lo starts at +big, th_hi at 0
-        std::vector<double> init(2 * (size_t)nbands);
-        for (int k = 0; k < nbands; ++k) { init[2 * k] = planar ? INFINITY : 4.0; init[2 * k + 1] = 0.0; }
-        st = check_hip(hipMemcpyAsync(d_band_th, init.data(), init.size() * sizeof(double), hipMemcpyHostToDevice, s),
-                       "copy band init");
-        if (st == Z3_OK) st = check_hip(hipStreamSynchronize(s), "sync");
-        if (st != Z3_OK) return bail2(st);
-    }
+    // th_lo starts at +big, th_hi at 0
+    hipLaunchKernelGGL(k_init_band_th, dim3((unsigned)((nbands + 255) / 256)), dim3(256), 0, s, d_band_th, nbands,
+                       planar ? INFINITY : 4.0);
+    if ((st = check_launch("k_init_band_th")) != Z3_OK) return bail2(st);
     if (n > 0 && planar) {
         hipLaunchKernelGGL(k_band_of_point_plane, dim3(grid_for(n)), dim3(256), 0, s, xyz, n, idx->plane_y0, 1.0 / h,
                            idx->plane_x0, idx->plane_sx, nbands, d_band, d_phi, d_band_count, d_band_th);
@@ -618,33 +629,13 @@ z3_status build_index_impl(int64_t n, const double *xyz, const double *w, int nb
                            d_phi, d_band_count, d_band_th);
         if ((st = check_launch("k_band_of_point")) != Z3_OK) return bail2(st);
     }
-    // sky positions must be unit vectors: the windows are angular while membership is the
-    // chord test on the raw vectors, and the windows' guards (1e-9 relative) cover a
-    // deviation | |r|^2 - 1 | of up to kMaxNormDev only
-    double *d_dev = nullptr;
-    if (!planar) {
-        if ((st = dalloc(&d_dev, 1, "alloc norm deviation")) != Z3_OK) return bail2(st);
-        st = check_hip(hipMemsetAsync(d_dev, 0, sizeof(double), s), "clear norm deviation");
-        if (st == Z3_OK && n > 0) {
-            hipLaunchKernelGGL(k_norm_dev, dim3(grid_for(n)), dim3(256), 0, s, xyz, n, d_dev);
-            st = check_launch("k_norm_dev");
-        }
-        if (st != Z3_OK) { (void)hipStreamSynchronize(s); (void)hipFree(d_dev); return bail2(st); }
-    }
     std::vector<int> bcount(nbands);
     std::vector<double> bth(2 * (size_t)nbands);
-    double dev = 0.0;
     st = check_hip(hipMemcpyAsync(bcount.data(), d_band_count, nbands * sizeof(int), hipMemcpyDeviceToHost, s), "copy");
     if (st == Z3_OK)
         st = check_hip(hipMemcpyAsync(bth.data(), d_band_th, bth.size() * sizeof(double), hipMemcpyDeviceToHost, s), "copy");
-    if (st == Z3_OK && d_dev) st = check_hip(hipMemcpyAsync(&dev, d_dev, sizeof(double), hipMemcpyDeviceToHost, s), "copy");
     if (st == Z3_OK) st = check_hip(hipStreamSynchronize(s), "sync");
-    if (d_dev) (void)hipFree(d_dev);
     if (st != Z3_OK) return bail2(st);
-    if (!(dev <= kMaxNormDev))
-        return bail2(fail(Z3_ERR_INVALID_ARG,
-                          "z3_build_index: positions are not unit vectors (max | |r|^2 - 1 | = %g, limit %g)", dev,
-                          kMaxNormDev));
 
     // the multipole kernel addresses a band's doubled records (64 B per point) with 32-bit
     // byte offsets
@@ -694,13 +685,8 @@ z3_status build_index_impl(int64_t n, const double *xyz, const double *w, int nb
     }
     if ((st = exclusive_scan(d_cell_count, cells, idx->d_cell_start, s)) != Z3_OK) return bail2(st);
     // cell_start[cells] = n (bands are contiguous and cover all points)
-    {
-        int nn = (int)n;
-        st = check_hip(hipMemcpyAsync(idx->d_cell_start + cells, &nn, sizeof(int), hipMemcpyHostToDevice, s),
-                       "copy total");
-        if (st == Z3_OK) st = check_hip(hipStreamSynchronize(s), "sync");
-        if (st != Z3_OK) return bail2(st);
-    }
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, idx->d_cell_start + cells, (int)n);
+    if ((st = check_launch("k_set_int")) != Z3_OK) return bail2(st);
     if ((st = dalloc(&idx->d_perm, n, "alloc perm")) != Z3_OK) return bail2(st);
     hipLaunchKernelGGL(k_fill_int, dim3(grid_for(cells + 1)), dim3(256), 0, s, d_cell_count, cells + 1, 0);
     if (n > 0) {

@@ -25,3 +25,24 @@ def test_help_lists_the_workload_options():
     for opt in ("--config", "--prec", "--approx", "--adjoint", "--graph", "--cross", "--exclude-self",
                 "--shard", "--nside", "--m-max", "--cpu-sample"):
         assert opt in r.stdout, opt
+
+
+def test_entry_errors_one_map_and_several_maps():
+    import numpy as np
+    sys.path.insert(0, ROOT)
+    import bench
+    rng = np.random.default_rng(0)
+    ref = rng.normal(size=(3, 5, 4, 4)) + 1j * rng.normal(size=(3, 5, 4, 4))
+    ref = ref + np.conj(np.swapaxes(ref, -1, -2))  # Hermitian per m, like zeta_m
+    test = ref * (1 + 1e-7 * rng.normal(size=ref.shape))
+    one = bench.entry_errors(test[1], ref[1])
+    many = bench.entry_errors(test, ref)
+    assert many["entries"] == 3 * one["entries"]
+    assert one["max_rel_err"] <= many["max_rel_err"] < 1e-6
+    assert len(many["max_rel_err_per_m"]) == 5 and "map" in many["worst"][0]
+    assert "map" not in one["worst"][0]
+
+
+def test_fftlog_option_is_listed():
+    r = _run("--help")
+    assert "--fftlog" in r.stdout and "--hist" in r.stdout
