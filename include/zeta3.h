@@ -222,7 +222,10 @@ z3_status z3_estimate(z3_index idx, int map, int m_max, int prec, int64_t p0, in
  * for every m (0 where W_{p,b} = 0), accumulated in FP64 on either precision path, so that
  * zeta holds the triplet sum over k != j; the other entries are those of z3_estimate.
  * Same arguments, chunking and accumulation (zeta +=, unnormalised) as z3_estimate;
- * the removal adds a workspace of 8 x nbins bytes per 64 pivots of a chunk.
+ * the removal adds a workspace of 8 x nbins bytes per 64 pivots of a chunk.  With the flag
+ * Z3_PREC_MIXED stores and contracts the multipoles in FP64 (as Z3_PREC_FP64 does): the
+ * removed self terms can be most of |X_m(b)|^2, and FP32 storage would leave an error
+ * relative to the full product rather than to the smaller result.
  */
 z3_status z3_estimate_ex(z3_index idx, int map, int m_max, int prec, unsigned flags, int64_t p0,
                          int64_t p1, double *zeta, uint64_t *pair_total, void *stream);

@@ -487,6 +487,11 @@ static z3_status estimate_chunks(z3_index idx, int map, int m_max, int prec, boo
                                  double *zeta, uint64_t *pair_total, hipStream_t s, void *fixed, size_t fixed_bytes)
 {
     z3_status st = Z3_OK;
+    // Without the k = j terms the mixed path keeps FP64 storage and contraction: the exact
+    // self terms removed from the diagonal can be most of |X_m(b)|^2, and the FP32 rounding
+    // of X would leave an error relative to that full product, not to the smaller result.
+    // Its multipoles are FP64 arithmetic on both paths, so this costs no time.
+    if (no_self) prec = Z3_PREC_FP64;
     const size_t elem = prec == Z3_PREC_FP64 ? 8 : 4;
     const size_t per_piv = (size_t)(m_max + 1) * 2 * idx->nbins * elem;
     auto round256 = [](size_t b) { return (b + 255) / 256 * 256; };

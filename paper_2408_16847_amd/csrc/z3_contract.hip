@@ -107,7 +107,7 @@ __global__ __launch_bounds__(NW * 64) void k_pair_lds(PairArgs c)
     const int ldr = c.ldr;
     E *t1 = reinterpret_cast<E *>(smem);                          // [kCrossKP][ldr]
     E *t2 = SYM ? t1 : t1 + kCrossKP * ldr;                       // [kCrossKP][ldr]
-    double *vt = reinterpret_cast<double *>(t1 + 2 * kCrossKP * ldr);  // [kCrossKP]
+    double *vt = reinterpret_cast<double *>(t1 + (SYM ? 1 : 2) * kCrossKP * ldr);  // [kCrossKP]
     const int64_t unit = blockIdx.x;  // (segment, map, m)
     const int m = (int)(unit % c.M1);
     const int map = (int)((unit / c.M1) % c.nmaps);
@@ -245,7 +245,8 @@ static z3_status launch_pair(const PairArgs &c0, bool f32, bool sym, int64_t nse
 {
     PairArgs c = c0;
     c.ldr = 2 * c.nb + ((17 - 2 * c.nb) % 32 + 32) % 32;
-    const size_t lds = 2 * (size_t)kCrossKP * c.ldr * (f32 ? 4 : 8) + kCrossKP * sizeof(double);
+    const size_t tile = (size_t)kCrossKP * c.ldr * (f32 ? 4 : 8);
+    const size_t lds = (sym ? 1 : 2) * (tile + 7) / 8 * 8 + kCrossKP * sizeof(double);
     int dev = 0, lds_max = 0;
     z3_status st = check_hip(hipGetDevice(&dev), "hipGetDevice");
     if (st == Z3_OK)
