@@ -343,6 +343,13 @@ def main():
     precs = ["fp64", "mixed"] if args.prec == "both" else [args.prec]
     res = {}
     for prec in precs:
+        if args.adjoint and not args.graph:
+            # the workload's pair count, once and outside the timed steps (the autograd step
+            # does not return it; a counting pass costs ~2/3 of a forward)
+            pidx = z3.Index(xyz, E)
+            pidx.set_values(x)
+            pairs_of(pidx, prec)
+            pidx.free()
         for w in range(args.warmup):
             step(prec)
             log(f"[bench] {prec} warmup {w + 1}/{args.warmup} done")

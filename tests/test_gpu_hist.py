@@ -3,7 +3,8 @@ z3_accumulate_histogram, z3_estimate_histogram) against the oracle's oracle/hist
 per-(pivot, radial bin, angular bin) pair counts bit-exact, W and N exact, per-pivot
 multipoles within 1e-11 of each bin's scale (FP64; the FP32 storage of the mixed path
 within 1.2e-7), zeta within 1e-10 (FP64) and 1e-6 (mixed); the three-point golden values;
-full-sky HEALPix pivots at both poles and across the longitude wrap; m_max up to 127;
+full-sky HEALPix pivots at both poles and across the longitude wrap; the bench's largest
+configuration (nside512, m_max 64, 130 angular bins) on sampled pivots; m_max up to 127;
 argument checks."""
 
 import ctypes
@@ -189,3 +190,50 @@ def test_arguments():
     with pytest.raises(_lib.Zeta3Error):
         pidx.set_phi_bins(phi_boundaries(16))
     pidx.free()
+
+
+def _neighbour_subset(xyz, piv, theta_max):
+    """Indices of the points within theta_max (plus a margin) of any of the pivots, by a
+    chunked dot-product filter: every pair the exact chord test accepts is among them."""
+    c = np.cos(theta_max + 1e-6)
+    keep = np.zeros(xyz.shape[1], dtype=bool)
+    for s in range(0, xyz.shape[1], 1 << 18):
+        d = xyz[:, s:s + (1 << 18)].T @ piv
+        keep[s:s + (1 << 18)] = (d > c).any(axis=1)
+    return np.nonzero(keep)[0]
+
+
+def test_fullsize_nside512_sampled_pivots():
+    """The bench's largest histogram configuration (nside512, m_max 64, 130 angular bins) on
+    sampled pivot ranges at the north pole, across the longitude wrap near the equator and
+    at the south pole, each against the oracle on the neighbours within reach."""
+    cfg = CONFIGS["nside512"]
+    M, n_phi = 64, 130
+    G.say("case: histogram full size", cfg.name, "m_max", M, "n_phi", n_phi)
+    xyz_d = make_positions(cfg, device="cuda")
+    x_d = make_values(cfg, xyz_d, seed=0)
+    E = cfg.edges_chord2()
+    idx = z3.Index(xyz_d, E)
+    idx.set_values(x_d)
+    bnd = phi_boundaries(n_phi)
+    idx.set_phi_bins(bnd)
+    xyz, x = xyz_d.cpu().numpy(), x_d.cpu().numpy()
+    perm = G.perm(idx)
+    n = len(perm)
+    lo = n // 2 - 20000
+    seg = perm[lo:n // 2 + 20000]
+    phi = np.arctan2(xyz[1, seg], xyz[0, seg]) % (2 * np.pi)
+    wrap = lo + int(np.nonzero(phi[1:] < phi[:-1] - np.pi)[0][0]) + 1
+    theta_max = 2.0 * np.arcsin(np.sqrt(E[-1]) / 2.0)
+    for p0, p1 in ((0, 211), (wrap - 100, wrap + 141), (n - 190, n)):
+        pm = perm[p0:p1]
+        sub = _neighbour_subset(xyz, xyz[:, pm], theta_max)
+        ao, Wo, No, Ho, Co = hist.multipoles_hist(xyz[:, pm], xyz[:, sub], np.ones(len(sub)), x[sub], E, M, bnd,
+                                                  want_hist=True)
+        scale = np.abs(ao).max(axis=1, keepdims=True) + 1e-300
+        a, W, N, C = _gpu_cells(idx, M, p0, p1, prec="fp64")
+        assert np.array_equal(C, Co) and np.array_equal(N, No) and np.array_equal(W, Wo)
+        err = (np.abs(a - ao) / scale).max()
+        G.say("  pivots", p0, p1, "neighbours", len(sub), "cells", int(Co.sum()), "err", err)
+        assert err < 1e-11, err
+    idx.free()
