@@ -443,6 +443,7 @@ def main():
         out["config"]["workload"] += "+graph"
     if args.save_zeta:
         np.savez(args.save_zeta, **{p: res[p]["zeta"] for p in res})
+    out["config"]["inputs_sha256"] = inputs_digest(xyz, x if x3 is None else x3, torch)
     if args.cpu_sample != 0 and cfg.nmaps == 1 and not args.cross and cfg.kind != "plane" and shard is None \
             and not args.hist:
         out["cpu_baseline"] = cpu_baseline(cfg, xyz, x, nbr, E, M, args.cpu_sample, z3, torch, self_pairs)
@@ -453,6 +454,19 @@ def main():
         torch.cuda.empty_cache()
         out["nside4096"] = nside4096_record(z3, torch)
     print(json.dumps(out), flush=True)
+
+
+def inputs_digest(xyz, x, torch):
+    """SHA-256 of the workload's inputs as the library receives them (positions, then values,
+    FP64 bytes in catalogue order), streamed from the device in slices after the timed steps,
+    so that a record names exactly the data it measured."""
+    import hashlib
+    h = hashlib.sha256()
+    for t in (xyz, x):
+        flat = t.reshape(-1)
+        for s in range(0, flat.numel(), 1 << 24):
+            h.update(flat[s:s + (1 << 24)].to(torch.float64).cpu().numpy().tobytes())
+    return h.hexdigest()
 
 
 def entry_errors(test, ref):
@@ -617,6 +631,7 @@ def fftlog_bench(args, z3, torch):
     dominant kernel is the product of the angle factor's s1 >= 0 half with the Hankel matrix of
     the chi integrals (three launches per pass, one per function): 8 ntheta (N + 1) (N/2 + 1)
     flop per launch and model (complex FP64 multiply-adds)."""
+    import hashlib
     from synth import fftlog_inputs
     S = FFTLOG_SETTINGS
     nm = args.fftlog
@@ -681,7 +696,8 @@ def fftlog_bench(args, z3, torch):
         "data": "synthetic",
         "config": {"workload": f"fftlog N={S['N']} k=[1e-6,100] nchi={S['nchi']} ntheta={S['ntheta']} "
                                f"models={nm}", "nu": list(FFTLOG_NU), **S, "nmodels": nm,
-                   "total_flops_per_step": total_flops},
+                   "total_flops_per_step": total_flops,
+                   "inputs_sha256": hashlib.sha256(Pk.tobytes() + F.tobytes() + theta.tobytes()).hexdigest()},
         "roofline": {"bound": "mfma", "kernel": "k_cgemm<2>", "achieved": achieved,
                      "peak": PEAK_MFMA_TFLOPS["fp64"], "unit": "TFLOP/s",
                      "frac": achieved / PEAK_MFMA_TFLOPS["fp64"] if achieved else None, "traffic": None,
