@@ -245,17 +245,26 @@ __global__ __launch_bounds__(256) void k_cgemm(CGemm g)
     const int jb = j0 + r;
     const bool jin = jb < g.N;
 
+    // per-lane row pointers of A and column pointer of B; k offsets stay 32-bit (k a_k, k b_k
+    // < 2^31 for every product launched)
+    const double2 *Ar[RM];
+    bool rok[RM];
+#pragma unroll
+    for (int u = 0; u < RM; ++u) {
+        const int i = i0 + 16 * u + r;
+        rok[u] = u < nrm && i < g.M;
+        Ar[u] = A + (rok[u] ? (size_t)i * g.a_i : 0);
+    }
+    const BT *Bc = B + (jin ? (size_t)jb * g.b_j : 0);
+    const int ak = (int)g.a_k, bk = (int)g.b_k;
     auto load = [&](int k, double2 (&av)[RM], BT &bv) {
         const bool kin = k < g.K;
 #pragma unroll
-        for (int u = 0; u < RM; ++u) {
-            const int i = i0 + 16 * u + r;
-            av[u] = (kin && u < nrm && i < g.M) ? A[i * g.a_i + k * g.a_k] : make_double2(0.0, 0.0);
-        }
+        for (int u = 0; u < RM; ++u) av[u] = (kin && rok[u]) ? Ar[u][k * ak] : make_double2(0.0, 0.0);
         if constexpr (BREAL)
-            bv = (kin && jin) ? B[k * g.b_k + jb * g.b_j] : 0.0;
+            bv = (kin && jin) ? Bc[k * bk] : 0.0;
         else
-            bv = (kin && jin) ? B[k * g.b_k + jb * g.b_j] : make_double2(0.0, 0.0);
+            bv = (kin && jin) ? Bc[k * bk] : make_double2(0.0, 0.0);
     };
     v4d re[RM], im[RM];
 #pragma unroll
