@@ -22,10 +22,11 @@
 // pivots), the same band windows, records and one-ahead record requests as k_multipoles.
 // Each lane owns one column of an LDS histogram [n_phi][64] (consecutive lanes in
 // consecutive words: no bank conflicts whatever the bins), cleared per radial bin; a run of
-// pairs in one angular bin is summed in registers first.  After the
-// bin's windows each lane sums its column against the bin-centre phases
-// exp(-i pi j / n_phi), j = m (2k + 1) mod 2 n_phi, read from an LDS table at a wave-uniform
-// address (one broadcast read per phase), kHistMC multipoles at a time.  Sums stay in FP64 on both precision
+// pairs in one angular bin is summed in registers first.  After the bin's windows each lane
+// forms its multipoles from its column, a_m = e^{-i m dphi/2} sum_k H_k e^{-i m k dphi}, by
+// Clenshaw's recurrence over the angular bins (one FMA and one subtraction per bin and
+// multipole, kHistMC multipoles per pass; the constants come from an LDS table of
+// (cos, sin)(pi j / n_phi) read at wave-uniform addresses).  Sums stay in FP64 on both precision
 // paths; the mixed path stores the multipoles in FP32.
 #include "z3_internal.h"
 #include "z3_device.h"
@@ -59,7 +60,7 @@ struct HistArgs {
     int nblocks;
 };
 
-constexpr int kHistMC = 16;  // multipoles per pass of the transform
+constexpr int kHistMC = 8;  // multipoles per pass of the transform
 
 __device__ __forceinline__ bool left_of(const double2 *D, int k, double u1, double u2)
 {
@@ -222,24 +223,28 @@ __global__ __launch_bounds__(kWave) void k_multipoles_hist(HistArgs a)
         }
         double inv = 1.0;
         if (a.norm == Z3_NORM_BIN) inv = Wb > 0.0 ? 1.0 / Wb : 0.0;
-        // Fourier sum over the angular bins at their centres
+        // Fourier sum over the angular bins at their centres,
+        //   a_m = e^{-i m dphi/2} sum_k H_k z^k,  z = e^{-i w}, w = m dphi,
+        // by Clenshaw's recurrence over k (backwards): b_k = H_k + 2 cos(w) b_{k+1} - b_{k+2},
+        // then sum_k H_k cos(k w) = b_0 - cos(w) b_1 and sum_k H_k sin(k w) = sin(w) b_1: one FMA
+        // and one subtraction per (k, m), kHistMC multipoles per pass over the column
         if (a.A) {
-            const int n2 = 2 * n;
             for (int m0 = 0; m0 <= a.m_max; m0 += kHistMC) {
-                double Y[kHistMC], Z[kHistMC];
+                double tc[kHistMC], b1[kHistMC], b2[kHistMC];
 #pragma unroll
-                for (int i = 0; i < kHistMC; ++i) { Y[i] = 0.0; Z[i] = 0.0; }
-                for (int k = 0; k < n; ++k) {
+                for (int i = 0; i < kHistMC; ++i) {
+                    const int m = m0 + i <= a.m_max ? m0 + i : 0;
+                    tc[i] = 2.0 * T[2 * m].x;  // 2 cos(m dphi) = 2 cos(pi 2m / n_phi)
+                    b1[i] = 0.0;
+                    b2[i] = 0.0;
+                }
+                for (int k = n - 1; k >= 0; --k) {
                     const double h = H[k * kWave + lane];
-                    const int step = 2 * k + 1;
-                    int j = (m0 * step) % n2;
 #pragma unroll
                     for (int i = 0; i < kHistMC; ++i) {
-                        const double2 w = T[j];  // wave-uniform address: one broadcast read
-                        Y[i] = fma(h, w.x, Y[i]);
-                        Z[i] = fma(h, w.y, Z[i]);
-                        j += step;
-                        j = j >= n2 ? j - n2 : j;
+                        const double b0 = fma(tc[i], b1[i], h) - b2[i];
+                        b2[i] = b1[i];
+                        b1[i] = b0;
                     }
                 }
                 if (valid) {
@@ -247,8 +252,13 @@ __global__ __launch_bounds__(kWave) void k_multipoles_hist(HistArgs a)
                     for (int i = 0; i < kHistMC; ++i) {
                         const int m = m0 + i;
                         if (m > a.m_max) break;
-                        const double re = Y[i] * inv;
-                        const double im = m == 0 ? 0.0 : -Z[i] * inv;
+                        const double2 cw = T[2 * m], hw = T[m];  // (cos, sin)(m dphi), (cos, sin)(m dphi / 2)
+                        const double pr = b1[i] - cw.x * b2[i], pi = -cw.y * b2[i];  // sum_k H_k z^k
+                        // a_m = e^{-i m dphi / 2} (pr + i pi) = Y - i Z
+                        const double Y = hw.x * pr + hw.y * pi;
+                        const double Z = hw.y * pr - hw.x * pi;
+                        const double re = Y * inv;
+                        const double im = m == 0 ? 0.0 : -Z * inv;
                         const size_t ore = ((size_t)(2 * m) * nb + bin) * (size_t)a.ldA + col;
                         const size_t oim = ((size_t)(2 * m + 1) * nb + bin) * (size_t)a.ldA + col;
                         if constexpr (F32OUT) {
