@@ -384,10 +384,11 @@ def main():
         rf_unit_note = "2 (2 m_max + 1) flop per (pair, map)"
     elif args.hist:
         # per pair: separation 3, chord 5 + 2 tests, tangent components 10, sign tests 6,
-        # histogram add 1 = 27 flop; per (pivot, bin, angular bin, m): 4 flop of the transform
+        # histogram add 1 = 27 flop; per (pivot, bin, angular bin, m): 3 flop of the transform
+        # (one step of Clenshaw's recurrence, a multiply-add and a subtraction)
         rf_kernel, rf_bound, rf_peak = "k_multipoles_hist", "alu", PEAK_VALU_TFLOPS["fp64"]
-        rf_flops = 27.0 * r["pairs"] + 4.0 * n * cfg.nbins * args.hist * (M + 1)
-        rf_unit_note = "27 flop per pair + 4 flop per (pivot, radial bin, angular bin, m)"
+        rf_flops = 27.0 * r["pairs"] + 3.0 * n * cfg.nbins * args.hist * (M + 1)
+        rf_unit_note = "27 flop per pair + 3 flop per (pivot, radial bin, angular bin, m)"
     else:
         rf_kernel, rf_bound, rf_peak = "k_multipoles", "alu", PEAK_VALU_TFLOPS[main_prec]
         rf_flops = FLOPS_PER_UPDATE * updates
