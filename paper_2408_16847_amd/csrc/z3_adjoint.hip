@@ -12,7 +12,7 @@
 // between chunks); (2) k_adjoint_prep forms D_p(a) / W_{p,a} and adds the pivot term
 // (grid y: the maps of the pass);
 // (3) k_adjoint_scatter walks the same bin/band windows as the forward kernel, rebuilds
-// cos(m phi), sin(m phi) per pair and adds the neighbour term to the neighbour's gradient
+// the harmonics per pair (as second-kind Chebyshev polynomials of cos phi) and adds the neighbour term to the neighbour's gradient
 // with an FP64 atomic (index order; permuted to catalogue order at the end).  The atomics
 // make the last bits of the gradient depend on scheduling.
 #include "z3_internal.h"
@@ -244,14 +244,26 @@ void k_adjoint_scatter(ScatterArgs a)
         const double hav_out = a.edges->hav_out[bin + 1], hav_in = a.edges->hav_in[bin];
         int klo, khi;
         band_range(f.th, a.edges->rad_out[bin + 1], a.inv_h, a.nbands, klo, khi);
-        double Dr[K][M + 1], Di[K][M + 1];
+        // sum_m cos(m phi) Dr_m + sin(m phi) Di_m rewritten on the second-kind polynomials of
+        // c = cos phi (T_m = (U_m - U_{m-2}) / 2, sin(m phi) = sin(phi) U_{m-1}):
+        //   sum_k U_k(c) (Al_k + 2 sin(phi) Bt_k),
+        //   Al_0 = Dr_0 - Dr_2 / 2,  Al_k = (Dr_k - Dr_{k+2}) / 2,  Bt_k = Di_{k+1} / 2,
+        // so that each pair runs one unit chain U_k and two FMAs per k and map.
+        double Al[K][M + 1], Bt[K][M + 1];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const double *Dk = a.D + (mp0 + k) * a.d_stride;
+            double Dr[M + 1], Di[M + 1];
 #pragma unroll
             for (int m = 0; m <= M; ++m) {
-                Dr[k][m] = vp[k] * Dk[((size_t)(2 * m) * nb + bin) * (size_t)a.ldD + col];
-                Di[k][m] = vp[k] * Dk[((size_t)(2 * m + 1) * nb + bin) * (size_t)a.ldD + col];
+                Dr[m] = vp[k] * Dk[((size_t)(2 * m) * nb + bin) * (size_t)a.ldD + col];
+                Di[m] = vp[k] * Dk[((size_t)(2 * m + 1) * nb + bin) * (size_t)a.ldD + col];
+            }
+#pragma unroll
+            for (int m = 0; m <= M; ++m) {
+                const double hi = m + 2 <= M ? 0.5 * Dr[m + 2 <= M ? m + 2 : 0] : 0.0;
+                Al[k][m] = (m == 0 ? Dr[0] : 0.5 * Dr[m]) - hi;
+                Bt[k][m] = m < M ? 0.5 * Di[m < M ? m + 1 : 0] : 0.0;
             }
         }
         for (int kb = klo; kb <= khi; ++kb) {
@@ -280,25 +292,23 @@ void k_adjoint_scatter(ScatterArgs a)
                     if (d2 >= elo && d2 < ehi) {
                         const double u1 = fma(dx, f.nx, fma(dy, f.ny, dz * f.nz));
                         const double u2 = fma(dx, f.ex, fma(dy, f.ey, dz * f.ez));
-                        double c, sn;
-                        unit_bearing(u1, u2, c, sn);
+                        double tc, ts;  // 2 cos(phi), 2 sin(phi)
+                        twice_unit_bearing(u1, u2, tc, ts);
                         // sum_m Re(exp(-i m phi) D(m)) = sum_m cos(m phi) Re D + sin(m phi) Im D
                         double acc[K];
 #pragma unroll
-                        for (int k = 0; k < K; ++k) acc[k] = Dr[k][0];
+                        for (int k = 0; k < K; ++k) acc[k] = M >= 1 ? fma(ts, Bt[k][0], Al[k][0]) : Al[k][0];
                         if constexpr (M >= 1) {
-                            const double tc = c + c;
-                            double t2 = 1.0, t1 = c, s2 = 0.0, s1 = sn;
+                            double ua = 1.0, ub = tc;  // U_0, U_1
 #pragma unroll
-                            for (int k = 0; k < K; ++k) acc[k] = fma(t1, Dr[k][1], fma(s1, Di[k][1], acc[k]));
+                            for (int m = 1; m <= M; ++m) {
 #pragma unroll
-                            for (int m = 2; m <= M; ++m) {
-                                const double tm = fma(tc, t1, -t2);
-                                const double sm = fma(tc, s1, -s2);
-#pragma unroll
-                                for (int k = 0; k < K; ++k) acc[k] = fma(tm, Dr[k][m], fma(sm, Di[k][m], acc[k]));
-                                t2 = t1; t1 = tm;
-                                s2 = s1; s1 = sm;
+                                for (int k = 0; k < K; ++k)
+                                    acc[k] = fma(ub, m < M ? fma(ts, Bt[k][m], Al[k][m]) : Al[k][m], acc[k]);
+                                if (m < M) {
+                                    const double um = fma(tc, ub, -ua);
+                                    ua = ub; ub = um;
+                                }
                             }
                         }
                         if (!unit_w) {

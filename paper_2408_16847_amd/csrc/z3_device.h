@@ -245,6 +245,18 @@ __device__ __forceinline__ void unit_bearing(double u1, double u2, double &c, do
     s = u2 * r;
 }
 
+// (2 cos phi, 2 sin phi) of the bearing: unit_bearing's refinement with the factor 2 folded
+// into the refined reciprocal length (2 r = 2 r0 + e r0).
+__device__ __forceinline__ void twice_unit_bearing(double u1, double u2, double &c2, double &s2)
+{
+    const double q = fma(u1, u1, fma(u2, u2, 1e-37));
+    const double r0 = (double)__builtin_amdgcn_rsqf((float)q);
+    const double e = fma(-q * r0, r0, 1.0);
+    const double r2 = fma(e, r0, r0 + r0);
+    c2 = u1 * r2;
+    s2 = u2 * r2;
+}
+
 // XCD-aware block order: the hardware hands consecutive block ids to the 8 XCDs in turn;
 // this bijection gives each XCD a contiguous run of logical tiles, so the neighbour data
 // of adjacent pivots stays in one L2.

@@ -17,11 +17,16 @@
 // with the caller's FP64 edges.  The longitude windows are conservative (rounding
 // guards), so they never drop a pair that the d2 test accepts.
 //
-// Harmonics: cos(m phi) and sin(m phi) follow from cos(phi) by the Chebyshev three-term
-// recurrences T_m = 2 c T_{m-1} - T_{m-2} (first kind, for cos) and the same recurrence
-// for sin(m phi) = U_{m-1}(c) sin(phi) (second kind); the paper's code uses the same two
-// polynomial families so that no trigonometric function is evaluated per pair.  Scaling
-// both recurrences by w_j x_j folds the field value in: two FMAs and two adds per m.
+// Harmonics: the paper's remark after the binned estimator builds cos(m phi) and
+// sin(m phi) from Chebyshev polynomials of cos(phi), so that no trigonometric function is
+// evaluated per pair.  Here one second-kind chain per pair, u_k = v U_k(c) with
+// U_k = 2 c U_{k-1} - U_{k-2} (c = cos phi, v = w_j x_j), feeds two sums per bin:
+//   SU_k = sum u_k  and  SV_k = sum 2 sin(phi) u_k,
+// and the bin's epilogue forms Y_m = (SU_m - SU_{m-2}) / 2 (T_m = (U_m - U_{m-2}) / 2,
+// U_{-1} = 0) and Z_m = SV_{m-1} / 2 (sin(m phi) = sin(phi) U_{m-1}(c)).  Per pair and m:
+// one FMA of the chain, one add and one FMA into the sums, against two FMAs and two adds
+// for separate first- and second-kind chains.  Near phi = 0 or pi, U_m ~ m + 1 and the
+// difference gives up ~log2(m) bits: ~1e-14 of sum |v| at m = 10 in FP64.
 //
 // Pivots on a plane (PLANAR): the same loop over a strip x cell grid of (x, y, 0) records;
 // the frame is fixed (angles from +y towards +x) and the windows are planar_window's.
@@ -170,9 +175,10 @@ void k_multipoles(MultArgs a)
         klo = __builtin_amdgcn_readfirstlane(wave_min(klo));
         khi = __builtin_amdgcn_readfirstlane(wave_max(khi));
 
-        double Y[M + 1], Z[M + 1];
+        // SU_k = sum v U_k(cos phi) for k <= M, SV_k = sum v 2 sin(phi) U_k(cos phi) for k < M
+        double SU[M + 1], SV[M + 1];
 #pragma unroll
-        for (int m = 0; m <= M; ++m) { Y[m] = 0.0; Z[m] = 0.0; }
+        for (int m = 0; m <= M; ++m) { SU[m] = 0.0; SV[m] = 0.0; }
         double Wb = 0.0, Qb = 0.0;
         int cnt = 0;
         uint64_t hsum = 0;
@@ -217,21 +223,21 @@ void k_multipoles(MultArgs a)
                             if constexpr (SELF) Qb = fma(v, v, Qb);
                             const double u1 = fma(dx, nx, fma(dy, ny, dz * nz));
                             const double u2 = fma(dx, ex, fma(dy, ey, dz * ez));
-                            double c, sn;
-                            unit_bearing(u1, u2, c, sn);
-                            Y[0] += v;
+                            double tc, ts;  // 2 cos(phi), 2 sin(phi)
+                            twice_unit_bearing(u1, u2, tc, ts);
+                            SU[0] += v;
                             if constexpr (M >= 1) {
-                                const double tc = c + c;
-                                double t2 = v, t1 = v * c, s2 = 0.0, s1 = v * sn;
-                                Y[1] += t1;
-                                Z[1] += s1;
+                                // one chain v U_k(cos phi): SU_k takes it, SV_k takes it
+                                // times 2 sin(phi)
+                                double ua = v, ub = tc * v;
+                                SV[0] = fma(ts, v, SV[0]);
+                                SU[1] += ub;
 #pragma unroll
-                                for (int m = 2; m <= M; ++m) {
-                                    const double tm = fma(tc, t1, -t2), sm = fma(tc, s1, -s2);
-                                    Y[m] += tm;
-                                    Z[m] += sm;
-                                    t2 = t1; t1 = tm;
-                                    s2 = s1; s1 = sm;
+                                for (int k = 2; k <= M; ++k) {
+                                    SV[k - 1] = fma(ts, ub, SV[k - 1]);
+                                    const double uk = fma(tc, ub, -ua);
+                                    SU[k] += uk;
+                                    ua = ub; ub = uk;
                                 }
                             }
                         }
@@ -256,10 +262,13 @@ void k_multipoles(MultArgs a)
             if (a.norm == Z3_NORM_BIN) inv = Wb > 0.0 ? 1.0 / Wb : 0.0;
             if constexpr (SELF) self_t = a.pv[p] * Qb * inv * inv;
             if (a.A) {
+                // T_m = (U_m - U_{m-2}) / 2 (U_{-1} = 0) and sin(m phi) = sin(phi) U_{m-1}
+                const double hinv = 0.5 * inv;
 #pragma unroll
                 for (int m = 0; m <= M; ++m) {
-                    const double re = Y[m] * inv;
-                    const double im = m == 0 ? 0.0 : -Z[m] * inv;
+                    const double y = m >= 2 ? SU[m] - SU[m >= 2 ? m - 2 : 0] : SU[m];
+                    const double re = m == 0 ? y * inv : y * hinv;
+                    const double im = m == 0 ? 0.0 : -SV[m >= 1 ? m - 1 : 0] * hinv;
                     const size_t ore = ((size_t)(2 * m) * nb + bin) * (size_t)a.ldA + col;
                     const size_t oim = ((size_t)(2 * m + 1) * nb + bin) * (size_t)a.ldA + col;
                     if constexpr (F32OUT) {
@@ -292,9 +301,9 @@ void k_multipoles(MultArgs a)
 // ---- many maps over one set of positions -------------------------------------------------
 //
 // Same decomposition (one lane per pivot, bins in order, band windows), but every lane
-// carries kMapGroup maps: the pair test, the bearing and the unit harmonics
-// cos(m phi), sin(m phi) (Chebyshev recurrences with unit seed) are computed once per
-// pair, and each map adds v_k cos(m phi) and v_k sin(m phi) with two FMAs per m.
+// carries kMapGroup maps: the pair test, the bearing and the unit chain U_k(cos phi) are
+// computed once per pair, and each map adds v U_k and v 2 sin(phi) U_k with two FMAs per
+// k (the epilogue forms the harmonics' sums as in k_multipoles).
 
 struct MapArgs {
     const double *px, *py, *pz;   // index-order pivot positions
@@ -372,11 +381,13 @@ void k_multipoles_maps(MapArgs a)
         klo = __builtin_amdgcn_readfirstlane(wave_min(klo));
         khi = __builtin_amdgcn_readfirstlane(wave_max(khi));
 
-        double Y[K][M + 1], Z[K][M + 1];
+        // per map: SU_k = sum v U_k(cos phi), SV_k = sum v 2 sin(phi) U_k(cos phi), as in
+        // k_multipoles, with one unit chain U_k shared by the maps
+        double SU[K][M + 1], SV[K][M + 1];
 #pragma unroll
         for (int k = 0; k < K; ++k)
 #pragma unroll
-            for (int m = 0; m <= M; ++m) { Y[k][m] = 0.0; Z[k][m] = 0.0; }
+            for (int m = 0; m <= M; ++m) { SU[k][m] = 0.0; SV[k][m] = 0.0; }
         double Wb = 0.0;
         int cnt = 0;
 
@@ -401,29 +412,27 @@ void k_multipoles_maps(MapArgs a)
                         const double v[K] = {vv.x, vv.y, vv.z, vv.w};
                         const double u1 = fma(dx, nx, fma(dy, ny, dz * nz));
                         const double u2 = fma(dx, ex, fma(dy, ey, dz * ez));
-                        double c, sn;
-                        unit_bearing(u1, u2, c, sn);
+                        double tc, ts;  // 2 cos(phi), 2 sin(phi)
+                        twice_unit_bearing(u1, u2, tc, ts);
 #pragma unroll
-                        for (int k = 0; k < K; ++k) Y[k][0] += v[k];
+                        for (int k = 0; k < K; ++k) SU[k][0] += v[k];
                         if constexpr (M >= 1) {
-                            const double tc = c + c;
-                            double t2 = 1.0, t1 = c, s2 = 0.0, s1 = sn;
+                            double vs[K];
 #pragma unroll
                             for (int k = 0; k < K; ++k) {
-                                Y[k][1] = fma(v[k], t1, Y[k][1]);
-                                Z[k][1] = fma(v[k], s1, Z[k][1]);
+                                vs[k] = ts * v[k];
+                                SV[k][0] += vs[k];
+                                SU[k][1] = fma(v[k], tc, SU[k][1]);
                             }
+                            double ua = 1.0, ub = tc;  // U_0, U_1
 #pragma unroll
                             for (int m = 2; m <= M; ++m) {
-                                const double tm = fma(tc, t1, -t2);
-                                const double sm = fma(tc, s1, -s2);
 #pragma unroll
-                                for (int k = 0; k < K; ++k) {
-                                    Y[k][m] = fma(v[k], tm, Y[k][m]);
-                                    Z[k][m] = fma(v[k], sm, Z[k][m]);
-                                }
-                                t2 = t1; t1 = tm;
-                                s2 = s1; s1 = sm;
+                                for (int k = 0; k < K; ++k) SV[k][m - 1] = fma(vs[k], ub, SV[k][m - 1]);
+                                const double um = fma(tc, ub, -ua);
+#pragma unroll
+                                for (int k = 0; k < K; ++k) SU[k][m] = fma(v[k], um, SU[k][m]);
+                                ua = ub; ub = um;
                             }
                         }
                     }
@@ -435,13 +444,15 @@ void k_multipoles_maps(MapArgs a)
             my_pairs += (uint64_t)cnt;
             if (unit_w) Wb = (double)cnt;
             const double inv = Wb > 0.0 ? 1.0 / Wb : 0.0;
+            const double hinv = 0.5 * inv;
             if (a.W) a.W[(size_t)bin * (size_t)a.ldA + col] = Wb;
 #pragma unroll
             for (int k = 0; k < K; ++k) {
 #pragma unroll
                 for (int m = 0; m <= M; ++m) {
-                    const double re = Y[k][m] * inv;
-                    const double im = m == 0 ? 0.0 : -Z[k][m] * inv;
+                    const double y = m >= 2 ? SU[k][m] - SU[k][m >= 2 ? m - 2 : 0] : SU[k][m];
+                    const double re = m == 0 ? y * inv : y * hinv;
+                    const double im = m == 0 ? 0.0 : -SV[k][m >= 1 ? m - 1 : 0] * hinv;
                     const size_t ore = k * a.map_stride + ((size_t)(2 * m) * nb + bin) * (size_t)a.ldA + col;
                     const size_t oim = k * a.map_stride + ((size_t)(2 * m + 1) * nb + bin) * (size_t)a.ldA + col;
                     if constexpr (F32OUT) {
