@@ -270,8 +270,9 @@ z3_status z3_index_set_phi_bins(z3_index idx, int n_phi, const double *bounds);
  * 0 <= m_max < n_phi / 2 (and <= Z3_MAX_MMAX_HIST).  Outputs as z3_accumulate_multipoles
  * (A [m_max+1][2][nbins][P] FP64 or FP32 per prec, W, counts; each may be NULL), plus
  *   counts_phi [nbins][n_phi][P] int32 pairs per (pivot, radial bin, angular bin), or NULL
- * (needs 816 n_phi bytes of LDS per block, 560 n_phi without counts_phi; Z3_ERR_UNSUPPORTED
- * beyond the device's limit).  Sums are FP64 on both precisions.
+ * (LDS per block of 256 threads: 32 n_phi (64/L + 1) bytes, 48 n_phi (64/L + 1) with
+ * counts_phi, plus 48 n_phi, where L, the lanes per pivot, is the least power of two up to 16
+ * with n_phi <= 18 L: at most 74 KB; Z3_ERR_UNSUPPORTED beyond the device's limit).  Sums are FP64 on both precisions.
  */
 z3_status z3_accumulate_histogram(z3_index idx, int map, int m_max, int prec, int norm, int64_t p0,
                                   int64_t p1, void *A, double *W, int64_t *counts, int *counts_phi,

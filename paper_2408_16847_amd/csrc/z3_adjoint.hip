@@ -293,7 +293,7 @@ void k_adjoint_scatter(ScatterArgs a)
                         const double u1 = fma(dx, f.nx, fma(dy, f.ny, dz * f.nz));
                         const double u2 = fma(dx, f.ex, fma(dy, f.ey, dz * f.ez));
                         double tc, ts;  // 2 cos(phi), 2 sin(phi)
-                        twice_unit_bearing(u1, u2, tc, ts);
+                        twice_unit_bearing(u1, u2, kBearingTiny, tc, ts);
                         // sum_m Re(exp(-i m phi) D(m)) = sum_m cos(m phi) Re D + sin(m phi) Im D
                         double acc[K];
 #pragma unroll

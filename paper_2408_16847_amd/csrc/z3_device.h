@@ -246,10 +246,13 @@ __device__ __forceinline__ void unit_bearing(double u1, double u2, double &c, do
 }
 
 // (2 cos phi, 2 sin phi) of the bearing: unit_bearing's refinement with the factor 2 folded
-// into the refined reciprocal length (2 r = 2 r0 + e r0).
-__device__ __forceinline__ void twice_unit_bearing(double u1, double u2, double &c2, double &s2)
+// into the refined reciprocal length (2 r = 2 r0 + e r0).  `tiny` is unit_bearing's addend
+// (kBearingTiny); a kernel that takes it as an argument holds it in scalar registers, so
+// the first FMA reads it there instead of from a vector register copied per pair.
+constexpr double kBearingTiny = 1e-37;
+__device__ __forceinline__ void twice_unit_bearing(double u1, double u2, double tiny, double &c2, double &s2)
 {
-    const double q = fma(u1, u1, fma(u2, u2, 1e-37));
+    const double q = fma(u1, u1, fma(u2, u2, tiny));
     const double r0 = (double)__builtin_amdgcn_rsqf((float)q);
     const double e = fma(-q * r0, r0, 1.0);
     const double r2 = fma(e, r0, r0 + r0);

@@ -18,16 +18,19 @@
 // decides every bearing farther than 5e-5 rad from a boundary; the others take the sign
 // tests, which confirm the estimate or move it to the neighbouring bin.
 //
-// Work decomposition: one wave per block, one lane per pivot (64 consecutive index-order
-// pivots), the same band windows, records and one-ahead record requests as k_multipoles.
-// Each lane owns one column of an LDS histogram [n_phi][64] (consecutive lanes in
-// consecutive words: no bank conflicts whatever the bins), cleared per radial bin; a run of
-// pairs in one angular bin is summed in registers first.  After the bin's windows each lane
-// forms its multipoles from its column, a_m = e^{-i m dphi/2} sum_k H_k e^{-i m k dphi}, by
-// Clenshaw's recurrence over the angular bins (one FMA and one subtraction per bin and
-// multipole, kHistMC multipoles per pass; the constants come from an LDS table of
-// (cos, sin)(pi j / n_phi) read at wave-uniform addresses).  Sums stay in FP64 on both precision
-// paths; the mixed path stores the multipoles in FP32.
+// Work decomposition: blocks of four waves; LPP lanes per pivot (LPP = 1..16 grows with
+// n_phi, so that a wave's histogram stays within 9 KiB of LDS and 4 waves per SIMD fit),
+// 64 / LPP consecutive index-order pivots per wave, the same band windows, records and
+// one-ahead record requests as k_multipoles.  Lane q of a pivot takes the candidates
+// q, q + LPP, ... of each window and sums runs of consecutive pairs in one angular bin in
+// registers, adding a run into the pivot's row of the wave's LDS histogram [n_phi][64/LPP+1]
+// with an FP64 LDS atomic when the bin changes (the order of the adds is fixed by the
+// program and the lane order, so results are reproducible).  After the bin's windows the
+// pivot's lanes split its multipoles (m = q, q + LPP, ...) and form each from the pivot's
+// row, a_m = e^{-i m dphi/2} sum_k H_k e^{-i m k dphi}, by Clenshaw's recurrence over the
+// angular bins (one FMA and one subtraction per bin and multipole; the constants come from
+// an LDS table of (cos, sin)(pi j / n_phi)).  Sums stay in FP64 on both precision paths;
+// the mixed path stores the multipoles in FP32.
 #include "z3_internal.h"
 #include "z3_device.h"
 
@@ -60,7 +63,10 @@ struct HistArgs {
     int nblocks;
 };
 
-constexpr int kHistMC = 8;  // multipoles per pass of the transform
+// Multipoles per lane and pass of the transform.  The lanes-per-pivot choice below keeps
+// n_phi / LPP <= 18, and m_max < n_phi / 2, so each lane's share of the m_max + 1
+// multipoles is at most 9: one pass.
+constexpr int kHistMC = 9;
 
 __device__ __forceinline__ bool left_of(const double2 *D, int k, double u1, double u2)
 {
@@ -113,22 +119,51 @@ __device__ __forceinline__ int angular_bin(const double2 *D, int n, float scale,
     return k;
 }
 
-template <bool F32OUT, bool CNT>
-__global__ __launch_bounds__(kWave) void k_multipoles_hist(HistArgs a)
+// LDS layout of a block of kHistWaves waves with LPP lanes per pivot (G = 64 / LPP pivots per
+// wave): per wave a histogram H [n_phi][G + 1] FP64 (row stride G + 1, odd, so that lanes of
+// one pivot adding into different angular bins mostly hit different banks) and, with
+// per-cell counts, C [n_phi][G + 1] int32; per block the boundary table D [n_phi] and the
+// phase table T [2 n_phi] (double2).
+constexpr int kHistWaves = 4;
+
+__host__ __device__ constexpr int hist_row(int lpp) { return kWave / lpp + 1; }
+
+size_t hist_lds_bytes(int n_phi, bool counts, int lpp)
 {
+    const size_t row = (size_t)hist_row(lpp) * n_phi;
+    return kHistWaves * row * (sizeof(double) + (counts ? sizeof(int) : 0)) + 3 * (size_t)n_phi * sizeof(double2);
+}
+
+// Lanes per pivot for n_phi angular bins: the smallest power of two that keeps a wave's
+// histogram within 9 KiB, so that LDS admits the 16 waves per CU (4 per SIMD) that the
+// register budget allows.
+int hist_lanes_per_pivot(int n_phi)
+{
+    int lpp = 1;
+    while (lpp < 16 && (size_t)n_phi * (kWave / lpp) * sizeof(double) > 9216) lpp *= 2;
+    return lpp;
+}
+
+template <bool F32OUT, bool CNT, int LPP>
+__global__ __launch_bounds__(kHistWaves * kWave) __attribute__((amdgpu_waves_per_eu(4)))
+void k_multipoles_hist(HistArgs a)
+{
+    constexpr int G = kWave / LPP;     // pivots per wave
+    constexpr int HS = hist_row(LPP);  // histogram row stride (doubles)
     extern __shared__ double smem[];
     const int n = a.n_phi;
-    double *H = smem;                                                  // [n][64]
-    double2 *D = reinterpret_cast<double2 *>(H + (size_t)n * kWave);   // [n]
-    double2 *T = D + n;                                                // [2n]
-    int *C = reinterpret_cast<int *>(T + 2 * n);                       // [n][64] (CNT)
-    const int lane = threadIdx.x;
-    for (int k = lane; k < n; k += kWave) D[k] = a.bounds[k];
-    for (int j = lane; j < 2 * n; j += kWave) T[j] = a.tab[j];
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int pl = lane / LPP, q = lane % LPP;  // pivot slot in the wave, lane within the pivot
+    double *H = smem + (size_t)wave * n * HS;                                    // [n][HS]
+    double2 *D = reinterpret_cast<double2 *>(smem + (size_t)kHistWaves * n * HS);  // [n]
+    double2 *T = D + n;                                                          // [2n]
+    int *C = reinterpret_cast<int *>(T + 2 * n) + (size_t)wave * n * HS;         // [n][HS] (CNT)
+    for (int k = threadIdx.x; k < n; k += kHistWaves * kWave) D[k] = a.bounds[k];
+    for (int j = threadIdx.x; j < 2 * n; j += kHistWaves * kWave) T[j] = a.tab[j];
     __syncthreads();
 
     const int lb = xcd_block(blockIdx.x, a.nblocks);
-    const int64_t p = a.p0 + (int64_t)lb * kWave + lane;
+    const int64_t p = a.p0 + ((int64_t)lb * kHistWaves + wave) * G + pl;
     const bool valid = p < a.p1;
     const int64_t pp = valid ? p : a.p1 - 1;  // idle lanes shadow the last pivot
     const double xp = a.px[pp], yp = a.py[pp], zp = a.pz[pp];
@@ -156,19 +191,21 @@ __global__ __launch_bounds__(kWave) void k_multipoles_hist(HistArgs a)
     uint64_t my_pairs = 0;
 
     for (int bin = 0; bin < nb; ++bin) {
-        for (int k = 0; k < n; ++k) {
-            H[k * kWave + lane] = 0.0;
-            if constexpr (CNT) C[k * kWave + lane] = 0;
+        for (int e = lane; e < n * HS; e += kWave) {
+            H[e] = 0.0;
+            if constexpr (CNT) C[e] = 0;
         }
+        // this wave's LDS writes are done before any lane of it adds into the histogram
+        __builtin_amdgcn_s_waitcnt(0xc07f);
+        __builtin_amdgcn_wave_barrier();
         const double elo = a.edges->e[bin], ehi = a.edges->e[bin + 1];
         const double hav_out = a.edges->hav_out[bin + 1], hav_in = a.edges->hav_in[bin];
         int klo, khi;
         band_range(th, a.edges->rad_out[bin + 1], a.inv_h, a.nbands, klo, khi);
         double Wb = 0.0;
         int cnt = 0;
-        // run of consecutive pairs in one angular bin, summed in registers and added to the
-        // LDS column when the bin changes (neighbouring candidates of a window mostly share
-        // a bin, so most pairs skip the LDS read-modify-write)
+        // run of consecutive pairs (of this lane) in one angular bin, summed in registers and
+        // added to the pivot's histogram row by an LDS atomic when the bin changes
         int krun = 0, crun = 0;
         double vrun = 0.0;
         for (int kb = klo; kb <= khi; ++kb) {
@@ -188,8 +225,10 @@ __global__ __launch_bounds__(kWave) void k_multipoles_hist(HistArgs a)
                     const double u2 = (dx * ex + dy * ey) + dz * ez;
                     const int k = angular_bin(D, n, a.phi_scale, a.phi_guard, u1, u2);
                     if (k != krun) {
-                        H[krun * kWave + lane] += vrun;
-                        if constexpr (CNT) C[krun * kWave + lane] += crun;
+                        if (crun) {
+                            atomicAdd(&H[krun * HS + pl], vrun);
+                            if constexpr (CNT) atomicAdd(&C[krun * HS + pl], crun);
+                        }
                         krun = k;
                         vrun = 0.0;
                         crun = 0;
@@ -198,48 +237,60 @@ __global__ __launch_bounds__(kWave) void k_multipoles_hist(HistArgs a)
                     crun += 1;
                 }
             };
+            // lane q of a pivot takes the candidates q, q + LPP, q + 2 LPP, ... of each window
+            constexpr uint32_t step = 32u * LPP;
 #pragma unroll
             for (int seg = 0; seg < 2; ++seg) {
-                uint32_t off = (uint32_t)(seg == 0 ? s0 : s1) * 32u;
-                const uint32_t oend = off + (uint32_t)(seg == 0 ? l0 : l1) * 32u;
+                uint32_t off = (uint32_t)((seg == 0 ? s0 : s1) + q) * 32u;
+                const uint32_t oend = (uint32_t)((seg == 0 ? s0 + l0 : s1 + l1)) * 32u;
                 // record requested one candidate ahead, two record registers in turn; past
                 // the window a request reads an unused record of the band (or zeros past it)
                 double4 ra = load_record(rband, off < oend ? off : 0u);
-                for (; off < oend; off += 64u) {
-                    const double4 rb = load_record(rband, off + 32u);
+                for (; off < oend; off += 2u * step) {
+                    const double4 rb = load_record(rband, off + step);
                     cand(ra, off);
-                    if (off + 32u >= oend) break;
-                    ra = load_record(rband, off + 64u);
-                    cand(rb, off + 32u);
+                    if (off + step >= oend) break;
+                    ra = load_record(rband, off + 2u * step);
+                    cand(rb, off + step);
                 }
             }
         }
-
-        H[krun * kWave + lane] += vrun;
-        if constexpr (CNT) C[krun * kWave + lane] += crun;
-        if (valid) {
-            my_pairs += (uint64_t)cnt;
-            if (unit_w) Wb = (double)cnt;
+        if (crun) {
+            atomicAdd(&H[krun * HS + pl], vrun);
+            if constexpr (CNT) atomicAdd(&C[krun * HS + pl], crun);
         }
+        if (valid) my_pairs += (uint64_t)cnt;
+        // the pivot's pair count and weight sum over its LPP lanes (a butterfly: every lane of
+        // the pivot ends with the same, fixed-order sum)
+#pragma unroll
+        for (int o = 1; o < LPP; o <<= 1) {
+            cnt += __shfl_xor(cnt, o, kWave);
+            if (!unit_w) Wb += __shfl_xor(Wb, o, kWave);
+        }
+        if (unit_w) Wb = (double)cnt;
         double inv = 1.0;
         if (a.norm == Z3_NORM_BIN) inv = Wb > 0.0 ? 1.0 / Wb : 0.0;
+        // every lane's atomics into the wave's histogram are done before it is read
+        __builtin_amdgcn_s_waitcnt(0xc07f);
+        __builtin_amdgcn_wave_barrier();
         // Fourier sum over the angular bins at their centres,
         //   a_m = e^{-i m dphi/2} sum_k H_k z^k,  z = e^{-i w}, w = m dphi,
         // by Clenshaw's recurrence over k (backwards): b_k = H_k + 2 cos(w) b_{k+1} - b_{k+2},
         // then sum_k H_k cos(k w) = b_0 - cos(w) b_1 and sum_k H_k sin(k w) = sin(w) b_1: one FMA
-        // and one subtraction per (k, m), kHistMC multipoles per pass over the column
+        // and one subtraction per (k, m); lane q of a pivot takes m = q, q + LPP, ..., kHistMC
+        // of them per pass over the pivot's row
         if (a.A) {
-            for (int m0 = 0; m0 <= a.m_max; m0 += kHistMC) {
+            for (int m0 = q; m0 <= a.m_max; m0 += kHistMC * LPP) {
                 double tc[kHistMC], b1[kHistMC], b2[kHistMC];
 #pragma unroll
                 for (int i = 0; i < kHistMC; ++i) {
-                    const int m = m0 + i <= a.m_max ? m0 + i : 0;
+                    const int m = m0 + i * LPP <= a.m_max ? m0 + i * LPP : 0;
                     tc[i] = 2.0 * T[2 * m].x;  // 2 cos(m dphi) = 2 cos(pi 2m / n_phi)
                     b1[i] = 0.0;
                     b2[i] = 0.0;
                 }
                 for (int k = n - 1; k >= 0; --k) {
-                    const double h = H[k * kWave + lane];
+                    const double h = H[k * HS + pl];
 #pragma unroll
                     for (int i = 0; i < kHistMC; ++i) {
                         const double b0 = fma(tc[i], b1[i], h) - b2[i];
@@ -250,7 +301,7 @@ __global__ __launch_bounds__(kWave) void k_multipoles_hist(HistArgs a)
                 if (valid) {
 #pragma unroll
                     for (int i = 0; i < kHistMC; ++i) {
-                        const int m = m0 + i;
+                        const int m = m0 + i * LPP;
                         if (m > a.m_max) break;
                         const double2 cw = T[2 * m], hw = T[m];  // (cos, sin)(m dphi), (cos, sin)(m dphi / 2)
                         const double pr = b1[i] - cw.x * b2[i], pi = -cw.y * b2[i];  // sum_k H_k z^k
@@ -274,25 +325,37 @@ __global__ __launch_bounds__(kWave) void k_multipoles_hist(HistArgs a)
         }
         if (valid) {
             const size_t ob = (size_t)bin * (size_t)a.ldA + col;
-            if (a.W) a.W[ob] = Wb;
-            if (a.counts) a.counts[ob] = cnt;
+            if (q == 0) {
+                if (a.W) a.W[ob] = Wb;
+                if (a.counts) a.counts[ob] = cnt;
+            }
             if constexpr (CNT) {
-                for (int k = 0; k < n; ++k)
-                    a.counts_phi[((size_t)bin * n + k) * (size_t)a.ldA + col] = C[k * kWave + lane];
+                for (int k = q; k < n; k += LPP)
+                    a.counts_phi[((size_t)bin * n + k) * (size_t)a.ldA + col] = C[k * HS + pl];
             }
         }
+        // the histogram is read by every lane of the wave before the next bin clears it
+        __builtin_amdgcn_s_waitcnt(0xc07f);
+        __builtin_amdgcn_wave_barrier();
     }
 
     if (a.pair_total) {
-        const uint64_t tot = wave_sum_u64(valid ? my_pairs : 0);
+        const uint64_t tot = wave_sum_u64(my_pairs);
         if (lane == 0 && tot) atomicAdd((unsigned long long *)a.pair_total, (unsigned long long)tot);
     }
 }
 
-size_t hist_lds_bytes(int n_phi, bool counts)
+template <bool F32OUT, bool CNT>
+static void launch_hist_lpp(int lpp, dim3 grid, size_t lds, hipStream_t s, const HistArgs &a)
 {
-    return (size_t)n_phi * kWave * sizeof(double) + 3 * (size_t)n_phi * sizeof(double2) +
-           (counts ? (size_t)n_phi * kWave * sizeof(int) : 0);
+    const dim3 block(kHistWaves * kWave);
+    switch (lpp) {
+    case 1: hipLaunchKernelGGL((k_multipoles_hist<F32OUT, CNT, 1>), grid, block, lds, s, a); break;
+    case 2: hipLaunchKernelGGL((k_multipoles_hist<F32OUT, CNT, 2>), grid, block, lds, s, a); break;
+    case 4: hipLaunchKernelGGL((k_multipoles_hist<F32OUT, CNT, 4>), grid, block, lds, s, a); break;
+    case 8: hipLaunchKernelGGL((k_multipoles_hist<F32OUT, CNT, 8>), grid, block, lds, s, a); break;
+    default: hipLaunchKernelGGL((k_multipoles_hist<F32OUT, CNT, 16>), grid, block, lds, s, a); break;
+    }
 }
 
 z3_status launch_multipoles_hist(const z3_index_s *idx, int map, int m_max, int prec, int norm, int64_t p0,
@@ -303,11 +366,13 @@ z3_status launch_multipoles_hist(const z3_index_s *idx, int map, int m_max, int 
         return fail(Z3_ERR_INVALID_ARG, "angular bins not set on this index (z3_index_set_phi_bins)");
     if (m_max < 0 || 2 * m_max >= idx->n_phi)
         return fail(Z3_ERR_INVALID_ARG, "m_max=%d needs m_max < n_phi / 2 = %d / 2", m_max, idx->n_phi);
-    const int64_t nblk = (p1 - p0 + kWave - 1) / kWave;
+    const int lpp = hist_lanes_per_pivot(idx->n_phi);
+    const int64_t per_block = (int64_t)kHistWaves * (kWave / lpp);
+    const int64_t nblk = (p1 - p0 + per_block - 1) / per_block;
     if (nblk > 0x7fffffff) return fail(Z3_ERR_OVERFLOW, "too many pivot blocks");
     if (nblk == 0) return Z3_OK;
     const bool cnt = counts_phi != nullptr;
-    const size_t lds = hist_lds_bytes(idx->n_phi, cnt);
+    const size_t lds = hist_lds_bytes(idx->n_phi, cnt, lpp);
     int dev = 0, lds_max = 0;
     z3_status st = check_hip(hipGetDevice(&dev), "hipGetDevice");
     if (st == Z3_OK)
@@ -341,13 +406,13 @@ z3_status launch_multipoles_hist(const z3_index_s *idx, int map, int m_max, int 
     const bool f32 = prec == Z3_PREC_MIXED;
     hipEvent_t ev0;
     profile_begin(s, &ev0);
-    const dim3 grid((unsigned)nblk), block(kWave);
+    const dim3 grid((unsigned)nblk);
     if (f32) {
-        if (cnt) hipLaunchKernelGGL((k_multipoles_hist<true, true>), grid, block, lds, s, a);
-        else hipLaunchKernelGGL((k_multipoles_hist<true, false>), grid, block, lds, s, a);
+        if (cnt) launch_hist_lpp<true, true>(lpp, grid, lds, s, a);
+        else launch_hist_lpp<true, false>(lpp, grid, lds, s, a);
     } else {
-        if (cnt) hipLaunchKernelGGL((k_multipoles_hist<false, true>), grid, block, lds, s, a);
-        else hipLaunchKernelGGL((k_multipoles_hist<false, false>), grid, block, lds, s, a);
+        if (cnt) launch_hist_lpp<false, true>(lpp, grid, lds, s, a);
+        else launch_hist_lpp<false, false>(lpp, grid, lds, s, a);
     }
     st = check_launch("k_multipoles_hist");
     profile_end(s, ev0);

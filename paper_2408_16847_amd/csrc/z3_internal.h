@@ -155,7 +155,8 @@ z3_status launch_multipoles(const z3_index_s *idx, Pivots piv, int map, int m_ma
 z3_status launch_multipoles_hist(const z3_index_s *idx, int map, int m_max, int prec, int norm, int64_t p0,
                                  int64_t p1, void *A, int64_t ldA, double *W, int64_t *counts, int *counts_phi,
                                  uint64_t *pair_total, hipStream_t s);
-size_t hist_lds_bytes(int n_phi, bool counts);
+size_t hist_lds_bytes(int n_phi, bool counts, int lanes_per_pivot);
+int hist_lanes_per_pivot(int n_phi);
 
 int batch_ldv(int nmaps);
 int batch_num_shapes();

@@ -71,6 +71,7 @@ struct MultArgs {
     const double *pv;             // SELF: index-order pivot products w_p x_p
     double *self_part;            // SELF: [waves of the launch][nb] sums of v_p Q / W^2
     double px0, py0, psx;         // PLANAR: plane origin and cell-coordinate scale
+    double tiny;                  // kBearingTiny, passed so that it sits in scalar registers
     int nblocks;
 };
 
@@ -224,7 +225,7 @@ void k_multipoles(MultArgs a)
                             const double u1 = fma(dx, nx, fma(dy, ny, dz * nz));
                             const double u2 = fma(dx, ex, fma(dy, ey, dz * ez));
                             double tc, ts;  // 2 cos(phi), 2 sin(phi)
-                            twice_unit_bearing(u1, u2, tc, ts);
+                            twice_unit_bearing(u1, u2, a.tiny, tc, ts);
                             SU[0] += v;
                             if constexpr (M >= 1) {
                                 // one chain v U_k(cos phi): SU_k takes it, SV_k takes it
@@ -413,7 +414,7 @@ void k_multipoles_maps(MapArgs a)
                         const double u1 = fma(dx, nx, fma(dy, ny, dz * nz));
                         const double u2 = fma(dx, ex, fma(dy, ey, dz * ez));
                         double tc, ts;  // 2 cos(phi), 2 sin(phi)
-                        twice_unit_bearing(u1, u2, tc, ts);
+                        twice_unit_bearing(u1, u2, kBearingTiny, tc, ts);
 #pragma unroll
                         for (int k = 0; k < K; ++k) SU[k][0] += v[k];
                         if constexpr (M >= 1) {
@@ -568,6 +569,7 @@ z3_status launch_multipoles(const z3_index_s *idx, Pivots piv, int map, int m_ma
     a.W = W; a.counts = counts; a.idhash = idhash; a.pair_total = pair_total;
     a.pv = self_pv; a.self_part = self_part;
     a.px0 = idx->plane_x0; a.py0 = idx->plane_y0; a.psx = idx->plane_sx;
+    a.tiny = kBearingTiny;
     a.nblocks = (int)nblk;
     const bool mixed = prec == Z3_PREC_MIXED, ids = idhash != nullptr, self = self_part != nullptr;
     hipEvent_t ev0;
