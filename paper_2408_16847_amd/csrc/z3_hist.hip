@@ -76,33 +76,13 @@ __device__ __forceinline__ bool left_of(const double2 *D, int k, double u1, doub
     return a - b >= 0.0;
 }
 
-__device__ __forceinline__ int angular_bin(const double2 *D, int n, float scale, float guard, double u1,
-                                           double u2)
+// The angular bin by the exact rule, starting from the estimate k: the signs "left of
+// boundary k" form one circular run, so the bin (the run's end) is reached by stepping
+// towards it; at most n steps.
+__device__ __forceinline__ int exact_angular_bin(const double2 *D, int n, int k, double u1, double u2)
 {
-    // bearing from an FP32 arctangent: octant reduction and the odd polynomial of
-    // Abramowitz & Stegun 4.4.49 on [0, 1] (error <= 1e-5 rad); with the FP32 rounding of
-    // u1, u2, of the reciprocal and of the octant arithmetic the estimate is within 2e-5 rad
-    // of the bearing.  A bearing farther than `guard` (5e-5 rad, in bins) from the nearest
-    // boundary is in the estimated bin by the exact rule too; nearer ones take the sign tests.
-    const float f1 = (float)u1, f2 = (float)u2;
-    const float ax = fabsf(f1), ay = fabsf(f2);
-    const float mn = fminf(ax, ay), mx = fmaxf(ax, ay);
-    const float t = mx > 0.0f ? mn * __builtin_amdgcn_rcpf(mx) : 0.0f;
-    const float t2 = t * t;
-    const float at = t * fmaf(t2, fmaf(t2, fmaf(t2, fmaf(t2, 0.0208351f, -0.0851330f), 0.1801410f), -0.3302995f),
-                              0.9998660f);
-    float ph = ay > ax ? 1.57079633f - at : at;
-    ph = f1 < 0.0f ? 3.14159265f - ph : ph;
-    ph = f2 < 0.0f ? 6.28318531f - ph : ph;
-    const float q = ph * scale;
-    int k = (int)q;
-    k = min(max(k, 0), n - 1);
-    const float fr = q - (float)k;
-    if (fr > guard && fr < 1.0f - guard) return k;
     int k1 = k + 1 == n ? 0 : k + 1;
     bool lk = left_of(D, k, u1, u2), lk1 = left_of(D, k1, u1, u2);
-    // the signs "left of boundary k" form one circular run, so the bin (the run's end) is
-    // reached by stepping towards it; at most n steps
     for (int it = 0; it < n && !(lk && !lk1); ++it) {
         if (!lk) {
             k1 = k;
@@ -116,6 +96,33 @@ __device__ __forceinline__ int angular_bin(const double2 *D, int n, float scale,
             lk1 = left_of(D, k1, u1, u2);
         }
     }
+    return k;
+}
+
+// Estimate of the angular bin from an FP32 arctangent of (v1, v2), the tangent components
+// in any FP64 rounding (they differ from the exact rule's by ~1e-16 rad): octant reduction
+// and the odd polynomial of Abramowitz & Stegun 4.4.49 on [0, 1] (error <= 1e-5 rad); with
+// the FP32 rounding of v1, v2, of the reciprocal and of the octant arithmetic the estimate
+// is within 2e-5 rad of the bearing.  Returns the bin, and sets `sure` when the bearing lies
+// farther than `guard` (5e-5 rad, in bins) from the nearest boundary, where the exact rule
+// gives the same bin.  (v1, v2) = 0 cannot be a pair in range; it would give a NaN estimate,
+// which is never sure.
+__device__ __forceinline__ int angular_estimate(int n, float scale, float guard, double v1, double v2, bool &sure)
+{
+    const float f1 = (float)v1, f2 = (float)v2;
+    const float ax = fabsf(f1), ay = fabsf(f2);
+    const float mn = fminf(ax, ay), mx = fmaxf(ax, ay);
+    const float t = mn * __builtin_amdgcn_rcpf(mx);
+    const float t2 = t * t;
+    const float at = t * fmaf(t2, fmaf(t2, fmaf(t2, fmaf(t2, 0.0208351f, -0.0851330f), 0.1801410f), -0.3302995f),
+                              0.9998660f);
+    float ph = ay > ax ? 1.57079633f - at : at;
+    ph = f1 < 0.0f ? 3.14159265f - ph : ph;
+    ph = f2 < 0.0f ? 6.28318531f - ph : ph;
+    const float q = ph * scale;  // >= 0
+    const int k = min((int)q, n - 1);
+    const float fr = q - (float)k;
+    sure = fr > guard && fr < 1.0f - guard;
     return k;
 }
 
@@ -135,12 +142,15 @@ size_t hist_lds_bytes(int n_phi, bool counts, int lpp)
 }
 
 // Lanes per pivot for n_phi angular bins: the smallest power of two that keeps a wave's
-// histogram within 9 KiB, so that LDS admits the 16 waves per CU (4 per SIMD) that the
-// register budget allows.
+// histogram within Z3_HIST_WAVE_LDS bytes (9 KiB: LDS then admits the 16 waves per CU, 4 per
+// SIMD, that the register budget allows).
+#ifndef Z3_HIST_WAVE_LDS
+#define Z3_HIST_WAVE_LDS 9216
+#endif
 int hist_lanes_per_pivot(int n_phi)
 {
     int lpp = 1;
-    while (lpp < 16 && (size_t)n_phi * (kWave / lpp) * sizeof(double) > 9216) lpp *= 2;
+    while (lpp < 16 && (size_t)n_phi * (kWave / lpp) * sizeof(double) > (size_t)Z3_HIST_WAVE_LDS) lpp *= 2;
     return lpp;
 }
 
@@ -221,9 +231,16 @@ void k_multipoles_hist(HistArgs a)
                 if (d2 >= elo && d2 < ehi) {
                     cnt += 1;
                     if (!unit_w) Wb += a.wdbl[base + (int)(o >> 5)];
-                    const double u1 = (dx * nx + dy * ny) + dz * nz;
-                    const double u2 = (dx * ex + dy * ey) + dz * ez;
-                    const int k = angular_bin(D, n, a.phi_scale, a.phi_guard, u1, u2);
+                    bool sure;
+                    int k = angular_estimate(n, a.phi_scale, a.phi_guard, fma(dx, nx, fma(dy, ny, dz * nz)),
+                                             fma(dx, ex, fma(dy, ey, dz * ez)), sure);
+                    if (!sure) {
+                        // the exact rule's tangent components: every product and sum rounded
+                        // on its own (this file is compiled with -ffp-contract=off)
+                        const double u1 = (dx * nx + dy * ny) + dz * nz;
+                        const double u2 = (dx * ex + dy * ey) + dz * ez;
+                        k = exact_angular_bin(D, n, k, u1, u2);
+                    }
                     if (k != krun) {
                         if (crun) {
                             atomicAdd(&H[krun * HS + pl], vrun);
