@@ -218,11 +218,8 @@ void k_multipoles_hist(HistArgs a)
         // added to the pivot's histogram row by an LDS atomic when the bin changes
         int krun = 0, crun = 0;
         double vrun = 0.0;
-        for (int kb = klo; kb <= khi; ++kb) {
-            const Band bd = a.bands[kb];
-            if (bd.npts == 0) continue;
-            int s0, l0, s1, l1;
-            band_window(bd, a.cell_start, th, sh, ch, inv_sp, phf, hav_out, hav_in, s0, l0, s1, l1);
+        // the pairs of one band: the pivot's windows (s0, l0) and (s1, l1) of band bd
+        auto walk = [&](const Band &bd, int s0, int l0, int s1, int l1) __attribute__((always_inline)) {
             const int base = 2 * bd.pt_start;
             const __amdgpu_buffer_rsrc_t rband = buffer_view(a.rec + base, (uint32_t)bd.npts * 64u);
             auto cand = [&](const double4 &r, uint32_t o) __attribute__((always_inline)) {
@@ -269,6 +266,38 @@ void k_multipoles_hist(HistArgs a)
                     if (off + step >= oend) break;
                     ra = load_record(rband, off + 2u * step);
                     cand(rb, off + step);
+                }
+            }
+        };
+        if constexpr (LPP < 4) {
+            // every lane computes its pivot's windows one band at a time from the band's
+            // wave-uniform record
+            for (int kb = klo; kb <= khi; ++kb) {
+                const Band bd = a.bands[kb];
+                if (bd.npts == 0) continue;
+                int s0, l0, s1, l1;
+                band_window(bd, a.cell_start, th, sh, ch, inv_sp, phf, hav_out, hav_in, s0, l0, s1, l1);
+                walk(bd, s0, l0, s1, l1);
+            }
+        } else {
+            // lane q of each pivot computes the pivot's windows in band kb0 + q; the pivot's
+            // lanes then walk these LPP bands in turn, each band's windows taken from the lane
+            // that computed them (the window arithmetic once per pivot and band, where one band
+            // at a time would repeat it on every lane of the pivot)
+            for (int kb0 = klo; kb0 <= khi; kb0 += LPP) {
+                int w0 = 0, wl0 = 0, w1 = 0, wl1 = 0;
+                if (kb0 + q <= khi) {
+                    const Band bq = a.bands[kb0 + q];
+                    if (bq.npts > 0)
+                        band_window(bq, a.cell_start, th, sh, ch, inv_sp, phf, hav_out, hav_in, w0, wl0, w1, wl1);
+                }
+                const int nband = min(LPP, khi - kb0 + 1);
+                for (int b = 0; b < nband; ++b) {
+                    const Band bd = a.bands[kb0 + b];
+                    if (bd.npts == 0) continue;
+                    const int src = (lane & ~(LPP - 1)) + b;
+                    walk(bd, __shfl(w0, src, kWave), __shfl(wl0, src, kWave), __shfl(w1, src, kWave),
+                         __shfl(wl1, src, kWave));
                 }
             }
         }
