@@ -88,6 +88,23 @@ static z3_status pool_for_current_device(hipMemPool_t *pool)
     return Z3_OK;
 }
 
+// Scratch blocks kept per (device, stream) between calls.  A chunk workspace has the same
+// size call after call; handing the same block back without returning it to the runtime
+// avoids the re-mapping that stream-ordered pool allocations of ~16 GiB have cost now and
+// then (0.2-1.3 s for one allocation, measured, with the pool's release threshold at its
+// maximum).  A block is reused only on the stream it was allocated on, so stream order keeps
+// calls from overlapping on it; within a call a block is busy until scratch_free.  Idle
+// blocks of a stream that are too small for a new request are given back first.
+struct WsBlock {
+    int dev;
+    hipStream_t s;
+    void *p;
+    size_t bytes;
+    bool busy;
+};
+static std::mutex g_ws_mu;
+static std::vector<WsBlock> g_ws;
+
 static thread_local CallScope *t_scope = nullptr;
 
 CallScope::CallScope(z3_index i, hipStream_t s) : idx(i), prev(t_scope)
@@ -122,17 +139,57 @@ z3_status scratch_alloc(void **p, size_t bytes, hipStream_t s)
     }
     z3_status st = alloc_allowed(aligned, "scratch workspace");
     if (st != Z3_OK) return st;
+    int dev = 0;
+    if ((st = check_hip(hipGetDevice(&dev), "hipGetDevice")) != Z3_OK) return st;
+    std::vector<void *> evict;
+    {
+        std::lock_guard<std::mutex> lk(g_ws_mu);
+        WsBlock *best = nullptr;
+        for (WsBlock &b : g_ws)
+            if (!b.busy && b.dev == dev && b.s == s && b.bytes >= aligned && (!best || b.bytes < best->bytes)) best = &b;
+        if (best) {
+            best->busy = true;
+            *p = best->p;
+            if (sc) sc->used += aligned;
+            return Z3_OK;
+        }
+        // idle blocks of this stream too small for the request are given back
+        for (size_t i = 0; i < g_ws.size();) {
+            if (!g_ws[i].busy && g_ws[i].dev == dev && g_ws[i].s == s) {
+                evict.push_back(g_ws[i].p);
+                g_ws[i] = g_ws.back();
+                g_ws.pop_back();
+            } else {
+                ++i;
+            }
+        }
+    }
+    for (void *q : evict) (void)hipFreeAsync(q, s);
     hipMemPool_t pool;
     if ((st = pool_for_current_device(&pool)) != Z3_OK) return st;
     st = check_hip(hipMallocFromPoolAsync(p, aligned, pool, s), "hipMallocFromPoolAsync");
-    if (st == Z3_OK && sc) sc->used += aligned;
-    return st;
+    if (st != Z3_OK) return st;
+    {
+        std::lock_guard<std::mutex> lk(g_ws_mu);
+        g_ws.push_back(WsBlock{dev, s, *p, aligned, true});
+    }
+    if (sc) sc->used += aligned;
+    return Z3_OK;
 }
 
 void scratch_free(void *p, hipStream_t s)
 {
     if (t_scope && t_scope->capturing) return;  // a slice of the index's capture workspace
-    if (p) (void)hipFreeAsync(p, s);
+    if (!p) return;
+    {
+        std::lock_guard<std::mutex> lk(g_ws_mu);
+        for (WsBlock &b : g_ws)
+            if (b.p == p) {
+                b.busy = false;  // kept for the next call on its stream
+                return;
+            }
+    }
+    (void)hipFreeAsync(p, s);
 }
 
 // ---- kernel timing -------------------------------------------------------------------
