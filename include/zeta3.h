@@ -94,8 +94,8 @@ enum {
  *   nbins          1 .. Z3_MAX_NBINS
  *   edges_chord2   [host] nbins+1 strictly increasing chord-squared edges, 0 < E_0,
  *                  E_nbins <= 4
- *   cell_size      band height in radians; <= 0 selects 0.6 * sqrt(A / n) where A is
- *                  the area of the catalogue's colatitude range
+ *   cell_size      band height in radians; <= 0 selects 1.4 * sqrt(A / n) where A is
+ *                  the area of the catalogue's colatitude range (about two HEALPix rings)
  *   out            receives the index; free it with z3_index_free
  * Synchronises on `stream` (to size its tables, and before it returns).  The input arrays
  * may be freed after it returns.
