@@ -123,9 +123,10 @@ z3_status z3_index_update_values(z3_index idx, const double *x, void *stream);
 
 /*
  * Graph capture.  The estimator and adjoint calls take their chunk workspaces from the
- * library's stream-ordered memory pool and keep them, per device and stream, for the next
- * call on the same stream (held until the process ends; a later call that needs more gives
- * the stream's idle blocks back first); while their stream is being captured into a HIP
+ * library's stream-ordered memory pool and keep them per device for later calls (held until
+ * the process ends; a call that needs more than every idle block gives those back first; a
+ * call waits for a kept block's last use, on whatever stream, before it uses the block);
+ * while their stream is being captured into a HIP
  * graph they take them instead from a workspace held by the index, so that the captured
  * kernels point at memory that stays valid for every replay.  This call reserves that
  * workspace: max(min_bytes, the largest total any eager call on this index has used so

@@ -88,19 +88,21 @@ static z3_status pool_for_current_device(hipMemPool_t *pool)
     return Z3_OK;
 }
 
-// Scratch blocks kept per (device, stream) between calls.  A chunk workspace has the same
-// size call after call; handing the same block back without returning it to the runtime
-// avoids the re-mapping that stream-ordered pool allocations of ~16 GiB have cost now and
-// then (0.2-1.3 s for one allocation, measured, with the pool's release threshold at its
-// maximum).  A block is reused only on the stream it was allocated on, so stream order keeps
-// calls from overlapping on it; within a call a block is busy until scratch_free.  Idle
-// blocks of a stream that are too small for a new request are given back first.
+// Scratch blocks kept per device between calls.  A chunk workspace has the same size call
+// after call; handing the same block back without returning it to the runtime avoids the
+// re-mapping that stream-ordered pool allocations of ~16 GiB have cost now and then (0.2-1.3 s
+// for one allocation, measured, with the pool's release threshold at its maximum).  When a
+// call gives a block back, an event is recorded on its stream; a later call, on any stream,
+// waits for that event before it uses the block (free on the same stream, whose order already
+// implies it), so a block moves between streams as safely as pool memory does.  Within a call
+// a block is busy until scratch_free.  Idle blocks too small for a new request are given back
+// to the pool first.
 struct WsBlock {
     int dev;
-    hipStream_t s;
     void *p;
     size_t bytes;
     bool busy;
+    hipEvent_t done;  // recorded when the block was last given back
 };
 static std::mutex g_ws_mu;
 static std::vector<WsBlock> g_ws;
@@ -141,22 +143,23 @@ z3_status scratch_alloc(void **p, size_t bytes, hipStream_t s)
     if (st != Z3_OK) return st;
     int dev = 0;
     if ((st = check_hip(hipGetDevice(&dev), "hipGetDevice")) != Z3_OK) return st;
-    std::vector<void *> evict;
+    std::vector<WsBlock> evict;
     {
         std::lock_guard<std::mutex> lk(g_ws_mu);
         WsBlock *best = nullptr;
         for (WsBlock &b : g_ws)
-            if (!b.busy && b.dev == dev && b.s == s && b.bytes >= aligned && (!best || b.bytes < best->bytes)) best = &b;
+            if (!b.busy && b.dev == dev && b.bytes >= aligned && (!best || b.bytes < best->bytes)) best = &b;
         if (best) {
+            if ((st = check_hip(hipStreamWaitEvent(s, best->done, 0), "hipStreamWaitEvent")) != Z3_OK) return st;
             best->busy = true;
             *p = best->p;
             if (sc) sc->used += aligned;
             return Z3_OK;
         }
-        // idle blocks of this stream too small for the request are given back
+        // no idle block fits: the device's idle blocks are all too small, give them back
         for (size_t i = 0; i < g_ws.size();) {
-            if (!g_ws[i].busy && g_ws[i].dev == dev && g_ws[i].s == s) {
-                evict.push_back(g_ws[i].p);
+            if (!g_ws[i].busy && g_ws[i].dev == dev) {
+                evict.push_back(g_ws[i]);
                 g_ws[i] = g_ws.back();
                 g_ws.pop_back();
             } else {
@@ -164,14 +167,25 @@ z3_status scratch_alloc(void **p, size_t bytes, hipStream_t s)
             }
         }
     }
-    for (void *q : evict) (void)hipFreeAsync(q, s);
+    for (const WsBlock &b : evict) {
+        // freed in the order of this stream, after the block's last use on its own
+        (void)hipStreamWaitEvent(s, b.done, 0);
+        (void)hipFreeAsync(b.p, s);
+        (void)hipEventDestroy(b.done);
+    }
     hipMemPool_t pool;
     if ((st = pool_for_current_device(&pool)) != Z3_OK) return st;
+    hipEvent_t done = nullptr;
+    if ((st = check_hip(hipEventCreateWithFlags(&done, hipEventDisableTiming), "hipEventCreateWithFlags")) != Z3_OK)
+        return st;
     st = check_hip(hipMallocFromPoolAsync(p, aligned, pool, s), "hipMallocFromPoolAsync");
-    if (st != Z3_OK) return st;
+    if (st != Z3_OK) {
+        (void)hipEventDestroy(done);
+        return st;
+    }
     {
         std::lock_guard<std::mutex> lk(g_ws_mu);
-        g_ws.push_back(WsBlock{dev, s, *p, aligned, true});
+        g_ws.push_back(WsBlock{dev, *p, aligned, true, done});
     }
     if (sc) sc->used += aligned;
     return Z3_OK;
@@ -185,7 +199,9 @@ void scratch_free(void *p, hipStream_t s)
         std::lock_guard<std::mutex> lk(g_ws_mu);
         for (WsBlock &b : g_ws)
             if (b.p == p) {
-                b.busy = false;  // kept for the next call on its stream
+                // kept for the next call; its last use is this stream's work so far
+                (void)hipEventRecord(b.done, s);
+                b.busy = false;
                 return;
             }
     }

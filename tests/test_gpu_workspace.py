@@ -1,10 +1,11 @@
-"""Chunk workspaces kept per (device, stream) between calls.
+"""Chunk workspaces kept per device between calls.
 
-The fused estimator takes its chunk workspace from blocks the library keeps per device and
-stream: a later call on the same stream gets a kept block back (the smallest idle one that
-fits), and a request larger than every idle block of the stream gives those back and takes a
-new one.  Every sum has a fixed order, so the result of a call must not depend on which
-block it gets, on the stream it runs on, or on the calls before it: bit for bit.
+The fused estimator takes its chunk workspace from blocks the library keeps per device: a
+later call gets a kept block back (the smallest idle one that fits) after waiting for the
+block's last use on whatever stream, and a request larger than every idle block gives those
+back and takes a new one.  Every sum has a fixed order, so the result of a call must not
+depend on which block it gets, on the stream it runs on, or on the calls before it: bit for
+bit.
 """
 
 import numpy as np
