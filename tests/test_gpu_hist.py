@@ -4,8 +4,8 @@ per-(pivot, radial bin, angular bin) pair counts bit-exact, W and N exact, per-p
 multipoles within 1e-11 of each bin's scale (FP64; the FP32 storage of the mixed path
 within 1.2e-7), zeta within 1e-10 (FP64) and 1e-6 (mixed); the three-point golden values;
 full-sky HEALPix pivots at both poles and across the longitude wrap; the bench's largest
-configuration (nside512, m_max 64, 130 angular bins) on sampled pivots; m_max up to 127;
-argument checks."""
+configuration (nside512, m_max 64, 130 angular bins) on sampled pivots; m_max up to 127, with
+weights and per-cell counts on the widest lane layouts; argument checks."""
 
 import ctypes
 
@@ -160,6 +160,22 @@ def test_large_m(n_phi, M):
         G.say("  err", prec, e.max())
         assert pairs == po
         assert e.max() < tol
+    idx.free()
+
+
+@pytest.mark.parametrize("n_phi,M", [(130, 64), (256, 127)])
+def test_large_m_weighted_cells(n_phi, M):
+    """Weighted catalogue on the widest lane layouts (8 and 16 lanes per pivot, whose lanes
+    split the bands and sum the pivot's weights): per-pivot multipoles, weights, pair counts
+    and per-cell counts on a ragged pivot range."""
+    G.say("case: histogram large m, weighted, cells", n_phi, M)
+    xyz, w, x = pins.random_cap(1500, 4.0, 45)
+    E = pins.small_edges(4, lo=0.1, hi=2.0, log=True)
+    bnd = phi_boundaries(n_phi)
+    idx = G.build(xyz, x, E, w=w)
+    idx.set_phi_bins(bnd)
+    perm = G.perm(idx)
+    _check_pivots(idx, xyz, x, w, E, M, bnd, 37, 261, perm)
     idx.free()
 
 
