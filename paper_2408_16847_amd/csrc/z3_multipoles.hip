@@ -107,13 +107,17 @@ void k_multipoles(MultArgs a)
     const double xp = a.px[pp], yp = a.py[pp], zp = a.pz[pp];
     double th, sh = 0.0, ch = 0.0, phd = 0.0;
     float inv_sp = 0.0f, phf = 0.0f;
-    double nx, ny, nz, ex, ey, ez;
+    // local north n and east e.  Off the poles e = n x r_p = (-y, x, 0) / |n| has no z
+    // component for any pivot length; in the pole fallback (north along x, |y| < 1e-12) its z
+    // component is y / |n|, and leaving that term out of the east coordinate turns the
+    // bearing by less than 1e-12 |dz| / |d| (dz ~ |d|^2 / 2 there).  So e_z is never used.
+    double nx, ny, nz, ex, ey;
     if constexpr (PLANAR) {
         // plane: strips of y, cells of x; angles from +y ("north") towards +x ("east")
         th = yp - a.py0;
         phd = (xp - a.px0) * a.psx;
         nx = 0.0; ny = 1.0; nz = 0.0;
-        ex = 1.0; ey = 0.0; ez = 0.0;
+        ex = 1.0; ey = 0.0;
     } else {
         const double sinth = sqrt(xp * xp + yp * yp);
         th = atan2(sinth, zp);
@@ -130,7 +134,7 @@ void k_multipoles(MultArgs a)
             nn = sqrt(nx * nx + ny * ny + nz * nz);
         }
         nx /= nn; ny /= nn; nz /= nn;
-        ex = ny * zp - nz * yp; ey = nz * xp - nx * zp; ez = nx * yp - ny * xp;
+        ex = ny * zp - nz * yp; ey = nz * xp - nx * zp;
     }
 
     // External pivots need not be unit vectors (the index's points are, to within the
@@ -207,8 +211,11 @@ void k_multipoles(MultArgs a)
                     // record of the band that is never used (or, past the band, zeros from
                     // the buffer's range check).
                     auto cand = [&](const double4 &r, uint32_t o) __attribute__((always_inline)) {
-                        const double dx = r.x - xp, dy = r.y - yp, dz = r.z - zp;
-                        const double d2 = (dx * dx + dy * dy) + dz * dz;
+                        const double dx = r.x - xp, dy = r.y - yp;
+                        // on the plane both z are 0, and adding dz * dz = +0 to the
+                        // non-negative sum changes nothing: the same d2 without that term
+                        const double dz = PLANAR ? 0.0 : r.z - zp;
+                        const double d2 = PLANAR ? dx * dx + dy * dy : (dx * dx + dy * dy) + dz * dz;
                         if (d2 >= elo && d2 < ehi) {
                             cnt += 1;
                             if (IDS || !unit_w) {  // wave-uniform
@@ -222,8 +229,9 @@ void k_multipoles(MultArgs a)
                             }
                             const double v = r.w;
                             if constexpr (SELF) Qb = fma(v, v, Qb);
-                            const double u1 = fma(dx, nx, fma(dy, ny, dz * nz));
-                            const double u2 = fma(dx, ex, fma(dy, ey, dz * ez));
+                            // plane: north +y, east +x, so the coordinates are dy and dx
+                            const double u1 = PLANAR ? dy : fma(dx, nx, fma(dy, ny, dz * nz));
+                            const double u2 = PLANAR ? dx : fma(dx, ex, dy * ey);
                             double tc, ts;  // 2 cos(phi), 2 sin(phi)
                             twice_unit_bearing(u1, u2, a.tiny, tc, ts);
                             SU[0] += v;
@@ -364,7 +372,8 @@ void k_multipoles_maps(MapArgs a)
         nn = sqrt(nx * nx + ny * ny + nz * nz);
     }
     nx /= nn; ny /= nn; nz /= nn;
-    const double ex = ny * zp - nz * yp, ey = nz * xp - nx * zp, ez = nx * yp - ny * xp;
+    // east without its z component, as in k_multipoles
+    const double ex = ny * zp - nz * yp, ey = nz * xp - nx * zp;
 
     const int64_t col = p - a.p0;
     const int nb = a.nb;
@@ -412,7 +421,7 @@ void k_multipoles_maps(MapArgs a)
                         const double4 vv = *reinterpret_cast<const double4 *>(a.vgrp + (size_t)j * K);
                         const double v[K] = {vv.x, vv.y, vv.z, vv.w};
                         const double u1 = fma(dx, nx, fma(dy, ny, dz * nz));
-                        const double u2 = fma(dx, ex, fma(dy, ey, dz * ez));
+                        const double u2 = fma(dx, ex, dy * ey);
                         double tc, ts;  // 2 cos(phi), 2 sin(phi)
                         twice_unit_bearing(u1, u2, kBearingTiny, tc, ts);
 #pragma unroll
