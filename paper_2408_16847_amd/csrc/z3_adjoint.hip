@@ -192,7 +192,7 @@ __device__ __forceinline__ PivotFrame plane_frame(double xp, double yp, double z
     f.th = yp - y0;
     f.sh = 0.0; f.ch = 0.0; f.inv_sp = 0.0f; f.phf = 0.0f;
     f.nx = 0.0; f.ny = 1.0; f.nz = 0.0;
-    f.ex = 1.0; f.ey = 0.0; f.ez = 0.0;
+    f.ex = 1.0; f.ey = 0.0;
     return f;
 }
 
@@ -291,7 +291,7 @@ void k_adjoint_scatter(ScatterArgs a)
                     const double d2 = (dx * dx + dy * dy) + dz * dz;
                     if (d2 >= elo && d2 < ehi) {
                         const double u1 = fma(dx, f.nx, fma(dy, f.ny, dz * f.nz));
-                        const double u2 = fma(dx, f.ex, fma(dy, f.ey, dz * f.ez));
+                        const double u2 = fma(dx, f.ex, dy * f.ey);
                         double tc, ts;  // 2 cos(phi), 2 sin(phi)
                         twice_unit_bearing(u1, u2, kBearingTiny, tc, ts);
                         // sum_m Re(exp(-i m phi) D(m)) = sum_m cos(m phi) Re D + sin(m phi) Im D

@@ -167,7 +167,7 @@ void k_multipoles_batch(BatchArgs a)
                 if (in) {
                     cnt += 1;
                     const double u1 = fma(dx, f.nx, fma(dy, f.ny, dz * f.nz));
-                    const double u2 = fma(dx, f.ex, fma(dy, f.ey, dz * f.ez));
+                    const double u2 = fma(dx, f.ex, dy * f.ey);
                     double c1, sn1;
                     unit_bearing(u1, u2, c1, sn1);
                     // cos(m phi) = T_m(cos phi), sin(m phi) = sin phi U_{m-1}(cos phi): the

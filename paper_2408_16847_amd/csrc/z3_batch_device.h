@@ -44,7 +44,7 @@ __device__ __forceinline__ PivotFrame uniform_frame(PivotFrame f)
     f.th = uniform_f64(f.th); f.sh = uniform_f64(f.sh); f.ch = uniform_f64(f.ch);
     f.inv_sp = uniform_f32(f.inv_sp); f.phf = uniform_f32(f.phf);
     f.nx = uniform_f64(f.nx); f.ny = uniform_f64(f.ny); f.nz = uniform_f64(f.nz);
-    f.ex = uniform_f64(f.ex); f.ey = uniform_f64(f.ey); f.ez = uniform_f64(f.ez);
+    f.ex = uniform_f64(f.ex); f.ey = uniform_f64(f.ey);
     return f;
 }
 

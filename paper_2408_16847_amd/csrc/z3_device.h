@@ -277,7 +277,7 @@ struct PivotFrame {
     double th, sh, ch;     // colatitude and sin/cos of its half
     float inv_sp, phf;     // 1 / sin(colatitude), longitude in [0, 2 pi)
     double nx, ny, nz;     // local north
-    double ex, ey, ez;     // local east
+    double ex, ey;         // local east; its z component is left out (see pivot_frame)
 };
 
 __device__ __forceinline__ PivotFrame pivot_frame(double xp, double yp, double zp)
@@ -298,9 +298,11 @@ __device__ __forceinline__ PivotFrame pivot_frame(double xp, double yp, double z
         nn = sqrt(nx * nx + ny * ny + nz * nz);
     }
     f.nx = nx / nn; f.ny = ny / nn; f.nz = nz / nn;
+    // east = north x r_p.  Off the poles that is (-y, x, 0) / |n|, with no z component for
+    // any pivot length; in the pole fallback its z component is y / |n| with |y| < 1e-12, and
+    // leaving it out of the east coordinate turns the bearing by less than 1e-12 |dz| / |d|.
     f.ex = f.ny * zp - f.nz * yp;
     f.ey = f.nz * xp - f.nx * zp;
-    f.ez = f.nx * yp - f.ny * xp;
     return f;
 }
 
