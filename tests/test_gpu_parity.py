@@ -132,6 +132,32 @@ def test_full_sky_healpix_poles_and_wrap():
         assert np.array_equal(N, No) and np.array_equal(H, Ho)
 
 
+def test_pivots_on_and_next_to_the_poles():
+    """External pivots exactly at the poles and within 1e-12 of them (where local north is
+    undefined and both sides measure angles from the x axis), with ordinary pivots beside
+    them, against the oracle on the Nside 64 full sky: pair counts equal, zeta within the
+    usual bars."""
+    G.say("case: pivots at the poles")
+    xyz = ring_centres(64).numpy()
+    x = make_values(CONFIGS["nside512"], torch.from_numpy(xyz)).numpy()
+    w = np.ones(xyz.shape[1])
+    E = chord2_edges(theta_edges(math.radians(1.0), math.radians(12.0), 6, True))
+    idx = G.build(xyz, x, E)
+    pv = np.array([[0.0, 0.0, 1.0], [0.0, 0.0, -1.0], [3e-13, -4e-13, 1.0], [-2e-13, 7e-14, -1.0],
+                   [0.0, 1e-13, 1.0], [0.6, 0.0, 0.8], [0.0, -0.28, -0.96]]).T.copy()
+    px = np.array([0.7, -1.3, 2.1, 0.4, -0.9, 1.1, -0.5])
+    pw = np.array([1.0, 0.5, 2.0, 1.5, 0.8, 1.2, 0.9])
+    zo, po = cpu.estimate(pv, xyz, w, x, E, 10, pw, px)
+    for prec, tol in (("fp64", 1e-10), ("mixed", 1e-6)):
+        z, pairs = z3.estimate_pivots(idx, torch.from_numpy(pv).cuda(), torch.from_numpy(px).cuda(),
+                                      torch.from_numpy(pw).cuda(), m_max=10, prec=prec)
+        assert pairs == po
+        e = G.err_m(z, zo)
+        G.say("err_m", prec, e.max())
+        assert e.max() < tol
+    idx.free()
+
+
 def test_empty_and_degenerate_inputs():
     G.say("case: empty/degenerate")
     E = pins.small_edges(3)
