@@ -184,7 +184,10 @@ void k_multipoles(MultArgs a)
         double SU[M + 1], SV[M + 1];
 #pragma unroll
         for (int m = 0; m <= M; ++m) { SU[m] = 0.0; SV[m] = 0.0; }
-        double Wb = 0.0, Qb = 0.0;
+        // wpend: the weight of the lane's previous pair, added at its next pair (or after the
+        // bin), so that its load overlaps a candidate's work instead of stalling the pair that
+        // requested it; the additions keep their order
+        double Wb = 0.0, Qb = 0.0, wpend = 0.0;
         int cnt = 0;
         uint64_t hsum = 0;
 
@@ -224,7 +227,10 @@ void k_multipoles(MultArgs a)
                                 uint32_t jo;
                                 asm("v_lshrrev_b32 %0, 5, %1" : "=v"(jo) : "v"(o));
                                 const int j = base + (int)jo;
-                                if (!unit_w) Wb += a.wdbl[j];
+                                if (!unit_w) {
+                                    Wb += wpend;
+                                    wpend = a.wdbl[j];
+                                }
                                 if constexpr (IDS) hsum += mix64((uint64_t)a.permdbl[j]);
                             }
                             const double v = r.w;
@@ -263,6 +269,7 @@ void k_multipoles(MultArgs a)
             }
         }
 
+        Wb += wpend;
         double self_t = 0.0;
         if (valid) {
             my_pairs += (uint64_t)cnt;
