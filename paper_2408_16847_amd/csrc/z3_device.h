@@ -59,6 +59,14 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_view(const void *base, 
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
 }
 
+// One FP64 value at byte offset `off` of a buffer view (0 past its range).
+__device__ __forceinline__ double load_f64(__amdgpu_buffer_rsrc_t v, uint32_t off)
+{
+    typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+    const u2 a = __builtin_amdgcn_raw_buffer_load_b64(v, off, 0, 0);
+    return __builtin_bit_cast(double, (uint64_t)a.x | (uint64_t)a.y << 32);
+}
+
 __device__ __forceinline__ double4 load_record(__amdgpu_buffer_rsrc_t v, uint32_t off)
 {
     typedef unsigned int u4 __attribute__((ext_vector_type(4)));

@@ -212,7 +212,9 @@ void k_multipoles_hist(HistArgs a)
         const double hav_out = a.edges->hav_out[bin + 1], hav_in = a.edges->hav_in[bin];
         int klo, khi;
         band_range(th, a.edges->rad_out[bin + 1], a.inv_h, a.nbands, klo, khi);
-        double Wb = 0.0;
+        // wpend: the weight of the lane's previous pair, added at its next pair (or after the
+        // bin), so that its load overlaps a candidate's work; the additions keep their order
+        double Wb = 0.0, wpend = 0.0;
         int cnt = 0;
         // run of consecutive pairs (of this lane) in one angular bin, summed in registers and
         // added to the pivot's histogram row by an LDS atomic when the bin changes
@@ -222,12 +224,18 @@ void k_multipoles_hist(HistArgs a)
         auto walk = [&](const Band &bd, int s0, int l0, int s1, int l1) __attribute__((always_inline)) {
             const int base = 2 * bd.pt_start;
             const __amdgpu_buffer_rsrc_t rband = buffer_view(a.rec + base, (uint32_t)bd.npts * 64u);
+            // and its doubled weights (8 B per record: byte offset = record offset / 4)
+            const __amdgpu_buffer_rsrc_t wband = buffer_view(unit_w ? nullptr : a.wdbl + base,
+                                                             unit_w ? 0u : (uint32_t)bd.npts * 16u);
             auto cand = [&](const double4 &r, uint32_t o) __attribute__((always_inline)) {
                 const double dx = r.x - xp, dy = r.y - yp, dz = r.z - zp;
                 const double d2 = (dx * dx + dy * dy) + dz * dz;
                 if (d2 >= elo && d2 < ehi) {
                     cnt += 1;
-                    if (!unit_w) Wb += a.wdbl[base + (int)(o >> 5)];
+                    if (!unit_w) {
+                        Wb += wpend;
+                        wpend = load_f64(wband, o >> 2);
+                    }
                     bool sure;
                     int k = angular_estimate(n, a.phi_scale, a.phi_guard, fma(dx, nx, fma(dy, ny, dz * nz)),
                                              fma(dx, ex, fma(dy, ey, dz * ez)), sure);
@@ -306,6 +314,7 @@ void k_multipoles_hist(HistArgs a)
             if constexpr (CNT) atomicAdd(&C[krun * HS + pl], crun);
         }
         if (valid) my_pairs += (uint64_t)cnt;
+        Wb += wpend;
         // the pivot's pair count and weight sum over its LPP lanes (a butterfly: every lane of
         // the pivot ends with the same, fixed-order sum)
 #pragma unroll

@@ -202,6 +202,9 @@ void k_multipoles(MultArgs a)
             const int base = 2 * bd.pt_start;
             // the band's doubled records (wave-uniform base), walked by byte offset
             const __amdgpu_buffer_rsrc_t rband = buffer_view(a.rec + base, (uint32_t)bd.npts * 64u);
+            // and its doubled weights (8 B per record: byte offset = record offset / 4)
+            const __amdgpu_buffer_rsrc_t wband = buffer_view(unit_w ? nullptr : a.wdbl + base,
+                                                             unit_w ? 0u : (uint32_t)bd.npts * 16u);
 #pragma unroll
             for (int seg = 0; seg < 2; ++seg) {
                 uint32_t off = (uint32_t)(seg == 0 ? s0 : s1) * 32u;
@@ -221,17 +224,16 @@ void k_multipoles(MultArgs a)
                         const double d2 = PLANAR ? dx * dx + dy * dy : (dx * dx + dy * dy) + dz * dz;
                         if (d2 >= elo && d2 < ehi) {
                             cnt += 1;
-                            if (IDS || !unit_w) {  // wave-uniform
+                            if constexpr (IDS) {
                                 // record index from the byte offset, as an opaque shift so
                                 // that the compiler keeps no second induction variable
                                 uint32_t jo;
                                 asm("v_lshrrev_b32 %0, 5, %1" : "=v"(jo) : "v"(o));
-                                const int j = base + (int)jo;
-                                if (!unit_w) {
-                                    Wb += wpend;
-                                    wpend = a.wdbl[j];
-                                }
-                                if constexpr (IDS) hsum += mix64((uint64_t)a.permdbl[j]);
+                                hsum += mix64((uint64_t)a.permdbl[base + (int)jo]);
+                            }
+                            if (!unit_w) {  // wave-uniform
+                                Wb += wpend;
+                                wpend = load_f64(wband, o >> 2);
                             }
                             const double v = r.w;
                             if constexpr (SELF) Qb = fma(v, v, Qb);
