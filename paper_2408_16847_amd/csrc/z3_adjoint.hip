@@ -528,7 +528,7 @@ z3_status adjoint_maps_impl(z3_index idx, int m_max, int64_t p0, int64_t p1, con
                 st = launch_multipoles_batch(idx, m_max, Z3_PREC_FP64, shape, c0, c1, wd, wa, c1 - c0, stride,
                                              static_cast<double *>(ww), nullptr, s);
             else
-                st = launch_multipoles_maps(idx, g, m_max, Z3_PREC_FP64, c0, c1, wa, c1 - c0, stride,
+                st = launch_multipoles_maps(idx, g, nm, m_max, Z3_PREC_FP64, c0, c1, wa, c1 - c0, stride,
                                             static_cast<double *>(ww), nullptr, s);
             if (st == Z3_OK)
                 st = adjoint_chunk_maps(idx, map0, nm, m_max, c0, c1, static_cast<const double *>(wa), stride,

@@ -816,8 +816,12 @@ Z3_API z3_status z3_estimate_cross(z3_index idx, int map_a, int map_b, int map_c
     const int grp = need[0] / kMapGroup;
     bool grouped = !idx->planar && idx->ngroups > grp && nneed > 2;
     for (int k = 0; k < nneed; ++k) grouped = grouped && need[k] / kMapGroup == grp;
+    int top_slot = 0;  // the group kernel writes slots 0..top_slot at least
     if (grouped)
-        for (int t = 0; t < 3; ++t) slot_of[t] = fa[t] % kMapGroup;
+        for (int t = 0; t < 3; ++t) {
+            slot_of[t] = fa[t] % kMapGroup;
+            top_slot = slot_of[t] > top_slot ? slot_of[t] : top_slot;
+        }
     const int nslots = grouped ? kMapGroup : nneed;
     int64_t chunk = chunk_pivots(idx, m_max, prec) / nslots;
     chunk = (chunk / kBlock) * kBlock;
@@ -832,7 +836,8 @@ Z3_API z3_status z3_estimate_cross(z3_index idx, int map_a, int map_b, int map_c
     for (int64_t c0 = p0; c0 < p1 && st == Z3_OK; c0 += chunk) {
         const int64_t c1 = c0 + chunk < p1 ? c0 + chunk : p1;
         if (grouped)
-            st = launch_multipoles_maps(idx, grp, m_max, prec, c0, c1, wa, c1 - c0, slot_elems, nullptr, pair_total, s);
+            st = launch_multipoles_maps(idx, grp, top_slot + 1, m_max, prec, c0, c1, wa, c1 - c0, slot_elems, nullptr,
+                                        pair_total, s);
         for (int k = 0; k < nneed && st == Z3_OK && !grouped; ++k)
             st = launch_multipoles(idx, Pivots{idx->d_x, idx->d_y, idx->d_z}, need[k], m_max, prec, Z3_NORM_BIN, c0,
                                    c1, static_cast<char *>(wa) + (size_t)k * slot_elems * elem, c1 - c0, nullptr,
@@ -1003,10 +1008,10 @@ Z3_API z3_status z3_estimate_maps(z3_index idx, int m_max, int prec, int64_t p0,
             int64_t c1 = c0 + chunk < p1 ? c0 + chunk : p1;
             // the chunk's multipoles use a leading dimension equal to the chunk length
             const size_t stride = (size_t)(c1 - c0) * (m_max + 1) * 2 * idx->nbins;
-            st = launch_multipoles_maps(idx, g, m_max, prec, c0, c1, wa, c1 - c0, stride, nullptr,
-                                        g == 0 ? pair_total : nullptr, s);
             const int map0 = g * kMapGroup;
             const int nm = idx->nmaps - map0 < kMapGroup ? idx->nmaps - map0 : kMapGroup;
+            st = launch_multipoles_maps(idx, g, nm, m_max, prec, c0, c1, wa, c1 - c0, stride, nullptr,
+                                        g == 0 ? pair_total : nullptr, s);
             if (st == Z3_OK)
                 st = launch_contract_maps(c1 - c0, m_max, idx->nbins, prec, nm, wa, c1 - c0, stride,
                                           idx->d_v + (size_t)map0 * idx->n + c0, (size_t)idx->n, zeta + map0 * zstride,

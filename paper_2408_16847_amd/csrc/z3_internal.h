@@ -167,7 +167,9 @@ z3_status batch_shape(z3_index idx, int m_max, int prec, int64_t p0, int64_t p1,
 z3_status launch_multipoles_batch(const z3_index_s *idx, int m_max, int prec, int shape, int64_t p0, int64_t p1,
                                   void *stage, void *A, int64_t ldA, size_t map_stride, double *W,
                                   uint64_t *pair_total, hipStream_t s);
-z3_status launch_multipoles_maps(const z3_index_s *idx, int group, int m_max, int prec, int64_t p0,
+// Multipoles of the maps of attached group `group` (kMapGroup maps, map_stride elements apart
+// in A); only the first `nslots` (1..kMapGroup) are guaranteed written.
+z3_status launch_multipoles_maps(const z3_index_s *idx, int group, int nslots, int m_max, int prec, int64_t p0,
                                  int64_t p1, void *A, int64_t ldA, size_t map_stride, double *W,
                                  uint64_t *pair_total, hipStream_t s);
 

@@ -319,9 +319,10 @@ void k_multipoles(MultArgs a)
 // ---- many maps over one set of positions -------------------------------------------------
 //
 // Same decomposition (one lane per pivot, bins in order, band windows), but every lane
-// carries kMapGroup maps: the pair test, the bearing and the unit chain U_k(cos phi) are
-// computed once per pair, and each map adds v U_k and v 2 sin(phi) U_k with two FMAs per
-// k (the epilogue forms the harmonics' sums as in k_multipoles).
+// carries K maps of a group of kMapGroup (K = 3 when the caller reads at most the first three,
+// else 4): the pair test, the bearing and the unit chain U_k(cos phi) are computed once per
+// pair, and each map adds v U_k and v 2 sin(phi) U_k with two FMAs per k (the epilogue forms
+// the harmonics' sums as in k_multipoles).
 
 struct MapArgs {
     const double *px, *py, *pz;   // index-order pivot positions
@@ -349,11 +350,11 @@ constexpr int maps_waves_per_eu()
     return M <= 6 ? 3 : 2;
 }
 
-template <int M, bool F32OUT>
+template <int M, bool F32OUT, int K>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(maps_waves_per_eu<M>())))
 void k_multipoles_maps(MapArgs a)
 {
-    constexpr int K = kMapGroup;
+    static_assert(K == 3 || K == kMapGroup, "three or four maps per lane");
     const int nblk = a.nblocks;
     const int bid = blockIdx.x;
     const int per = nblk / 8, rem = nblk % 8;
@@ -427,8 +428,10 @@ void k_multipoles_maps(MapArgs a)
                     if (d2 >= elo && d2 < ehi) {
                         cnt += 1;
                         if (!unit_w) Wb += a.wdbl[j];
-                        const double4 vv = *reinterpret_cast<const double4 *>(a.vgrp + (size_t)j * K);
-                        const double v[K] = {vv.x, vv.y, vv.z, vv.w};
+                        const double4 vv = *reinterpret_cast<const double4 *>(a.vgrp + (size_t)j * kMapGroup);
+                        double v[K];
+                        v[0] = vv.x; v[1] = vv.y; v[2] = vv.z;
+                        if constexpr (K == 4) v[3] = vv.w;
                         const double u1 = fma(dx, nx, fma(dy, ny, dz * nz));
                         const double u2 = fma(dx, ex, dy * ey);
                         double tc, ts;  // 2 cos(phi), 2 sin(phi)
@@ -493,17 +496,23 @@ void k_multipoles_maps(MapArgs a)
 }
 
 template <int M>
-static void launch_maps_m(bool f32out, const MapArgs &a, hipStream_t s)
+static void launch_maps_m(bool f32out, bool three, const MapArgs &a, hipStream_t s)
 {
     dim3 grid(a.nblocks), block(kBlock);
-    if (f32out) hipLaunchKernelGGL((k_multipoles_maps<M, true>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_multipoles_maps<M, false>), grid, block, 0, s, a);
+    if (three) {
+        if (f32out) hipLaunchKernelGGL((k_multipoles_maps<M, true, 3>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_multipoles_maps<M, false, 3>), grid, block, 0, s, a);
+    } else {
+        if (f32out) hipLaunchKernelGGL((k_multipoles_maps<M, true, kMapGroup>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_multipoles_maps<M, false, kMapGroup>), grid, block, 0, s, a);
+    }
 }
 
-z3_status launch_multipoles_maps(const z3_index_s *idx, int group, int m_max, int prec, int64_t p0, int64_t p1,
-                                 void *A, int64_t ldA, size_t map_stride, double *W, uint64_t *pair_total,
-                                 hipStream_t s)
+z3_status launch_multipoles_maps(const z3_index_s *idx, int group, int nslots, int m_max, int prec, int64_t p0,
+                                 int64_t p1, void *A, int64_t ldA, size_t map_stride, double *W,
+                                 uint64_t *pair_total, hipStream_t s)
 {
+    if (nslots < 1 || nslots > kMapGroup) return fail(Z3_ERR_INVALID_ARG, "map slots %d outside 1..%d", nslots, kMapGroup);
     int64_t nblk = (p1 - p0 + kBlock - 1) / kBlock;
     if (nblk > 0x7fffffff) return fail(Z3_ERR_OVERFLOW, "too many pivot blocks");
     MapArgs a;
@@ -526,7 +535,7 @@ z3_status launch_multipoles_maps(const z3_index_s *idx, int group, int m_max, in
     hipEvent_t ev0;
     profile_begin(s, &ev0);
     switch (m_max) {
-#define Z3_CASE(MM) case MM: launch_maps_m<MM>(f32, a, s); break;
+#define Z3_CASE(MM) case MM: launch_maps_m<MM>(f32, nslots <= 3, a, s); break;
         Z3_CASE(0) Z3_CASE(1) Z3_CASE(2) Z3_CASE(3) Z3_CASE(4) Z3_CASE(5) Z3_CASE(6) Z3_CASE(7)
         Z3_CASE(8) Z3_CASE(9) Z3_CASE(10) Z3_CASE(11) Z3_CASE(12) Z3_CASE(13) Z3_CASE(14)
         Z3_CASE(15) Z3_CASE(16)
