@@ -140,6 +140,26 @@ def test_cross_fields_in_different_map_groups(cap3, prec, tol):
     assert G.err_m(zg, zo).max() <= tol
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("mixed", 1e-6)])
+def test_cross_fields_in_the_last_slot_of_a_group(cap3, prec, tol):
+    # four attached maps, fields read from slots 1, 2, 3 and 3, 0, 2 of the group: the shared
+    # pass then carries all four maps per lane, where fields 0, 1, 2 need only three
+    cfg, xyz, f = cap3
+    G.say("case: cap20k fields in slot 3 of a map group", prec)
+    E = cfg.edges_chord2()
+    w = np.ones(xyz.shape[1])
+    four = np.concatenate([f, (f[1] - f[2])[None]])
+    idx = G.build(xyz, four, E)
+    for maps in ((1, 2, 3), (3, 0, 2)):
+        z, pairs = z3.estimate_cross(idx, maps, cfg.m_max, prec=prec, cyclic=True)
+        fo = tuple(four[k] for k in maps)
+        zo, po = cpu.estimate_cross(xyz, xyz, w, fo, E, cfg.m_max, w, fo, cyclic=True)
+        assert pairs == po
+        e = G.err_m(z, zo)
+        G.say("err_m", maps, prec, e.max())
+        assert e.max() <= tol
+
+
 def _catalogues():
     # three different point sets on one 4-degree cap, each with its own weights and a
     # lognormal field (galaxy samples of different surveys, say)
