@@ -149,13 +149,15 @@ z3_status z3_index_info(z3_index idx, int64_t *n, int *nbins, int *nmaps, int *n
 z3_status z3_index_perm(z3_index idx, int64_t *perm, void *stream);
 
 /*
- * Block shape of the MFMA many-map kernel (z3_estimate_maps, z3_adjoint_maps with more
- * than 4 maps): one block per pivot with `waves` wave64s, each owning `maps_per_wave`
- * maps; compiled shapes are (4, 16), (2, 32), (2, 16) and (4, 32).  (0, 0), the default,
- * lets the library time every compiled shape on a 4096-pivot sample of the first eager
- * call for each (m_max, prec) and keep the fastest for this index.  Every shape gives
- * bit-identical results.  Attaching new values (z3_index_set_values) forgets the tuned
- * shapes.  Z3_ERR_INVALID_ARG for a shape that is not compiled.
+ * Block shape of the MFMA many-map kernel (z3_estimate_maps with more than 24 maps on the
+ * FP64 path or 16 on the mixed path, z3_adjoint_maps with more than 24): one block per
+ * pivot with `waves` wave64s, each owning `maps_per_wave` maps; compiled shapes are (4, 16),
+ * (2, 32), (2, 16) and (4, 32).  A fixed shape also selects the MFMA kernel for any count
+ * above 4 maps.  (0, 0), the default, lets the library time every compiled shape on a
+ * 4096-pivot sample of the first eager call for each (m_max, prec) and keep the fastest for
+ * this index.  Every shape gives bit-identical results.  Attaching new values
+ * (z3_index_set_values) forgets the tuned shapes.  Z3_ERR_INVALID_ARG for a shape that is
+ * not compiled.
  */
 z3_status z3_index_set_batch_shape(z3_index idx, int waves, int maps_per_wave);
 
@@ -333,15 +335,15 @@ z3_status z3_estimate_cross_catalogues(z3_index idx_b, int map_b, z3_index idx_c
  * bearing and cos/sin(m phi) are computed once and applied to the values of all maps.
  * zeta [nmaps][m_max+1][nbins][nbins][2] += (unnormalised, one block per map, in map
  * order); pair_total += the number of pairs (counted once, not per map), or NULL.
- * Up to 4 maps: one-map passes for 1 or 2 maps, otherwise the
- * register-tiled kernel, FP64 multipole sums.  More maps: the per-pair
- * harmonics of a group of 64 x (waves per block) candidates form the B operand of MFMA
- * products with the maps' values (block shape: see z3_index_set_batch_shape); FP64 path
- * in FP64 MFMA, mixed path in FP32 MFMA with the FP32 sums added into FP64 every 128
- * candidates.  `prec` also selects the FP64 or the mixed (FP32 storage, split FP32 MFMA)
- * contraction.
- * Synchronous on `stream` the first time an (m_max, prec) is used with more than 4
- * maps and an automatic shape (the shapes are timed then), unless the stream is capturing.
+ * One-map passes for 1 or 2 maps; up to 24 maps on the FP64 path and 16 on the mixed
+ * path, one pass of the register-tiled kernel per group of 4 maps (3 or 4 maps per lane,
+ * FP64 multipole sums).  More maps, or more than 4 maps with a block shape fixed by
+ * z3_index_set_batch_shape: the per-pair harmonics of a group of 64 x (waves per block)
+ * candidates form the B operand of MFMA products with the maps' values; FP64 path in FP64
+ * MFMA, mixed path in FP32 MFMA with the FP32 sums added into FP64 every 128 candidates.
+ * `prec` also selects the FP64 or the mixed (FP32 storage, split FP32 MFMA) contraction.
+ * Synchronous on `stream` the first time an (m_max, prec) uses the MFMA kernel with an
+ * automatic shape (the shapes are timed then), unless the stream is capturing.
  */
 z3_status z3_estimate_maps(z3_index idx, int m_max, int prec, int64_t p0, int64_t p1,
                            double *zeta, uint64_t *pair_total, void *stream);

@@ -490,16 +490,17 @@ z3_status adjoint_impl(z3_index idx, int map, int m_max, int64_t p0, int64_t p1,
     return st;
 }
 
-// All attached maps.  Up to kMapGroup maps: their multipoles are recomputed together by the
-// register-tiled many-map kernel; more maps: by the MFMA many-map kernel, all maps of a pivot
-// chunk at once.  Then one prep and one scatter launch cover every map of the pass.
+// All attached maps.  Their multipoles are recomputed group by group (kMapGroup maps) by the
+// register-tiled many-map kernel, or, for many maps (many_maps_on_mfma), by the MFMA
+// many-map kernel, all maps of a pivot chunk at once.  Then one prep and one scatter launch
+// cover every map of the pass.
 // `budget` is the pivot count whose single-map FP64 multipoles fill the workspace budget.
 z3_status adjoint_maps_impl(z3_index idx, int m_max, int64_t p0, int64_t p1, const double *G, double scale,
                             double *grad_x, hipStream_t s, int64_t budget)
 {
     ProfileMute mute;  // the recomputed multipoles are not forward launches
     const int nb = idx->nbins;
-    const bool batch = idx->nmaps > kMapGroup;
+    const bool batch = many_maps_on_mfma(idx, Z3_PREC_FP64);  // the recompute runs in FP64
     int shape = 0;
     z3_status st = Z3_OK;
     if (batch && (st = batch_shape(idx, m_max, Z3_PREC_FP64, p0, p1, s, &shape)) != Z3_OK) return st;

@@ -956,7 +956,7 @@ Z3_API z3_status z3_estimate_maps(z3_index idx, int m_max, int prec, int64_t p0,
             st = z3_estimate(idx, k, m_max, prec, p0, p1, zeta + k * zstride, k == 0 ? pair_total : nullptr, stream);
         return st;
     }
-    if (idx->nmaps > kMapGroup) {
+    if (many_maps_on_mfma(idx, prec)) {
         // MFMA many-map kernel: all maps of a pivot chunk in one launch, then one
         // contraction launch for all maps
         int shape = 0;

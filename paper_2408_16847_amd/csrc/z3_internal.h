@@ -167,6 +167,19 @@ z3_status batch_shape(z3_index idx, int m_max, int prec, int64_t p0, int64_t p1,
 z3_status launch_multipoles_batch(const z3_index_s *idx, int m_max, int prec, int shape, int64_t p0, int64_t p1,
                                   void *stage, void *A, int64_t ldA, size_t map_stride, double *W,
                                   uint64_t *pair_total, hipStream_t s);
+// Many maps over one set of positions: the MFMA kernel (one block per pivot, every map at
+// once) or passes of the register-tiled kernel over the groups of kMapGroup maps.  Measured on
+// the Nside 512 map at m_max = 10, one MFMA pass costs about the same for 5 to 16 maps (1.05-
+// 1.10 s FP64, 0.69-0.72 s mixed; 1.83 / 1.15 s at 64 maps) and one group pass 0.145 / 0.138 s,
+// so the groups are faster up to ~28 (FP64) and ~20 (mixed) maps.  A block shape fixed by the
+// caller (z3_index_set_batch_shape) selects the MFMA kernel for more than kMapGroup maps.
+inline bool many_maps_on_mfma(const z3_index_s *idx, int prec)
+{
+    if (idx->nmaps <= kMapGroup) return false;
+    if (idx->batch_shape_forced >= 0) return true;
+    return idx->nmaps > (prec == Z3_PREC_FP64 ? 24 : 16);
+}
+
 // Multipoles of the maps of attached group `group` (kMapGroup maps, map_stride elements apart
 // in A); only the first `nslots` (1..kMapGroup) are guaranteed written.
 z3_status launch_multipoles_maps(const z3_index_s *idx, int group, int nslots, int m_max, int prec, int64_t p0,

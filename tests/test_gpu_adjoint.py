@@ -91,12 +91,12 @@ def test_autograd_quadratic_loss_batch_of_maps():
         assert np.abs(gx[s] - go).max() <= 1e-10 * np.abs(go).max()
 
 
-@pytest.mark.parametrize("nmaps", [3, 6])
-def test_adjoint_maps_matches_per_map_adjoint(monkeypatch, nmaps):
+@pytest.mark.parametrize("nmaps,shape", [(3, None), (6, None), (6, (4, 16))])
+def test_adjoint_maps_matches_per_map_adjoint(monkeypatch, nmaps, shape):
     """z3_adjoint_maps (multipoles of several maps recomputed together: the register-tiled
-    kernel for 3 maps, the MFMA kernel for 6; several pivot chunks, a pivot sub-range)
-    against z3_adjoint map by map."""
-    G.say("case: adjoint_maps vs per-map adjoint", nmaps)
+    kernel group by group, or the MFMA kernel when a block shape is fixed; several pivot
+    chunks, a pivot sub-range) against z3_adjoint map by map."""
+    G.say("case: adjoint_maps vs per-map adjoint", nmaps, shape)
     monkeypatch.setenv("Z3_WORKSPACE_MB", "1")
     xyz, w, _ = pins.random_cap(3000, 5.0, 17)
     E = pins.small_edges(6, lo=0.1, hi=2.5, log=True)
@@ -104,6 +104,8 @@ def test_adjoint_maps_matches_per_map_adjoint(monkeypatch, nmaps):
     rng = np.random.default_rng(4)
     xs = rng.normal(size=(nmaps, xyz.shape[1]))
     idx = G.build(xyz, xs, E, w=w)
+    if shape:
+        idx.set_batch_shape(*shape)
     Gs = torch.stack([_G_tensor(_rand_G(20 + k, M, 6)) for k in range(nmaps)])
     p0, p1 = 37, 2811
     got = z3.adjoint_maps(idx, Gs, 0.5, M, p0=p0, p1=p1).cpu().numpy()

@@ -98,12 +98,13 @@ def test_batch_autotune_picks_a_shape(weighted_cap64):
     idx.free()
 
 
-@pytest.mark.parametrize("nmaps", [2, 3, 4, 20])
+@pytest.mark.parametrize("nmaps", [2, 3, 4, 20, 40])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_many_maps_match_one_map_kernel(nmaps, prec):
     """HEALPix Nside 64 (full sky: poles, wrap-around, full bands), maps against the FP64
-    one-map kernel; 2 maps (and 3 on the mixed path) run one-map passes, 3-4 maps the
-    register-tiled kernel, 20 the MFMA kernel."""
+    one-map kernel; 2 maps run one-map passes, 3-4 maps the register-tiled kernel, 20 maps
+    that kernel group by group on the FP64 path and the MFMA kernel on the mixed path, 40
+    maps the MFMA kernel."""
     G.say("case: many maps vs one-map kernel", nmaps, prec)
     xyz_t = ring_centres(64)
     cfg = CONFIGS["nside512"]
@@ -126,12 +127,14 @@ def test_many_maps_match_one_map_kernel(nmaps, prec):
 
 @pytest.mark.parametrize("M", [0, 1, 7, 8, 15, 16])
 def test_batch_harmonic_column_tiles(M):
-    """m_max at the edges of the 16-column MFMA tiles (2M+1 = 1, 3, 15, 17, 31, 33 columns)."""
+    """m_max at the edges of the 16-column MFMA tiles (2M+1 = 1, 3, 15, 17, 31, 33 columns);
+    five maps, the MFMA kernel selected by a fixed block shape."""
     G.say("case: batch column tiles, M =", M)
     xyz, w, _ = pins.random_cap(1200, 3.0, 5)
     xs = _lognormal_maps(xyz, 5)
     E = pins.small_edges(4, lo=0.1, hi=1.5, log=False)
     idx = G.build(xyz, xs, E, w=w)
+    idx.set_batch_shape(4, 16)
     for prec, tol in (("fp64", 1e-10), ("mixed", 1e-6)):
         zs, pairs = z3.estimate_maps(idx, M, prec=prec)
         for s in (0, 4):
@@ -163,17 +166,20 @@ def test_batch_pivot_subranges_compose(weighted_cap64):
 
 
 @pytest.mark.parametrize("nb,M", [(20, 10), (25, 8)])
-@pytest.mark.parametrize("nmaps", [1, 3, 6])
-def test_contraction_unit_budgets(nb, M, nmaps):
+@pytest.mark.parametrize("nmaps,shape", [(1, None), (3, None), (6, None), (6, (2, 16))])
+def test_contraction_unit_budgets(nb, M, nmaps, shape):
     """The contraction at both sides of its register budget: 20 bins with m <= 10 (66
     (m, tile pair) units, the LDS-staged kernel at 9 units per wave) and 25 bins with m <= 8
     (90 units, beyond it: the tile-pair kernel, after a transpose on the many-map path), for
-    the one-map, register-tiled (3 maps) and MFMA (6 maps) multipole kernels."""
-    G.say("case: contraction units, nb", nb, "M", M, "maps", nmaps)
+    the one-map kernel, the register-tiled kernel (3 maps; 6 maps in two groups) and the MFMA
+    kernel (6 maps with a fixed block shape)."""
+    G.say("case: contraction units, nb", nb, "M", M, "maps", nmaps, "shape", shape)
     xyz, w, _ = pins.random_cap(1500, 4.0, 11)
     xs = _lognormal_maps(xyz, nmaps)
     E = pins.small_edges(nb, lo=0.05, hi=2.0, log=True)
     idx = G.build(xyz, xs if nmaps > 1 else xs[0], E, w=w)
+    if shape:
+        idx.set_batch_shape(*shape)
     for prec, tol in (("fp64", 1e-10), ("mixed", 1e-6)):
         zs, pairs = z3.estimate_maps(idx, M, prec=prec)
         for s in sorted({0, nmaps - 1}):

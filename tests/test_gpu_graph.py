@@ -62,15 +62,20 @@ def test_autograd_forward_is_estimate_then_finalize(nmaps, prec):
     idx.free()
 
 
-@pytest.mark.parametrize("nmaps,prec", [(6, "mixed"), (6, "fp64"), (3, "mixed"), (1, "mixed")])
-def test_graph_replays_match_eager(nmaps, prec):
-    G.say("case: graph step", nmaps, prec)
+@pytest.mark.parametrize("nmaps,prec,shape", [(6, "mixed", (2, 16)), (6, "fp64", (2, 16)), (6, "mixed", None),
+                                              (3, "mixed", None), (1, "mixed", None)])
+def test_graph_replays_match_eager(nmaps, prec, shape):
+    # six maps: the MFMA kernel (fixed block shape) or the register-tiled kernel in two groups
+    G.say("case: graph step", nmaps, prec, shape)
     xyz, w, _ = pins.random_cap(3000, 5.0, 31)
     E = pins.small_edges(5, lo=0.1, hi=2.0, log=True)
     M = 6
     x0 = _maps(xyz, nmaps, 100)
     idx = G.build(xyz, x0.numpy(), E, w=w)
     ref_idx = G.build(xyz, x0.numpy(), E, w=w)
+    if shape:
+        idx.set_batch_shape(*shape)
+        ref_idx.set_batch_shape(*shape)
     t = torch.from_numpy(np.random.default_rng(5).normal(size=(nmaps, M + 1, 5, 5, 2))).cuda() * 1e-3
     step = z3.GraphStep(idx, M, t, prec=prec)
     for r in range(3):
