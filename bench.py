@@ -129,6 +129,8 @@ def main():
     ap.add_argument("--nside", type=int, default=0,
                     help="run the chosen HEALPix workload's recipe (field, bins, m) at this resolution instead")
     ap.add_argument("--m-max", type=int, default=-1, help="override the workload's largest multipole")
+    ap.add_argument("--maps", type=int, default=0,
+                    help="override the workload's number of maps (HEALPix and cap workloads)")
     ap.add_argument("--shard", default="",
                     help="I/N: time one GPU's share of an N-GPU run, index-order pivots [I n/N, (I+1) n/N) "
                          "against the whole neighbour catalogue (one-map exact search)")
@@ -199,6 +201,10 @@ def main():
         cfg = dataclasses.replace(cfg, n_or_nside=args.nside, name=f"{cfg.name}@nside{args.nside}")
     if args.m_max >= 0:
         cfg = dataclasses.replace(cfg, m_max=args.m_max, name=f"{cfg.name}@m{args.m_max}")
+    if args.maps > 0:
+        if cfg.kind == "plane":
+            sys.exit("--maps needs a sky workload")
+        cfg = dataclasses.replace(cfg, nmaps=args.maps, name=f"{cfg.name}@maps{args.maps}")
     if cfg.kind == "plane" and (args.approx or args.adjoint or args.cross or args.graph):
         print("the plane workload runs the one-map estimator only", file=sys.stderr)
         sys.exit(2)
@@ -377,8 +383,9 @@ def main():
         log(f"[bench] adjoint: max |dL/dx| {max(grads):.3g}")
     launches_per_step = r["kernel_launches"] / args.steps
     kern_s_per_step = r["kernel_ms_total"] / args.steps / 1e3
-    if cfg.nmaps > 4:
-        # MFMA many-map kernel: one FMA per (pair, map, harmonic column) is the useful work
+    if cfg.nmaps > (56 if main_prec == "fp64" else 24):
+        # MFMA many-map kernel (the library's choice above 56 maps on the FP64 path and 24 on
+        # the mixed one): one FMA per (pair, map, harmonic column) is the useful work
         rf_kernel, rf_bound, rf_peak = "k_multipoles_batch", "mfma", PEAK_MFMA_TFLOPS[main_prec]
         rf_flops = 2.0 * (2 * M + 1) * r["pairs"] * cfg.nmaps
         rf_unit_note = "2 (2 m_max + 1) flop per (pair, map)"
@@ -390,7 +397,10 @@ def main():
         rf_flops = 27.0 * r["pairs"] + 3.0 * n * cfg.nbins * args.hist * (M + 1)
         rf_unit_note = "27 flop per pair + 3 flop per (pivot, radial bin, angular bin, m)"
     else:
-        rf_kernel, rf_bound, rf_peak = "k_multipoles", "alu", PEAK_VALU_TFLOPS[main_prec]
+        # one-map kernel, or the register-tiled kernel over groups of maps (three fields, or
+        # 3 to 56 / 24 maps), whose pair geometry is shared by the maps of a lane
+        rf_kernel = "k_multipoles_maps" if (args.cross or cfg.nmaps > 2) else "k_multipoles"
+        rf_bound, rf_peak = "alu", PEAK_VALU_TFLOPS[main_prec]
         rf_flops = FLOPS_PER_UPDATE * updates
         rf_unit_note = f"{FLOPS_PER_UPDATE} flop per pair-multipole update"
     achieved = rf_flops / kern_s_per_step / 1e12 if kern_s_per_step > 0 else None

@@ -149,8 +149,8 @@ z3_status z3_index_info(z3_index idx, int64_t *n, int *nbins, int *nmaps, int *n
 z3_status z3_index_perm(z3_index idx, int64_t *perm, void *stream);
 
 /*
- * Block shape of the MFMA many-map kernel (z3_estimate_maps with more than 24 maps on the
- * FP64 path or 16 on the mixed path, z3_adjoint_maps with more than 24): one block per
+ * Block shape of the MFMA many-map kernel (z3_estimate_maps with more than 56 maps on the
+ * FP64 path or 24 on the mixed path, z3_adjoint_maps with more than 56): one block per
  * pivot with `waves` wave64s, each owning `maps_per_wave` maps; compiled shapes are (4, 16),
  * (2, 32), (2, 16) and (4, 32).  A fixed shape also selects the MFMA kernel for any count
  * above 4 maps.  (0, 0), the default, lets the library time every compiled shape on a
@@ -335,7 +335,7 @@ z3_status z3_estimate_cross_catalogues(z3_index idx_b, int map_b, z3_index idx_c
  * bearing and cos/sin(m phi) are computed once and applied to the values of all maps.
  * zeta [nmaps][m_max+1][nbins][nbins][2] += (unnormalised, one block per map, in map
  * order); pair_total += the number of pairs (counted once, not per map), or NULL.
- * One-map passes for 1 or 2 maps; up to 24 maps on the FP64 path and 16 on the mixed
+ * One-map passes for 1 or 2 maps; up to 56 maps on the FP64 path and 24 on the mixed
  * path, one pass of the register-tiled kernel per group of 4 maps (3 or 4 maps per lane,
  * FP64 multipole sums).  More maps, or more than 4 maps with a block shape fixed by
  * z3_index_set_batch_shape: the per-pair harmonics of a group of 64 x (waves per block)

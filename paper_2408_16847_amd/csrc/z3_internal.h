@@ -169,15 +169,17 @@ z3_status launch_multipoles_batch(const z3_index_s *idx, int m_max, int prec, in
                                   uint64_t *pair_total, hipStream_t s);
 // Many maps over one set of positions: the MFMA kernel (one block per pivot, every map at
 // once) or passes of the register-tiled kernel over the groups of kMapGroup maps.  Measured on
-// the Nside 512 map at m_max = 10, one MFMA pass costs about the same for 5 to 16 maps (1.05-
-// 1.10 s FP64, 0.69-0.72 s mixed; 1.83 / 1.15 s at 64 maps) and one group pass 0.145 / 0.138 s,
-// so the groups are faster up to ~28 (FP64) and ~20 (mixed) maps.  A block shape fixed by the
-// caller (z3_index_set_batch_shape) selects the MFMA kernel for more than kMapGroup maps.
+// the Nside 512 map at m_max = 10 (estimator step, multipoles and contraction): a group pass
+// costs ~0.148 s (FP64) / ~0.14 s (mixed), so n maps take ~37 / ~35 ms per map; the MFMA
+// kernel takes 1.05-1.10 / 0.69-0.72 s for 5 to 16 maps, 1.39 / 0.89 s for 32, 2.06 / 1.33 s
+// for 48 and 2.15 / 1.37 s for 64.  The groups are therefore faster up to ~56 maps on the
+// FP64 path and ~24 on the mixed one.  A block shape fixed by the caller
+// (z3_index_set_batch_shape) selects the MFMA kernel for more than kMapGroup maps.
 inline bool many_maps_on_mfma(const z3_index_s *idx, int prec)
 {
     if (idx->nmaps <= kMapGroup) return false;
     if (idx->batch_shape_forced >= 0) return true;
-    return idx->nmaps > (prec == Z3_PREC_FP64 ? 24 : 16);
+    return idx->nmaps > (prec == Z3_PREC_FP64 ? 56 : 24);
 }
 
 // Multipoles of the maps of attached group `group` (kMapGroup maps, map_stride elements apart

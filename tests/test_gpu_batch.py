@@ -81,7 +81,7 @@ def test_batch_tiles_identical_and_match_oracle(weighted_cap64, field, prec, tol
 def test_batch_autotune_picks_a_shape(weighted_cap64):
     G.say("case: batch autotune")
     xyz, w, xs, E = weighted_cap64
-    idx = G.build(xyz, xs[:48], E, w=w)
+    idx = G.build(xyz, xs, E, w=w)  # 64 maps: the MFMA kernel on both paths
     assert idx.batch_shape(6, "fp64") == (0, 0)
     a, pa = _raw(idx, 6, "fp64")
     t = idx.batch_shape(6, "fp64")
@@ -98,13 +98,13 @@ def test_batch_autotune_picks_a_shape(weighted_cap64):
     idx.free()
 
 
-@pytest.mark.parametrize("nmaps", [2, 3, 4, 20, 40])
+@pytest.mark.parametrize("nmaps", [2, 3, 4, 20, 32, 60])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_many_maps_match_one_map_kernel(nmaps, prec):
     """HEALPix Nside 64 (full sky: poles, wrap-around, full bands), maps against the FP64
     one-map kernel; 2 maps run one-map passes, 3-4 maps the register-tiled kernel, 20 maps
-    that kernel group by group on the FP64 path and the MFMA kernel on the mixed path, 40
-    maps the MFMA kernel."""
+    that kernel group by group, 32 maps the groups on the FP64 path and the MFMA kernel on the
+    mixed one, 60 maps the MFMA kernel."""
     G.say("case: many maps vs one-map kernel", nmaps, prec)
     xyz_t = ring_centres(64)
     cfg = CONFIGS["nside512"]
