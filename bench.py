@@ -131,6 +131,9 @@ def main():
     ap.add_argument("--m-max", type=int, default=-1, help="override the workload's largest multipole")
     ap.add_argument("--maps", type=int, default=0,
                     help="override the workload's number of maps (HEALPix and cap workloads)")
+    ap.add_argument("--batch-shape", default="",
+                    help="W,T: fix the MFMA many-map kernel's block shape (waves, maps per wave), "
+                         "which also selects that kernel for any count above 4 maps")
     ap.add_argument("--shard", default="",
                     help="I/N: time one GPU's share of an N-GPU run, index-order pivots [I n/N, (I+1) n/N) "
                          "against the whole neighbour catalogue (one-map exact search)")
@@ -276,10 +279,17 @@ def main():
     graphs = {}
     last = {}
 
+    shape = tuple(int(v) for v in args.batch_shape.split(",")) if args.batch_shape else None
+
+    def fix_shape(idx):
+        if shape:
+            idx.set_batch_shape(*shape)
+
     def graph_step(prec):
         # index and captured graph built once per precision (outside the timed steps)
         if prec not in graphs:
             idx = z3.Index(xyz, E)
+            fix_shape(idx)
             idx.set_values(x)
             z0 = z3.estimate_maps_raw(idx, M, prec) if cfg.nmaps > 1 else z3.estimate_raw(idx, M, prec).unsqueeze(0)
             sw = torch.zeros(1, dtype=torch.float64, device="cuda")
@@ -304,6 +314,7 @@ def main():
         sw = torch.zeros(1, dtype=torch.float64, device="cuda")
         if args.adjoint:
             idx = z3.Index(xyz, E)
+            fix_shape(idx)
             xg = x.clone().requires_grad_(True)
             zt = z3.Zeta3Fn.apply(xg, idx, M, prec)
             loss = ((zt - targets(zt)) ** 2).sum()
@@ -317,6 +328,7 @@ def main():
         if cfg.nmaps > 1:
             zeta = torch.zeros((cfg.nmaps, M + 1, cfg.nbins, cfg.nbins, 2), dtype=torch.float64, device="cuda")
             idx = z3.Index(xyz, E)
+            fix_shape(idx)
             idx.set_values(x)
             z3.estimate_maps_raw(idx, M, prec=prec, zeta=zeta, pair_total=pairs, sum_w=sw)
         elif x3 is not None:
@@ -383,9 +395,10 @@ def main():
         log(f"[bench] adjoint: max |dL/dx| {max(grads):.3g}")
     launches_per_step = r["kernel_launches"] / args.steps
     kern_s_per_step = r["kernel_ms_total"] / args.steps / 1e3
-    if cfg.nmaps > (56 if main_prec == "fp64" else 24):
+    if cfg.nmaps > 4 and (shape or cfg.nmaps > (56 if main_prec == "fp64" else 24)):
         # MFMA many-map kernel (the library's choice above 56 maps on the FP64 path and 24 on
-        # the mixed one): one FMA per (pair, map, harmonic column) is the useful work
+        # the mixed one, or with a fixed block shape): one FMA per (pair, map, harmonic
+        # column) is the useful work
         rf_kernel, rf_bound, rf_peak = "k_multipoles_batch", "mfma", PEAK_MFMA_TFLOPS[main_prec]
         rf_flops = 2.0 * (2 * M + 1) * r["pairs"] * cfg.nmaps
         rf_unit_note = "2 (2 m_max + 1) flop per (pair, map)"
