@@ -337,7 +337,7 @@ z3_status z3_estimate_cross_catalogues(z3_index idx_b, int map_b, z3_index idx_c
  * order); pair_total += the number of pairs (counted once, not per map), or NULL.
  * One-map passes for 1 or 2 maps; up to 56 maps on the FP64 path and 24 on the mixed
  * path, one pass of the register-tiled kernel per group of 4 maps (3 or 4 maps per lane,
- * FP64 multipole sums).  More maps, or more than 4 maps with a block shape fixed by
+ * FP64 multipole sums), one or two maps left over in one-map passes.  More maps, or more than 4 maps with a block shape fixed by
  * z3_index_set_batch_shape: the per-pair harmonics of a group of 64 x (waves per block)
  * candidates form the B operand of MFMA products with the maps' values; FP64 path in FP64
  * MFMA, mixed path in FP32 MFMA with the FP32 sums added into FP64 every 128 candidates.
