@@ -517,7 +517,10 @@ z3_status adjoint_maps_impl(z3_index idx, int m_max, int64_t p0, int64_t p1, con
     if (st == Z3_OK) st = scratch_alloc(&ww, (size_t)chunk * nb * sizeof(double), s);
     if (st == Z3_OK) st = scratch_alloc(&wg, (size_t)idx->nmaps * idx->n * sizeof(double), s);
     if (st == Z3_OK) st = launch_fill(static_cast<double *>(wg), (int64_t)idx->nmaps * idx->n, 0.0, s);
-    const int ngroups = batch ? 1 : idx->ngroups;
+    // one or two maps left over after the full groups run one-map adjoints (cheaper than a
+    // group pass), once the groups' workspace is released
+    const int rest = batch ? 0 : (idx->nmaps % kMapGroup <= 2 ? idx->nmaps % kMapGroup : 0);
+    const int ngroups = batch ? 1 : (idx->nmaps - rest + kMapGroup - 1) / kMapGroup;
     for (int g = 0; g < ngroups && st == Z3_OK; ++g) {
         const int map0 = g * kMapGroup;
         const int nm = batch ? idx->nmaps : (idx->nmaps - map0 < kMapGroup ? idx->nmaps - map0 : kMapGroup);
@@ -538,12 +541,14 @@ z3_status adjoint_maps_impl(z3_index idx, int m_max, int64_t p0, int64_t p1, con
                                         s);
         }
     }
-    for (int map = 0; map < idx->nmaps && st == Z3_OK; ++map)
+    for (int map = 0; map < idx->nmaps - rest && st == Z3_OK; ++map)
         st = grad_to_catalogue(idx, static_cast<double *>(wg) + (size_t)map * idx->n, grad_x + (size_t)map * idx->n, s);
     scratch_free(wg, s);
     scratch_free(ww, s);
     scratch_free(wd, s);
     scratch_free(wa, s);
+    for (int k = idx->nmaps - rest; k < idx->nmaps && st == Z3_OK; ++k)
+        st = ::z3_adjoint(idx, k, m_max, p0, p1, G + k * gstride, scale, grad_x + (size_t)k * idx->n, s);
     return st;
 }
 
