@@ -352,9 +352,12 @@ z3_status z3_estimate_maps(z3_index idx, int m_max, int prec, int64_t p0, int64_
  * Fused estimator for an external pivot catalogue against the index's neighbours (the
  * pivot field of the cross-correlation remark in the harmonic-decomposition section;
  * also the approximate search, whose neighbour catalogue is a coarsened map):
- *   piv_xyz  [3][npiv] FP64 positions ([2][npiv] positions for a planar index) in the
- *            caller's order (a spatially coherent order, such as HEALPix RING, keeps
- *            neighbouring pivots in one wave).  Normally unit vectors; a pivot of another
+ *   piv_xyz  [3][npiv] FP64 positions ([2][npiv] positions for a planar index) in any
+ *            order: each pivot chunk is sorted by the index's bands (a stable radix sort,
+ *            256 cells per band) before its multipoles are formed, so an unordered
+ *            catalogue runs as fast as a coherent one and repeated calls give identical
+ *            results; only the order of the FP64 sum over pivots depends on the order
+ *            given.  Normally unit vectors; a pivot of another
  *            length keeps the chord test on the raw vectors (its windows are rescaled),
  *            so pair lists match a direct evaluation of d2 on the same vectors
  *   piv_w    [npiv] pivot weights, or NULL for all 1

@@ -257,6 +257,32 @@ def test_external_pivots_subset_and_cross_catalogue(cap):
     assert G.err_m(z, zo).max() < 1e-10
 
 
+def test_external_pivots_in_any_order(cap):
+    """External pivots are sorted by the index's bands inside the library: a random order gives
+    the pair count of the given order and zeta to rounding of the FP64 sum over pivots, on
+    both precision paths, and a repeated call gives identical bits."""
+    cfg, xyz, x = cap
+    G.say("case: external pivots in a random order")
+    E = cfg.edges_chord2()
+    idx = G.build(xyz, x, E)
+    sel = np.arange(2000, 12000)
+    order = np.random.default_rng(12).permutation(len(sel))
+    pw = np.random.default_rng(13).uniform(0.5, 2.0, len(sel))
+    for prec, tol in (("fp64", 1e-12), ("mixed", 1e-6)):
+        runs = []
+        for o in (np.arange(len(sel)), order, order):
+            pxyz = torch.from_numpy(np.ascontiguousarray(xyz[:, sel[o]])).cuda()
+            runs.append(z3.estimate_pivots(idx, pxyz, torch.from_numpy(x[sel[o]]).cuda(),
+                                           torch.from_numpy(pw[o]).cuda(), m_max=cfg.m_max, prec=prec))
+        (za, pa), (zb, pb), (zc, pc) = runs
+        assert pa == pb == pc
+        e = G.err_m(zb, za)
+        G.say("err_m random vs given order", prec, e.max())
+        assert e.max() < tol
+        assert np.array_equal(zb, zc)
+    idx.free()
+
+
 def test_position_lengths(cap):
     """Index positions must be unit vectors to 1e-10 (Z3_ERR_INVALID_ARG otherwise); external
     pivots may have any length near 1: their windows follow the chord test on the raw
