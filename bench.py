@@ -131,6 +131,8 @@ def main():
     ap.add_argument("--m-max", type=int, default=-1, help="override the workload's largest multipole")
     ap.add_argument("--maps", type=int, default=0,
                     help="override the workload's number of maps (HEALPix and cap workloads)")
+    ap.add_argument("--pivot-order", default="ring", choices=["ring", "random"],
+                    help="approximate search: pivots in HEALPix RING order or in a seeded random order")
     ap.add_argument("--batch-shape", default="",
                     help="W,T: fix the MFMA many-map kernel's block shape (waves, maps per wave), "
                          "which also selects that kernel for any count above 4 maps")
@@ -247,6 +249,11 @@ def main():
             sys.exit("--approx needs a HEALPix workload")
         nxyz, nx_, nw = degrade_ring(cfg.n_or_nside, x)
         nbr = (nxyz, nx_, nw)
+        if args.pivot_order == "random":
+            # the library sorts each pivot chunk by the index's bands; this order tests that
+            perm = torch.randperm(xyz.shape[1], generator=torch.Generator().manual_seed(11)).to(xyz.device)
+            xyz, x = xyz[:, perm].contiguous(), x[perm].contiguous()
+            del perm
     torch.cuda.synchronize()
     log(f"[bench] inputs {cfg.name}{' approx' if nbr else ''}: n={xyz.shape[1]} generated in "
         f"{time.time() - t0:.1f}s; delta min {float(x.min()):.3g} max {float(x.max()):.3g}")
@@ -431,6 +438,7 @@ def main():
         "dtype": "f64" if main_prec == "fp64" else "f64 multipoles, f32 storage + split-f32 MFMA",
         "data": "synthetic",
         "config": {"workload": cfg.name + ("+approx" if nbr else "") + ("+adjoint" if args.adjoint else "")
+                   + ("+random-order" if nbr and args.pivot_order == "random" else "")
                    + (f"+hist{args.hist}" if args.hist else "")
                    + ("+noself" if not self_pairs else "") + ("+cross3" if args.cross else "")
                    + (f"+shard{shard[0]}of{shard[1]}" if shard else ""),

@@ -906,23 +906,25 @@ Z3_API z3_status z3_estimate_cross_catalogues(z3_index idx_b, int map_b, z3_inde
     const size_t elem = prec == Z3_PREC_FP64 ? 8 : 4;
     const size_t slot_bytes = (size_t)chunk * (size_t)(m_max + 1) * 2 * nb * elem;
     const size_t pbytes = cross_partial_bytes(chunk, m_max, nb);
-    void *wa = nullptr, *wp = nullptr, *wv = nullptr, *wz = nullptr, *wg = nullptr;
+    void *wa = nullptr, *wp = nullptr, *wz = nullptr, *wg = nullptr;
     if ((st = scratch_alloc(&wa, 2 * slot_bytes, s)) != Z3_OK) return st;
-    if ((st = scratch_alloc(&wp, pbytes, s)) == Z3_OK) st = scratch_alloc(&wv, (size_t)chunk * sizeof(double), s);
+    st = scratch_alloc(&wp, pbytes, s);
     // plane: pivots are [2][npiv] (x, y); a zero row stands for z
     if (st == Z3_OK && idx_b->planar) st = scratch_alloc(&wz, (size_t)npiv * sizeof(double), s);
     if (st == Z3_OK && idx_b->planar) st = launch_fill(static_cast<double *>(wz), npiv, 0.0, s);
-    // each chunk's pivots and values, gathered in catalogue B's band order
-    if (st == Z3_OK) st = scratch_alloc(&wg, (size_t)4 * chunk * sizeof(double), s);
+    // the pivots in catalogue B's band order (one sort), each chunk's gathered in that order
     const Pivots piv{piv_xyz, piv_xyz + npiv,
                      idx_b->planar ? static_cast<const double *>(wz) : piv_xyz + 2 * npiv};
+    void *wperm = nullptr;
+    if (st == Z3_OK) st = scratch_alloc(&wg, (size_t)4 * chunk * sizeof(double), s);
+    if (st == Z3_OK) st = scratch_alloc(&wperm, (size_t)(p1 - p0) * sizeof(int), s);
+    if (st == Z3_OK) st = sort_pivots(idx_b, piv, p0, p1 - p0, static_cast<int *>(wperm), s);
     double *gx = static_cast<double *>(wg), *gy = gx + chunk, *gz = gy + chunk, *gv = gz + chunk;
     for (int64_t c0 = p0; c0 < p1 && st == Z3_OK; c0 += chunk) {
         const int64_t c1 = c0 + chunk < p1 ? c0 + chunk : p1;
         const int64_t len = c1 - c0;
-        st = launch_pivot_values(piv_w ? piv_w + c0 : nullptr, piv_x + c0, len, static_cast<double *>(wv), s);
-        if (st == Z3_OK)
-            st = sort_pivot_chunk(idx_b, piv, c0, len, static_cast<const double *>(wv), gx, gy, gz, gv, s);
+        st = gather_pivots(static_cast<const int *>(wperm) + (c0 - p0), len, piv, p0, piv_w, piv_x, gx, gy, gz, gv,
+                           s);
         const Pivots sorted{gx, gy, gz};
         if (st == Z3_OK)
             st = launch_multipoles(idx_b, sorted, map_b, m_max, prec, Z3_NORM_BIN, 0, len, wa, len, nullptr, nullptr,
@@ -934,9 +936,9 @@ Z3_API z3_status z3_estimate_cross_catalogues(z3_index idx_b, int map_b, z3_inde
             st = launch_contract_cross(len, m_max, nb, prec, wa, static_cast<char *>(wa) + slot_bytes, len, gv, zeta,
                                        wp, pbytes, s);
     }
+    scratch_free(wperm, s);
     scratch_free(wg, s);
     scratch_free(wz, s);
-    scratch_free(wv, s);
     scratch_free(wp, s);
     scratch_free(wa, s);
     return st;
@@ -1073,31 +1075,34 @@ Z3_API z3_status z3_estimate_pivots(z3_index idx, int map, int64_t npiv, const d
     size_t elem = prec == Z3_PREC_FP64 ? 8 : 4;
     size_t abytes = (size_t)chunk * (size_t)(m_max + 1) * 2 * idx->nbins * elem;
     size_t pbytes = contract_partial_bytes(chunk, m_max, idx->nbins);
-    void *wa = nullptr, *wp = nullptr, *wv = nullptr, *wz = nullptr, *wg = nullptr;
+    void *wa = nullptr, *wp = nullptr, *wz = nullptr, *wg = nullptr;
     if ((st = scratch_alloc(&wa, abytes, s)) != Z3_OK) return st;
-    if ((st = scratch_alloc(&wp, pbytes, s)) == Z3_OK) st = scratch_alloc(&wv, (size_t)chunk * sizeof(double), s);
+    st = scratch_alloc(&wp, pbytes, s);
     // plane: pivots are [2][npiv] (x, y); a zero row stands for z
     if (st == Z3_OK && idx->planar) st = scratch_alloc(&wz, (size_t)npiv * sizeof(double), s);
     if (st == Z3_OK && idx->planar) st = launch_fill(static_cast<double *>(wz), npiv, 0.0, s);
-    // each chunk's pivots (x, y, z) and values, gathered in the index's band order
-    if (st == Z3_OK) st = scratch_alloc(&wg, (size_t)4 * chunk * sizeof(double), s);
+    // the pivots in the index's band order (one sort), each chunk's positions and values
+    // gathered in that order
     const Pivots piv{piv_xyz, piv_xyz + npiv,
                      idx->planar ? static_cast<const double *>(wz) : piv_xyz + 2 * npiv};
+    void *wperm = nullptr;
+    if (st == Z3_OK) st = scratch_alloc(&wg, (size_t)4 * chunk * sizeof(double), s);
+    if (st == Z3_OK) st = scratch_alloc(&wperm, (size_t)(p1 - p0) * sizeof(int), s);
+    if (st == Z3_OK) st = sort_pivots(idx, piv, p0, p1 - p0, static_cast<int *>(wperm), s);
     double *gx = static_cast<double *>(wg), *gy = gx + chunk, *gz = gy + chunk, *gv = gz + chunk;
     for (int64_t c0 = p0; c0 < p1 && st == Z3_OK; c0 += chunk) {
         int64_t c1 = c0 + chunk < p1 ? c0 + chunk : p1;
-        st = launch_pivot_values(piv_w ? piv_w + c0 : nullptr, piv_x + c0, c1 - c0, static_cast<double *>(wv), s);
-        if (st == Z3_OK)
-            st = sort_pivot_chunk(idx, piv, c0, c1 - c0, static_cast<const double *>(wv), gx, gy, gz, gv, s);
+        st = gather_pivots(static_cast<const int *>(wperm) + (c0 - p0), c1 - c0, piv, p0, piv_w, piv_x, gx, gy, gz,
+                           gv, s);
         if (st == Z3_OK)
             st = launch_multipoles(idx, Pivots{gx, gy, gz}, map, m_max, prec, Z3_NORM_BIN, 0, c1 - c0, wa, c1 - c0,
                                    nullptr, nullptr, nullptr, pair_total, s);
         if (st == Z3_OK)
             st = launch_contract(c1 - c0, m_max, idx->nbins, prec, wa, c1 - c0, gv, zeta, wp, pbytes, s);
     }
+    scratch_free(wperm, s);
     scratch_free(wg, s);
     scratch_free(wz, s);
-    scratch_free(wv, s);
     scratch_free(wp, s);
     scratch_free(wa, s);
     return st;

@@ -167,11 +167,12 @@ z3_status batch_shape(z3_index idx, int m_max, int prec, int64_t p0, int64_t p1,
 z3_status launch_multipoles_batch(const z3_index_s *idx, int m_max, int prec, int shape, int64_t p0, int64_t p1,
                                   void *stage, void *A, int64_t ldA, size_t map_stride, double *W,
                                   uint64_t *pair_total, hipStream_t s);
-// Pivots [c0, c0 + len) of `piv` and their values v [len] gathered into gx, gy, gz, gv [len]
-// in the index's band order (stable radix sort of a band / position-along-band key;
-// z3_pivsort.hip).
-z3_status sort_pivot_chunk(const z3_index_s *idx, Pivots piv, int64_t c0, int64_t len, const double *v,
-                           double *gx, double *gy, double *gz, double *gv, hipStream_t s);
+// External pivots in the index's band order (z3_pivsort.hip): sort_pivots writes perm [len],
+// the stable order of pivots [p0, p0 + len) by band and 256 cells per band; gather_pivots
+// copies pivots p0 + perm[i] (i < len) and their values w x (w null: x) into gx, gy, gz, gv.
+z3_status sort_pivots(const z3_index_s *idx, Pivots piv, int64_t p0, int64_t len, int *perm, hipStream_t s);
+z3_status gather_pivots(const int *perm, int64_t len, Pivots piv, int64_t p0, const double *w, const double *x,
+                        double *gx, double *gy, double *gz, double *gv, hipStream_t s);
 
 // Many maps over one set of positions: the MFMA kernel (one block per pivot, every map at
 // once) or passes of the register-tiled kernel over the groups of kMapGroup maps.  Measured on

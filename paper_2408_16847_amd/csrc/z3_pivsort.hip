@@ -5,11 +5,12 @@
 // neighbours.  A caller's catalogue in no spatial order (a galaxy survey in the order of its
 // target list, say) puts far-apart pivots in one wave: the band union then covers most of
 // the sky and every lane reads its own cache lines, about 24 times the time of the same
-// pivots in HEALPix RING order on the Nside 512 map.  Each pivot chunk is therefore sorted
-// by a key of the index's grid -- band (colatitude, or y on a plane), then one of 256 cells
-// along the band -- with a stable radix sort, which keeps the caller's order inside a cell,
-// and the chunk's positions and values are gathered in that order before the multipole and
-// contraction launches.  zeta is a sum over the pivots, so
+// pivots in HEALPix RING order on the Nside 512 map.  The call's pivots are therefore sorted
+// once by a key of the index's grid -- band (colatitude, or y on a plane), then one of 256
+// cells along the band -- with a stable radix sort, which keeps the caller's order inside a
+// cell; each pivot chunk then gathers its positions and values in that order before the
+// multipole and contraction launches (a chunk is a contiguous run of the sorted pivots, so it
+// is as dense on the sky as the catalogue).  zeta is a sum over the pivots, so
 // only the order of its FP64 additions changes; the sort is stable, so repeated calls give
 // identical results.
 #include "z3_internal.h"
@@ -46,20 +47,19 @@ __global__ void k_pivot_keys(Pivots piv, int64_t c0, int64_t len, int planar, do
     val[i] = (int)i;
 }
 
-__global__ void k_gather_pivots(const int *perm, int64_t len, Pivots piv, int64_t c0, const double *v, double *gx,
-                                double *gy, double *gz, double *gv)
+__global__ void k_gather_pivots(const int *perm, int64_t len, Pivots piv, int64_t p0, const double *w,
+                                const double *x, double *gx, double *gy, double *gz, double *gv)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= len) return;
-    const int64_t j = perm[i];
-    gx[i] = piv.x[c0 + j];
-    gy[i] = piv.y[c0 + j];
-    gz[i] = piv.z[c0 + j];
-    gv[i] = v[j];
+    const int64_t j = p0 + perm[i];
+    gx[i] = piv.x[j];
+    gy[i] = piv.y[j];
+    gz[i] = piv.z[j];
+    gv[i] = w ? w[j] * x[j] : x[j];  // v = w x, as for the index's own pivots
 }
 
-z3_status sort_pivot_chunk(const z3_index_s *idx, Pivots piv, int64_t c0, int64_t len, const double *v,
-                           double *gx, double *gy, double *gz, double *gv, hipStream_t s)
+z3_status sort_pivots(const z3_index_s *idx, Pivots piv, int64_t p0, int64_t len, int *perm, hipStream_t s)
 {
     if (len <= 0) return Z3_OK;
     int bits = 1;
@@ -70,32 +70,35 @@ z3_status sort_pivot_chunk(const z3_index_s *idx, Pivots piv, int64_t c0, int64_
     const int fb = 32 - bits < 8 ? 32 - bits : 8;
     void *wk = nullptr, *wt = nullptr;
     const size_t n = (size_t)len;
-    z3_status st = scratch_alloc(&wk, n * 4 * sizeof(uint32_t), s);
+    z3_status st = scratch_alloc(&wk, n * 3 * sizeof(uint32_t), s);
     if (st != Z3_OK) return st;
     uint32_t *k_in = static_cast<uint32_t *>(wk), *k_out = k_in + n;
-    int *v_in = reinterpret_cast<int *>(k_out + n), *v_out = v_in + n;
+    int *v_in = reinterpret_cast<int *>(k_out + n);
     size_t tbytes = 0;
-    st = check_hip(rocprim::radix_sort_pairs(nullptr, tbytes, k_in, k_out, v_in, v_out, n, 0, 32, s),
+    st = check_hip(rocprim::radix_sort_pairs(nullptr, tbytes, k_in, k_out, v_in, perm, n, 0, 32, s),
                    "pivot sort size");
     // a non-null temporary buffer: a null one only asks for its size
     if (st == Z3_OK) st = scratch_alloc(&wt, tbytes > 256 ? tbytes : 256, s);
     if (st == Z3_OK) {
-        const unsigned grid = (unsigned)((len + 255) / 256);
-        hipLaunchKernelGGL(k_pivot_keys, dim3(grid), dim3(256), 0, s, piv, c0, len, idx->planar ? 1 : 0,
-                           1.0 / idx->band_h, idx->plane_x0, idx->plane_y0, idx->plane_sx, idx->nbands, fb, k_in,
-                           v_in);
+        hipLaunchKernelGGL(k_pivot_keys, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, s, piv, p0, len,
+                           idx->planar ? 1 : 0, 1.0 / idx->band_h, idx->plane_x0, idx->plane_y0, idx->plane_sx,
+                           idx->nbands, fb, k_in, v_in);
         st = check_launch("k_pivot_keys");
     }
     if (st == Z3_OK)
-        st = check_hip(rocprim::radix_sort_pairs(wt, tbytes, k_in, k_out, v_in, v_out, n, 0, 32, s), "pivot sort");
-    if (st == Z3_OK) {
-        hipLaunchKernelGGL(k_gather_pivots, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, s, v_out, len, piv, c0,
-                           v, gx, gy, gz, gv);
-        st = check_launch("k_gather_pivots");
-    }
+        st = check_hip(rocprim::radix_sort_pairs(wt, tbytes, k_in, k_out, v_in, perm, n, 0, 32, s), "pivot sort");
     scratch_free(wt, s);
     scratch_free(wk, s);
     return st;
+}
+
+z3_status gather_pivots(const int *perm, int64_t len, Pivots piv, int64_t p0, const double *w, const double *x,
+                        double *gx, double *gy, double *gz, double *gv, hipStream_t s)
+{
+    if (len <= 0) return Z3_OK;
+    hipLaunchKernelGGL(k_gather_pivots, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, s, perm, len, piv, p0, w,
+                       x, gx, gy, gz, gv);
+    return check_launch("k_gather_pivots");
 }
 
 }  // namespace z3
