@@ -137,7 +137,9 @@ z3_status z3_index_update_values(z3_index idx, const double *x, void *stream);
  * the reservation allocates a new workspace for later captures and keeps the previous one
  * (graphs captured before still point at it) until z3_index_free.  Graphs captured on one
  * index may share a workspace: their replays must not overlap in time.
- * z3_contract and z3_build_index / z3_index_set_values cannot be captured.
+ * z3_contract and z3_build_index / z3_index_set_values cannot be captured, nor should
+ * z3_estimate_pivots and z3_estimate_cross_catalogues be: their pivot sort is rocPRIM's
+ * radix sort, whose launches are not part of what the library checks under capture.
  */
 z3_status z3_index_prepare_capture(z3_index idx, size_t min_bytes, size_t *reserved);
 
